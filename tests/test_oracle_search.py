@@ -1,0 +1,197 @@
+"""Oracle pins for the impulse search (Section III).
+
+* every emitted TS recounts to its (a,b) and is its own Tree();
+* the search finds every smallest trapping set that brute force enumerates;
+* its (a,0) sets reproduce the exact minimum distance (Gray code);
+* the whole search commutes with the QC shift automorphism.
+"""
+from collections import Counter
+
+import numpy as np
+import pytest
+
+import workloads
+
+
+def test_patterns_tiny(oracle_mod, tiny):
+    c, oc = tiny
+    s = oracle_mod.patterns(oc, oracle_mod.PAT_SINGLES)
+    assert s.shape == (96, 1) and (s[:, 0] == np.arange(96)).all()
+    p = oracle_mod.patterns(oc, oracle_mod.PAT_PAIRS)
+    # every variable has 15 variables at distance 2 (girth 6, dv=3, dc=6)
+    rp, col = oc.csr()
+    nb2 = [set() for _ in range(oc.n)]
+    for r in range(oc.m):
+        vs = col[rp[r]:rp[r + 1]]
+        for u in vs:
+            nb2[u].update(int(v) for v in vs if v != u)
+    assert all(len(x) == 15 for x in nb2)
+    want = set()
+    for u in range(oc.n):
+        d4 = set(nb2[u])
+        for w in nb2[u]:
+            d4 |= nb2[w]
+        d4.discard(u)
+        want |= {(min(u, v), max(u, v)) for v in d4}
+    assert set(map(tuple, p.tolist())) == want
+    assert (np.diff(p[:, 0]) >= 0).all()
+    t = oracle_mod.patterns(oc, oracle_mod.PAT_TRIPLES)
+    assert (t[:, 0] < t[:, 1]).all() and (t[:, 1] < t[:, 2]).all()
+    # 96 roots * 15 second variables * 10 third variables / 2 directions, except
+    # that the three variables of a 6-cycle are reached through three middles
+    n6 = oracle_mod.brute_ts(oc, 3, 12)[1][3].sum()
+    assert len(t) == 96 * 15 * 10 // 2 - 2 * n6
+
+
+def test_search_outputs_consistent(oracle_mod, tiny, tiny_search):
+    c, oc = tiny
+    pats, res = tiny_search
+    kc, ic, il = res["k_crit"], res["iters_crit"], res["iters_lo"]
+    assert ((kc == -1) | ((kc >= 1) & (kc <= 512))).all()
+    fails = kc >= 0
+    assert ((ic[fails] >= 1) & (ic[fails] <= 20)).all()
+    assert ((il >= 1) & (il <= 20)).all()
+    # decodes = 1 for patterns that never fail, 1 + 9 for the others
+    assert res["decodes"] == int((~fails).sum()) + 10 * int(fails.sum())
+    # re-decoding a pattern at k* fails and at k*-1 succeeds
+    qb = oracle_mod.q_base(3.0, 0.5)
+    rng = np.random.default_rng(3)
+    for p in rng.choice(np.nonzero(fails)[0], 25, replace=False):
+        for k, want in ((kc[p], 1), (kc[p] - 1, 0)):
+            q = np.full(oc.n, qb)
+            for v in pats[p]:
+                if v >= 0:
+                    q[v] = oracle_mod.q_impulse(qb, int(k))
+            r = oracle_mod.decode_oms(oc, q, 20, 1)
+            assert r["fail"] == want or (k == 0 and want == 0)
+            if want:
+                assert r["iters"] == ic[p]
+
+
+def test_emitted_sets_are_trapping_sets(oracle_mod, tiny, tiny_search):
+    """Definition check (Section II) on 100% of the emitted sets."""
+    c, oc = tiny
+    _, res = tiny_search
+    assert len(res["ts"]) > 0
+    seen = set()
+    for r in res["ts"]:
+        assert 1 <= r.a <= 6 and len(r.bits) == r.a
+        assert oracle_mod.count_b(oc, r.bits) == r.b
+        assert tuple(oracle_mod.tree(oc, r.bits)) == r.bits
+        cs, orbit = oracle_mod.canon(oc, r.bits)
+        assert tuple(cs) == r.bits and orbit == r.orbit
+        assert r.bits not in seen
+        seen.add(r.bits)
+    # total order: b/a, then a, then the tuple
+    keys = [(r.b / r.a, r.a, r.bits) for r in res["ts"]]
+    assert keys == sorted(keys)
+
+
+def test_search_recall_smallest_sets(oracle_mod, tiny, tiny_search):
+    """Brute force over all connected TS with a <= 6: the search recovers every
+    orbit of the smallest sizes (a <= 4), including the (4,0) codeword."""
+    c, oc = tiny
+    _, res = tiny_search
+    brute = oracle_mod.brute_ts_list(oc, 6)
+    found = {r.bits for r in res["ts"]}
+    by_cell = Counter((a, b) for a, b, _ in brute)
+    hit = Counter((a, b) for a, b, s in brute if s in found)
+    a_min = min(a for a, _ in by_cell)
+    for (a, b), n in by_cell.items():
+        if a <= 4:
+            assert hit[(a, b)] == n, ((a, b), hit[(a, b)], n)
+    assert a_min == 3
+    # every connected emitted set is one of the brute-force sets
+    brute_set = {s for _, _, s in brute}
+    adj = _var_adjacency(oc)
+    for r in res["ts"]:
+        if _connected(r.bits, adj):
+            assert r.bits in brute_set
+
+
+def _var_adjacency(oc):
+    rp, col = oc.csr()
+    adj = [set() for _ in range(oc.n)]
+    for r in range(oc.m):
+        vs = [int(v) for v in col[rp[r]:rp[r + 1]]]
+        for u in vs:
+            adj[u].update(v for v in vs if v != u)
+    return adj
+
+
+def _connected(s, adj):
+    s = set(s)
+    start = next(iter(s))
+    seen = {start}
+    stack = [start]
+    while stack:
+        u = stack.pop()
+        for v in adj[u] & s:
+            if v not in seen:
+                seen.add(v)
+                stack.append(v)
+    return seen == s
+
+
+def test_dmin_equals_smallest_codeword_ts(oracle_mod):
+    """Section II: TS(d_min, 0) are the minimum-weight codewords.  On the Z=8
+    variant (dimension small enough for Gray-code enumeration) the exact d_min,
+    the brute-force smallest (a,0) set and the search's smallest (a,0) set agree."""
+    c = workloads.tiny_code_z8()
+    oc = oracle_mod.OCode(c)
+    d, word = oracle_mod.dmin(oc)
+    assert oracle_mod.count_b(oc, word) == 0 and len(word) == d
+    n, counts, _ = oracle_mod.brute_ts(oc, 6, 12)
+    a0 = [a for a in range(7) if counts[a, 0]]
+    assert a0 and a0[0] == d
+    pats = oracle_mod.pattern_list(oc, [oracle_mod.PAT_SINGLES, oracle_mod.PAT_PAIRS])
+    res = oracle_mod.search(oc, pats, a_max=8)
+    cw = [r.a for r in res["ts"] if r.b == 0]
+    assert cw and min(cw) == d
+
+
+def test_dmin_tiny_code(oracle_mod, tiny, tiny_search):
+    """A minimum-weight codeword's support is connected and its own 2-core, so the
+    brute-force (a <= 6) list holds every codeword of weight <= 6."""
+    c, oc = tiny
+    n, counts, orbits = oracle_mod.brute_ts(oc, 6, 12)
+    assert counts[4, 0] == 16 and orbits[4, 0] == 1 and counts[:4, 0].sum() == 0
+    _, res = tiny_search
+    assert [r.a for r in res["ts"] if r.b == 0] == [4]
+
+
+@pytest.mark.parametrize("t", [1, 5, 11])
+def test_search_commutes_with_qc_shift(oracle_mod, tiny, tiny_search, t):
+    """QC automorphism: the search on sigma_t(patterns) gives identical k*,
+    iteration counts and the same canonical TS list."""
+    c, oc = tiny
+    pats, res = tiny_search
+    z = c.z
+    sp = np.where(pats >= 0, (pats // z) * z + (pats % z + t) % z, -1).astype(np.int32)
+    r2 = oracle_mod.search(oc, sp, a_max=6)
+    for key in ("k_crit", "iters_crit", "iters_lo", "tmin_crit", "n_cand"):
+        assert (r2[key] == res[key]).all(), key
+    a = [(r.a, r.b, r.orbit, r.k_crit, r.bits) for r in res["ts"]]
+    b = [(r.a, r.b, r.orbit, r.k_crit, r.bits) for r in r2["ts"]]
+    assert a == b
+
+
+def test_extract_critical_is_subset(oracle_mod, tiny, tiny_search):
+    c, oc = tiny
+    pats, res = tiny_search
+    r2 = oracle_mod.search(oc, pats, a_max=6, extract_mode=oracle_mod.EXTRACT_CRITICAL)
+    assert (r2["k_crit"] == res["k_crit"]).all()
+    assert (r2["n_cand"] <= res["n_cand"]).all()
+    assert {r.bits for r in r2["ts"]} <= {r.bits for r in res["ts"]}
+
+
+def test_spa_search_small(oracle_mod, tiny):
+    c, oc = tiny
+    pats = oracle_mod.patterns(oc, oracle_mod.PAT_PAIRS)[:200]
+    res = oracle_mod.search(oc, pats, decoder=oracle_mod.DEC_SPA, max_iter=50,
+                            k_max=32 * 1024, k_den=1024, a_max=6)
+    kc = res["k_crit"]
+    assert ((kc == -1) | (kc >= 1)).all()
+    assert res["decodes"] == int((kc < 0).sum()) + 16 * int((kc >= 0).sum())
+    for r in res["ts"]:
+        assert oracle_mod.count_b(oc, r.bits) == r.b
