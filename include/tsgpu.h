@@ -1,0 +1,230 @@
+/*
+ * tsgpu: trapping-set search of the modified Cole importance-sampling method
+ * (V. Usatyuk, "A Modified Cole's Importance Sampling Method for Low Error Floor
+ * QC-LDPC Codes Construction", arXiv 2208.05795) on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Every call returns a ts_status (0 = TS_OK, negative = error); the text
+ * of the last error of the calling thread is returned by ts_last_error().
+ *
+ * Conventions
+ *  - Indices are 0-based.  For a QC code the variable in block column j at
+ *    circulant position c is j*z + c, the check in block row i at position r is
+ *    i*z + r (Section II).
+ *  - The caller owns every input and output array; inputs are copied or consumed
+ *    before the call returns.  ts_ctx and ts_code are opaque and owned by the
+ *    library until ts_destroy / ts_free_code.
+ *  - Arrays named in ts_search_opts.mem == TS_MEM_DEVICE must be device memory on
+ *    the context's device (e.g. torch tensors); otherwise host memory.
+ *  - Every call on a context runs on the context's stream and returns after that
+ *    stream has finished the call's work.  Calls on one context are serialised by
+ *    an internal mutex; separate contexts are independent.
+ *  - No CPU fallback exists: without a usable HIP device, ts_create fails with
+ *    TS_E_DEVICE.
+ */
+#ifndef TSGPU_H
+#define TSGPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ts_ctx ts_ctx;
+typedef struct ts_code ts_code;
+
+typedef enum {
+    TS_OK = 0,
+    TS_E_INVAL = -1,     /* bad argument, shape or code */
+    TS_E_NOMEM = -2,     /* device or host allocation failed */
+    TS_E_DEVICE = -3,    /* HIP runtime error or no usable device */
+    TS_E_STATE = -4,     /* object used in the wrong state (e.g. wrong context) */
+    TS_E_BUSY = -5,      /* admission refused (memory budget) */
+    TS_E_TRUNC = -6,     /* output buffer too small; sizes were still reported */
+    TS_E_CANCELLED = -7  /* job cancelled */
+} ts_status;
+
+/* ---- context --------------------------------------------------------------- */
+
+typedef struct {
+    int32_t device;        /* HIP device ordinal */
+    void *hip_stream;      /* borrowed hipStream_t; NULL = the library creates one */
+    /* optional device allocator (both NULL = hipMalloc/hipFree); alloc returns
+     * NULL on failure */
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *user;
+    size_t hbm_budget_bytes;   /* 0 = no limit; the serving admission check uses it */
+} ts_ctx_opts;
+
+/* Creates a context on opts->device.  opts may be NULL (device 0, own stream).
+ * Errors: TS_E_DEVICE (no device / HIP failure), TS_E_INVAL. */
+int ts_create(const ts_ctx_opts *opts, ts_ctx **out);
+/* Frees the context and every code still loaded on it. */
+int ts_destroy(ts_ctx *ctx);
+/* Message of the last failed call on this thread ("" if none).  Valid until the
+ * thread's next call. */
+const char *ts_last_error(void);
+
+/* ---- codes (Section II, eq. 1-3) ------------------------------------------ */
+
+#define TS_CODE_CSR 1
+#define TS_CODE_QC 2
+
+typedef struct {
+    int32_t kind;              /* TS_CODE_CSR or TS_CODE_QC */
+    /* CSR form: H with rows = checks; row_ptr[m+1] (int64), col_idx[nnz] */
+    int32_t n, m;
+    int64_t nnz;
+    const int64_t *row_ptr;
+    const int32_t *col_idx;
+    /* QC form: mb x nb exponent matrix, row-major; -1 = zero block P^inf,
+     * 0..z-1 = the circulant P^s whose row r has its one in column (r+s) mod z */
+    int32_t mb, nb, z;
+    const int32_t *shifts;
+} ts_code_desc;
+
+/* Validates and expands the code, computes its girth (shortest Tanner-graph
+ * cycle, 0 = none) and uploads the graph to the device.  Host arrays only.
+ * Rejects (TS_E_INVAL): out-of-range entries, duplicate edges, empty columns,
+ * checks of degree < 2, n or m above 2^24. */
+int ts_load_code(ts_ctx *ctx, const ts_code_desc *desc, ts_code **out);
+
+typedef struct {
+    int32_t n, m;
+    int64_t e;          /* edges (nonzeros of H) */
+    int32_t girth;      /* 0 = cycle-free */
+    int32_t z;          /* circulant size, 0 for CSR codes */
+    int32_t dv_max, dc_max;
+} ts_code_info_t;
+int ts_code_info(const ts_code *code, ts_code_info_t *out);
+/* Check-major CSR of the expanded H (host arrays row_ptr[m+1], col[e]). */
+int ts_code_csr(const ts_code *code, int64_t *row_ptr, int32_t *col);
+int ts_free_code(ts_ctx *ctx, ts_code *code);
+
+/* ---- impulse patterns (Section III, impulse tree of Fig. 3) ----------------- */
+
+#define TS_PAT_SINGLES 1   /* every variable alone (width 1) */
+#define TS_PAT_PAIRS 2     /* every pair at Tanner distance 2 or 4 (width 2) */
+#define TS_PAT_TRIPLES 3   /* every {v1,v2,v3} on a tree path v1-c-v2-c'-v3, c != c' (width 3) */
+
+/* Writes the sorted pattern list of one family (row-major, width = kind) to the
+ * host array out when cap (in patterns) allows; *n_out = number of patterns.
+ * Returns TS_E_TRUNC when cap is too small (out untouched). */
+int ts_make_patterns(ts_ctx *ctx, const ts_code *code, int32_t kind, int32_t *out,
+                     int64_t cap, int64_t *n_out);
+
+/* ---- impulse search with bisection (Section III) --------------------------- */
+
+#define TS_DEC_OMS_I8 0     /* offset min-sum, saturating int8 messages */
+#define TS_DEC_SPA_F32 1    /* sum-product, float32 */
+#define TS_EXTRACT_PATH 0      /* candidates from every failing decode of the bisection */
+#define TS_EXTRACT_CRITICAL 1  /* candidates from the decode at k* only */
+#define TS_MEM_HOST 0
+#define TS_MEM_DEVICE 1
+
+typedef struct {
+    int32_t decoder;           /* TS_DEC_* */
+    int32_t max_iter;          /* flooding iterations per decode, 1..64 */
+    int32_t oms_offset;        /* OMS offset beta on the int8 scale (>= 0) */
+    double ebn0_db, rate;      /* sigma^2 = 1/(2 rate 10^(ebn0/10)), h = 2/sigma^2 */
+    double llr_scale;          /* OMS: int8 value of an unperturbed bit is round(llr_scale*h) */
+    int32_t k_max;             /* amplitude grid eps_k = k/k_den, k = 0..k_max */
+    int32_t k_den;             /* OMS requires 16 */
+    int32_t a_max;             /* largest TS kept, 1..16 */
+    int32_t extract_mode;      /* TS_EXTRACT_* */
+    int32_t collect_from_iter; /* first iteration whose error set is sieved; -1 = girth/2 */
+    int32_t mem;               /* TS_MEM_HOST / TS_MEM_DEVICE for patterns and outputs */
+} ts_search_opts;
+
+typedef struct {            /* caller-owned arrays of n_patterns entries */
+    int32_t *k_crit;        /* critical grid index k*, -1 = decoded at every amplitude */
+    int32_t *iters_crit;    /* iterations of the decode at k* (0 if k* = -1) */
+    int32_t *iters_lo;      /* iterations of the last successful decode on the path */
+    int32_t *tmin_crit;     /* first minimum-syndrome iteration at k* (0 if k* = -1) */
+    int32_t *n_cand;        /* nonempty candidate sets with a <= a_max (before dedup) */
+} ts_search_out;
+
+/* For every pattern (row p of patterns[n_patterns][width], entries -1 = unused,
+ * width 1..16) the impulse bits get h(1 - eps), all others h, on the all-zero
+ * BPSK codeword.  The decode at k_max runs first; if it fails, bisection on
+ * [0, k_max] finds k* (fail at k*, success at k*-1).  From failing decodes the
+ * error sets S(x_t) of iterations collect_from_iter..last are sieved into
+ * S1 = Tree(S u I) and S2 = Tree(TS(S u I)) when |S u I| <= 2 a_max; every
+ * nonempty result with a <= a_max is canonicalised to its QC-orbit
+ * representative and merged into the code's TS table (read by ts_collect).
+ * Tree(V): variables of the 2-core of the subgraph induced by V.  TS(V): V plus
+ * every outside variable with two checks in one connected component of it. */
+int ts_impulse_search(ts_ctx *ctx, ts_code *code, const ts_search_opts *opts,
+                      const int32_t *patterns, int32_t n_patterns, int32_t width,
+                      ts_search_out *out);
+
+/* ---- collected trapping sets (Section II TS(a,b), Section III ordering) ----- */
+
+typedef struct {
+    int32_t a, b;            /* |set|, odd-degree checks of the induced subgraph */
+    int32_t orbit;           /* size of its QC shift orbit (1 for CSR codes) */
+    int32_t first_pattern;   /* smallest pattern index that produced it */
+    int32_t k_crit;          /* smallest k* among the patterns that produced it */
+    int32_t reserved;
+    int64_t bits_off;        /* offset of its variables in the bits array */
+} ts_record;
+
+/* Copies the code's TS table, ordered by b/a, then a, then the canonical tuple.
+ * recs[cap] and bits[bits_cap] are host arrays; cap = 0 queries sizes only.
+ * *n_out / *bits_out always receive the full sizes; TS_E_TRUNC if they exceed
+ * the capacities. */
+int ts_collect(ts_ctx *ctx, const ts_code *code, ts_record *recs, int64_t cap,
+               int64_t *n_out, int32_t *bits, int64_t bits_cap, int64_t *bits_out);
+/* Empties the code's TS table. */
+int ts_reset_ts(ts_ctx *ctx, ts_code *code);
+
+/* ---- importance sampling of one TS (Section I/II, Cole's TS weighting) ------ */
+
+typedef struct {
+    int32_t max_iter;        /* SPA iterations */
+    double ebn0_db, rate;
+    double shift;            /* mean shift s of the TS bits; < 0: s = eps* of the
+                              * SPA impulse on the whole set (grid 2^-10 up to 32) */
+    int64_t n_frames;        /* >= 2 */
+    uint64_t seed;           /* Philox key */
+    uint64_t frame_base;     /* first frame counter (resumable streams) */
+    uint32_t stream;         /* Philox stream tag */
+} ts_is_opts;
+
+typedef struct {
+    double p_hat, var, ci_lo, ci_hi, sum_w, sum_w2;
+    int64_t n, n_fail;
+    double shift_used;
+} ts_is_result;
+
+/* Frame f draws n_v ~ N(0,1) from Philox4x32-10 (counter (v>>2, f_lo, f_hi,
+ * stream), key = seed, Box-Muller), receives y_v = 1 - s[v in T] + sigma n_v,
+ * is decoded by float32 SPA, and contributes 1[fail] w with
+ * w = exp(-a s^2/(2 sigma^2) + (s/sigma) sum_{v in T} n_v).  P = mean, Var =
+ * sample variance / K, 95% CI = P +- 1.96 sqrt(Var).  fail_out (optional host
+ * array [n_frames]) receives each frame's failure flag. */
+int ts_is_estimate(ts_ctx *ctx, ts_code *code, const int32_t *ts_bits, int32_t a,
+                   const ts_is_opts *opts, ts_is_result *res, uint8_t *fail_out);
+
+/* ---- measurements of the last call ---------------------------------------- */
+
+typedef struct {
+    double decode_ms;        /* summed HIP-event time of the decode kernels */
+    double extract_ms;       /* same for the sieve/canonicalise/insert kernels */
+    double total_ms;         /* the whole call on the stream */
+    int64_t decodes;         /* decodes executed */
+    int64_t edge_updates;    /* sum over decodes of iterations x edges */
+    int64_t candidates;      /* raw candidate error sets written */
+    int32_t decode_launches;
+    int32_t extract_launches;
+    int32_t block_threads;   /* workgroup size of the decode kernel */
+    int32_t grid_blocks;     /* workgroups of the decode kernel */
+} ts_stats;
+int ts_get_stats(ts_ctx *ctx, ts_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TSGPU_H */

@@ -1,0 +1,265 @@
+"""tsgpu: the trapping-set search of the modified Cole importance-sampling method
+(arXiv 2208.05795) on AMD Instinct MI355X.
+
+Thin Python binding over the C ABI of include/tsgpu.h: it only marshals
+arguments.  Every step runs inside libtsgpu.so (HIP kernels for gfx950); PyTorch
+provides device memory (its caching allocator) and the stream.  There is no CPU
+fallback: without the built library or a GPU every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import _capi as A
+
+__all__ = ["Context", "Code", "TsRecord", "TsgError", "DEC_OMS", "DEC_SPA",
+           "PAT_SINGLES", "PAT_PAIRS", "PAT_TRIPLES", "EXTRACT_PATH", "EXTRACT_CRITICAL"]
+
+DEC_OMS, DEC_SPA = A.TS_DEC_OMS_I8, A.TS_DEC_SPA_F32
+PAT_SINGLES, PAT_PAIRS, PAT_TRIPLES = A.TS_PAT_SINGLES, A.TS_PAT_PAIRS, A.TS_PAT_TRIPLES
+EXTRACT_PATH, EXTRACT_CRITICAL = A.TS_EXTRACT_PATH, A.TS_EXTRACT_CRITICAL
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = A.load()
+    return _lib
+
+
+class TsgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"tsgpu status {status}: {msg}")
+        self.status = status
+
+
+def _check(rc: int):
+    if rc != A.TS_OK:
+        raise TsgError(rc, lib().ts_last_error().decode(errors="replace"))
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _is_torch_cuda(x) -> bool:
+    return type(x).__module__.startswith("torch") and getattr(x, "is_cuda", False)
+
+
+@dataclass
+class TsRecord:
+    a: int
+    b: int
+    orbit: int
+    first_pattern: int
+    k_crit: int
+    bits: Tuple[int, ...]
+
+
+class Context:
+    """A device, a stream and an allocator.  By default the stream and the
+    allocator are torch's (current stream, caching allocator)."""
+
+    def __init__(self, device: int = 0, torch_stream: bool = True, torch_alloc: bool = True,
+                 hbm_budget_bytes: int = 0):
+        L = lib()
+        self._keep = []
+        opts = A.CtxOpts()
+        opts.device = device
+        opts.hbm_budget_bytes = hbm_budget_bytes
+        self.device = device
+        if torch_stream or torch_alloc:
+            import torch
+            if not torch.cuda.is_available():
+                raise TsgError(A.TS_E_DEVICE, "no GPU visible to torch")
+            torch.cuda.set_device(device)
+            if torch_stream:
+                opts.hip_stream = C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+            if torch_alloc:
+                dev = device
+
+                def _alloc(nbytes, user):
+                    try:
+                        return torch.cuda.caching_allocator_alloc(
+                            int(nbytes), dev, torch.cuda.current_stream(dev))
+                    except Exception:   # noqa: BLE001 - reported to C as NULL
+                        return None
+
+                def _free(ptr, user):
+                    torch.cuda.caching_allocator_delete(ptr)
+
+                fa, ff = A.ALLOC_FN(_alloc), A.FREE_FN(_free)
+                self._keep += [fa, ff]
+                opts.alloc = fa
+                opts.free = ff
+        h = C.c_void_p()
+        _check(L.ts_create(C.byref(opts), C.byref(h)))
+        self._h = h
+        self._codes: List[Code] = []
+
+    @property
+    def handle(self):
+        return self._h
+
+    def load_code(self, code) -> "Code":
+        return Code(self, code)
+
+    def stats(self) -> dict:
+        s = A.Stats()
+        _check(lib().ts_get_stats(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in A.Stats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for c in list(self._codes):
+                c._h = None
+            lib().ts_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:   # noqa: BLE001
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Code:
+    """A parity-check matrix loaded on a context (QC or CSR form, see workloads.Code)."""
+
+    def __init__(self, ctx: Context, code):
+        self.ctx = ctx
+        self.src = code
+        d = A.CodeDesc()
+        keep = []
+        if code.kind == "qc":
+            sh = _i32(code.shifts).ravel()
+            keep.append(sh)
+            d.kind, d.mb, d.nb, d.z = A.TS_CODE_QC, code.mb, code.nb, code.z
+            d.shifts = sh.ctypes.data
+        else:
+            rp = np.ascontiguousarray(code.row_ptr, dtype=np.int64)
+            col = _i32(code.col)
+            keep += [rp, col]
+            d.kind, d.n, d.m, d.nnz = A.TS_CODE_CSR, code.n, code.m, int(rp[-1])
+            d.row_ptr, d.col_idx = rp.ctypes.data, col.ctypes.data
+        h = C.c_void_p()
+        _check(lib().ts_load_code(ctx.handle, C.byref(d), C.byref(h)))
+        self._h = h
+        ctx._codes.append(self)
+        info = A.CodeInfo()
+        _check(lib().ts_code_info(h, C.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in A.CodeInfo._fields_}
+        self.n, self.m, self.e = info.n, info.m, info.e
+        self.girth, self.z = info.girth, info.z
+
+    def csr(self):
+        rp = np.zeros(self.m + 1, dtype=np.int64)
+        col = np.zeros(self.e, dtype=np.int32)
+        _check(lib().ts_code_csr(self._h, rp.ctypes.data, col.ctypes.data))
+        return rp, col
+
+    def make_patterns(self, kind: int) -> np.ndarray:
+        n = C.c_int64()
+        _check(lib().ts_make_patterns(self.ctx.handle, self._h, kind, None, 0, C.byref(n)))
+        out = np.zeros((n.value, kind), dtype=np.int32)
+        _check(lib().ts_make_patterns(self.ctx.handle, self._h, kind, out.ctypes.data,
+                                      n.value, C.byref(n)))
+        return out
+
+    def pattern_list(self, kinds: Sequence[int]) -> np.ndarray:
+        parts = [self.make_patterns(k) for k in kinds]
+        w = max(p.shape[1] for p in parts)
+        rows = [np.pad(p, ((0, 0), (0, w - p.shape[1])), constant_values=-1) for p in parts]
+        return np.ascontiguousarray(np.concatenate(rows, axis=0).astype(np.int32))
+
+    def impulse_search(self, patterns, decoder: int = DEC_OMS, max_iter: int = 20,
+                       oms_offset: int = 1, ebn0_db: float = 3.0, rate: Optional[float] = None,
+                       llr_scale: float = 4.0, k_max: int = 512, k_den: int = 16, a_max: int = 6,
+                       extract_mode: int = EXTRACT_PATH, collect_from_iter: int = -1) -> dict:
+        """Patterns: numpy (host) or a torch int32 CUDA tensor [P, width] (device);
+        outputs come back in the same kind of memory."""
+        rate = (1.0 - self.m / self.n) if rate is None else rate
+        o = A.SearchOpts(decoder, max_iter, oms_offset, ebn0_db, rate, llr_scale, k_max, k_den,
+                         a_max, extract_mode, collect_from_iter, A.TS_MEM_HOST)
+        out = A.SearchOut()
+        if _is_torch_cuda(patterns):
+            import torch
+            pats = patterns.contiguous()
+            if pats.dtype != torch.int32 or pats.dim() != 2:
+                raise ValueError("device patterns must be an int32 [P, width] tensor")
+            P, W = pats.shape
+            res = {k: torch.empty(P, dtype=torch.int32, device=pats.device)
+                   for k in ("k_crit", "iters_crit", "iters_lo", "tmin_crit", "n_cand")}
+            o.mem = A.TS_MEM_DEVICE
+            ptr = pats.data_ptr()
+        else:
+            pats = _i32(patterns)
+            if pats.ndim == 1:
+                pats = pats.reshape(-1, 1)
+            P, W = pats.shape
+            res = {k: np.zeros(P, dtype=np.int32)
+                   for k in ("k_crit", "iters_crit", "iters_lo", "tmin_crit", "n_cand")}
+            ptr = pats.ctypes.data
+
+        def addr(x):
+            return x.data_ptr() if o.mem == A.TS_MEM_DEVICE else x.ctypes.data
+
+        out.k_crit, out.iters_crit = addr(res["k_crit"]), addr(res["iters_crit"])
+        out.iters_lo, out.tmin_crit = addr(res["iters_lo"]), addr(res["tmin_crit"])
+        out.n_cand = addr(res["n_cand"])
+        _check(lib().ts_impulse_search(self.ctx.handle, self._h, C.byref(o), ptr, int(P), int(W),
+                                       C.byref(out)))
+        res["stats"] = self.ctx.stats()
+        return res
+
+    def collect(self) -> List[TsRecord]:
+        L = lib()
+        n, nb = C.c_int64(), C.c_int64()
+        _check(L.ts_collect(self.ctx.handle, self._h, None, 0, C.byref(n), None, 0, C.byref(nb)))
+        recs = (A.Record * max(n.value, 1))()
+        bits = np.zeros(max(nb.value, 1), dtype=np.int32)
+        _check(L.ts_collect(self.ctx.handle, self._h, recs, n.value, C.byref(n),
+                            bits.ctypes.data, nb.value, C.byref(nb)))
+        out = []
+        for i in range(n.value):
+            r = recs[i]
+            out.append(TsRecord(r.a, r.b, r.orbit, r.first_pattern, r.k_crit,
+                                tuple(int(x) for x in bits[r.bits_off:r.bits_off + r.a])))
+        return out
+
+    def reset_ts(self):
+        _check(lib().ts_reset_ts(self.ctx.handle, self._h))
+
+    def is_estimate(self, ts_bits, ebn0_db: float, shift: float, n_frames: int, seed: int,
+                    frame_base: int = 0, stream: int = 0, max_iter: int = 50,
+                    rate: Optional[float] = None, want_fail: bool = False) -> dict:
+        rate = (1.0 - self.m / self.n) if rate is None else rate
+        t = _i32(ts_bits)
+        o = A.IsOpts(max_iter, ebn0_db, rate, shift, n_frames, seed, frame_base, stream)
+        r = A.IsResult()
+        fo = np.zeros(n_frames, dtype=np.uint8) if want_fail else None
+        _check(lib().ts_is_estimate(self.ctx.handle, self._h, t.ctypes.data, t.size, C.byref(o),
+                                    C.byref(r), fo.ctypes.data if want_fail else None))
+        out = {f: getattr(r, f) for f, _ in A.IsResult._fields_}
+        out["stats"] = self.ctx.stats()
+        if want_fail:
+            out["fail"] = fo
+        return out
+
+    def free(self):
+        if getattr(self, "_h", None) and self.ctx.handle:
+            _check(lib().ts_free_code(self.ctx.handle, self._h))
+            self.ctx._codes.remove(self)
+        self._h = None

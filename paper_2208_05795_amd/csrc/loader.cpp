@@ -1,0 +1,270 @@
+// Code loading: validation, QC expansion, adjacency, girth, device upload, and
+// the impulse pattern families.
+//
+// QC expansion (Section II, eq. 1-3): the circulant P^s has the one of row r in
+// column (r+s) mod z; block (i,j) with exponent s joins check i*z+r to variable
+// j*z+(r+s) mod z, and exponent -1 is the zero block.
+#include <algorithm>
+#include <array>
+#include <cstring>
+#include <queue>
+
+#include "internal.h"
+
+namespace tsg {
+
+namespace {
+
+// Shortest cycle of the Tanner graph: breadth-first search from every variable
+// with the parent node recorded; a non-tree edge (x,y) closes a cycle of length
+// d(x) + d(y) + 1 through the root's tree, and the minimum over all roots is
+// the girth.
+int girth_bfs(const ts_code *c) {
+    const int nv = c->n, nn = c->n + c->m;
+    std::vector<int> dist(nn, -1), parent(nn, -1), touched;
+    std::vector<int> q;
+    q.reserve(nn);
+    touched.reserve(nn);
+    int best = 0;
+    for (int root = 0; root < nv; ++root) {
+        for (int x : touched) dist[x] = -1;
+        touched.clear();
+        q.clear();
+        dist[root] = 0;
+        parent[root] = -1;
+        touched.push_back(root);
+        q.push_back(root);
+        for (size_t h = 0; h < q.size(); ++h) {
+            const int x = q[h];
+            if (best && 2 * dist[x] + 1 >= best) break;
+            const bool is_var = x < nv;
+            const int64_t lo = is_var ? c->vptr[x] : c->row_ptr[x - nv];
+            const int64_t hi = is_var ? c->vptr[x + 1] : c->row_ptr[x - nv + 1];
+            for (int64_t k = lo; k < hi; ++k) {
+                const int y = is_var ? nv + c->vchk[k] : c->col[k];
+                if (y == parent[x]) continue;
+                if (dist[y] < 0) {
+                    dist[y] = dist[x] + 1;
+                    parent[y] = x;
+                    touched.push_back(y);
+                    q.push_back(y);
+                } else {
+                    const int len = dist[x] + dist[y] + 1;
+                    if (!best || len < best) best = len;
+                }
+            }
+        }
+    }
+    return best;
+}
+
+}  // namespace
+
+int build_code(const ts_code_desc *d, ts_code *c) {
+    if (!d) { set_error("null code description"); return TS_E_INVAL; }
+    if (d->kind == TS_CODE_QC) {
+        if (d->mb <= 0 || d->nb <= 0 || d->z <= 0 || !d->shifts) {
+            set_error("QC code needs mb, nb, z > 0 and shifts");
+            return TS_E_INVAL;
+        }
+        const int64_t n = (int64_t)d->nb * d->z, m = (int64_t)d->mb * d->z;
+        if (n > (1 << 24) || m > (1 << 24)) { set_error("code too large"); return TS_E_INVAL; }
+        for (int i = 0; i < d->mb * d->nb; ++i)
+            if (d->shifts[i] < -1 || d->shifts[i] >= d->z) {
+                set_error("shift %d at %d outside [-1, z)", d->shifts[i], i);
+                return TS_E_INVAL;
+            }
+        c->n = (int)n;
+        c->m = (int)m;
+        c->z = d->z;
+        c->mb = d->mb;
+        c->nb = d->nb;
+        c->row_ptr.assign((size_t)m + 1, 0);
+        c->col.clear();
+        for (int i = 0; i < d->mb; ++i)
+            for (int r = 0; r < d->z; ++r) {
+                const size_t start = c->col.size();
+                for (int j = 0; j < d->nb; ++j) {
+                    const int s = d->shifts[i * d->nb + j];
+                    if (s >= 0) c->col.push_back(j * d->z + (r + s) % d->z);
+                }
+                std::sort(c->col.begin() + start, c->col.end());
+                c->row_ptr[(size_t)i * d->z + r + 1] = (int64_t)c->col.size();
+            }
+    } else if (d->kind == TS_CODE_CSR) {
+        if (d->n <= 0 || d->m <= 0 || !d->row_ptr || (d->nnz > 0 && !d->col_idx)) {
+            set_error("CSR code needs n, m > 0 and arrays");
+            return TS_E_INVAL;
+        }
+        if (d->n > (1 << 24) || d->m > (1 << 24)) { set_error("code too large"); return TS_E_INVAL; }
+        if (d->row_ptr[0] != 0 || d->row_ptr[d->m] != d->nnz) {
+            set_error("row_ptr must start at 0 and end at nnz");
+            return TS_E_INVAL;
+        }
+        c->n = d->n;
+        c->m = d->m;
+        c->z = 0;
+        c->row_ptr.assign(d->row_ptr, d->row_ptr + d->m + 1);
+        c->col.assign(d->col_idx, d->col_idx + d->nnz);
+        for (int r = 0; r < d->m; ++r) {
+            if (c->row_ptr[r + 1] < c->row_ptr[r]) { set_error("row_ptr not monotone"); return TS_E_INVAL; }
+            std::sort(c->col.begin() + c->row_ptr[r], c->col.begin() + c->row_ptr[r + 1]);
+        }
+        for (int64_t k = 0; k < d->nnz; ++k)
+            if (c->col[k] < 0 || c->col[k] >= d->n) {
+                set_error("column %d out of range", c->col[k]);
+                return TS_E_INVAL;
+            }
+    } else {
+        set_error("unknown code kind %d", d->kind);
+        return TS_E_INVAL;
+    }
+    c->e = (int64_t)c->col.size();
+    if (c->e >= (int64_t)1 << 30) { set_error("too many edges"); return TS_E_INVAL; }
+    c->dc_max = 0;
+    for (int r = 0; r < c->m; ++r) {
+        const int deg = (int)(c->row_ptr[r + 1] - c->row_ptr[r]);
+        if (deg < 2) { set_error("check %d has degree %d (< 2)", r, deg); return TS_E_INVAL; }
+        for (int64_t k = c->row_ptr[r] + 1; k < c->row_ptr[r + 1]; ++k)
+            if (c->col[k] == c->col[k - 1]) { set_error("duplicate edge in check %d", r); return TS_E_INVAL; }
+        c->dc_max = std::max(c->dc_max, deg);
+    }
+    // variable side: counting sort of the edges by variable
+    c->vptr.assign((size_t)c->n + 1, 0);
+    for (int32_t v : c->col) c->vptr[v + 1]++;
+    for (int v = 0; v < c->n; ++v) c->vptr[v + 1] += c->vptr[v];
+    c->vchk.assign((size_t)c->e, 0);
+    c->vedge.assign((size_t)c->e, 0);
+    std::vector<int64_t> pos(c->vptr.begin(), c->vptr.end() - 1);
+    for (int r = 0; r < c->m; ++r)
+        for (int64_t k = c->row_ptr[r]; k < c->row_ptr[r + 1]; ++k) {
+            const int v = c->col[k];
+            c->vchk[pos[v]] = r;
+            c->vedge[pos[v]] = (int32_t)k;
+            pos[v]++;
+        }
+    c->dv_max = 0;
+    for (int v = 0; v < c->n; ++v) {
+        const int deg = (int)(c->vptr[v + 1] - c->vptr[v]);
+        if (deg == 0) { set_error("variable %d has no check", v); return TS_E_INVAL; }
+        c->dv_max = std::max(c->dv_max, deg);
+    }
+    c->girth = girth_bfs(c);
+    return TS_OK;
+}
+
+int upload_code(ts_ctx *ctx, ts_code *c) {
+    DevCode &d = c->dev;
+    d.n = c->n;
+    d.m = c->m;
+    d.e = (int)c->e;
+    d.dv_max = c->dv_max;
+    d.dc_max = c->dc_max;
+    d.z = c->z;
+    // padded tables: cn_tab[j][check] = j-th variable of the check, vn_tab[d][var] =
+    // edge of the var's d-th check; both with a column stride rounded to 64
+    d.dc_pad = c->dc_max;
+    d.m_tab = (c->m + 63) / 64 * 64;
+    d.dv_pad = c->dv_max;
+    d.n_tab = (c->n + 63) / 64 * 64;
+    std::vector<int32_t> rp32(c->row_ptr.begin(), c->row_ptr.end());
+    std::vector<int32_t> vp32(c->vptr.begin(), c->vptr.end());
+    std::vector<int32_t> cn((size_t)d.dc_pad * d.m_tab, -1), vn((size_t)d.dv_pad * d.n_tab, -1);
+    for (int r = 0; r < c->m; ++r)
+        for (int64_t k = c->row_ptr[r]; k < c->row_ptr[r + 1]; ++k)
+            cn[(size_t)(k - c->row_ptr[r]) * d.m_tab + r] = c->col[k];
+    for (int v = 0; v < c->n; ++v)
+        for (int64_t k = c->vptr[v]; k < c->vptr[v + 1]; ++k)
+            vn[(size_t)(k - c->vptr[v]) * d.n_tab + v] = c->vedge[k];
+    struct Up { const void *src; size_t bytes; const int **dst; } ups[] = {
+        {rp32.data(), rp32.size() * 4, &d.row_ptr}, {c->col.data(), c->col.size() * 4, &d.col},
+        {vp32.data(), vp32.size() * 4, &d.vptr},    {c->vchk.data(), c->vchk.size() * 4, &d.vchk},
+        {c->vedge.data(), c->vedge.size() * 4, &d.vedge}, {cn.data(), cn.size() * 4, &d.cn_tab},
+        {vn.data(), vn.size() * 4, &d.vn_tab},
+    };
+    for (auto &u : ups) {
+        void *p = ctx->dalloc(u.bytes ? u.bytes : 4);
+        if (!p) { set_error("device allocation of %zu bytes failed", u.bytes); return TS_E_NOMEM; }
+        c->dev_allocs.push_back(p);
+        TSG_HIP(hipMemcpyAsync(p, u.src, u.bytes, hipMemcpyHostToDevice, ctx->stream));
+        *u.dst = (const int *)p;
+    }
+    TSG_HIP(hipStreamSynchronize(ctx->stream));
+    return TS_OK;
+}
+
+// Impulse pattern families drawn from the depth-3 impulse tree of Section III
+// (VN1-CN1-VN2-CN2-VN3): single roots, pairs of variables at Tanner distance 2
+// or 4, and the variable sets of tree paths v1-c-v2-c'-v3 with c != c'.
+int64_t make_patterns(const ts_code *c, int kind, int32_t *out, int64_t cap) {
+    const int n = c->n;
+    auto checks_of = [&](int v, auto &&f) {
+        for (int64_t p = c->vptr[v]; p < c->vptr[v + 1]; ++p) f(c->vchk[p]);
+    };
+    auto vars_of = [&](int ch, auto &&f) {
+        for (int64_t q = c->row_ptr[ch]; q < c->row_ptr[ch + 1]; ++q) f(c->col[q]);
+    };
+    int64_t cnt = 0;
+    if (kind == TS_PAT_SINGLES) {
+        for (int v = 0; v < n; ++v) {
+            if (cnt < cap) out[cnt] = v;
+            ++cnt;
+        }
+        return cnt;
+    }
+    if (kind == TS_PAT_PAIRS) {
+        std::vector<int> stamp(n, -1), ring1;
+        std::vector<int> near;
+        for (int u = 0; u < n; ++u) {
+            ring1.clear();
+            near.clear();
+            stamp[u] = u;
+            checks_of(u, [&](int ch) {
+                vars_of(ch, [&](int w) {
+                    if (stamp[w] != u) { stamp[w] = u; ring1.push_back(w); near.push_back(w); }
+                });
+            });
+            for (int w : ring1)
+                checks_of(w, [&](int ch) {
+                    vars_of(ch, [&](int x) {
+                        if (stamp[x] != u) { stamp[x] = u; near.push_back(x); }
+                    });
+                });
+            std::sort(near.begin(), near.end());
+            for (int v : near)
+                if (v > u) {
+                    if (cnt < cap) { out[2 * cnt] = u; out[2 * cnt + 1] = v; }
+                    ++cnt;
+                }
+        }
+        return cnt;
+    }
+    if (kind == TS_PAT_TRIPLES) {
+        std::vector<std::array<int32_t, 3>> all;
+        for (int v1 = 0; v1 < n; ++v1)
+            checks_of(v1, [&](int ch) {
+                vars_of(ch, [&](int v2) {
+                    if (v2 == v1) return;
+                    checks_of(v2, [&](int ch2) {
+                        if (ch2 == ch) return;
+                        vars_of(ch2, [&](int v3) {
+                            if (v3 == v1 || v3 == v2) return;
+                            std::array<int32_t, 3> t{v1, v2, v3};
+                            std::sort(t.begin(), t.end());
+                            all.push_back(t);
+                        });
+                    });
+                });
+            });
+        std::sort(all.begin(), all.end());
+        all.erase(std::unique(all.begin(), all.end()), all.end());
+        for (auto &t : all) {
+            if (cnt < cap) std::memcpy(out + 3 * cnt, t.data(), 12);
+            ++cnt;
+        }
+        return cnt;
+    }
+    return -1;
+}
+
+}  // namespace tsg

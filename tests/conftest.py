@@ -3,6 +3,11 @@ import sys
 
 import pytest
 
+try:   # imported at collection so that its first (slow) load is not charged to a test
+    import torch  # noqa: F401
+except Exception:  # noqa: BLE001
+    torch = None
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

@@ -1,0 +1,91 @@
+"""The C-ABI library loads, exports every function include/tsgpu.h declares, and
+refuses to run without a GPU (no CPU fallback).  No compute calls here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tsgpu.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ts_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def libpath():
+    from paper_2208_05795_amd import _capi
+    if not os.path.exists(_capi.LIB_PATH):
+        from paper_2208_05795_amd import build
+        build.build()
+    return _capi.LIB_PATH
+
+
+def test_every_declared_symbol_is_exported(libpath):
+    lib = ctypes.CDLL(libpath)
+    names = _declared()
+    assert "ts_impulse_search" in names and "ts_collect" in names and "ts_is_estimate" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_header():
+    from paper_2208_05795_amd import _capi
+    assert set(_capi.PROTOTYPES) == set(_declared())
+
+
+def test_struct_sizes_match_header(libpath, tmp_path):
+    """Compile a host probe against the header and compare sizeof/offsetof with ctypes."""
+    import shutil
+    import subprocess
+    from paper_2208_05795_amd import _capi as A
+    gcc = shutil.which("gcc")
+    if not gcc:
+        pytest.skip("gcc missing")
+    structs = {"ts_ctx_opts": A.CtxOpts, "ts_code_desc": A.CodeDesc, "ts_code_info_t": A.CodeInfo,
+               "ts_search_opts": A.SearchOpts, "ts_search_out": A.SearchOut, "ts_record": A.Record,
+               "ts_is_opts": A.IsOpts, "ts_is_result": A.IsResult, "ts_stats": A.Stats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "tsgpu.h"', "int main(void){"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0;}")
+    src = tmp_path / "p.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "p"
+    subprocess.run([gcc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True,
+                                                         text=True).stdout.split("\n") if l)
+    for cname, py in structs.items():
+        assert int(out[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(out[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
+def test_no_gpu_means_device_error(libpath):
+    """Without a GPU the library reports TS_E_DEVICE instead of computing anything."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2208_05795_amd import _capi as A
+    lib = A.load()
+    h = ctypes.c_void_p()
+    rc = lib.ts_create(None, ctypes.byref(h))
+    assert rc == A.TS_E_DEVICE
+    assert b"device" in lib.ts_last_error()
+
+
+def test_python_binding_raises_without_gpu(libpath):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    import paper_2208_05795_amd as tsg
+    with pytest.raises(tsg.TsgError):
+        tsg.Context(0)
+    with pytest.raises(tsg.TsgError):
+        tsg.Context(0, torch_stream=False, torch_alloc=False)
