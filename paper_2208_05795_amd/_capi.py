@@ -93,7 +93,16 @@ PROTOTYPES = {
 
 
 def load(path: str = LIB_PATH):
-    """Loads the library and declares every prototype.  Raises if it is missing."""
+    """Loads the library and declares every prototype.  Raises if it is missing.
+
+    torch ships its own HIP runtime under the same soname (libamdhip64.so.7).
+    Importing torch first makes the dynamic linker bind this library to that
+    already-loaded runtime, so the process holds one HIP runtime and torch's
+    streams and allocations are valid here."""
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(path):
         raise RuntimeError(
             f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "

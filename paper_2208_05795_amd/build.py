@@ -23,6 +23,8 @@ def _hipcc() -> str:
 
 def flags():
     return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+            # code objects loadable by the HIP runtime that torch bundles as well
+            "-mcode-object-version=5",
             # keep the compiler from emitting packed fp32 instructions
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wall", "-Wno-unused-result"]
