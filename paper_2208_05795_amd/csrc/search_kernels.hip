@@ -1,30 +1,32 @@
-// Impulse search kernels (Section III): error-impulse channel, flooding decoding
-// iteration by iteration, bisection on the impulse amplitude and the write-out
-// of the error sets that are sieved into trapping-set candidates.
+// Decoding kernels of the trapping-set search (Section III) and of the IS
+// estimator: error-impulse or noisy channel on the all-zero BPSK codeword,
+// flooding message passing iteration by iteration, bisection on the impulse
+// amplitude, and the write-out of the error sets that the sieve turns into
+// trapping-set candidates.
 //
-// Layout.  One workgroup owns one impulse pattern at a time (persistent grid,
-// patterns taken from an atomic queue) and keeps the whole frame on chip for
-// all of its decodes: the APP values live in LDS, the check-to-variable
-// messages of the checks a thread owns live in that thread's registers, and the
-// check neighbour lists are loaded into registers once per kernel.  A thread
-// owns checks tid, tid+B, ... (B = workgroup size); for a QC code consecutive
-// threads own consecutive rows of a circulant, so their APP reads
-// APP[j*z + (r+s) mod z] are consecutive LDS words.  HBM traffic per decode is
-// only the pattern and the per-pattern results.
+// Layout.  One workgroup owns one frame at a time (persistent grid; patterns or
+// IS frames come from an atomic queue) and keeps it on chip for every decode:
+//   - the check neighbour lists of the checks a thread owns (tid, tid+B, ...)
+//     and their check-to-variable messages live in that thread's registers;
+//   - the APP values live in LDS as a ring of three int32 buffers: iteration t
+//     reads APP_{t-1}, adds its messages into APP_t (initialised to lambda) with
+//     LDS integer atomics, and initialises APP_{t+1}, so one barrier per
+//     iteration suffices and the sums are exact whatever the atomic order;
+//   - the hard decision x_t = [APP_t < 0] and the syndrome weight w_t are taken
+//     during the check pass of iteration t+1, which reads the same APP values.
+// For a QC code consecutive threads own consecutive rows of a circulant, so
+// their APP accesses j*z + (r+s) mod z hit consecutive LDS words.  HBM traffic
+// per decode is the pattern and the per-pattern results only.
 //
-// Offset min-sum (int8 messages, exact integer arithmetic):
-//   v2c = sat127(APP - c2v); c2v' = sign-product * max(min - beta, 0) over the
-//   other edges (min / second-min / argmin per check); APP' = lambda + sum c2v'
-//   accumulated with LDS integer atomics (order-free, hence exact).
-// Sum-product (float32):
-//   c2v' = sign-product * phi(sum_{others} phi(min(|v2c|, 30))), phi(x) =
-//   log1p(2 / expm1(max(x, 2^-20))); the exclusive sums come from prefix and
-//   suffix sums; c2v' is staged in LDS in edge order and each variable sums its
-//   messages in ascending check order (deterministic).
-//
-// After iteration t the hard decision x_t = [APP_t < 0] and the syndrome weight
-// w_t are produced during the next iteration's check pass (it reads the same
-// APP values), so one workgroup barrier per iteration suffices for OMS.
+// Check rules:
+//   offset min-sum (int8 scale): v2c = sat127(APP - c2v);
+//     c2v' = sign-product * max(min - beta, 0) over the other edges (min,
+//     second min and argmin per check);
+//   sum-product (float32 arithmetic on Q20 fixed-point APP / messages):
+//     c2v' = sign-product * phi(sum_{others} phi(min(|v2c|, 30))),
+//     phi(x) = ln((1 + e^-x) / (1 - e^-x)) at max(x, 2^-20), evaluated with the
+//     hardware exp2 / log2 / reciprocal and series at both ends; the exclusive
+//     sums come from prefix and suffix sums; messages are rounded to 2^-20.
 #include <climits>
 #include <cmath>
 
@@ -33,6 +35,10 @@
 
 namespace tsg {
 namespace {
+
+constexpr float kQ = 1048576.0f;        // Q20 scale of the sum-product APP values
+constexpr float kQinv = 1.0f / 1048576.0f;
+constexpr float kLamMax = 1024.0f;      // |lambda| bound of the Q20 format
 
 __device__ __forceinline__ int q_impulse(int qb, int k) {
     // round_half_away(qb * (16 - k) / 16), saturated to [-127, 127]
@@ -43,32 +49,109 @@ __device__ __forceinline__ int q_impulse(int qb, int k) {
     return (int)q;
 }
 
-__device__ __forceinline__ float phi_f(float x) {
-    x = fmaxf(x, 0x1p-20f);
-    return log1pf(2.0f / expm1f(x));
+__device__ __forceinline__ int to_q20(float l) {
+    l = fminf(fmaxf(l, -kLamMax), kLamMax);
+    return __float2int_rn(l * kQ);
 }
 
-// Shared-memory layout common to both decoders (offsets in bytes from the base).
-struct Lds {
-    int np, W, T;
-    size_t app, c2v, lam, hist, imask, wsyn, pcnt, sh, total;
+// phi(x) = -ln tanh(x/2) = ln((1+u)/(1-u)), u = e^-x, for x >= 0.
+__device__ __forceinline__ float phi_fast(float x) {
+    x = fmaxf(x, 0x1p-20f);
+    const float u = __builtin_amdgcn_exp2f(-x * 1.4426950408889634f);
+    // 1 - e^-x: Taylor series below 1/8, direct difference above
+    const float ser = x * (1.0f - x * (0.5f - x * (0.16666667f - x * (0.041666668f - x * 0.0083333333f))));
+    const float den = x < 0.125f ? ser : 1.0f - u;
+    const float r = (1.0f + u) * __builtin_amdgcn_rcpf(den);
+    const float big = __builtin_amdgcn_logf(r) * 0.69314718055994531f;
+    // small u: ln((1+u)/(1-u)) = 2 (u + u^3/3 + u^5/5 + ...)
+    const float u2 = u * u;
+    const float small = 2.0f * u * (1.0f + u2 * (0.33333334f + u2 * 0.2f));
+    return u < 0.0625f ? small : big;
+}
+
+struct OmsRule {
+    static constexpr int kDummy = 127;   // padded edges read as a saturated positive message
+    template <int DC>
+    __device__ static __forceinline__ void update(const int (&val)[DC], int (&c2v)[DC],
+                                                  const int (&nb)[DC], int pad_id, int offset) {
+        int mn1 = 127, mn2 = 127, idx = 0, sgn = 0;
+        int v2[DC];
+#pragma unroll
+        for (int j = 0; j < DC; ++j) {
+            int x = val[j] - c2v[j];
+            x = x > 127 ? 127 : (x < -127 ? -127 : x);
+            if (nb[j] == pad_id) x = 127;
+            v2[j] = x;
+            const int ax = x < 0 ? -x : x;
+            sgn ^= (x < 0);
+            if (ax < mn1) {
+                mn2 = mn1;
+                mn1 = ax;
+                idx = j;
+            } else if (ax < mn2) {
+                mn2 = ax;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < DC; ++j) {
+            int mag = (j == idx ? mn2 : mn1) - offset;
+            mag = mag < 0 ? 0 : mag;
+            c2v[j] = (sgn ^ (v2[j] < 0)) ? -mag : mag;
+        }
+    }
 };
 
-__host__ __device__ inline Lds lds_layout(int decoder, int n, int e, int T) {
+struct SpaRule {
+    static constexpr int kDummy = 0;
+    template <int DC>
+    __device__ static __forceinline__ void update(const int (&val)[DC], int (&c2v)[DC],
+                                                  const int (&nb)[DC], int pad_id, int) {
+        float ph[DC];
+        int neg[DC];
+        int sgn = 0;
+#pragma unroll
+        for (int j = 0; j < DC; ++j) {
+            const int d = val[j] - c2v[j];
+            const bool pad = nb[j] == pad_id;
+            neg[j] = (d < 0) & !pad;
+            sgn ^= neg[j];
+            const float ax = fminf(fabsf((float)d * kQinv), 30.0f);
+            ph[j] = pad ? 0.0f : phi_fast(ax);
+        }
+        float pre[DC + 1], suf[DC + 1];
+        pre[0] = 0.0f;
+        suf[DC] = 0.0f;
+#pragma unroll
+        for (int j = 0; j < DC; ++j) pre[j + 1] = pre[j] + ph[j];
+#pragma unroll
+        for (int j = DC - 1; j >= 0; --j) suf[j] = suf[j + 1] + ph[j];
+#pragma unroll
+        for (int j = 0; j < DC; ++j) {
+            const int q = __float2int_rn(phi_fast(pre[j] + suf[j + 1]) * kQ);
+            c2v[j] = (sgn ^ neg[j]) ? -q : q;
+        }
+    }
+};
+
+// Shared-memory layout of a frame (byte offsets).
+struct Lds {
+    int np, W, T;
+    size_t lam, app, hist, imask, wsyn, pcnt, sh, extra, total;
+};
+
+__host__ __device__ inline Lds lds_layout(int n, int T, bool with_hist) {
     Lds L;
-    L.np = (n + 1 + 63) & ~63;   // +1: slot n is a dummy for padded edges
+    L.np = (n + 1 + 63) & ~63;   // +1: slot n is the dummy target of padded edges
     L.W = L.np >> 6;
     L.T = T;
     size_t o = 0;
-    L.app = o;
-    o += (size_t)(decoder == TS_DEC_OMS_I8 ? 3 : 1) * L.np * 4;
     L.lam = o;
-    if (decoder != TS_DEC_OMS_I8) o += (size_t)L.np * 4;
-    L.c2v = o;
-    if (decoder != TS_DEC_OMS_I8) o += (size_t)((e + 63) & ~63) * 4;
+    o += (size_t)L.np * 4;
+    L.app = o;
+    o += (size_t)3 * L.np * 4;
     o = (o + 15) & ~(size_t)15;
     L.hist = o;
-    o += (size_t)T * L.W * 8;
+    if (with_hist) o += (size_t)T * L.W * 8;
     L.imask = o;
     o += (size_t)L.W * 8;
     L.wsyn = o;
@@ -77,8 +160,111 @@ __host__ __device__ inline Lds lds_layout(int decoder, int n, int e, int T) {
     o += (size_t)(T + 2) * 4;
     L.sh = o;
     o += 32 * 4;
+    o = (o + 15) & ~(size_t)15;
+    L.extra = o;   // IS: Philox normals of the TS bits (doubles) and the TS bits
+    o += (size_t)kMaxWidth * 8 + (size_t)kMaxWidth * 4;
     L.total = (o + 15) & ~(size_t)15;
     return L;
+}
+
+struct Frame {
+    int *lam, *app;
+    unsigned long long *hist;   // nullable
+    int *wsyn, *pcnt;
+    int n, np, W, T;
+};
+
+struct DecRes {
+    int fail, iters, tmin;
+};
+
+template <int DC, int CPT>
+__device__ __forceinline__ void load_neighbours(const DevCode &cd, int (&nb)[CPT][DC]) {
+    const int B = blockDim.x, tid = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int chk = tid + c * B;
+#pragma unroll
+        for (int j = 0; j < DC; ++j) {
+            int v = -1;
+            if (chk < cd.m && j < cd.dc_pad) v = cd.cn_tab[(size_t)j * cd.m_tab + chk];
+            nb[c][j] = v < 0 ? cd.n : v;
+        }
+    }
+}
+
+// One decode.  On entry lam[] holds the channel values, APP slots 0 and 1 equal
+// lam[], wsyn/pcnt are zero and all threads have passed a barrier.
+template <class Rule, int DC, int CPT>
+__device__ __forceinline__ DecRes run_decode(const Frame &F, const int (&nb)[CPT][DC],
+                                             int (&c2v)[CPT][DC], int offset) {
+    const int n = F.n, np = F.np, W = F.W, T = F.T;
+    const int B = blockDim.x, NW = B >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+#pragma unroll
+        for (int j = 0; j < DC; ++j) c2v[c][j] = 0;
+    int cur = 0, nxt = 1, spare = 2;
+    int iters = T, wmin = INT_MAX, tmin = 0;
+    for (int t = 1; t <= T + 1; ++t) {
+        const int *A = F.app + cur * np;
+        int *N = F.app + nxt * np;
+        int unsat = 0;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            int val[DC];
+#pragma unroll
+            for (int j = 0; j < DC; ++j) val[j] = A[nb[c][j]];
+            int par = 0;
+#pragma unroll
+            for (int j = 0; j < DC; ++j) par ^= (val[j] < 0);
+            unsat += par;
+            if (t <= T) {
+                Rule::template update<DC>(val, c2v[c], nb[c], n, offset);
+#pragma unroll
+                for (int j = 0; j < DC; ++j)
+                    if (nb[c][j] != n) atomicAdd(&N[nb[c][j]], c2v[c][j]);
+            }
+        }
+        if (t >= 2) {
+            const int us = wave_sum(unsat);
+            if (lane == 0 && us) atomicAdd(&F.wsyn[t - 1], us);
+            int pc = 0;
+            for (int i = wid; i < W; i += NW) {
+                const int v = i * 64 + lane;
+                const unsigned long long mask = __ballot((v < n) && (A[v] < 0));
+                if (F.hist && lane == 0) F.hist[(size_t)(t - 2) * W + i] = mask;
+                pc += __popcll(mask);
+            }
+            if (lane == 0 && pc) atomicAdd(&F.pcnt[t - 1], pc);
+        }
+        if (t < T) {
+            int *S = F.app + spare * np;
+            for (int v = tid; v < np; v += B) S[v] = F.lam[v];
+        }
+        __syncthreads();
+        if (t >= 2) {
+            const int w = F.wsyn[t - 1];
+            if (w < wmin) {
+                wmin = w;
+                tmin = t - 1;
+            }
+            if (w == 0) {
+                iters = t - 1;
+                break;
+            }
+        }
+        const int tmp = cur;
+        cur = nxt;
+        nxt = spare;
+        spare = tmp;
+    }
+    DecRes r;
+    r.iters = iters;
+    r.tmin = tmin;
+    r.fail = F.pcnt[iters] > 0;
+    return r;
 }
 
 // Writes the candidate error sets U_t = S(x_t) u I, t = t0..iters, of one
@@ -146,364 +332,56 @@ __device__ void write_candidates(const SearchLaunch &a, const unsigned long long
     __syncthreads();
 }
 
-struct DecRes {
-    int fail, iters, tmin;
-};
-
 // ---------------------------------------------------------------------------
-// offset min-sum, int8 messages
+// impulse search: one pattern per workgroup, bisection on the amplitude
 // ---------------------------------------------------------------------------
-template <int DC, int CPT>
-__global__ __launch_bounds__(256) void k_search_oms(SearchLaunch a, DevCode cd) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int n = cd.n, m = cd.m, T = a.max_iter;
-    const Lds L = lds_layout(TS_DEC_OMS_I8, n, cd.e, T);
-    const int np = L.np, W = L.W;
-    int *app = (int *)(smem + L.app);
-    unsigned long long *hist = (unsigned long long *)(smem + L.hist);
-    unsigned long long *imask = (unsigned long long *)(smem + L.imask);
-    int *wsyn = (int *)(smem + L.wsyn);
-    int *pcnt = (int *)(smem + L.pcnt);
-    int *sh = (int *)(smem + L.sh);
-    const int B = blockDim.x, NW = B >> 6;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-
-    int nb[CPT][DC];
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-        const int chk = tid + c * B;
-#pragma unroll
-        for (int j = 0; j < DC; ++j) {
-            int v = -1;
-            if (chk < m && j < cd.dc_pad) v = cd.cn_tab[(size_t)j * cd.m_tab + chk];
-            nb[c][j] = v < 0 ? n : v;
-        }
-    }
-    int c2v[CPT][DC];
-    unsigned long long my_iters = 0, my_dec = 0;
-    int qi = 0;
-    const int qb = a.q_base;
-
-    auto lam_of = [&](int v) -> int {
-        if (v < n) return ((imask[v >> 6] >> (v & 63)) & 1ull) ? qi : qb;
-        return v == n ? 127 : 0;
-    };
-
-    auto decode = [&](int k) -> DecRes {
-        __syncthreads();   // previous readers of the shared state are done
-        qi = q_impulse(qb, k);
-        for (int v = tid; v < np; v += B) {
-            const int l = lam_of(v);
-            app[v] = l;
-            app[np + v] = l;
-        }
-        for (int i = tid; i < T + 2; i += B) {
-            wsyn[i] = 0;
-            pcnt[i] = 0;
-        }
-#pragma unroll
-        for (int c = 0; c < CPT; ++c)
-#pragma unroll
-            for (int j = 0; j < DC; ++j) c2v[c][j] = 0;
-        __syncthreads();
-        int cur = 0, nxt = 1, spare = 2;
-        int iters = T, wmin = INT_MAX, tmin = 0;
-        for (int t = 1; t <= T + 1; ++t) {
-            const int *A = app + cur * np;
-            int *N = app + nxt * np;
-            int unsat = 0;
-#pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-                int val[DC];
-#pragma unroll
-                for (int j = 0; j < DC; ++j) val[j] = A[nb[c][j]];
-                int par = 0;
-#pragma unroll
-                for (int j = 0; j < DC; ++j) par ^= (val[j] < 0);
-                unsat += par;
-                if (t <= T) {
-                    int mn1 = 127, mn2 = 127, idx = 0, sgn = 0;
-                    int v2[DC];
-#pragma unroll
-                    for (int j = 0; j < DC; ++j) {
-                        int x = val[j] - c2v[c][j];
-                        x = x > 127 ? 127 : (x < -127 ? -127 : x);
-                        if (nb[c][j] == n) x = 127;
-                        v2[j] = x;
-                        const int ax = x < 0 ? -x : x;
-                        sgn ^= (x < 0);
-                        if (ax < mn1) {
-                            mn2 = mn1;
-                            mn1 = ax;
-                            idx = j;
-                        } else if (ax < mn2) {
-                            mn2 = ax;
-                        }
-                    }
-#pragma unroll
-                    for (int j = 0; j < DC; ++j) {
-                        int mag = (j == idx ? mn2 : mn1) - a.offset;
-                        mag = mag < 0 ? 0 : mag;
-                        const int out = (sgn ^ (v2[j] < 0)) ? -mag : mag;
-                        c2v[c][j] = out;
-                        if (nb[c][j] != n) atomicAdd(&N[nb[c][j]], out);
-                    }
-                }
-            }
-            if (t >= 2) {
-                const int us = wave_sum(unsat);
-                if (lane == 0 && us) atomicAdd(&wsyn[t - 1], us);
-                int pc = 0;
-                for (int i = wid; i < W; i += NW) {
-                    const int v = i * 64 + lane;
-                    const unsigned long long mask = __ballot((v < n) && (A[v] < 0));
-                    if (lane == 0) hist[(size_t)(t - 2) * W + i] = mask;
-                    pc += __popcll(mask);
-                }
-                if (lane == 0 && pc) atomicAdd(&pcnt[t - 1], pc);
-            }
-            if (t < T) {
-                int *S = app + spare * np;
-                for (int v = tid; v < np; v += B) S[v] = lam_of(v);
-            }
-            __syncthreads();
-            if (t >= 2) {
-                const int w = wsyn[t - 1];
-                if (w < wmin) {
-                    wmin = w;
-                    tmin = t - 1;
-                }
-                if (w == 0) {
-                    iters = t - 1;
-                    break;
-                }
-            }
-            const int tmp = cur;
-            cur = nxt;
-            nxt = spare;
-            spare = tmp;
-        }
-        DecRes r;
-        r.iters = iters;
-        r.tmin = tmin;
-        r.fail = pcnt[iters] > 0;
-        my_iters += iters;
-        my_dec += 1;
-        return r;
-    };
-
-    for (;;) {
-        __syncthreads();
-        if (tid == 0) sh[0] = atomicAdd(a.queue, 1);
-        __syncthreads();
-        const int pl = sh[0];
-        if (pl >= a.n_patterns) break;
-        for (int i = tid; i < W; i += B) imask[i] = 0ull;
-        if (tid < kMaxWidth) sh[1 + tid] = tid < a.width ? a.patterns[(size_t)pl * a.width + tid] : -1;
-        __syncthreads();
-        if (tid < kMaxWidth) {
-            const int v = sh[1 + tid];
-            if (v >= n || v < -1) atomicOr(a.err, 1);
-            else if (v >= 0) atomicOr(&imask[v >> 6], 1ull << (v & 63));
-        }
-        const int pg = a.pat_base + pl;
-        DecRes r = decode(a.k_max);
-        int kc = -1, it_hi = 0, tm_hi = 0, it_lo = r.iters;
-        if (r.fail) {
-            write_candidates(a, hist, imask, W, r.iters, pg, a.k_max);
-            int lo = 0, hi = a.k_max;
-            it_hi = r.iters;
-            tm_hi = r.tmin;
-            it_lo = 1;   // D(0) is the noiseless decode: success at the first iteration
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                r = decode(mid);
-                if (r.fail) {
-                    hi = mid;
-                    it_hi = r.iters;
-                    tm_hi = r.tmin;
-                    write_candidates(a, hist, imask, W, r.iters, pg, mid);
-                } else {
-                    lo = mid;
-                    it_lo = r.iters;
-                }
-            }
-            kc = hi;
-        }
-        if (tid == 0) {
-            a.k_crit[pg] = kc;
-            a.iters_crit[pg] = it_hi;
-            a.iters_lo[pg] = it_lo;
-            a.tmin_crit[pg] = tm_hi;
-            a.n_cand[pg] = 0;
-        }
-    }
-    if (tid == 0) {
-        atomicAdd(&a.counters[0], my_dec);
-        atomicAdd(&a.counters[1], my_iters);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// sum-product, float32
-// ---------------------------------------------------------------------------
-
-// Register state of the checks one thread owns.
-template <int DC, int CPT>
-struct SpaRegs {
-    int nb[CPT][DC];
-    int ebase[CPT];
-    float c2v[CPT][DC];
-
-    __device__ void load(const DevCode &cd) {
-        const int B = blockDim.x, tid = threadIdx.x;
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            const int chk = tid + c * B;
-            ebase[c] = chk < cd.m ? cd.row_ptr[chk] : 0;
-#pragma unroll
-            for (int j = 0; j < DC; ++j) {
-                int v = -1;
-                if (chk < cd.m && j < cd.dc_pad) v = cd.cn_tab[(size_t)j * cd.m_tab + chk];
-                nb[c][j] = v < 0 ? cd.n : v;
-            }
-        }
-    }
-};
-
-// One SPA decode.  On entry lam[] and app[] hold the channel LLRs, wsyn/pcnt
-// are zero and every thread has passed a barrier; c2v is cleared here.  hist
-// (optional) receives the hard decision of every iteration.
-template <int DC, int CPT>
-__device__ DecRes spa_run(const DevCode &cd, SpaRegs<DC, CPT> &R, float *app, const float *lam,
-                          float *c2e, unsigned long long *hist, int W, int *wsyn, int *pcnt,
-                          int T) {
-    const int n = cd.n, B = blockDim.x, NW = B >> 6;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-#pragma unroll
-    for (int c = 0; c < CPT; ++c)
-#pragma unroll
-        for (int j = 0; j < DC; ++j) R.c2v[c][j] = 0.0f;
-    int iters = T, wmin = INT_MAX, tmin = 0;
-    for (int t = 1; t <= T + 1; ++t) {
-        int unsat = 0;
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            float val[DC];
-#pragma unroll
-            for (int j = 0; j < DC; ++j) val[j] = app[R.nb[c][j]];
-            int par = 0;
-#pragma unroll
-            for (int j = 0; j < DC; ++j) par ^= (R.nb[c][j] != n) & (val[j] < 0.0f);
-            unsat += par;
-            if (t <= T) {
-                float ph[DC];
-                int neg[DC];
-                int sgn = 0;
-#pragma unroll
-                for (int j = 0; j < DC; ++j) {
-                    const float x = val[j] - R.c2v[c][j];
-                    neg[j] = x < 0.0f;
-                    sgn ^= neg[j] & (R.nb[c][j] != n);
-                    ph[j] = R.nb[c][j] != n ? phi_f(fminf(fabsf(x), 30.0f)) : 0.0f;
-                }
-                float pre[DC + 1], suf[DC + 1];
-                pre[0] = 0.0f;
-                suf[DC] = 0.0f;
-#pragma unroll
-                for (int j = 0; j < DC; ++j) pre[j + 1] = pre[j] + ph[j];
-#pragma unroll
-                for (int j = DC - 1; j >= 0; --j) suf[j] = suf[j + 1] + ph[j];
-#pragma unroll
-                for (int j = 0; j < DC; ++j) {
-                    const float mag = phi_f(pre[j] + suf[j + 1]);
-                    const float out = (sgn ^ neg[j]) ? -mag : mag;
-                    R.c2v[c][j] = out;
-                    if (R.nb[c][j] != n) c2e[R.ebase[c] + j] = out;
-                }
-            }
-        }
-        if (t >= 2) {
-            const int us = wave_sum(unsat);
-            if (lane == 0 && us) atomicAdd(&wsyn[t - 1], us);
-            int pc = 0;
-            for (int i = wid; i < W; i += NW) {
-                const int v = i * 64 + lane;
-                const unsigned long long mask = __ballot((v < n) && (app[v] < 0.0f));
-                if (hist && lane == 0) hist[(size_t)(t - 2) * W + i] = mask;
-                pc += __popcll(mask);
-            }
-            if (lane == 0 && pc) atomicAdd(&pcnt[t - 1], pc);
-        }
-        __syncthreads();
-        if (t >= 2) {
-            const int w = wsyn[t - 1];
-            if (w < wmin) {
-                wmin = w;
-                tmin = t - 1;
-            }
-            if (w == 0) {
-                iters = t - 1;
-                break;
-            }
-        }
-        if (t == T + 1) break;
-        // variable pass: APP_t = lambda + messages in ascending check order
-        for (int v = tid; v < n; v += B) {
-            float s = lam[v];
-            for (int d = 0; d < cd.dv_pad; ++d) {
-                const int e = cd.vn_tab[(size_t)d * cd.n_tab + v];
-                if (e >= 0) s += c2e[e];
-            }
-            app[v] = s;
-        }
-        __syncthreads();
-    }
-    DecRes r;
-    r.iters = iters;
-    r.tmin = tmin;
-    r.fail = pcnt[iters] > 0;
-    return r;
-}
-
-template <int DC, int CPT>
-__global__ __launch_bounds__(256) void k_search_spa(SearchLaunch a, DevCode cd) {
+template <class Rule, int DC, int CPT>
+__global__ __launch_bounds__(256) void k_search(SearchLaunch a, DevCode cd) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = cd.n, T = a.max_iter;
-    const Lds L = lds_layout(TS_DEC_SPA_F32, n, cd.e, T);
+    const Lds L = lds_layout(n, T, true);
     const int np = L.np, W = L.W;
-    float *app = (float *)(smem + L.app);
-    float *lam = (float *)(smem + L.lam);
-    float *c2e = (float *)(smem + L.c2v);
-    unsigned long long *hist = (unsigned long long *)(smem + L.hist);
+    Frame F;
+    F.lam = (int *)(smem + L.lam);
+    F.app = (int *)(smem + L.app);
+    F.hist = (unsigned long long *)(smem + L.hist);
+    F.wsyn = (int *)(smem + L.wsyn);
+    F.pcnt = (int *)(smem + L.pcnt);
+    F.n = n;
+    F.np = np;
+    F.W = W;
+    F.T = T;
     unsigned long long *imask = (unsigned long long *)(smem + L.imask);
-    int *wsyn = (int *)(smem + L.wsyn);
-    int *pcnt = (int *)(smem + L.pcnt);
     int *sh = (int *)(smem + L.sh);
     const int B = blockDim.x, tid = threadIdx.x;
+    const bool oms = Rule::kDummy == OmsRule::kDummy;
 
-    SpaRegs<DC, CPT> R;
-    R.load(cd);
+    int nb[CPT][DC];
+    load_neighbours<DC, CPT>(cd, nb);
+    int c2v[CPT][DC];
     unsigned long long my_iters = 0, my_dec = 0;
-    const float h = a.h;
-#define TSG_SPA_DECODE(K, OUT)                                                           \
-    do {                                                                                \
-        __syncthreads();                                                                \
-        const float li_ = h * (1.0f - (float)(K) / (float)a.k_den);                     \
-        for (int v = tid; v < np; v += B) {                                             \
-            float l_ = 0.0f;                                                            \
-            if (v < n) l_ = ((imask[v >> 6] >> (v & 63)) & 1ull) ? li_ : h;             \
-            lam[v] = l_;                                                                \
-            app[v] = l_;                                                                \
-        }                                                                               \
-        for (int i = tid; i < T + 2; i += B) {                                          \
-            wsyn[i] = 0;                                                                \
-            pcnt[i] = 0;                                                                \
-        }                                                                               \
-        __syncthreads();                                                                \
-        OUT = spa_run<DC, CPT>(cd, R, app, lam, c2e, hist, W, wsyn, pcnt, T);           \
-        my_iters += OUT.iters;                                                          \
-        my_dec += 1;                                                                    \
+    const int lam_base = oms ? a.q_base : to_q20(a.h);
+
+#define TSG_DECODE(K, OUT)                                                                  \
+    do {                                                                                   \
+        __syncthreads();                                                                   \
+        const int li_ = oms ? q_impulse(a.q_base, (K))                                     \
+                            : to_q20(a.h * (1.0f - (float)(K) / (float)a.k_den));          \
+        for (int v = tid; v < np; v += B) {                                                \
+            int l_ = v == n ? Rule::kDummy : 0;                                            \
+            if (v < n) l_ = ((imask[v >> 6] >> (v & 63)) & 1ull) ? li_ : lam_base;          \
+            F.lam[v] = l_;                                                                 \
+            F.app[v] = l_;                                                                 \
+            F.app[np + v] = l_;                                                            \
+        }                                                                                  \
+        for (int i = tid; i < T + 2; i += B) {                                             \
+            F.wsyn[i] = 0;                                                                 \
+            F.pcnt[i] = 0;                                                                 \
+        }                                                                                  \
+        __syncthreads();                                                                   \
+        OUT = run_decode<Rule, DC, CPT>(F, nb, c2v, a.offset);                             \
+        my_iters += OUT.iters;                                                             \
+        my_dec += 1;                                                                       \
     } while (0)
 
     for (;;) {
@@ -522,22 +400,22 @@ __global__ __launch_bounds__(256) void k_search_spa(SearchLaunch a, DevCode cd) 
         }
         const int pg = a.pat_base + pl;
         DecRes r;
-        TSG_SPA_DECODE(a.k_max, r);
+        TSG_DECODE(a.k_max, r);
         int kc = -1, it_hi = 0, tm_hi = 0, it_lo = r.iters;
         if (r.fail) {
-            write_candidates(a, hist, imask, W, r.iters, pg, a.k_max);
+            write_candidates(a, F.hist, imask, W, r.iters, pg, a.k_max);
             int lo = 0, hi = a.k_max;
             it_hi = r.iters;
             tm_hi = r.tmin;
-            it_lo = 1;
+            it_lo = 1;   // D(0) is the noiseless decode: success at the first iteration
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
-                TSG_SPA_DECODE(mid, r);
+                TSG_DECODE(mid, r);
                 if (r.fail) {
                     hi = mid;
                     it_hi = r.iters;
                     tm_hi = r.tmin;
-                    write_candidates(a, hist, imask, W, r.iters, pg, mid);
+                    write_candidates(a, F.hist, imask, W, r.iters, pg, mid);
                 } else {
                     lo = mid;
                     it_lo = r.iters;
@@ -553,15 +431,15 @@ __global__ __launch_bounds__(256) void k_search_spa(SearchLaunch a, DevCode cd) 
             a.n_cand[pg] = 0;
         }
     }
+#undef TSG_DECODE
     if (tid == 0) {
         atomicAdd(&a.counters[0], my_dec);
         atomicAdd(&a.counters[1], my_iters);
     }
-#undef TSG_SPA_DECODE
 }
 
 // ---------------------------------------------------------------------------
-// importance-sampling frames (float32 SPA on Philox noise)
+// importance-sampling frames: sum-product on Philox noise
 // ---------------------------------------------------------------------------
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
@@ -597,42 +475,30 @@ struct IsDev {
     unsigned long long *counters;
 };
 
-__host__ __device__ inline size_t is_lds_bytes(int n, int e, int T, size_t *o_lam, size_t *o_c2v,
-                                               size_t *o_misc) {
-    const int np = (n + 1 + 63) & ~63;
-    size_t o = (size_t)np * 4;   // app
-    *o_lam = o;
-    o += (size_t)np * 4;
-    *o_c2v = o;
-    o += (size_t)((e + 63) & ~63) * 4;
-    o = (o + 15) & ~(size_t)15;
-    *o_misc = o;
-    // wsyn[T+2], pcnt[T+2], sh[32] ints, tn[kMaxWidth] doubles, ts[kMaxWidth] ints
-    o += (size_t)(2 * (T + 2) + 32) * 4;
-    o = (o + 7) & ~(size_t)7;
-    o += (size_t)kMaxWidth * 8 + (size_t)kMaxWidth * 4;
-    return (o + 15) & ~(size_t)15;
-}
-
 template <int DC, int CPT>
-__global__ __launch_bounds__(256) void k_is_spa(IsDev a, DevCode cd) {
+__global__ __launch_bounds__(256) void k_is(IsDev a, DevCode cd) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = cd.n, T = a.max_iter;
-    size_t o_lam, o_c2v, o_misc;
-    is_lds_bytes(n, cd.e, T, &o_lam, &o_c2v, &o_misc);
-    const int np = (n + 1 + 63) & ~63, W = np >> 6;
-    float *app = (float *)smem;
-    float *lam = (float *)(smem + o_lam);
-    float *c2e = (float *)(smem + o_c2v);
-    int *wsyn = (int *)(smem + o_misc);
-    int *pcnt = wsyn + (T + 2);
-    int *sh = pcnt + (T + 2);
-    double *tn = (double *)(((size_t)(sh + 32) + 7) & ~(size_t)7);
+    const Lds L = lds_layout(n, T, false);
+    const int np = L.np;
+    Frame F;
+    F.lam = (int *)(smem + L.lam);
+    F.app = (int *)(smem + L.app);
+    F.hist = nullptr;
+    F.wsyn = (int *)(smem + L.wsyn);
+    F.pcnt = (int *)(smem + L.pcnt);
+    F.n = n;
+    F.np = np;
+    F.W = L.W;
+    F.T = T;
+    int *sh = (int *)(smem + L.sh);
+    double *tn = (double *)(smem + L.extra);
     int *tsl = (int *)(tn + kMaxWidth);
     const int B = blockDim.x, tid = threadIdx.x;
 
-    SpaRegs<DC, CPT> R;
-    R.load(cd);
+    int nb[CPT][DC];
+    load_neighbours<DC, CPT>(cd, nb);
+    int c2v[CPT][DC];
     if (tid < kMaxWidth) tsl[tid] = tid < a.a ? a.ts[tid] : -1;
     unsigned long long my_iters = 0;
     const unsigned k0 = (unsigned)a.seed, k1 = (unsigned)(a.seed >> 32);
@@ -663,22 +529,24 @@ __global__ __launch_bounds__(256) void k_is_spa(IsDev a, DevCode cd) {
                 for (int q = 0; q < a.a; ++q)
                     if (tsl[q] == v) slot = q;
                 const double y = 1.0 - (slot >= 0 ? a.shift : 0.0) + a.sigma * nv[i];
-                const float l = (float)(2.0 * y / a.sigma2);
-                lam[v] = l;
-                app[v] = l;
+                const int l = to_q20((float)(2.0 * y / a.sigma2));
+                F.lam[v] = l;
+                F.app[v] = l;
+                F.app[np + v] = l;
                 if (slot >= 0) tn[slot] = nv[i];
             }
         }
         for (int v = n + tid; v < np; v += B) {
-            lam[v] = 0.0f;
-            app[v] = 0.0f;
+            F.lam[v] = 0;
+            F.app[v] = 0;
+            F.app[np + v] = 0;
         }
         for (int i = tid; i < T + 2; i += B) {
-            wsyn[i] = 0;
-            pcnt[i] = 0;
+            F.wsyn[i] = 0;
+            F.pcnt[i] = 0;
         }
         __syncthreads();
-        const DecRes r = spa_run<DC, CPT>(cd, R, app, lam, c2e, nullptr, W, wsyn, pcnt, T);
+        const DecRes r = run_decode<SpaRule, DC, CPT>(F, nb, c2v, 0);
         my_iters += r.iters;
         if (tid == 0) {
             double st = 0.0;
@@ -744,7 +612,6 @@ __global__ void k_fill(int *p, int value, long long count) {
 // kernel table
 // ---------------------------------------------------------------------------
 typedef void (*SearchKernel)(SearchLaunch, DevCode);
-
 typedef void (*IsKernel)(IsDev, DevCode);
 
 struct KEntry {
@@ -753,7 +620,8 @@ struct KEntry {
     IsKernel is;
 };
 
-#define TSG_K(DC, CPT) {DC, CPT, k_search_oms<DC, CPT>, k_search_spa<DC, CPT>, k_is_spa<DC, CPT>}
+#define TSG_K(DC, CPT) \
+    {DC, CPT, k_search<OmsRule, DC, CPT>, k_search<SpaRule, DC, CPT>, k_is<DC, CPT>}
 const KEntry kTable[] = {
     TSG_K(6, 1),  TSG_K(6, 2),  TSG_K(6, 4),  TSG_K(6, 8),  TSG_K(8, 1),  TSG_K(8, 2),
     TSG_K(8, 4),  TSG_K(8, 8),  TSG_K(12, 1), TSG_K(12, 2), TSG_K(12, 4), TSG_K(16, 1),
@@ -767,9 +635,9 @@ const KEntry *find_kernel(int dc, int cpt) {
     return nullptr;
 }
 
-}  // namespace
-
-int plan_search(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter, SearchPlan *plan) {
+// Smallest instantiated padded degree and checks-per-thread for the code:
+// workgroups of at most 256 threads, as few checks per thread as fit.
+int pick_shape(const ts_code *c, int *dc_out, int *cpt_out, int *block_out) {
     static const int dcs[] = {6, 8, 12, 16, 24, 32};
     int dc = 0;
     for (int d : dcs)
@@ -778,25 +646,30 @@ int plan_search(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter, Search
         set_error("check degree %d above the decoder's limit 32", c->dc_max);
         return TS_E_INVAL;
     }
-    const Lds L = lds_layout(decoder, c->n, (int)c->e, max_iter);
+    for (int cp : {1, 2, 4, 8}) {
+        if (!find_kernel(dc, cp)) continue;
+        const int b = ((c->m + cp - 1) / cp + 63) / 64 * 64;
+        if (b <= 256) {
+            *dc_out = dc;
+            *cpt_out = cp;
+            *block_out = b;
+            return TS_OK;
+        }
+    }
+    set_error("code has too many checks (%d) for one workgroup at check degree %d", c->m, c->dc_max);
+    return TS_E_INVAL;
+}
+
+}  // namespace
+
+int plan_search(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter, SearchPlan *plan) {
+    int dc = 0, cpt = 0, block = 0;
+    int rc = pick_shape(c, &dc, &cpt, &block);
+    if (rc) return rc;
+    const Lds L = lds_layout(c->n, max_iter, true);
     if (L.total > ctx->lds_per_block) {
         set_error("code needs %zu bytes of LDS per workgroup, the device has %zu", L.total,
                   ctx->lds_per_block);
-        return TS_E_INVAL;
-    }
-    // smallest checks-per-thread that keeps the workgroup at <= 256 threads
-    // (<= 1024 for large codes), among the instantiated kernels
-    int cpt = 0, block = 0;
-    for (int lim : {256, 1024}) {
-        for (int cp : {1, 2, 4, 8}) {
-            if (!find_kernel(dc, cp)) continue;
-            const int b = ((c->m + cp - 1) / cp + 63) / 64 * 64;
-            if (b <= lim) { cpt = cp; block = b; break; }
-        }
-        if (cpt) break;
-    }
-    if (!cpt) {
-        set_error("code has too many checks (%d) for one workgroup", c->m);
         return TS_E_INVAL;
     }
     const KEntry *ke = find_kernel(dc, cpt);
@@ -842,31 +715,22 @@ int launch_fill(ts_ctx *ctx, int *p, int value, int64_t count) {
 }
 
 int launch_is(ts_ctx *ctx, const ts_code *c, const IsLaunch &a, int *grid_out, int *block_out) {
-    static const int dcs[] = {6, 8, 12, 16, 24, 32};
-    int dc = 0;
-    for (int d : dcs)
-        if (d >= c->dc_max) { dc = d; break; }
-    if (!dc) { set_error("check degree %d above the decoder's limit 32", c->dc_max); return TS_E_INVAL; }
-    size_t o1, o2, o3;
-    const size_t lds = is_lds_bytes(c->n, (int)c->e, a.max_iter, &o1, &o2, &o3);
-    if (lds > ctx->lds_per_block) {
-        set_error("code needs %zu bytes of LDS per workgroup, the device has %zu", lds, ctx->lds_per_block);
+    int dc = 0, cpt = 0, block = 0;
+    int rc = pick_shape(c, &dc, &cpt, &block);
+    if (rc) return rc;
+    const Lds L = lds_layout(c->n, a.max_iter, false);
+    if (L.total > ctx->lds_per_block) {
+        set_error("code needs %zu bytes of LDS per workgroup, the device has %zu", L.total,
+                  ctx->lds_per_block);
         return TS_E_INVAL;
     }
-    int cpt = 0, block = 0;
-    for (int lim : {256, 1024}) {
-        for (int cp : {1, 2, 4, 8}) {
-            if (!find_kernel(dc, cp)) continue;
-            const int b = ((c->m + cp - 1) / cp + 63) / 64 * 64;
-            if (b <= lim) { cpt = cp; block = b; break; }
-        }
-        if (cpt) break;
-    }
-    if (!cpt) { set_error("code has too many checks (%d) for one workgroup", c->m); return TS_E_INVAL; }
     IsKernel kern = find_kernel(dc, cpt)->is;
     int per_cu = 0;
-    TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, block, lds));
-    if (per_cu < 1) { set_error("IS kernel does not fit on a compute unit"); return TS_E_INVAL; }
+    TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, block, L.total));
+    if (per_cu < 1) {
+        set_error("IS kernel does not fit on a compute unit");
+        return TS_E_INVAL;
+    }
     long long grid = (long long)per_cu * ctx->num_cu;
     if (grid > a.n_frames) grid = a.n_frames;
     IsDev d;
@@ -885,7 +749,7 @@ int launch_is(ts_ctx *ctx, const ts_code *c, const IsLaunch &a, int *grid_out, i
     d.wf = a.wf;
     d.queue = a.queue;
     d.counters = a.counters;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(block), lds, ctx->stream, d, c->dev);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(block), L.total, ctx->stream, d, c->dev);
     TSG_HIP(hipGetLastError());
     if (grid_out) *grid_out = (int)grid;
     if (block_out) *block_out = block;
