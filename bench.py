@@ -21,9 +21,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per edge-update of the edge-major streaming formulation
-# (messages read + written, lambda read, APP read + written; dv = 3)
+# Bytes per edge-update of an edge-major streaming decoder (messages read and
+# written, lambda read, APP read and written; dv = 3).  The kernels here keep
+# each frame on chip, so this is an equivalence figure, not their traffic.
 BYTES_PER_EU = {"oms": 3.67, "spa": 12.0}
+# VALU issue peak in lane-operations: 256 CUs x 128 FP32 lanes x 2.4 GHz
+# (the 157.3 TFLOP/s FP32 vector figure counts an FMA as two operations).
+VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
+# Algorithmic VALU issue slots per edge-update of each check rule: SPA = two
+# phi evaluations of 3 quarter-rate transcendentals (exp2, rcp, log2; 4 slots
+# each) and 5 full-rate operations, plus 6 operations for v2c, the prefix /
+# suffix sums, the sign and the message rounding; OMS = 15 full-rate integer
+# operations (difference, saturation, |.|, sign, min/second-min/argmin
+# tracking, offset, clamp, sign application).
+VALU_SLOTS_PER_EU = {"oms": 15.0, "spa": 2 * (3 * 4 + 5) + 6.0}
+# HBM traffic per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (scaled x2 and x1 by a 1 GiB copy); None once the kernel changes.
+MEASURED_TRAFFIC_BYTES = {"spa": (11.93e6 + 167.06e6)}
 
 
 def parse():
@@ -34,6 +48,8 @@ def parse():
     p.add_argument("--is-frames", type=int, default=10000)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
+    p.add_argument("--calib-copy", action="store_true",
+                   help="copy 1 GiB once before timing (reference for HBM byte counters)")
     return p.parse_args()
 
 
@@ -80,6 +96,12 @@ def main():
         rec["ts_oms"], rec["ts_spa"], rec["is_res"] = len(ts_oms), len(ts_spa), is_res
         return rec
 
+    if args.calib_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -109,14 +131,21 @@ def main():
     # dominant kernel: the one with the largest time in the step
     dom = max(("oms", "spa"), key=lambda k: last[k]["decode_ms"])
     dk = last[dom]
-    achieved = BYTES_PER_EU[dom] * dk["edge_updates"] / (dk["decode_ms"] * 1e-3) / 1e9
+    launch_s = dk["decode_ms"] * 1e-3 / max(dk["decode_launches"], 1)
+    eu_per_launch = dk["edge_updates"] / max(dk["decode_launches"], 1)
+    achieved = VALU_SLOTS_PER_EU[dom] * eu_per_launch / launch_s / 1e12
+    hbm_equiv = BYTES_PER_EU[dom] * eu_per_launch / launch_s / 1e9
     roofline = {
-        "bound": "hbm", "kernel": f"k_search_{dom}",
-        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-        "bytes_per_edge_update": BYTES_PER_EU[dom],
-        "launch_ms": dk["decode_ms"] / max(dk["decode_launches"], 1),
-        "launches": dk["decode_launches"],
+        "bound": "alu", "kernel": f"k_search<{'SpaRule' if dom == 'spa' else 'OmsRule'}>",
+        "achieved": round(achieved, 2), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TFLOP/s",
+        "frac": round(achieved / VALU_PEAK_TOPS, 4),
+        "traffic": MEASURED_TRAFFIC_BYTES.get(dom),
+        "per_unit": f"{VALU_SLOTS_PER_EU[dom]:g} VALU issue slots per edge-update",
+        "units_per_launch": eu_per_launch,
+        "launch_ms": launch_s * 1e3,
+        "hbm_equivalent": {"bytes_per_edge_update": BYTES_PER_EU[dom],
+                           "achieved_GBs": round(hbm_equiv, 1),
+                           "frac_of_peak": round(hbm_equiv / HBM_PEAK_GBS, 4)},
     }
     line = {
         "metric": "BP edge-updates/s (TS search + IS, one job)",
