@@ -15,9 +15,11 @@
  *    library until ts_destroy / ts_free_code.
  *  - Arrays named in ts_search_opts.mem == TS_MEM_DEVICE must be device memory on
  *    the context's device (e.g. torch tensors); otherwise host memory.
- *  - Every call on a context runs on the context's stream and returns after that
- *    stream has finished the call's work.  Calls on one context are serialised by
- *    an internal mutex; separate contexts are independent.
+ *  - Every synchronous call on a context runs on the context's stream and
+ *    returns after that stream has finished the call's work.  Synchronous calls
+ *    on one context are serialised by an internal mutex; separate contexts are
+ *    independent.  Submitted jobs (ts_submit) run on the serving workers' own
+ *    streams, concurrently with each other and with synchronous calls.
  *  - No CPU fallback exists: without a usable HIP device, ts_create fails with
  *    TS_E_DEVICE.
  */
@@ -207,6 +209,67 @@ typedef struct {
  * array [n_frames]) receives each frame's failure flag. */
 int ts_is_estimate(ts_ctx *ctx, ts_code *code, const int32_t *ts_bits, int32_t a,
                    const ts_is_opts *opts, ts_is_result *res, uint8_t *fail_out);
+
+/* ---- serving: continuous batching of submitted jobs ------------------------ */
+
+#define TS_JOB_SEARCH 1
+#define TS_JOB_IS 2
+#define TS_JOB_QUEUED 0
+#define TS_JOB_RUNNING 1
+#define TS_JOB_DONE 2
+#define TS_JOB_CANCELLED 3
+
+typedef struct {
+    int32_t kind;              /* TS_JOB_SEARCH or TS_JOB_IS */
+    ts_code *code;             /* a code loaded on the same context */
+    /* TS_JOB_SEARCH: as ts_impulse_search; search.mem must be TS_MEM_HOST and
+     * patterns[n_patterns][width] is copied at submission */
+    ts_search_opts search;
+    const int32_t *patterns;
+    int32_t n_patterns, width;
+    /* TS_JOB_IS: as ts_is_estimate; ts_bits[a] is copied at submission */
+    ts_is_opts is;
+    const int32_t *ts_bits;
+    int32_t a;
+} ts_job_desc;
+
+typedef struct {
+    int32_t state;             /* TS_JOB_QUEUED / RUNNING / DONE / CANCELLED */
+    int32_t status;            /* ts_status of a finished job (TS_E_CANCELLED if cancelled) */
+    double submit_ms, start_ms, end_ms;   /* milliseconds since ts_create */
+    int64_t edge_updates;
+    int64_t device_bytes;      /* the admission estimate of the job */
+    int64_t n_ts, n_bits;      /* search jobs: size of the job's TS list */
+    int32_t n_patterns;
+    int32_t reserved;
+    ts_is_result is;           /* IS jobs: the estimate */
+} ts_job_info;
+
+/* Starts `slots` serving workers (1..16), each with its own HIP stream (default
+ * priority) and stream-ordered device allocations.  Optional: the first
+ * ts_submit starts 4.  The device-memory budget is ts_ctx_opts.hbm_budget_bytes,
+ * or half of the free device memory when that is 0.  TS_E_STATE if started. */
+int ts_serve_start(ts_ctx *ctx, int32_t slots);
+/* Queues a job (inputs copied) and returns its id.  A job starts as soon as a
+ * worker is free and its memory estimate fits beside the running jobs (first
+ * fit in submission order).  Each search job has its own TS table, so its
+ * results are those of the same call run alone.  TS_E_BUSY if the job alone
+ * exceeds the budget; TS_E_INVAL on bad arguments (checked at submission).
+ * Thread-safe. */
+int ts_submit(ts_ctx *ctx, const ts_job_desc *job, uint64_t *job_id);
+/* Reports a job's state; wait != 0 blocks until it is done or cancelled.  A
+ * failed job's message is available through ts_last_error(). Thread-safe. */
+int ts_poll(ts_ctx *ctx, uint64_t job_id, int32_t wait, ts_job_info *info);
+/* Copies a finished search job's outputs: per-pattern arrays into out (host,
+ * n_patterns each, any may be NULL) and its ordered TS list into recs[cap] /
+ * bits[bits_cap] (cap = bits_cap = 0 skips it; TS_E_TRUNC if too small). */
+int ts_job_outputs(ts_ctx *ctx, uint64_t job_id, ts_search_out *out, ts_record *recs,
+                   int64_t cap, int32_t *bits, int64_t bits_cap);
+/* Cancels a queued job at once; a running job finishes its kernels and is then
+ * reported as cancelled with no results.  Thread-safe. */
+int ts_cancel(ts_ctx *ctx, uint64_t job_id);
+/* Frees a finished or cancelled job's results; TS_E_BUSY while in flight. */
+int ts_release(ts_ctx *ctx, uint64_t job_id);
 
 /* ---- measurements of the last call ---------------------------------------- */
 

@@ -110,6 +110,72 @@ class Context:
     def load_code(self, code) -> "Code":
         return Code(self, code)
 
+    # ---- serving -----------------------------------------------------------
+    def serve_start(self, slots: int = 4):
+        _check(lib().ts_serve_start(self._h, slots))
+
+    def submit_search(self, code: "Code", patterns, decoder: int = DEC_OMS, max_iter: int = 20,
+                      oms_offset: int = 1, ebn0_db: float = 3.0, rate: Optional[float] = None,
+                      llr_scale: float = 4.0, k_max: int = 512, k_den: int = 16, a_max: int = 6,
+                      extract_mode: int = EXTRACT_PATH, collect_from_iter: int = -1) -> int:
+        pats = _i32(patterns)
+        if pats.ndim == 1:
+            pats = pats.reshape(-1, 1)
+        rate = (1.0 - code.m / code.n) if rate is None else rate
+        d = A.JobDesc()
+        d.kind, d.code = A.TS_JOB_SEARCH, code._h
+        d.search = A.SearchOpts(decoder, max_iter, oms_offset, ebn0_db, rate, llr_scale, k_max,
+                                k_den, a_max, extract_mode, collect_from_iter, A.TS_MEM_HOST)
+        d.patterns, d.n_patterns, d.width = pats.ctypes.data, pats.shape[0], pats.shape[1]
+        jid = C.c_uint64()
+        _check(lib().ts_submit(self._h, C.byref(d), C.byref(jid)))
+        return jid.value
+
+    def submit_is(self, code: "Code", ts_bits, ebn0_db: float, shift: float, n_frames: int,
+                  seed: int, frame_base: int = 0, stream: int = 0, max_iter: int = 50,
+                  rate: Optional[float] = None) -> int:
+        t = _i32(ts_bits)
+        rate = (1.0 - code.m / code.n) if rate is None else rate
+        d = A.JobDesc()
+        d.kind, d.code = A.TS_JOB_IS, code._h
+        d.is_ = A.IsOpts(max_iter, ebn0_db, rate, shift, n_frames, seed, frame_base, stream)
+        d.ts_bits, d.a = t.ctypes.data, t.size
+        jid = C.c_uint64()
+        _check(lib().ts_submit(self._h, C.byref(d), C.byref(jid)))
+        return jid.value
+
+    def poll(self, job_id: int, wait: bool = False) -> dict:
+        info = A.JobInfo()
+        _check(lib().ts_poll(self._h, job_id, int(wait), C.byref(info)))
+        out = {f: getattr(info, f) for f, _ in A.JobInfo._fields_ if f not in ("is_", "reserved")}
+        out["is"] = {f: getattr(info.is_, f) for f, _ in A.IsResult._fields_}
+        if info.state == A.TS_JOB_DONE and info.status != A.TS_OK:
+            out["error"] = lib().ts_last_error().decode(errors="replace")
+        return out
+
+    def job_outputs(self, job_id: int) -> dict:
+        info = self.poll(job_id)
+        P = info["n_patterns"]
+        res = {k: np.zeros(P, dtype=np.int32)
+               for k in ("k_crit", "iters_crit", "iters_lo", "tmin_crit", "n_cand")}
+        out = A.SearchOut(*(res[k].ctypes.data for k in
+                            ("k_crit", "iters_crit", "iters_lo", "tmin_crit", "n_cand")))
+        n, nb = info["n_ts"], info["n_bits"]
+        recs = (A.Record * max(n, 1))()
+        bits = np.zeros(max(nb, 1), dtype=np.int32)
+        _check(lib().ts_job_outputs(self._h, job_id, C.byref(out), recs, n, bits.ctypes.data, nb))
+        res["ts"] = [TsRecord(recs[i].a, recs[i].b, recs[i].orbit, recs[i].first_pattern,
+                              recs[i].k_crit,
+                              tuple(int(x) for x in bits[recs[i].bits_off:recs[i].bits_off + recs[i].a]))
+                     for i in range(n)]
+        return res
+
+    def cancel(self, job_id: int):
+        _check(lib().ts_cancel(self._h, job_id))
+
+    def release(self, job_id: int):
+        _check(lib().ts_release(self._h, job_id))
+
     def stats(self) -> dict:
         s = A.Stats()
         _check(lib().ts_get_stats(self._h, C.byref(s)))

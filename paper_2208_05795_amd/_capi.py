@@ -12,6 +12,8 @@ TS_PAT_SINGLES, TS_PAT_PAIRS, TS_PAT_TRIPLES = 1, 2, 3
 TS_DEC_OMS_I8, TS_DEC_SPA_F32 = 0, 1
 TS_EXTRACT_PATH, TS_EXTRACT_CRITICAL = 0, 1
 TS_MEM_HOST, TS_MEM_DEVICE = 0, 1
+TS_JOB_SEARCH, TS_JOB_IS = 1, 2
+TS_JOB_QUEUED, TS_JOB_RUNNING, TS_JOB_DONE, TS_JOB_CANCELLED = 0, 1, 2, 3
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -63,6 +65,19 @@ class IsResult(C.Structure):
                 ("n", C.c_int64), ("n_fail", C.c_int64), ("shift_used", C.c_double)]
 
 
+class JobDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("code", C.c_void_p), ("search", SearchOpts),
+                ("patterns", C.c_void_p), ("n_patterns", C.c_int32), ("width", C.c_int32),
+                ("is_", IsOpts), ("ts_bits", C.c_void_p), ("a", C.c_int32)]
+
+
+class JobInfo(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("submit_ms", C.c_double),
+                ("start_ms", C.c_double), ("end_ms", C.c_double), ("edge_updates", C.c_int64),
+                ("device_bytes", C.c_int64), ("n_ts", C.c_int64), ("n_bits", C.c_int64),
+                ("n_patterns", C.c_int32), ("reserved", C.c_int32), ("is_", IsResult)]
+
+
 class Stats(C.Structure):
     _fields_ = [("decode_ms", C.c_double), ("extract_ms", C.c_double), ("total_ms", C.c_double),
                 ("decodes", C.c_int64), ("edge_updates", C.c_int64), ("candidates", C.c_int64),
@@ -89,6 +104,13 @@ PROTOTYPES = {
     "ts_is_estimate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                  C.POINTER(IsOpts), C.POINTER(IsResult), C.c_void_p]),
     "ts_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
+    "ts_serve_start": (C.c_int, [C.c_void_p, C.c_int32]),
+    "ts_submit": (C.c_int, [C.c_void_p, C.POINTER(JobDesc), C.POINTER(C.c_uint64)]),
+    "ts_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, C.POINTER(JobInfo)]),
+    "ts_job_outputs": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(SearchOut), C.c_void_p,
+                                 C.c_int64, C.c_void_p, C.c_int64]),
+    "ts_cancel": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "ts_release": (C.c_int, [C.c_void_p, C.c_uint64]),
 }
 
 

@@ -1,6 +1,10 @@
 // C ABI of the tsgpu library: context and code lifecycle, the impulse search
-// driver (chunking, candidate buffer, table growth) and the TS read-out.
+// driver (chunking, candidate buffer, table growth), importance sampling and
+// the TS read-out.  The work of a call runs on an executor (stream, events,
+// staging, statistics): the context's own one for the synchronous calls, a
+// serving worker's one for submitted jobs.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -24,32 +28,44 @@ void set_error(const char *fmt, ...) {
 
 void clear_error() { g_err.clear(); }
 
+std::string last_error_copy() { return g_err; }
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
 }  // namespace tsg
 
 using namespace tsg;
 
-void *ts_ctx::dalloc(size_t bytes) {
+void *ts_exec::dalloc(size_t bytes) {
     if (bytes == 0) bytes = 4;
-    if (alloc) return alloc(bytes, user);
     void *p = nullptr;
+    if (stream_alloc) {
+        if (hipMallocAsync(&p, bytes, stream) != hipSuccess) return nullptr;
+        return p;
+    }
+    if (ctx->alloc) return ctx->alloc(bytes, ctx->user);
     if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
     return p;
 }
 
-void ts_ctx::dfree(void *p) {
+void ts_exec::dfree(void *p) {
     if (!p) return;
-    if (free_fn) free_fn(p, user);
+    if (stream_alloc) (void)hipFreeAsync(p, stream);
+    else if (ctx->free_fn) ctx->free_fn(p, ctx->user);
     else (void)hipFree(p);
 }
 
 namespace {
 
-// RAII device buffer from the context allocator
+// RAII device buffer from an executor
 struct DBuf {
-    ts_ctx *ctx;
+    ts_exec &ex;
     void *p = nullptr;
-    DBuf(ts_ctx *c, size_t bytes) : ctx(c) { p = c->dalloc(bytes); }
-    ~DBuf() { ctx->dfree(p); }
+    DBuf(ts_exec &e, size_t bytes) : ex(e) { p = e.dalloc(bytes); }
+    ~DBuf() { ex.dfree(p); }
     DBuf(const DBuf &) = delete;
     DBuf &operator=(const DBuf &) = delete;
     template <class T> T *as() { return (T *)p; }
@@ -59,7 +75,379 @@ double sigma2_of(double ebn0_db, double rate) { return 1.0 / (2.0 * rate * std::
 
 int sat127(long v) { return (int)(v > 127 ? 127 : (v < -127 ? -127 : v)); }
 
+int64_t rec_capacity(const ts_search_opts *o, int t0, int64_t P, bool sieve, int64_t *worst) {
+    const int d_fail_max = 2 + (int)std::ceil(std::log2((double)o->k_max));
+    const int64_t wp = sieve ? (int64_t)d_fail_max * std::max(1, o->max_iter - t0 + 1) : 0;
+    int64_t cap = std::min<int64_t>((256ll << 20) / (kRecStride * 4), wp * P);
+    cap = std::max<int64_t>(std::max<int64_t>(cap, wp), 1);
+    if (worst) *worst = wp;
+    return cap;
+}
+
+int first_iter(const ts_code *code, const ts_search_opts *o) {
+    int t0 = o->collect_from_iter >= 0 ? o->collect_from_iter : code->girth / 2;
+    return t0 < 1 ? 1 : t0;
+}
+
 }  // namespace
+
+namespace tsg {
+
+size_t search_bytes_estimate(const ts_code *code, const ts_search_opts *o, int64_t P, int32_t width) {
+    const int64_t cap = rec_capacity(o, first_iter(code, o), P, true, nullptr);
+    return (size_t)P * (width + 5) * 4 + (size_t)cap * kRecStride * 4 + table_bytes(1 << 16) + 4096;
+}
+
+int check_search_opts(const ts_code *code, const ts_search_opts *o, int32_t width) {
+    if (o->decoder != TS_DEC_OMS_I8 && o->decoder != TS_DEC_SPA_F32) {
+        set_error("unknown decoder %d", o->decoder);
+        return TS_E_INVAL;
+    }
+    if (o->max_iter < 1 || o->max_iter > kMaxIter) { set_error("max_iter must be 1..%d", kMaxIter); return TS_E_INVAL; }
+    if (o->a_max < 1 || o->a_max > kMaxAmax) { set_error("a_max must be 1..%d", kMaxAmax); return TS_E_INVAL; }
+    if (o->k_max < 1 || o->k_max > (1 << 24)) { set_error("k_max must be 1..2^24"); return TS_E_INVAL; }
+    if (o->decoder == TS_DEC_OMS_I8 && o->k_den != 16) { set_error("the int8 decoder uses k_den = 16"); return TS_E_INVAL; }
+    if (o->k_den < 1) { set_error("k_den must be positive"); return TS_E_INVAL; }
+    if (o->oms_offset < 0 || o->oms_offset > 127) { set_error("oms_offset must be 0..127"); return TS_E_INVAL; }
+    if (!(o->rate > 0.0 && o->rate <= 1.0) || !(o->llr_scale > 0.0)) { set_error("rate / llr_scale out of range"); return TS_E_INVAL; }
+    if (o->extract_mode != TS_EXTRACT_PATH && o->extract_mode != TS_EXTRACT_CRITICAL) { set_error("bad extract_mode"); return TS_E_INVAL; }
+    if (o->mem != TS_MEM_HOST && o->mem != TS_MEM_DEVICE) { set_error("bad mem kind"); return TS_E_INVAL; }
+    if (width < 1 || width > kMaxWidth) { set_error("width must be 1..%d", kMaxWidth); return TS_E_INVAL; }
+    if (code->dv_max > kDvMax) { set_error("variable degree %d above the sieve's limit %d", code->dv_max, kDvMax); return TS_E_INVAL; }
+    return TS_OK;
+}
+
+// Autotuner: times every candidate launch shape once on a probe of the job's own
+// patterns (candidate writing off) and keeps the fastest per (code, decoder,
+// iteration count).  Shapes only change the schedule, never the results.
+static int tune_shape(ts_exec &ex, const std::vector<SearchPlan> &cands,
+                      const SearchLaunch &base, int64_t P, SearchPlan *best) {
+    int64_t probe = 0;
+    for (const SearchPlan &p : cands) probe = std::max<int64_t>(probe, 2 * (int64_t)p.grid);
+    probe = std::min(probe, P);
+    float best_ms = 0.0f;
+    for (const SearchPlan &p : cands) {
+        SearchLaunch a = base;
+        a.t0 = a.max_iter + 1;   // no candidate is written while timing
+        a.n_patterns = (int)probe;
+        a.pat_base = 0;
+        int rc = launch_fill(ex.stream, a.queue, 0, 2);
+        if (rc) return rc;
+        TSG_HIP(hipEventRecord(ex.ev[0], ex.stream));
+        rc = launch_search(ex.stream, p, a);
+        if (rc) return rc;
+        TSG_HIP(hipEventRecord(ex.ev[1], ex.stream));
+        TSG_HIP(hipStreamSynchronize(ex.stream));
+        float ms = 0.0f;
+        TSG_HIP(hipEventElapsedTime(&ms, ex.ev[0], ex.ev[1]));
+        if (best_ms == 0.0f || ms < best_ms) {
+            best_ms = ms;
+            *best = p;
+        }
+    }
+    return TS_OK;
+}
+
+// Runs the search on device-resident patterns / outputs into `table`.  With
+// sieve = false no candidate is written (only k* and the iteration counts).
+int run_search(ts_exec &ex, ts_code *code, DevTable &table, const ts_search_opts *o,
+               const int32_t *d_pat, int64_t P, int32_t width, int32_t *const d_out[5], bool sieve) {
+    ts_ctx *ctx = ex.ctx;
+    hipStream_t s = ex.stream;
+    std::vector<SearchPlan> shapes;
+    int rc = plan_candidates(ctx, code, o->decoder, o->max_iter, &shapes);
+    if (rc) return rc;
+    SearchPlan plan = shapes.front();
+    const int tune_key = o->decoder * 1000 + o->max_iter;
+    bool need_tune = false;
+    {
+        std::lock_guard<std::mutex> g(code->tune_mu);
+        auto it = code->tuned.find(tune_key);
+        if (it != code->tuned.end()) {
+            for (const SearchPlan &p : shapes)
+                if (p.cpt == it->second.cpt) plan = p;
+        } else {
+            need_tune = shapes.size() > 1 && P >= 256;
+        }
+    }
+    const double s2 = sigma2_of(o->ebn0_db, o->rate);
+    const double h = 2.0 / s2;
+    const int q_base = sat127(std::lround(o->llr_scale * h));
+    int t0 = first_iter(code, o);
+    if (!sieve) t0 = o->max_iter + 1;   // no iteration qualifies: nothing is written
+
+    DBuf misc(ex, 64 * 4);
+    if (!misc.p) { set_error("device allocation failed"); return TS_E_NOMEM; }
+    int *d_misc = misc.as<int>();
+    // misc layout: [0] queue, [1] rec_count, [2] err, [4..7] counters (2 x u64)
+    rc = launch_fill(s, d_misc, 0, 64);
+    if (rc) return rc;
+    const int64_t rec_cap = rec_capacity(o, t0, P, sieve, nullptr);
+    DBuf recs(ex, (size_t)rec_cap * kRecStride * 4);
+    if (!recs.p) { set_error("device allocation of the candidate buffer failed"); return TS_E_NOMEM; }
+
+    SearchLaunch a{};
+    a.code = &code->dev;
+    a.decoder = o->decoder;
+    a.max_iter = o->max_iter;
+    a.offset = o->oms_offset;
+    a.q_base = q_base;
+    a.k_max = o->k_max;
+    a.k_den = o->k_den;
+    a.h = (float)h;
+    a.t0 = t0;
+    a.cap = 2 * o->a_max;
+    a.a_max = o->a_max;
+    a.extract_mode = o->extract_mode;
+    a.width = width;
+    a.k_crit = d_out[0];
+    a.iters_crit = d_out[1];
+    a.iters_lo = d_out[2];
+    a.tmin_crit = d_out[3];
+    a.n_cand = d_out[4];
+    a.queue = d_misc;
+    a.rec_count = d_misc + 1;
+    a.err = d_misc + 2;
+    a.counters = (unsigned long long *)(d_misc + 4);
+    a.recs = recs.as<int>();
+    a.rec_cap = (int)rec_cap;
+
+    if (need_tune) {
+        a.patterns = d_pat;
+        rc = tune_shape(ex, shapes, a, P, &plan);
+        if (rc) return rc;
+        std::lock_guard<std::mutex> g(code->tune_mu);
+        SearchShape sh;
+        sh.cpt = plan.cpt;
+        code->tuned[tune_key] = sh;
+        rc = launch_fill(s, d_misc, 0, 64);   // the probe's counters are not the job's
+        if (rc) return rc;
+    }
+    if (sieve) {
+        rc = table_init(ex, table, 1 << 16);
+        if (rc) return rc;
+    }
+    TSG_HIP(hipEventRecord(ex.ev[4], s));
+    int64_t chunk = P, pos = 0, cands = 0;
+    double dec_ms = 0.0, sieve_ms = 0.0;
+    while (pos < P) {
+        const int64_t len = std::min<int64_t>(chunk, P - pos);
+        rc = launch_fill(s, d_misc, 0, 2);   // queue, rec_count
+        if (rc) return rc;
+        a.patterns = d_pat + pos * width;
+        a.n_patterns = (int)len;
+        a.pat_base = (int)pos;
+        TSG_HIP(hipEventRecord(ex.ev[0], s));
+        rc = launch_search(s, plan, a);
+        if (rc) return rc;
+        TSG_HIP(hipEventRecord(ex.ev[1], s));
+        TSG_HIP(hipMemcpyAsync(ex.pinned, d_misc, 16, hipMemcpyDeviceToHost, s));
+        TSG_HIP(hipStreamSynchronize(s));
+        float ms = 0.0f;
+        TSG_HIP(hipEventElapsedTime(&ms, ex.ev[0], ex.ev[1]));
+        dec_ms += ms;
+        ex.stats.decode_launches++;
+        const int64_t nrec = ex.pinned[1];
+        if (ex.pinned[2] & 1) { set_error("pattern entry out of range"); return TS_E_INVAL; }
+        if (nrec > rec_cap) {
+            if (len == 1) { set_error("candidate buffer too small for one pattern"); return TS_E_NOMEM; }
+            chunk = std::max<int64_t>(1, len / 2);   // re-run this chunk in smaller pieces
+            continue;
+        }
+        if (sieve && nrec > 0) {
+            cands += nrec;
+            rc = table_grow_if_needed(ex, table, 2 * nrec);
+            if (rc) return rc;
+            TSG_HIP(hipEventRecord(ex.ev[2], s));
+            rc = launch_sieve(ex, code->dev, table, a, (int)nrec);
+            if (rc) return rc;
+            TSG_HIP(hipEventRecord(ex.ev[3], s));
+            TSG_HIP(hipStreamSynchronize(s));
+            TSG_HIP(hipEventElapsedTime(&ms, ex.ev[2], ex.ev[3]));
+            sieve_ms += ms;
+            ex.stats.extract_launches++;
+        }
+        pos += len;
+    }
+    TSG_HIP(hipMemcpyAsync(ex.pinned, d_misc, 32, hipMemcpyDeviceToHost, s));
+    TSG_HIP(hipEventRecord(ex.ev[5], s));
+    TSG_HIP(hipStreamSynchronize(s));
+    float tot = 0.0f;
+    TSG_HIP(hipEventElapsedTime(&tot, ex.ev[4], ex.ev[5]));
+    const int err = ex.pinned[2];
+    unsigned long long cnt[2];
+    std::memcpy(cnt, ex.pinned + 4, 16);
+    ex.stats.decode_ms += dec_ms;
+    ex.stats.extract_ms += sieve_ms;
+    ex.stats.total_ms += tot;
+    ex.stats.decodes += (int64_t)cnt[0];
+    ex.stats.edge_updates += (int64_t)cnt[1] * code->e;
+    ex.stats.candidates += cands;
+    ex.stats.block_threads = plan.block;
+    ex.stats.grid_blocks = (int)std::min<int64_t>(plan.grid, P);
+    if (err & 1) { set_error("pattern entry out of range"); return TS_E_INVAL; }
+    if (err & 4) { set_error("TS table insert timed out"); return TS_E_DEVICE; }
+    if (err & 8) { set_error("TS table full"); return TS_E_NOMEM; }
+    if (err & 16) { set_error("corrupt candidate record"); return TS_E_DEVICE; }
+    return TS_OK;
+}
+
+int check_is_opts(const ts_code *code, const int32_t *ts_bits, int32_t a, const ts_is_opts *o) {
+    if (a < 1 || a > kMaxWidth || !ts_bits) { set_error("TS size must be 1..%d", kMaxWidth); return TS_E_INVAL; }
+    if (o->n_frames < 2 || o->n_frames > (1ll << 31) - 1) { set_error("n_frames must be 2..2^31-1"); return TS_E_INVAL; }
+    if (o->max_iter < 1 || o->max_iter > kMaxIter) { set_error("max_iter must be 1..%d", kMaxIter); return TS_E_INVAL; }
+    if (!(o->rate > 0.0 && o->rate <= 1.0)) { set_error("rate out of range"); return TS_E_INVAL; }
+    if (!std::isfinite(o->ebn0_db) || !std::isfinite(o->shift)) { set_error("Eb/N0 and shift must be finite"); return TS_E_INVAL; }
+    std::vector<int32_t> t(ts_bits, ts_bits + a);
+    std::sort(t.begin(), t.end());
+    for (int i = 0; i < a; ++i)
+        if (t[i] < 0 || t[i] >= code->n || (i && t[i] == t[i - 1])) {
+            set_error("TS bits must be distinct variables of the code");
+            return TS_E_INVAL;
+        }
+    return TS_OK;
+}
+
+int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const ts_is_opts *o,
+           ts_is_result *res, uint8_t *fail_out) {
+    hipStream_t s = ex.stream;
+    int rc0 = check_is_opts(code, ts_bits, a, o);
+    if (rc0) return rc0;
+    std::vector<int32_t> t(ts_bits, ts_bits + a);
+    std::sort(t.begin(), t.end());
+    double shift = o->shift;
+    DBuf d_t(ex, kMaxWidth * 4);
+    if (!d_t.p) return TS_E_NOMEM;
+    TSG_HIP(hipMemcpyAsync(d_t.p, t.data(), a * 4, hipMemcpyHostToDevice, s));
+    if (shift < 0.0) {
+        // eps* of the noiseless SPA impulse on the whole set, grid 2^-10 up to 32
+        ts_search_opts so{};
+        so.decoder = TS_DEC_SPA_F32;
+        so.max_iter = o->max_iter;
+        so.ebn0_db = o->ebn0_db;
+        so.rate = o->rate;
+        so.llr_scale = 4.0;
+        so.k_max = 32 * 1024;
+        so.k_den = 1024;
+        so.a_max = 1;
+        so.extract_mode = TS_EXTRACT_CRITICAL;
+        so.collect_from_iter = -1;
+        so.mem = TS_MEM_DEVICE;
+        DBuf outs(ex, 5 * 4);
+        if (!outs.p) return TS_E_NOMEM;
+        int32_t *d_out[5];
+        for (int i = 0; i < 5; ++i) d_out[i] = outs.as<int32_t>() + i;
+        DevTable none{};
+        int rc = run_search(ex, code, none, &so, d_t.as<int32_t>(), 1, a, d_out, false);
+        if (rc) return rc;
+        TSG_HIP(hipMemcpyAsync(ex.pinned, d_out[0], 4, hipMemcpyDeviceToHost, s));
+        TSG_HIP(hipStreamSynchronize(s));
+        const int32_t kc = ex.pinned[0];
+        if (kc < 0) {
+            set_error("the impulse on the whole set never fails; give a shift");
+            return TS_E_INVAL;
+        }
+        shift = kc / 1024.0;
+    }
+    const int64_t K = o->n_frames;
+    DBuf d_fail(ex, (size_t)K), d_wf(ex, (size_t)K * 8), d_misc(ex, 64 * 4), d_red(ex, 8 * 8);
+    if (!d_fail.p || !d_wf.p || !d_misc.p || !d_red.p) { set_error("device allocation failed"); return TS_E_NOMEM; }
+    int rc = launch_fill(s, d_misc.as<int>(), 0, 64);
+    if (rc) return rc;
+    IsLaunch L{};
+    L.code = &code->dev;
+    L.max_iter = o->max_iter;
+    L.sigma2 = sigma2_of(o->ebn0_db, o->rate);
+    L.shift = shift;
+    L.n_frames = K;
+    L.seed = o->seed;
+    L.frame_base = o->frame_base;
+    L.stream = o->stream;
+    L.ts = d_t.as<int32_t>();
+    L.a = a;
+    L.fail = d_fail.as<unsigned char>();
+    L.wf = d_wf.as<double>();
+    L.queue = d_misc.as<int>();
+    L.counters = (unsigned long long *)(d_misc.as<int>() + 4);
+    int grid = 0, block = 0;
+    TSG_HIP(hipEventRecord(ex.ev[0], s));
+    rc = launch_is(ex, code, L, &grid, &block);
+    if (rc) return rc;
+    TSG_HIP(hipEventRecord(ex.ev[1], s));
+    rc = launch_is_reduce(s, L.wf, L.fail, K, 0, 0.0, d_red.as<double>());
+    if (rc) return rc;
+    double red[4];
+    TSG_HIP(hipMemcpyAsync(ex.pinned, d_red.p, 32, hipMemcpyDeviceToHost, s));
+    TSG_HIP(hipStreamSynchronize(s));
+    std::memcpy(red, ex.pinned, 32);
+    const double p = red[0] / (double)K;
+    rc = launch_is_reduce(s, L.wf, L.fail, K, 1, p, d_red.as<double>());
+    if (rc) return rc;
+    TSG_HIP(hipMemcpyAsync(ex.pinned, d_red.p, 32, hipMemcpyDeviceToHost, s));
+    TSG_HIP(hipMemcpyAsync(ex.pinned + 8, d_misc.as<int>() + 4, 16, hipMemcpyDeviceToHost, s));
+    if (fail_out) TSG_HIP(hipMemcpyAsync(fail_out, d_fail.p, (size_t)K, hipMemcpyDeviceToHost, s));
+    TSG_HIP(hipEventRecord(ex.ev[2], s));
+    TSG_HIP(hipStreamSynchronize(s));
+    red[3] = ((double *)ex.pinned)[3];
+    unsigned long long cnt[2];
+    std::memcpy(cnt, ex.pinned + 8, 16);
+    float ms = 0.0f, tot = 0.0f;
+    TSG_HIP(hipEventElapsedTime(&ms, ex.ev[0], ex.ev[1]));
+    TSG_HIP(hipEventElapsedTime(&tot, ex.ev[0], ex.ev[2]));
+    const double var = red[3] / ((double)K * (double)(K - 1));
+    res->p_hat = p;
+    res->var = var;
+    res->ci_lo = p - 1.96 * std::sqrt(var);
+    res->ci_hi = p + 1.96 * std::sqrt(var);
+    res->sum_w = red[0];
+    res->sum_w2 = red[1];
+    res->n = K;
+    res->n_fail = (int64_t)std::llround(red[2]);
+    res->shift_used = shift;
+    ex.stats.decode_ms += ms;
+    ex.stats.total_ms += tot;
+    ex.stats.decodes += K;
+    ex.stats.edge_updates += (int64_t)cnt[1] * code->e;
+    ex.stats.decode_launches += 1;
+    ex.stats.block_threads = block;
+    ex.stats.grid_blocks = grid;
+    return TS_OK;
+}
+
+}  // namespace tsg
+
+namespace {
+
+int exec_init(ts_exec &ex, ts_ctx *ctx, hipStream_t stream, bool stream_alloc) {
+    ex.ctx = ctx;
+    if (stream) {
+        ex.stream = stream;
+    } else {
+        // default priority: stream priorities are left alone
+        TSG_HIP(hipStreamCreateWithFlags(&ex.stream, hipStreamNonBlocking));
+        ex.own_stream = true;
+    }
+    ex.stream_alloc = stream_alloc;
+    for (auto &e : ex.ev) TSG_HIP(hipEventCreate(&e));
+    TSG_HIP(hipHostMalloc((void **)&ex.pinned, 64 * sizeof(int), hipHostMallocDefault));
+    return TS_OK;
+}
+
+void exec_fini(ts_exec &ex) {
+    if (ex.stream) (void)hipStreamSynchronize(ex.stream);
+    for (auto &e : ex.ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ex.pinned) (void)hipHostFree(ex.pinned);
+    if (ex.own_stream && ex.stream) (void)hipStreamDestroy(ex.stream);
+    ex = ts_exec{};
+}
+
+}  // namespace
+
+namespace tsg {
+int exec_create(ts_exec &ex, ts_ctx *ctx) { return exec_init(ex, ctx, nullptr, true); }
+void exec_destroy(ts_exec &ex) { exec_fini(ex); }
+}  // namespace tsg
 
 extern "C" {
 
@@ -84,40 +472,27 @@ int ts_create(const ts_ctx_opts *opts, ts_ctx **out) {
     ts_ctx *c = new (std::nothrow) ts_ctx();
     if (!c) { set_error("out of host memory"); return TS_E_NOMEM; }
     c->device = dev;
+    c->t0 = now_ms();
     if (opts) {
         c->alloc = opts->alloc;
         c->free_fn = opts->free;
         c->user = opts->user;
         c->budget = opts->hbm_budget_bytes;
     }
-    if (opts && opts->hip_stream) {
-        c->stream = (hipStream_t)opts->hip_stream;
-    } else {
-        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
-            delete c;
-            set_error("stream creation failed");
-            return TS_E_DEVICE;
-        }
-        c->own_stream = true;
-    }
     int ncu = 0, lds = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
-        if (c->own_stream) (void)hipStreamDestroy(c->stream);
         delete c;
         set_error("device query failed");
         return TS_E_DEVICE;
     }
     c->num_cu = ncu;
     c->lds_per_block = (size_t)lds;
-    for (auto &e : c->ev)
-        if (hipEventCreate(&e) != hipSuccess) {
-            set_error("event creation failed");
-            return TS_E_DEVICE;
-        }
-    if (hipHostMalloc((void **)&c->pinned, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
-        set_error("pinned allocation failed");
-        return TS_E_NOMEM;
+    const int rc = exec_init(c->main, c, opts ? (hipStream_t)opts->hip_stream : nullptr, false);
+    if (rc) {
+        exec_fini(c->main);
+        delete c;
+        return rc;
     }
     *out = c;
     return TS_OK;
@@ -128,9 +503,10 @@ int ts_free_code(ts_ctx *ctx, ts_code *code) {
     if (!ctx || !code) { set_error("null argument"); return TS_E_INVAL; }
     std::lock_guard<std::recursive_mutex> g(ctx->mu);
     if (code->ctx != ctx) { set_error("code belongs to another context"); return TS_E_STATE; }
-    (void)hipStreamSynchronize(ctx->stream);
-    table_free(ctx, code);
-    for (void *p : code->dev_allocs) ctx->dfree(p);
+    if (code->jobs_in_flight.load() > 0) { set_error("code has submitted jobs in flight"); return TS_E_BUSY; }
+    (void)hipStreamSynchronize(ctx->main.stream);
+    table_free(ctx->main, code->table);
+    for (void *p : code->dev_allocs) ctx->main.dfree(p);
     ctx->codes.erase(std::remove(ctx->codes.begin(), ctx->codes.end(), code), ctx->codes.end());
     delete code;
     return TS_OK;
@@ -139,14 +515,11 @@ int ts_free_code(ts_ctx *ctx, ts_code *code) {
 int ts_destroy(ts_ctx *ctx) {
     clear_error();
     if (!ctx) return TS_OK;
+    server_stop(ctx);
     {
         std::lock_guard<std::recursive_mutex> g(ctx->mu);
         while (!ctx->codes.empty()) ts_free_code(ctx, ctx->codes.back());
-        (void)hipStreamSynchronize(ctx->stream);
-        for (auto &e : ctx->ev)
-            if (e) (void)hipEventDestroy(e);
-        if (ctx->pinned) (void)hipHostFree(ctx->pinned);
-        if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+        exec_fini(ctx->main);
     }
     delete ctx;
     return TS_OK;
@@ -161,9 +534,9 @@ int ts_load_code(ts_ctx *ctx, const ts_code_desc *desc, ts_code **out) {
     if (!c) { set_error("out of host memory"); return TS_E_NOMEM; }
     c->ctx = ctx;
     int rc = build_code(desc, c);
-    if (rc == TS_OK) rc = upload_code(ctx, c);
+    if (rc == TS_OK) rc = upload_code(ctx->main, c);
     if (rc != TS_OK) {
-        for (void *p : c->dev_allocs) ctx->dfree(p);
+        for (void *p : c->dev_allocs) ctx->main.dfree(p);
         delete c;
         return rc;
     }
@@ -211,7 +584,8 @@ int ts_make_patterns(ts_ctx *ctx, const ts_code *code, int32_t kind, int32_t *ou
 int ts_get_stats(ts_ctx *ctx, ts_stats *out) {
     clear_error();
     if (!ctx || !out) { set_error("null argument"); return TS_E_INVAL; }
-    *out = ctx->stats;
+    std::lock_guard<std::recursive_mutex> g(ctx->mu);
+    *out = ctx->main.stats;
     return TS_OK;
 }
 
@@ -220,160 +594,10 @@ int ts_reset_ts(ts_ctx *ctx, ts_code *code) {
     if (!ctx || !code) { set_error("null argument"); return TS_E_INVAL; }
     std::lock_guard<std::recursive_mutex> g(ctx->mu);
     if (code->ctx != ctx) { set_error("code belongs to another context"); return TS_E_STATE; }
-    (void)hipStreamSynchronize(ctx->stream);
-    return table_free(ctx, code);
-}
-
-}  // extern "C"
-
-namespace {
-
-// Runs the search on device-resident patterns / outputs.  With sieve = false no
-// candidate is written (only k* and the iteration counts are produced).
-int run_search(ts_ctx *ctx, ts_code *code, const ts_search_opts *o, const int32_t *d_pat,
-               int64_t P, int32_t width, int32_t *const d_out[5], bool sieve) {
-    SearchPlan plan;
-    int rc = plan_search(ctx, code, o->decoder, o->max_iter, &plan);
-    if (rc) return rc;
-    const double s2 = sigma2_of(o->ebn0_db, o->rate);
-    const double h = 2.0 / s2;
-    const int q_base = sat127(std::lround(o->llr_scale * h));
-    int t0 = o->collect_from_iter >= 0 ? o->collect_from_iter : code->girth / 2;
-    if (t0 < 1) t0 = 1;
-    if (!sieve) t0 = o->max_iter + 1;   // no iteration qualifies: nothing is written
-
-    DBuf misc(ctx, 64 * 4);
-    if (!misc.p) { set_error("device allocation failed"); return TS_E_NOMEM; }
-    int *d_misc = misc.as<int>();
-    // misc layout: [0] queue, [1] rec_count, [2] err, [4..7] counters (2 x u64)
-    rc = launch_fill(ctx, d_misc, 0, 64);
-    if (rc) return rc;
-
-    // candidate record buffer: at most 256 MB, at least one pattern's worst case
-    const int d_fail_max = 2 + (int)std::ceil(std::log2((double)o->k_max));
-    const int64_t worst_per_pat = sieve ? (int64_t)d_fail_max * std::max(1, o->max_iter - t0 + 1) : 0;
-    int64_t rec_cap = std::min<int64_t>((256ll << 20) / (kRecStride * 4), worst_per_pat * P);
-    rec_cap = std::max<int64_t>(std::max<int64_t>(rec_cap, worst_per_pat), 1);
-    DBuf recs(ctx, (size_t)rec_cap * kRecStride * 4);
-    if (!recs.p) { set_error("device allocation of the candidate buffer failed"); return TS_E_NOMEM; }
-
-    SearchLaunch a{};
-    a.code = &code->dev;
-    a.decoder = o->decoder;
-    a.max_iter = o->max_iter;
-    a.offset = o->oms_offset;
-    a.q_base = q_base;
-    a.k_max = o->k_max;
-    a.k_den = o->k_den;
-    a.h = (float)h;
-    a.t0 = t0;
-    a.cap = 2 * o->a_max;
-    a.a_max = o->a_max;
-    a.extract_mode = o->extract_mode;
-    a.width = width;
-    a.k_crit = d_out[0];
-    a.iters_crit = d_out[1];
-    a.iters_lo = d_out[2];
-    a.tmin_crit = d_out[3];
-    a.n_cand = d_out[4];
-    a.queue = d_misc;
-    a.rec_count = d_misc + 1;
-    a.err = d_misc + 2;
-    a.counters = (unsigned long long *)(d_misc + 4);
-    a.recs = recs.as<int>();
-    a.rec_cap = (int)rec_cap;
-
-    if (sieve) {
-        rc = table_init(ctx, code, 1 << 16);
-        if (rc) return rc;
-    }
-    TSG_HIP(hipEventRecord(ctx->ev[4], ctx->stream));
-    int64_t chunk = P, pos = 0, cands = 0;
-    double dec_ms = 0.0, sieve_ms = 0.0;
-    while (pos < P) {
-        const int64_t len = std::min<int64_t>(chunk, P - pos);
-        rc = launch_fill(ctx, d_misc, 0, 2);   // queue, rec_count
-        if (rc) return rc;
-        a.patterns = d_pat + pos * width;
-        a.n_patterns = (int)len;
-        a.pat_base = (int)pos;
-        TSG_HIP(hipEventRecord(ctx->ev[0], ctx->stream));
-        rc = launch_search(ctx, plan, a);
-        if (rc) return rc;
-        TSG_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
-        TSG_HIP(hipMemcpyAsync(ctx->pinned, d_misc, 16, hipMemcpyDeviceToHost, ctx->stream));
-        TSG_HIP(hipStreamSynchronize(ctx->stream));
-        float ms = 0.0f;
-        TSG_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
-        dec_ms += ms;
-        ctx->stats.decode_launches++;
-        const int64_t nrec = ctx->pinned[1];
-        if (ctx->pinned[2] & 1) { set_error("pattern entry out of range"); return TS_E_INVAL; }
-        if (nrec > rec_cap) {
-            if (len == 1) { set_error("candidate buffer too small for one pattern"); return TS_E_NOMEM; }
-            chunk = std::max<int64_t>(1, len / 2);   // re-run this chunk in smaller pieces
-            continue;
-        }
-        if (sieve && nrec > 0) {
-            cands += nrec;
-            rc = table_grow_if_needed(ctx, code, 2 * nrec);
-            if (rc) return rc;
-            TSG_HIP(hipEventRecord(ctx->ev[2], ctx->stream));
-            rc = launch_sieve(ctx, code, a, (int)nrec);
-            if (rc) return rc;
-            TSG_HIP(hipEventRecord(ctx->ev[3], ctx->stream));
-            TSG_HIP(hipStreamSynchronize(ctx->stream));
-            TSG_HIP(hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]));
-            sieve_ms += ms;
-            ctx->stats.extract_launches++;
-        }
-        pos += len;
-    }
-    TSG_HIP(hipMemcpyAsync(ctx->pinned, d_misc, 32, hipMemcpyDeviceToHost, ctx->stream));
-    TSG_HIP(hipEventRecord(ctx->ev[5], ctx->stream));
-    TSG_HIP(hipStreamSynchronize(ctx->stream));
-    float tot = 0.0f;
-    TSG_HIP(hipEventElapsedTime(&tot, ctx->ev[4], ctx->ev[5]));
-    const int err = ctx->pinned[2];
-    unsigned long long cnt[2];
-    std::memcpy(cnt, ctx->pinned + 4, 16);
-    ctx->stats.decode_ms += dec_ms;
-    ctx->stats.extract_ms += sieve_ms;
-    ctx->stats.total_ms += tot;
-    ctx->stats.decodes += (int64_t)cnt[0];
-    ctx->stats.edge_updates += (int64_t)cnt[1] * code->e;
-    ctx->stats.candidates += cands;
-    ctx->stats.block_threads = plan.block;
-    ctx->stats.grid_blocks = (int)std::min<int64_t>(plan.grid, P);
-    if (err & 1) { set_error("pattern entry out of range"); return TS_E_INVAL; }
-    if (err & 4) { set_error("TS table insert timed out"); return TS_E_DEVICE; }
-    if (err & 8) { set_error("TS table full"); return TS_E_NOMEM; }
-    if (err & 16) { set_error("corrupt candidate record"); return TS_E_DEVICE; }
+    (void)hipStreamSynchronize(ctx->main.stream);
+    table_free(ctx->main, code->table);
     return TS_OK;
 }
-
-int check_search_opts(const ts_code *code, const ts_search_opts *o, int32_t width) {
-    if (o->decoder != TS_DEC_OMS_I8 && o->decoder != TS_DEC_SPA_F32) {
-        set_error("unknown decoder %d", o->decoder);
-        return TS_E_INVAL;
-    }
-    if (o->max_iter < 1 || o->max_iter > kMaxIter) { set_error("max_iter must be 1..%d", kMaxIter); return TS_E_INVAL; }
-    if (o->a_max < 1 || o->a_max > kMaxAmax) { set_error("a_max must be 1..%d", kMaxAmax); return TS_E_INVAL; }
-    if (o->k_max < 1 || o->k_max > (1 << 24)) { set_error("k_max must be 1..2^24"); return TS_E_INVAL; }
-    if (o->decoder == TS_DEC_OMS_I8 && o->k_den != 16) { set_error("the int8 decoder uses k_den = 16"); return TS_E_INVAL; }
-    if (o->k_den < 1) { set_error("k_den must be positive"); return TS_E_INVAL; }
-    if (o->oms_offset < 0 || o->oms_offset > 127) { set_error("oms_offset must be 0..127"); return TS_E_INVAL; }
-    if (!(o->rate > 0.0 && o->rate <= 1.0) || !(o->llr_scale > 0.0)) { set_error("rate / llr_scale out of range"); return TS_E_INVAL; }
-    if (o->extract_mode != TS_EXTRACT_PATH && o->extract_mode != TS_EXTRACT_CRITICAL) { set_error("bad extract_mode"); return TS_E_INVAL; }
-    if (o->mem != TS_MEM_HOST && o->mem != TS_MEM_DEVICE) { set_error("bad mem kind"); return TS_E_INVAL; }
-    if (width < 1 || width > kMaxWidth) { set_error("width must be 1..%d", kMaxWidth); return TS_E_INVAL; }
-    if (code->dv_max > kDvMax) { set_error("variable degree %d above the sieve's limit %d", code->dv_max, kDvMax); return TS_E_INVAL; }
-    return TS_OK;
-}
-
-}  // namespace
-
-extern "C" {
 
 int ts_impulse_search(ts_ctx *ctx, ts_code *code, const ts_search_opts *o, const int32_t *patterns,
                       int32_t n_patterns, int32_t width, ts_search_out *out) {
@@ -381,7 +605,8 @@ int ts_impulse_search(ts_ctx *ctx, ts_code *code, const ts_search_opts *o, const
     if (!ctx || !code || !o || !out) { set_error("null argument"); return TS_E_INVAL; }
     std::lock_guard<std::recursive_mutex> g(ctx->mu);
     if (code->ctx != ctx) { set_error("code belongs to another context"); return TS_E_STATE; }
-    ctx->stats = ts_stats{};
+    ts_exec &ex = ctx->main;
+    ex.stats = ts_stats{};
     int rc = check_search_opts(code, o, width);
     if (rc) return rc;
     if (n_patterns < 0) { set_error("negative pattern count"); return TS_E_INVAL; }
@@ -392,22 +617,23 @@ int ts_impulse_search(ts_ctx *ctx, ts_code *code, const ts_search_opts *o, const
     }
     const size_t P = (size_t)n_patterns;
     int32_t *d_out[5] = {out->k_crit, out->iters_crit, out->iters_lo, out->tmin_crit, out->n_cand};
-    if (o->mem == TS_MEM_DEVICE) return run_search(ctx, code, o, patterns, (int64_t)P, width, d_out, true);
+    if (o->mem == TS_MEM_DEVICE)
+        return run_search(ex, code, code->table, o, patterns, (int64_t)P, width, d_out, true);
     for (size_t i = 0; i < P * (size_t)width; ++i)
         if (patterns[i] < -1 || patterns[i] >= code->n) {
             set_error("pattern entry %d out of range", patterns[i]);
             return TS_E_INVAL;
         }
-    DBuf pat_buf(ctx, P * width * 4), out_buf(ctx, P * 5 * 4);
+    DBuf pat_buf(ex, P * width * 4), out_buf(ex, P * 5 * 4);
     if (!pat_buf.p || !out_buf.p) { set_error("device allocation failed"); return TS_E_NOMEM; }
-    TSG_HIP(hipMemcpyAsync(pat_buf.p, patterns, P * width * 4, hipMemcpyHostToDevice, ctx->stream));
+    TSG_HIP(hipMemcpyAsync(pat_buf.p, patterns, P * width * 4, hipMemcpyHostToDevice, ex.stream));
     int32_t *dev_out[5];
     for (int i = 0; i < 5; ++i) dev_out[i] = out_buf.as<int32_t>() + i * P;
-    rc = run_search(ctx, code, o, pat_buf.as<int32_t>(), (int64_t)P, width, dev_out, true);
+    rc = run_search(ex, code, code->table, o, pat_buf.as<int32_t>(), (int64_t)P, width, dev_out, true);
     if (rc) return rc;
     for (int i = 0; i < 5; ++i)
-        TSG_HIP(hipMemcpyAsync(d_out[i], dev_out[i], P * 4, hipMemcpyDeviceToHost, ctx->stream));
-    TSG_HIP(hipStreamSynchronize(ctx->stream));
+        TSG_HIP(hipMemcpyAsync(d_out[i], dev_out[i], P * 4, hipMemcpyDeviceToHost, ex.stream));
+    TSG_HIP(hipStreamSynchronize(ex.stream));
     return TS_OK;
 }
 
@@ -417,110 +643,8 @@ int ts_is_estimate(ts_ctx *ctx, ts_code *code, const int32_t *ts_bits, int32_t a
     if (!ctx || !code || !ts_bits || !o || !res) { set_error("null argument"); return TS_E_INVAL; }
     std::lock_guard<std::recursive_mutex> g(ctx->mu);
     if (code->ctx != ctx) { set_error("code belongs to another context"); return TS_E_STATE; }
-    ctx->stats = ts_stats{};
-    if (a < 1 || a > kMaxWidth) { set_error("TS size must be 1..%d", kMaxWidth); return TS_E_INVAL; }
-    if (o->n_frames < 2 || o->n_frames > (1ll << 31) - 1) { set_error("n_frames must be 2..2^31-1"); return TS_E_INVAL; }
-    if (o->max_iter < 1 || o->max_iter > kMaxIter) { set_error("max_iter must be 1..%d", kMaxIter); return TS_E_INVAL; }
-    if (!(o->rate > 0.0 && o->rate <= 1.0)) { set_error("rate out of range"); return TS_E_INVAL; }
-    std::vector<int32_t> t(ts_bits, ts_bits + a);
-    std::sort(t.begin(), t.end());
-    for (int i = 0; i < a; ++i)
-        if (t[i] < 0 || t[i] >= code->n || (i && t[i] == t[i - 1])) {
-            set_error("TS bits must be distinct variables of the code");
-            return TS_E_INVAL;
-        }
-    double shift = o->shift;
-    DBuf d_t(ctx, kMaxWidth * 4);
-    if (!d_t.p) return TS_E_NOMEM;
-    TSG_HIP(hipMemcpyAsync(d_t.p, t.data(), a * 4, hipMemcpyHostToDevice, ctx->stream));
-    if (shift < 0.0) {
-        // eps* of the noiseless SPA impulse on the whole set, grid 2^-10 up to 32
-        ts_search_opts so{};
-        so.decoder = TS_DEC_SPA_F32;
-        so.max_iter = o->max_iter;
-        so.ebn0_db = o->ebn0_db;
-        so.rate = o->rate;
-        so.llr_scale = 4.0;
-        so.k_max = 32 * 1024;
-        so.k_den = 1024;
-        so.a_max = 1;
-        so.extract_mode = TS_EXTRACT_CRITICAL;
-        so.collect_from_iter = -1;
-        so.mem = TS_MEM_DEVICE;
-        DBuf outs(ctx, 5 * 4);
-        if (!outs.p) return TS_E_NOMEM;
-        int32_t *d_out[5];
-        for (int i = 0; i < 5; ++i) d_out[i] = outs.as<int32_t>() + i;
-        int rc = run_search(ctx, code, &so, d_t.as<int32_t>(), 1, a, d_out, false);
-        if (rc) return rc;
-        int32_t kc = 0;
-        TSG_HIP(hipMemcpy(&kc, d_out[0], 4, hipMemcpyDeviceToHost));
-        if (kc < 0) {
-            set_error("the impulse on the whole set never fails; give a shift");
-            return TS_E_INVAL;
-        }
-        shift = kc / 1024.0;
-    }
-    const int64_t K = o->n_frames;
-    DBuf d_fail(ctx, (size_t)K), d_wf(ctx, (size_t)K * 8), d_misc(ctx, 64 * 4), d_red(ctx, 8 * 8);
-    if (!d_fail.p || !d_wf.p || !d_misc.p || !d_red.p) { set_error("device allocation failed"); return TS_E_NOMEM; }
-    int rc = launch_fill(ctx, d_misc.as<int>(), 0, 64);
-    if (rc) return rc;
-    IsLaunch L{};
-    L.code = &code->dev;
-    L.max_iter = o->max_iter;
-    L.sigma2 = sigma2_of(o->ebn0_db, o->rate);
-    L.shift = shift;
-    L.n_frames = K;
-    L.seed = o->seed;
-    L.frame_base = o->frame_base;
-    L.stream = o->stream;
-    L.ts = d_t.as<int32_t>();
-    L.a = a;
-    L.fail = d_fail.as<unsigned char>();
-    L.wf = d_wf.as<double>();
-    L.queue = d_misc.as<int>();
-    L.counters = (unsigned long long *)(d_misc.as<int>() + 4);
-    int grid = 0, block = 0;
-    TSG_HIP(hipEventRecord(ctx->ev[0], ctx->stream));
-    rc = launch_is(ctx, code, L, &grid, &block);
-    if (rc) return rc;
-    TSG_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
-    rc = launch_is_reduce(ctx, L.wf, L.fail, K, 0, 0.0, d_red.as<double>());
-    if (rc) return rc;
-    double red[4];
-    TSG_HIP(hipMemcpyAsync(red, d_red.p, 32, hipMemcpyDeviceToHost, ctx->stream));
-    TSG_HIP(hipStreamSynchronize(ctx->stream));
-    const double p = red[0] / (double)K;
-    rc = launch_is_reduce(ctx, L.wf, L.fail, K, 1, p, d_red.as<double>());
-    if (rc) return rc;
-    TSG_HIP(hipMemcpyAsync(red, d_red.p, 32, hipMemcpyDeviceToHost, ctx->stream));
-    unsigned long long cnt[2];
-    TSG_HIP(hipMemcpyAsync(cnt, d_misc.as<int>() + 4, 16, hipMemcpyDeviceToHost, ctx->stream));
-    if (fail_out) TSG_HIP(hipMemcpyAsync(fail_out, d_fail.p, (size_t)K, hipMemcpyDeviceToHost, ctx->stream));
-    TSG_HIP(hipEventRecord(ctx->ev[2], ctx->stream));
-    TSG_HIP(hipStreamSynchronize(ctx->stream));
-    float ms = 0.0f, tot = 0.0f;
-    TSG_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
-    TSG_HIP(hipEventElapsedTime(&tot, ctx->ev[0], ctx->ev[2]));
-    const double var = red[3] / ((double)K * (double)(K - 1));
-    res->p_hat = p;
-    res->var = var;
-    res->ci_lo = p - 1.96 * std::sqrt(var);
-    res->ci_hi = p + 1.96 * std::sqrt(var);
-    res->sum_w = red[0];
-    res->sum_w2 = red[1];
-    res->n = K;
-    res->n_fail = (int64_t)std::llround(red[2]);
-    res->shift_used = shift;
-    ctx->stats.decode_ms += ms;
-    ctx->stats.total_ms += tot;
-    ctx->stats.decodes += K;
-    ctx->stats.edge_updates += (int64_t)cnt[1] * code->e;
-    ctx->stats.decode_launches += 1;
-    ctx->stats.block_threads = block;
-    ctx->stats.grid_blocks = grid;
-    return TS_OK;
+    ctx->main.stats = ts_stats{};
+    return run_is(ctx->main, code, ts_bits, a, o, res, fail_out);
 }
 
 int ts_collect(ts_ctx *ctx, const ts_code *code, ts_record *recs, int64_t cap, int64_t *n_out,
@@ -530,7 +654,7 @@ int ts_collect(ts_ctx *ctx, const ts_code *code, ts_record *recs, int64_t cap, i
     std::lock_guard<std::recursive_mutex> g(ctx->mu);
     if (code->ctx != ctx) { set_error("code belongs to another context"); return TS_E_STATE; }
     std::vector<int32_t> rh, bh;
-    int rc = collect_table(ctx, code, rh, bh);
+    int rc = collect_table(ctx->main, code->table, rh, bh);
     if (rc) return rc;
     const int64_t n = (int64_t)rh.size() / 5;
     *n_out = n;

@@ -3,9 +3,14 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <condition_variable>
 #include <cstdint>
+#include <deque>
 #include <mutex>
 #include <string>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "tsgpu.h"
@@ -14,6 +19,7 @@ namespace tsg {
 
 void set_error(const char *fmt, ...);
 void clear_error();
+std::string last_error_copy();
 
 #define TSG_HIP(expr)                                                          \
     do {                                                                       \
@@ -59,35 +65,50 @@ struct DevTable {
     int *first;                // [cap] smallest pattern index
     int *kcrit;                // [cap] smallest k*
     int *count;                // [1]   claimed slots
-    int cap;                   // power of two
+    int cap;                   // power of two, 0 = not allocated
 };
 
-struct ts_code_impl;
+// A decoder launch shape picked by the autotuner.
+struct SearchShape {
+    int cpt = 0;
+};
 
 }  // namespace tsg
 
-struct ts_ctx {
-    int device = 0;
+struct ts_code;
+
+// One executor: a stream and the host/device state a call needs on it.  The
+// context owns one for the synchronous calls; every serving worker owns one.
+struct ts_exec {
+    ts_ctx *ctx = nullptr;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    bool stream_alloc = false;   // allocate with hipMallocAsync on this stream
+    hipEvent_t ev[6] = {};
+    int *pinned = nullptr;       // host staging for small device -> host reads
+    ts_stats stats{};
+
+    void *dalloc(size_t bytes);
+    void dfree(void *p);
+};
+
+namespace tsg {
+struct Server;
+}
+
+struct ts_ctx {
+    int device = 0;
     void *(*alloc)(size_t, void *) = nullptr;
     void (*free_fn)(void *, void *) = nullptr;
     void *user = nullptr;
     size_t budget = 0;
     std::recursive_mutex mu;
-    ts_stats stats{};
-    hipEvent_t ev[6] = {};
+    ts_exec main;
     std::vector<ts_code *> codes;
-    // reusable device scratch
-    void *scratch = nullptr;
-    size_t scratch_bytes = 0;
     int num_cu = 0;
     size_t lds_per_block = 0;
-    // pinned host staging for small device -> host reads
-    int *pinned = nullptr;
-
-    void *dalloc(size_t bytes);
-    void dfree(void *p);
+    tsg::Server *server = nullptr;
+    double t0 = 0.0;   // creation time (ms, steady clock)
 };
 
 struct ts_code {
@@ -103,29 +124,35 @@ struct ts_code {
     // device copies
     tsg::DevCode dev{};
     std::vector<void *> dev_allocs;
-    tsg::DevTable table{};
-    bool table_alloc = false;
+    tsg::DevTable table{};          // the code's TS table (synchronous calls)
+    std::atomic<int> jobs_in_flight{0};
+    // launch shapes chosen by the autotuner, keyed by (decoder, max_iter)
+    std::mutex tune_mu;
+    std::unordered_map<int, tsg::SearchShape> tuned;
 };
 
 namespace tsg {
 
+double now_ms();
+
 // loader.cpp
 int build_code(const ts_code_desc *d, ts_code *c);
-int upload_code(ts_ctx *ctx, ts_code *c);
+int upload_code(ts_exec &ex, ts_code *c);
 int64_t make_patterns(const ts_code *c, int kind, int32_t *out, int64_t cap);
 
-// table.cpp / ts_kernels.hip
-int table_init(ts_ctx *ctx, ts_code *c, int cap);
-int table_free(ts_ctx *ctx, ts_code *c);
-int table_grow_if_needed(ts_ctx *ctx, ts_code *c, int64_t incoming);
+// ts_kernels.hip
+int table_init(ts_exec &ex, DevTable &t, int cap);
+void table_free(ts_exec &ex, DevTable &t);
+int table_grow_if_needed(ts_exec &ex, DevTable &t, int64_t incoming);
+int collect_table(ts_exec &ex, const DevTable &t, std::vector<int32_t> &rec_host,
+                  std::vector<int32_t> &bits_host);
+size_t table_bytes(int cap);
 
 // search (search_kernels.hip)
 struct SearchPlan {
     int block;      // threads per workgroup
     int cpt;        // checks per thread
     int dc;         // padded check degree of the kernel
-    int vpt;        // variables per thread (SPA)
-    int dv;         // padded variable degree of the kernel (SPA)
     size_t lds;     // dynamic LDS bytes
     int grid;       // persistent workgroups
 };
@@ -148,15 +175,14 @@ struct SearchLaunch {
 };
 
 int plan_search(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter, SearchPlan *plan);
-int launch_search(ts_ctx *ctx, const SearchPlan &plan, const SearchLaunch &a);
-int launch_sieve(ts_ctx *ctx, ts_code *c, const SearchLaunch &a, int n_waves_hint);
-int launch_fill(ts_ctx *ctx, int *p, int value, int64_t count);
+int plan_candidates(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter,
+                    std::vector<SearchPlan> *out);
+int launch_search(hipStream_t s, const SearchPlan &plan, const SearchLaunch &a);
+int launch_sieve(ts_exec &ex, const DevCode &cd, const DevTable &t, const SearchLaunch &a,
+                 int n_records);
+int launch_fill(hipStream_t s, int *p, int value, int64_t count);
 
-// collect
-int collect_table(ts_ctx *ctx, const ts_code *c, std::vector<int32_t> &rec_host,
-                  std::vector<int32_t> &bits_host);
-
-// importance sampling (is_kernels.hip)
+// importance sampling
 struct IsLaunch {
     const DevCode *code;
     int max_iter;
@@ -170,9 +196,22 @@ struct IsLaunch {
     int *queue;
     unsigned long long *counters;
 };
-int launch_is(ts_ctx *ctx, const ts_code *c, const IsLaunch &a, int *grid_out, int *block_out);
+int launch_is(ts_exec &ex, const ts_code *c, const IsLaunch &a, int *grid_out, int *block_out);
 // mode 0: out[0..2] = sum w, sum w^2, failures; mode 1: out[3] = sum (w - mean)^2
-int launch_is_reduce(ts_ctx *ctx, const double *wf, const unsigned char *fail, int64_t n, int mode,
+int launch_is_reduce(hipStream_t s, const double *wf, const unsigned char *fail, int64_t n, int mode,
                      double mean, double *out);
+
+// api.cpp: the work of one search / IS call on an executor
+int check_search_opts(const ts_code *code, const ts_search_opts *o, int32_t width);
+int run_search(ts_exec &ex, ts_code *code, DevTable &table, const ts_search_opts *o,
+               const int32_t *d_pat, int64_t P, int32_t width, int32_t *const d_out[5], bool sieve);
+int check_is_opts(const ts_code *code, const int32_t *ts_bits, int32_t a, const ts_is_opts *o);
+int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const ts_is_opts *o,
+           ts_is_result *res, uint8_t *fail_out);
+size_t search_bytes_estimate(const ts_code *code, const ts_search_opts *o, int64_t P, int32_t width);
+
+// serve.cpp
+struct Server;
+void server_stop(ts_ctx *ctx);
 
 }  // namespace tsg

@@ -153,7 +153,7 @@ int build_code(const ts_code_desc *d, ts_code *c) {
     return TS_OK;
 }
 
-int upload_code(ts_ctx *ctx, ts_code *c) {
+int upload_code(ts_exec &ex, ts_code *c) {
     DevCode &d = c->dev;
     d.n = c->n;
     d.m = c->m;
@@ -183,13 +183,13 @@ int upload_code(ts_ctx *ctx, ts_code *c) {
         {vn.data(), vn.size() * 4, &d.vn_tab},
     };
     for (auto &u : ups) {
-        void *p = ctx->dalloc(u.bytes ? u.bytes : 4);
+        void *p = ex.dalloc(u.bytes ? u.bytes : 4);
         if (!p) { set_error("device allocation of %zu bytes failed", u.bytes); return TS_E_NOMEM; }
         c->dev_allocs.push_back(p);
-        TSG_HIP(hipMemcpyAsync(p, u.src, u.bytes, hipMemcpyHostToDevice, ctx->stream));
+        TSG_HIP(hipMemcpyAsync(p, u.src, u.bytes, hipMemcpyHostToDevice, ex.stream));
         *u.dst = (const int *)p;
     }
-    TSG_HIP(hipStreamSynchronize(ctx->stream));
+    TSG_HIP(hipStreamSynchronize(ex.stream));
     return TS_OK;
 }
 

@@ -335,8 +335,19 @@ __device__ void write_candidates(const SearchLaunch &a, const unsigned long long
 // ---------------------------------------------------------------------------
 // impulse search: one pattern per workgroup, bisection on the amplitude
 // ---------------------------------------------------------------------------
+// Workgroup bound of a shape: small register footprints allow 1024 threads.
+template <int DC, int CPT>
+struct MaxBlock {
+    static constexpr int value = DC * CPT <= 16 ? 1024 : 256;
+};
+// The IS kernel also keeps the Philox state and the weight accumulators live.
+template <int DC, int CPT>
+struct MaxBlockIs {
+    static constexpr int value = DC * CPT <= 8 ? 1024 : 256;
+};
+
 template <class Rule, int DC, int CPT>
-__global__ __launch_bounds__(256) void k_search(SearchLaunch a, DevCode cd) {
+__global__ __launch_bounds__((MaxBlock<DC, CPT>::value)) void k_search(SearchLaunch a, DevCode cd) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = cd.n, T = a.max_iter;
     const Lds L = lds_layout(n, T, true);
@@ -476,7 +487,7 @@ struct IsDev {
 };
 
 template <int DC, int CPT>
-__global__ __launch_bounds__(256) void k_is(IsDev a, DevCode cd) {
+__global__ __launch_bounds__((MaxBlockIs<DC, CPT>::value)) void k_is(IsDev a, DevCode cd) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = cd.n, T = a.max_iter;
     const Lds L = lds_layout(n, T, false);
@@ -615,13 +626,14 @@ typedef void (*SearchKernel)(SearchLaunch, DevCode);
 typedef void (*IsKernel)(IsDev, DevCode);
 
 struct KEntry {
-    int dc, cpt;
+    int dc, cpt, max_block, is_max_block;
     SearchKernel oms, spa;
     IsKernel is;
 };
 
-#define TSG_K(DC, CPT) \
-    {DC, CPT, k_search<OmsRule, DC, CPT>, k_search<SpaRule, DC, CPT>, k_is<DC, CPT>}
+#define TSG_K(DC, CPT)                                                                \
+    {DC, CPT, MaxBlock<DC, CPT>::value, MaxBlockIs<DC, CPT>::value, k_search<OmsRule, DC, CPT>, \
+     k_search<SpaRule, DC, CPT>, k_is<DC, CPT>}
 const KEntry kTable[] = {
     TSG_K(6, 1),  TSG_K(6, 2),  TSG_K(6, 4),  TSG_K(6, 8),  TSG_K(8, 1),  TSG_K(8, 2),
     TSG_K(8, 4),  TSG_K(8, 8),  TSG_K(12, 1), TSG_K(12, 2), TSG_K(12, 4), TSG_K(16, 1),
@@ -635,21 +647,23 @@ const KEntry *find_kernel(int dc, int cpt) {
     return nullptr;
 }
 
-// Smallest instantiated padded degree and checks-per-thread for the code:
-// workgroups of at most 256 threads, as few checks per thread as fit.
-int pick_shape(const ts_code *c, int *dc_out, int *cpt_out, int *block_out) {
+int padded_degree(const ts_code *c) {
     static const int dcs[] = {6, 8, 12, 16, 24, 32};
-    int dc = 0;
     for (int d : dcs)
-        if (d >= c->dc_max) { dc = d; break; }
-    if (!dc) {
-        set_error("check degree %d above the decoder's limit 32", c->dc_max);
-        return TS_E_INVAL;
-    }
+        if (d >= c->dc_max) return d;
+    set_error("check degree %d above the decoder's limit 32", c->dc_max);
+    return 0;
+}
+
+// IS shape: the fewest checks per thread whose workgroup fits the IS kernel's bound.
+int pick_is_shape(const ts_code *c, int *dc_out, int *cpt_out, int *block_out) {
+    const int dc = padded_degree(c);
+    if (!dc) return TS_E_INVAL;
     for (int cp : {1, 2, 4, 8}) {
-        if (!find_kernel(dc, cp)) continue;
+        const KEntry *k = find_kernel(dc, cp);
+        if (!k) continue;
         const int b = ((c->m + cp - 1) / cp + 63) / 64 * 64;
-        if (b <= 256) {
+        if (b <= k->is_max_block) {
             *dc_out = dc;
             *cpt_out = cp;
             *block_out = b;
@@ -662,35 +676,50 @@ int pick_shape(const ts_code *c, int *dc_out, int *cpt_out, int *block_out) {
 
 }  // namespace
 
-int plan_search(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter, SearchPlan *plan) {
-    int dc = 0, cpt = 0, block = 0;
-    int rc = pick_shape(c, &dc, &cpt, &block);
-    if (rc) return rc;
+int plan_candidates(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter,
+                    std::vector<SearchPlan> *out) {
+    out->clear();
+    const int dc = padded_degree(c);
+    if (!dc) return TS_E_INVAL;
     const Lds L = lds_layout(c->n, max_iter, true);
     if (L.total > ctx->lds_per_block) {
         set_error("code needs %zu bytes of LDS per workgroup, the device has %zu", L.total,
                   ctx->lds_per_block);
         return TS_E_INVAL;
     }
-    const KEntry *ke = find_kernel(dc, cpt);
-    SearchKernel kern = decoder == TS_DEC_OMS_I8 ? ke->oms : ke->spa;
-    int per_cu = 0;
-    TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, block, L.total));
-    if (per_cu < 1) {
-        set_error("decoder kernel does not fit on a compute unit");
+    for (int cp : {1, 2, 4, 8}) {
+        const KEntry *ke = find_kernel(dc, cp);
+        if (!ke) continue;
+        const int block = ((c->m + cp - 1) / cp + 63) / 64 * 64;
+        if (block > ke->max_block) continue;
+        SearchKernel kern = decoder == TS_DEC_OMS_I8 ? ke->oms : ke->spa;
+        int per_cu = 0;
+        TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, block, L.total));
+        if (per_cu < 1) continue;
+        SearchPlan p;
+        p.block = block;
+        p.cpt = cp;
+        p.dc = dc;
+        p.lds = L.total;
+        p.grid = per_cu * ctx->num_cu;
+        out->push_back(p);
+    }
+    if (out->empty()) {
+        set_error("code has too many checks (%d) for one workgroup at check degree %d", c->m, c->dc_max);
         return TS_E_INVAL;
     }
-    plan->block = block;
-    plan->cpt = cpt;
-    plan->dc = dc;
-    plan->vpt = 0;
-    plan->dv = 0;
-    plan->lds = L.total;
-    plan->grid = per_cu * ctx->num_cu;
     return TS_OK;
 }
 
-int launch_search(ts_ctx *ctx, const SearchPlan &plan, const SearchLaunch &a) {
+int plan_search(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter, SearchPlan *plan) {
+    std::vector<SearchPlan> v;
+    const int rc = plan_candidates(ctx, c, decoder, max_iter, &v);
+    if (rc) return rc;
+    *plan = v.front();
+    return TS_OK;
+}
+
+int launch_search(hipStream_t stream, const SearchPlan &plan, const SearchLaunch &a) {
     const KEntry *ke = find_kernel(plan.dc, plan.cpt);
     if (!ke) {
         set_error("no kernel for dc %d cpt %d", plan.dc, plan.cpt);
@@ -699,24 +728,25 @@ int launch_search(ts_ctx *ctx, const SearchPlan &plan, const SearchLaunch &a) {
     SearchKernel kern = a.decoder == TS_DEC_OMS_I8 ? ke->oms : ke->spa;
     const int grid = a.n_patterns < plan.grid ? a.n_patterns : plan.grid;
     if (grid <= 0) return TS_OK;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(plan.block), plan.lds, ctx->stream, a, *a.code);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(plan.block), plan.lds, stream, a, *a.code);
     TSG_HIP(hipGetLastError());
     return TS_OK;
 }
 
-int launch_fill(ts_ctx *ctx, int *p, int value, int64_t count) {
+int launch_fill(hipStream_t stream, int *p, int value, int64_t count) {
     if (count <= 0) return TS_OK;
     const int blk = 256;
     const long long grid = (count + blk - 1) / blk;
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)grid), dim3(blk), 0, ctx->stream, p, value,
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)grid), dim3(blk), 0, stream, p, value,
                        (long long)count);
     TSG_HIP(hipGetLastError());
     return TS_OK;
 }
 
-int launch_is(ts_ctx *ctx, const ts_code *c, const IsLaunch &a, int *grid_out, int *block_out) {
+int launch_is(ts_exec &ex, const ts_code *c, const IsLaunch &a, int *grid_out, int *block_out) {
+    ts_ctx *ctx = ex.ctx;
     int dc = 0, cpt = 0, block = 0;
-    int rc = pick_shape(c, &dc, &cpt, &block);
+    int rc = pick_is_shape(c, &dc, &cpt, &block);
     if (rc) return rc;
     const Lds L = lds_layout(c->n, a.max_iter, false);
     if (L.total > ctx->lds_per_block) {
@@ -749,16 +779,16 @@ int launch_is(ts_ctx *ctx, const ts_code *c, const IsLaunch &a, int *grid_out, i
     d.wf = a.wf;
     d.queue = a.queue;
     d.counters = a.counters;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(block), L.total, ctx->stream, d, c->dev);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(block), L.total, ex.stream, d, c->dev);
     TSG_HIP(hipGetLastError());
     if (grid_out) *grid_out = (int)grid;
     if (block_out) *block_out = block;
     return TS_OK;
 }
 
-int launch_is_reduce(ts_ctx *ctx, const double *wf, const unsigned char *fail, int64_t n, int mode,
+int launch_is_reduce(hipStream_t stream, const double *wf, const unsigned char *fail, int64_t n, int mode,
                      double mean, double *out) {
-    hipLaunchKernelGGL(k_is_reduce, dim3(1), dim3(1024), 0, ctx->stream, wf, fail, (long long)n, mode,
+    hipLaunchKernelGGL(k_is_reduce, dim3(1), dim3(1024), 0, stream, wf, fail, (long long)n, mode,
                        mean, out);
     TSG_HIP(hipGetLastError());
     return TS_OK;

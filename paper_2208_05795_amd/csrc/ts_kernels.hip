@@ -432,11 +432,12 @@ __global__ void k_gather(DevTable t, const int *idx, int n, int *out, int stride
 
 }  // namespace
 
-int launch_sieve(ts_ctx *ctx, ts_code *c, const SearchLaunch &a, int n_records_hint) {
-    if (n_records_hint <= 0) return TS_OK;
+int launch_sieve(ts_exec &ex, const DevCode &cd, const DevTable &t, const SearchLaunch &a,
+                 int n_records) {
+    if (n_records <= 0) return TS_OK;
     SieveArgs s;
-    s.cd = c->dev;
-    s.tab = c->table;
+    s.cd = cd;
+    s.tab = t;
     s.recs = a.recs;
     s.rec_count = a.rec_count;
     s.rec_cap = a.rec_cap;
@@ -445,18 +446,19 @@ int launch_sieve(ts_ctx *ctx, ts_code *c, const SearchLaunch &a, int n_records_h
     s.a_max = a.a_max;
     s.extract_mode = a.extract_mode;
     s.err = a.err;
-    const int waves = n_records_hint;
-    int grid = (waves + kWaves - 1) / kWaves;
-    const int cap = ctx->num_cu * 8;
+    int grid = (n_records + kWaves - 1) / kWaves;
+    const int cap = ex.ctx->num_cu * 8;
     if (grid > cap) grid = cap;
-    hipLaunchKernelGGL(k_sieve, dim3(grid), dim3(kWaves * 64), 0, ctx->stream, s);
+    hipLaunchKernelGGL(k_sieve, dim3(grid), dim3(kWaves * 64), 0, ex.stream, s);
     TSG_HIP(hipGetLastError());
     return TS_OK;
 }
 
-static int alloc_table(ts_ctx *ctx, DevTable *t, int cap) {
-    size_t bytes = (size_t)cap * (8 + 4 * (5 + kMaxAmax)) + 64;
-    char *p = (char *)ctx->dalloc(bytes);
+size_t table_bytes(int cap) { return (size_t)cap * (8 + 4 * (5 + kMaxAmax)) + 64; }
+
+static int alloc_table(ts_exec &ex, DevTable *t, int cap) {
+    const size_t bytes = table_bytes(cap);
+    char *p = (char *)ex.dalloc(bytes);
     if (!p) {
         set_error("device allocation of the TS table (%zu bytes) failed", bytes);
         return TS_E_NOMEM;
@@ -470,108 +472,99 @@ static int alloc_table(ts_ctx *ctx, DevTable *t, int cap) {
     t->kcrit = t->first + cap;
     t->set = t->kcrit + cap;
     t->count = t->set + (size_t)cap * kMaxAmax;
-    // keys and ready flags start at 0 (fill kernels, not memset)
-    int rc = launch_fill(ctx, (int *)t->key, 0, (int64_t)cap * 2);
+    // keys, ready flags and the counter start at 0 (fill kernels, not memset)
+    int rc = launch_fill(ex.stream, (int *)t->key, 0, (int64_t)cap * 2);
     if (rc) return rc;
-    rc = launch_fill(ctx, t->ready, 0, cap);
+    rc = launch_fill(ex.stream, t->ready, 0, cap);
     if (rc) return rc;
-    return launch_fill(ctx, t->count, 0, 1);
+    return launch_fill(ex.stream, t->count, 0, 1);
 }
 
-int table_init(ts_ctx *ctx, ts_code *c, int cap) {
-    if (c->table_alloc) return TS_OK;
-    int rc = alloc_table(ctx, &c->table, cap);
-    if (rc) return rc;
-    c->table_alloc = true;
-    return TS_OK;
+int table_init(ts_exec &ex, DevTable &t, int cap) {
+    if (t.cap) return TS_OK;
+    return alloc_table(ex, &t, cap);
 }
 
-int table_free(ts_ctx *ctx, ts_code *c) {
-    if (c->table_alloc) ctx->dfree(c->table.key);
-    c->table_alloc = false;
-    c->table = DevTable{};
-    return TS_OK;
+void table_free(ts_exec &ex, DevTable &t) {
+    if (t.cap) ex.dfree(t.key);
+    t = DevTable{};
 }
 
 // Makes room for `incoming` more distinct sets at a load factor <= 1/2.
-int table_grow_if_needed(ts_ctx *ctx, ts_code *c, int64_t incoming) {
-    int rc = table_init(ctx, c, 1 << 16);
+int table_grow_if_needed(ts_exec &ex, DevTable &t, int64_t incoming) {
+    int rc = table_init(ex, t, 1 << 16);
     if (rc) return rc;
-    TSG_HIP(hipMemcpyAsync(ctx->pinned, c->table.count, 4, hipMemcpyDeviceToHost, ctx->stream));
-    TSG_HIP(hipStreamSynchronize(ctx->stream));
-    const int64_t need = 2 * ((int64_t)ctx->pinned[0] + incoming);
-    if (need <= c->table.cap) return TS_OK;
-    int64_t cap = c->table.cap;
+    TSG_HIP(hipMemcpyAsync(ex.pinned, t.count, 4, hipMemcpyDeviceToHost, ex.stream));
+    TSG_HIP(hipStreamSynchronize(ex.stream));
+    const int64_t need = 2 * ((int64_t)ex.pinned[0] + incoming);
+    if (need <= t.cap) return TS_OK;
+    int64_t cap = t.cap;
     while (cap < need) cap *= 2;
     if (cap > (1 << 30)) {
         set_error("TS table would exceed 2^30 slots");
         return TS_E_NOMEM;
     }
     DevTable nt{};
-    rc = alloc_table(ctx, &nt, (int)cap);
+    rc = alloc_table(ex, &nt, (int)cap);
     if (rc) return rc;
-    int *err = (int *)ctx->dalloc(16);
+    int *err = (int *)ex.dalloc(16);
     if (!err) return TS_E_NOMEM;
-    rc = launch_fill(ctx, err, 0, 1);
+    rc = launch_fill(ex.stream, err, 0, 1);
     if (rc) return rc;
     const int blk = 256;
-    hipLaunchKernelGGL(k_rehash, dim3((c->table.cap + blk - 1) / blk), dim3(blk), 0, ctx->stream,
-                       c->table, nt, err);
+    hipLaunchKernelGGL(k_rehash, dim3((t.cap + blk - 1) / blk), dim3(blk), 0, ex.stream, t, nt, err);
     TSG_HIP(hipGetLastError());
-    TSG_HIP(hipMemcpyAsync(ctx->pinned, err, 4, hipMemcpyDeviceToHost, ctx->stream));
-    TSG_HIP(hipStreamSynchronize(ctx->stream));
-    ctx->dfree(err);
-    ctx->dfree(c->table.key);
-    c->table = nt;
-    if (ctx->pinned[0]) {
+    TSG_HIP(hipMemcpyAsync(ex.pinned, err, 4, hipMemcpyDeviceToHost, ex.stream));
+    TSG_HIP(hipStreamSynchronize(ex.stream));
+    ex.dfree(err);
+    ex.dfree(t.key);
+    t = nt;
+    if (ex.pinned[0]) {
         set_error("rehash overflow");
         return TS_E_STATE;
     }
     return TS_OK;
 }
 
-int collect_table(ts_ctx *ctx, const ts_code *c, std::vector<int32_t> &rec_host,
+int collect_table(ts_exec &ex, const DevTable &t, std::vector<int32_t> &rec_host,
                   std::vector<int32_t> &bits_host) {
     rec_host.clear();
     bits_host.clear();
-    if (!c->table_alloc) return TS_OK;
-    const DevTable &t = c->table;
-    int *d_n = (int *)ctx->dalloc(16);
+    if (!t.cap) return TS_OK;
+    hipStream_t s = ex.stream;
+    int *d_n = (int *)ex.dalloc(16);
     if (!d_n) return TS_E_NOMEM;
-    int rc = launch_fill(ctx, d_n, 0, 1);
+    int *idx_all = (int *)ex.dalloc((size_t)t.cap * 4);
+    if (!idx_all) { ex.dfree(d_n); return TS_E_NOMEM; }
+    int rc = launch_fill(s, d_n, 0, 1);
     if (rc) return rc;
-    int *idx_all = (int *)ctx->dalloc((size_t)t.cap * 4);
-    if (!idx_all) { ctx->dfree(d_n); return TS_E_NOMEM; }
     const int blk = 256;
-    hipLaunchKernelGGL(k_compact, dim3((t.cap + blk - 1) / blk), dim3(blk), 0, ctx->stream, t,
-                       idx_all, d_n);
+    hipLaunchKernelGGL(k_compact, dim3((t.cap + blk - 1) / blk), dim3(blk), 0, s, t, idx_all, d_n);
     TSG_HIP(hipGetLastError());
-    TSG_HIP(hipMemcpyAsync(ctx->pinned, d_n, 4, hipMemcpyDeviceToHost, ctx->stream));
-    TSG_HIP(hipStreamSynchronize(ctx->stream));
-    const int n = ctx->pinned[0];
+    TSG_HIP(hipMemcpyAsync(ex.pinned, d_n, 4, hipMemcpyDeviceToHost, s));
+    TSG_HIP(hipStreamSynchronize(s));
+    const int n = ex.pinned[0];
     int P = 1;
     while (P < n) P <<= 1;
     if (n > 0) {
         // pad to a power of two with -1 (sorts last)
         if (P > n) {
-            rc = launch_fill(ctx, idx_all + n, -1, P - n);
+            rc = launch_fill(s, idx_all + n, -1, P - n);
             if (rc) return rc;
         }
         for (int k = 2; k <= P; k <<= 1)
             for (int j = k >> 1; j > 0; j >>= 1)
-                hipLaunchKernelGGL(k_bitonic, dim3((P + blk - 1) / blk), dim3(blk), 0, ctx->stream, t,
-                                   idx_all, P, k, j);
+                hipLaunchKernelGGL(k_bitonic, dim3((P + blk - 1) / blk), dim3(blk), 0, s, t, idx_all, P, k, j);
         TSG_HIP(hipGetLastError());
         const int stride = 5 + kMaxAmax;
-        int *out = (int *)ctx->dalloc((size_t)n * stride * 4);
+        int *out = (int *)ex.dalloc((size_t)n * stride * 4);
         if (!out) return TS_E_NOMEM;
-        hipLaunchKernelGGL(k_gather, dim3((n + blk - 1) / blk), dim3(blk), 0, ctx->stream, t,
-                           idx_all, n, out, stride);
+        hipLaunchKernelGGL(k_gather, dim3((n + blk - 1) / blk), dim3(blk), 0, s, t, idx_all, n, out, stride);
         TSG_HIP(hipGetLastError());
         std::vector<int32_t> raw((size_t)n * stride);
-        TSG_HIP(hipMemcpyAsync(raw.data(), out, raw.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
-        TSG_HIP(hipStreamSynchronize(ctx->stream));
-        ctx->dfree(out);
+        TSG_HIP(hipMemcpyAsync(raw.data(), out, raw.size() * 4, hipMemcpyDeviceToHost, s));
+        TSG_HIP(hipStreamSynchronize(s));
+        ex.dfree(out);
         rec_host.resize((size_t)n * 5);
         for (int i = 0; i < n; ++i) {
             const int32_t *r = raw.data() + (size_t)i * stride;
@@ -579,8 +572,9 @@ int collect_table(ts_ctx *ctx, const ts_code *c, std::vector<int32_t> &rec_host,
             for (int q = 0; q < r[0]; ++q) bits_host.push_back(r[5 + q]);
         }
     }
-    ctx->dfree(idx_all);
-    ctx->dfree(d_n);
+    ex.dfree(idx_all);
+    ex.dfree(d_n);
+    TSG_HIP(hipStreamSynchronize(s));
     return TS_OK;
 }
 

@@ -1,0 +1,160 @@
+"""Serving (ts_submit / ts_poll / ts_cancel): continuous batching of search and
+IS jobs on several streams.  Each job's result must equal the same call run
+alone (bit-exact: the decoders are deterministic and every search job has its
+own TS table); admission respects the memory budget; cancelled jobs report so.
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("k_crit", "iters_crit", "iters_lo", "tmin_crit", "n_cand")
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def _ts(recs):
+    return [(r.a, r.b, r.orbit, r.first_pattern, r.k_crit, tuple(r.bits)) for r in recs]
+
+
+@pytest.fixture(scope="module")
+def jobs(oracle_mod):
+    """A mixed job list: (kind, code name, arguments)."""
+    tiny = workloads.tiny_code()
+    peg = workloads.peg1008_code()
+    ot, op = oracle_mod.OCode(tiny), oracle_mod.OCode(peg)
+    tp = oracle_mod.pattern_list(ot, [1, 2])
+    pp = oracle_mod.pattern_list(op, [1, 2, 3])
+    rng = np.random.default_rng(41)
+    out = []
+    for i in range(4):
+        sel = np.sort(rng.choice(len(pp), 3000, replace=False))
+        out.append(("search", "peg", dict(patterns=pp[sel], a_max=12)))
+    out.append(("search", "tiny", dict(patterns=tp, a_max=6)))
+    for i in range(3):
+        sel = np.sort(rng.choice(len(pp), 40, replace=False))
+        out.append(("search", "peg", dict(patterns=pp[sel], decoder=1, max_iter=50,
+                                          k_max=32 * 1024, k_den=1024, a_max=12)))
+    ts = [(16, 42, 63, 68), (0, 1, 51, 74, 94, 95), (0, 6, 49, 58, 73, 92)]
+    for i, t in enumerate(ts):
+        out.append(("is", "tiny", dict(ts_bits=list(t), ebn0_db=2.0 + i, shift=1.0,
+                                        n_frames=20000, seed=9, stream=i)))
+    return {"tiny": tiny, "peg": peg}, out
+
+
+def _run_alone(codes, jobs):
+    import paper_2208_05795_amd as tsg
+    res = []
+    with tsg.Context(0) as ctx:
+        loaded = {k: ctx.load_code(v) for k, v in codes.items()}
+        for kind, name, kw in jobs:
+            c = loaded[name]
+            if kind == "search":
+                c.reset_ts()
+                kw2 = dict(kw)
+                pats = kw2.pop("patterns")
+                r = c.impulse_search(pats, **kw2)
+                res.append(({k: np.asarray(r[k]) for k in KEYS}, _ts(c.collect())))
+            else:
+                res.append(c.is_estimate(**kw))
+    return res
+
+
+def test_mix_equals_alone(jobs):
+    import paper_2208_05795_amd as tsg
+    codes, job_list = jobs
+    _say(f"{len(job_list)} jobs alone")
+    alone = _run_alone(codes, job_list)
+    _say("same jobs submitted together, 4 slots")
+    with tsg.Context(0, torch_stream=False, torch_alloc=False) as ctx:
+        loaded = {k: ctx.load_code(v) for k, v in codes.items()}
+        ctx.serve_start(4)
+        ids = []
+        for kind, name, kw in job_list:
+            if kind == "search":
+                kw2 = dict(kw)
+                ids.append(ctx.submit_search(loaded[name], kw2.pop("patterns"), **kw2))
+            else:
+                ids.append(ctx.submit_is(loaded[name], **kw))
+        infos = [ctx.poll(i, wait=True) for i in ids]
+        for (kind, name, kw), jid, info, ref in zip(job_list, ids, infos, alone):
+            assert info["state"] == 2 and info["status"] == 0, info
+            if kind == "search":
+                out = ctx.job_outputs(jid)
+                for k in KEYS:
+                    assert np.array_equal(out[k], ref[0][k]), (kind, name, k)
+                assert _ts(out["ts"]) == ref[1]
+            else:
+                for f in ("p_hat", "var", "sum_w", "sum_w2", "n_fail", "shift_used"):
+                    assert info["is"][f] == ref[f], f
+            ctx.release(jid)
+        # jobs overlapped on the device
+        spans = sorted((i["start_ms"], i["end_ms"]) for i in infos)
+        overlap = any(spans[k + 1][0] < spans[k][1] for k in range(len(spans) - 1))
+        lat = sorted(i["end_ms"] - i["submit_ms"] for i in infos)
+        _say(f"latency p50 {lat[len(lat) // 2]:.1f} ms max {lat[-1]:.1f} ms, overlap {overlap}")
+        assert overlap
+
+
+def test_budget_admission_and_cancel(jobs):
+    import paper_2208_05795_amd as tsg
+    codes, job_list = jobs
+    small = [(k, n, dict(kw, patterns=kw["patterns"][:800]))
+             for k, n, kw in job_list if k == "search" and n == "peg"][:4]
+    budget = 120 << 20
+    with tsg.Context(0, torch_stream=False, torch_alloc=False,
+                     hbm_budget_bytes=budget) as ctx:
+        c = ctx.load_code(codes["peg"])
+        ctx.serve_start(4)
+        # a job whose estimate exceeds the whole budget is refused at once
+        allp = np.concatenate([j[2]["patterns"] for j in small] * 60)
+        with pytest.raises(tsg.TsgError) as e:
+            ctx.submit_search(c, allp, a_max=12)
+        assert e.value.status == -5
+        ids = [ctx.submit_search(c, j[2]["patterns"], a_max=12) for j in small]
+        infos = [ctx.poll(i, wait=True) for i in ids]
+        est = infos[0]["device_bytes"]
+        _say(f"job estimate {est / 2**20:.1f} MiB, budget {budget >> 20} MiB")
+        spans = sorted((i["start_ms"], i["end_ms"]) for i in infos)
+        # never more jobs in flight than the budget admits
+        cap = budget // est
+        for t in [s for s, _ in spans]:
+            assert sum(1 for s, e in spans if s <= t < e) <= max(cap, 1)
+        # cancellation of a queued job
+        long_ids = [ctx.submit_search(c, small[0][2]["patterns"], a_max=12) for _ in range(6)]
+        ctx.cancel(long_ids[-1])
+        info = ctx.poll(long_ids[-1], wait=True)
+        assert info["state"] in (2, 3)
+        if info["state"] == 3:
+            assert info["status"] == -7
+            with pytest.raises(tsg.TsgError):
+                ctx.job_outputs(long_ids[-1])
+        for i in long_ids[:-1]:
+            assert ctx.poll(i, wait=True)["status"] == 0
+        for i in ids + long_ids:
+            ctx.release(i)
+        with pytest.raises(tsg.TsgError):
+            ctx.poll(ids[0])
+
+
+def test_submit_validation(jobs):
+    import paper_2208_05795_amd as tsg
+    codes, _ = jobs
+    with tsg.Context(0, torch_stream=False, torch_alloc=False) as ctx:
+        c = ctx.load_code(codes["tiny"])
+        with pytest.raises(tsg.TsgError):
+            ctx.submit_search(c, np.array([[96]]))
+        with pytest.raises(tsg.TsgError):
+            ctx.submit_is(c, [1, 1], 3.0, 1.0, 100, seed=1)
+        jid = ctx.submit_search(c, np.arange(96).reshape(-1, 1))
+        with pytest.raises(tsg.TsgError):   # code busy while a job is in flight
+            if ctx.poll(jid)["state"] in (0, 1):
+                c.free()
+            else:
+                raise tsg.TsgError(-5, "finished already")
+        assert ctx.poll(jid, wait=True)["status"] == 0
+        ctx.release(jid)
