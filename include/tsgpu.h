@@ -125,6 +125,14 @@ int ts_make_patterns(ts_ctx *ctx, const ts_code *code, int32_t kind, int32_t *ou
 #define TS_EXTRACT_CRITICAL 1  /* candidates from the decode at k* only */
 #define TS_MEM_HOST 0
 #define TS_MEM_DEVICE 1
+/* Decoder layouts.  Register: one workgroup per frame with the messages in
+ * registers and the APP values in LDS (codes whose checks fit one workgroup).
+ * Streamed: one workgroup per frame with the messages in global memory (any
+ * code whose APP values fit in LDS, n up to about 39k).  Both compute the same
+ * integers, so results do not depend on the layout. */
+#define TS_LAYOUT_AUTO 0       /* autotuned among the layouts and shapes that fit */
+#define TS_LAYOUT_REGISTER 1
+#define TS_LAYOUT_STREAMED 2
 
 typedef struct {
     int32_t decoder;           /* TS_DEC_* */
@@ -138,6 +146,7 @@ typedef struct {
     int32_t extract_mode;      /* TS_EXTRACT_* */
     int32_t collect_from_iter; /* first iteration whose error set is sieved; -1 = girth/2 */
     int32_t mem;               /* TS_MEM_HOST / TS_MEM_DEVICE for patterns and outputs */
+    int32_t layout;            /* TS_LAYOUT_*; TS_E_INVAL if the forced layout does not fit */
 } ts_search_opts;
 
 typedef struct {            /* caller-owned arrays of n_patterns entries */
@@ -193,6 +202,7 @@ typedef struct {
     uint64_t seed;           /* Philox key */
     uint64_t frame_base;     /* first frame counter (resumable streams) */
     uint32_t stream;         /* Philox stream tag */
+    int32_t layout;          /* TS_LAYOUT_* (AUTO: register layout when it fits) */
 } ts_is_opts;
 
 typedef struct {
@@ -284,6 +294,8 @@ typedef struct {
     int32_t extract_launches;
     int32_t block_threads;   /* workgroup size of the decode kernel */
     int32_t grid_blocks;     /* workgroups of the decode kernel */
+    int32_t layout;          /* TS_LAYOUT_REGISTER / TS_LAYOUT_STREAMED of the last decode */
+    int32_t checks_per_thread;   /* register layout: checks per thread */
 } ts_stats;
 int ts_get_stats(ts_ctx *ctx, ts_stats *out);
 

@@ -17,11 +17,13 @@ import numpy as np
 from . import _capi as A
 
 __all__ = ["Context", "Code", "TsRecord", "TsgError", "DEC_OMS", "DEC_SPA",
-           "PAT_SINGLES", "PAT_PAIRS", "PAT_TRIPLES", "EXTRACT_PATH", "EXTRACT_CRITICAL"]
+           "PAT_SINGLES", "PAT_PAIRS", "PAT_TRIPLES", "EXTRACT_PATH", "EXTRACT_CRITICAL",
+           "LAYOUT_AUTO", "LAYOUT_REGISTER", "LAYOUT_STREAMED"]
 
 DEC_OMS, DEC_SPA = A.TS_DEC_OMS_I8, A.TS_DEC_SPA_F32
 PAT_SINGLES, PAT_PAIRS, PAT_TRIPLES = A.TS_PAT_SINGLES, A.TS_PAT_PAIRS, A.TS_PAT_TRIPLES
 EXTRACT_PATH, EXTRACT_CRITICAL = A.TS_EXTRACT_PATH, A.TS_EXTRACT_CRITICAL
+LAYOUT_AUTO, LAYOUT_REGISTER, LAYOUT_STREAMED = A.TS_LAYOUT_AUTO, A.TS_LAYOUT_REGISTER, A.TS_LAYOUT_STREAMED
 
 _lib = None
 
@@ -117,7 +119,8 @@ class Context:
     def submit_search(self, code: "Code", patterns, decoder: int = DEC_OMS, max_iter: int = 20,
                       oms_offset: int = 1, ebn0_db: float = 3.0, rate: Optional[float] = None,
                       llr_scale: float = 4.0, k_max: int = 512, k_den: int = 16, a_max: int = 6,
-                      extract_mode: int = EXTRACT_PATH, collect_from_iter: int = -1) -> int:
+                      extract_mode: int = EXTRACT_PATH, collect_from_iter: int = -1,
+                      layout: int = 0) -> int:
         pats = _i32(patterns)
         if pats.ndim == 1:
             pats = pats.reshape(-1, 1)
@@ -125,7 +128,8 @@ class Context:
         d = A.JobDesc()
         d.kind, d.code = A.TS_JOB_SEARCH, code._h
         d.search = A.SearchOpts(decoder, max_iter, oms_offset, ebn0_db, rate, llr_scale, k_max,
-                                k_den, a_max, extract_mode, collect_from_iter, A.TS_MEM_HOST)
+                                k_den, a_max, extract_mode, collect_from_iter, A.TS_MEM_HOST,
+                                layout)
         d.patterns, d.n_patterns, d.width = pats.ctypes.data, pats.shape[0], pats.shape[1]
         jid = C.c_uint64()
         _check(lib().ts_submit(self._h, C.byref(d), C.byref(jid)))
@@ -133,12 +137,13 @@ class Context:
 
     def submit_is(self, code: "Code", ts_bits, ebn0_db: float, shift: float, n_frames: int,
                   seed: int, frame_base: int = 0, stream: int = 0, max_iter: int = 50,
-                  rate: Optional[float] = None) -> int:
+                  rate: Optional[float] = None, layout: int = 0) -> int:
         t = _i32(ts_bits)
         rate = (1.0 - code.m / code.n) if rate is None else rate
         d = A.JobDesc()
         d.kind, d.code = A.TS_JOB_IS, code._h
-        d.is_ = A.IsOpts(max_iter, ebn0_db, rate, shift, n_frames, seed, frame_base, stream)
+        d.is_ = A.IsOpts(max_iter, ebn0_db, rate, shift, n_frames, seed, frame_base, stream,
+                         layout)
         d.ts_bits, d.a = t.ctypes.data, t.size
         jid = C.c_uint64()
         _check(lib().ts_submit(self._h, C.byref(d), C.byref(jid)))
@@ -253,12 +258,14 @@ class Code:
     def impulse_search(self, patterns, decoder: int = DEC_OMS, max_iter: int = 20,
                        oms_offset: int = 1, ebn0_db: float = 3.0, rate: Optional[float] = None,
                        llr_scale: float = 4.0, k_max: int = 512, k_den: int = 16, a_max: int = 6,
-                       extract_mode: int = EXTRACT_PATH, collect_from_iter: int = -1) -> dict:
+                       extract_mode: int = EXTRACT_PATH, collect_from_iter: int = -1,
+                       layout: int = 0) -> dict:
         """Patterns: numpy (host) or a torch int32 CUDA tensor [P, width] (device);
-        outputs come back in the same kind of memory."""
+        outputs come back in the same kind of memory.  layout: LAYOUT_AUTO,
+        LAYOUT_REGISTER or LAYOUT_STREAMED."""
         rate = (1.0 - self.m / self.n) if rate is None else rate
         o = A.SearchOpts(decoder, max_iter, oms_offset, ebn0_db, rate, llr_scale, k_max, k_den,
-                         a_max, extract_mode, collect_from_iter, A.TS_MEM_HOST)
+                         a_max, extract_mode, collect_from_iter, A.TS_MEM_HOST, layout)
         out = A.SearchOut()
         if _is_torch_cuda(patterns):
             import torch
@@ -310,10 +317,11 @@ class Code:
 
     def is_estimate(self, ts_bits, ebn0_db: float, shift: float, n_frames: int, seed: int,
                     frame_base: int = 0, stream: int = 0, max_iter: int = 50,
-                    rate: Optional[float] = None, want_fail: bool = False) -> dict:
+                    rate: Optional[float] = None, want_fail: bool = False,
+                    layout: int = 0) -> dict:
         rate = (1.0 - self.m / self.n) if rate is None else rate
         t = _i32(ts_bits)
-        o = A.IsOpts(max_iter, ebn0_db, rate, shift, n_frames, seed, frame_base, stream)
+        o = A.IsOpts(max_iter, ebn0_db, rate, shift, n_frames, seed, frame_base, stream, layout)
         r = A.IsResult()
         fo = np.zeros(n_frames, dtype=np.uint8) if want_fail else None
         _check(lib().ts_is_estimate(self.ctx.handle, self._h, t.ctypes.data, t.size, C.byref(o),

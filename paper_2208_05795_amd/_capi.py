@@ -12,6 +12,7 @@ TS_PAT_SINGLES, TS_PAT_PAIRS, TS_PAT_TRIPLES = 1, 2, 3
 TS_DEC_OMS_I8, TS_DEC_SPA_F32 = 0, 1
 TS_EXTRACT_PATH, TS_EXTRACT_CRITICAL = 0, 1
 TS_MEM_HOST, TS_MEM_DEVICE = 0, 1
+TS_LAYOUT_AUTO, TS_LAYOUT_REGISTER, TS_LAYOUT_STREAMED = 0, 1, 2
 TS_JOB_SEARCH, TS_JOB_IS = 1, 2
 TS_JOB_QUEUED, TS_JOB_RUNNING, TS_JOB_DONE, TS_JOB_CANCELLED = 0, 1, 2, 3
 
@@ -39,7 +40,8 @@ class SearchOpts(C.Structure):
     _fields_ = [("decoder", C.c_int32), ("max_iter", C.c_int32), ("oms_offset", C.c_int32),
                 ("ebn0_db", C.c_double), ("rate", C.c_double), ("llr_scale", C.c_double),
                 ("k_max", C.c_int32), ("k_den", C.c_int32), ("a_max", C.c_int32),
-                ("extract_mode", C.c_int32), ("collect_from_iter", C.c_int32), ("mem", C.c_int32)]
+                ("extract_mode", C.c_int32), ("collect_from_iter", C.c_int32), ("mem", C.c_int32),
+                ("layout", C.c_int32)]
 
 
 class SearchOut(C.Structure):
@@ -56,7 +58,7 @@ class Record(C.Structure):
 class IsOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("ebn0_db", C.c_double), ("rate", C.c_double),
                 ("shift", C.c_double), ("n_frames", C.c_int64), ("seed", C.c_uint64),
-                ("frame_base", C.c_uint64), ("stream", C.c_uint32)]
+                ("frame_base", C.c_uint64), ("stream", C.c_uint32), ("layout", C.c_int32)]
 
 
 class IsResult(C.Structure):
@@ -82,7 +84,8 @@ class Stats(C.Structure):
     _fields_ = [("decode_ms", C.c_double), ("extract_ms", C.c_double), ("total_ms", C.c_double),
                 ("decodes", C.c_int64), ("edge_updates", C.c_int64), ("candidates", C.c_int64),
                 ("decode_launches", C.c_int32), ("extract_launches", C.c_int32),
-                ("block_threads", C.c_int32), ("grid_blocks", C.c_int32)]
+                ("block_threads", C.c_int32), ("grid_blocks", C.c_int32), ("layout", C.c_int32),
+                ("checks_per_thread", C.c_int32)]
 
 
 # name -> (restype, argtypes); every function of the header appears here

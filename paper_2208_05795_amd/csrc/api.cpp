@@ -95,7 +95,13 @@ namespace tsg {
 
 size_t search_bytes_estimate(const ts_code *code, const ts_search_opts *o, int64_t P, int32_t width) {
     const int64_t cap = rec_capacity(o, first_iter(code, o), P, true, nullptr);
-    return (size_t)P * (width + 5) * 4 + (size_t)cap * kRecStride * 4 + table_bytes(1 << 16) + 4096;
+    size_t scr = 0;   // decoder scratch of the largest streamed shape the autotuner may try
+    std::vector<SearchPlan> shapes;
+    if (plan_candidates(code->ctx, code, o->decoder, o->max_iter, &shapes) == TS_OK)
+        for (const SearchPlan &p : shapes)
+            if (p.kind == kPlanStreamed)
+                scr = std::max(scr, (size_t)std::min<int64_t>(p.grid, std::max<int64_t>(P, 1)) * p.slot_bytes);
+    return (size_t)P * (width + 5) * 4 + (size_t)cap * kRecStride * 4 + table_bytes(1 << 16) + scr + 4096;
 }
 
 int check_search_opts(const ts_code *code, const ts_search_opts *o, int32_t width) {
@@ -112,6 +118,7 @@ int check_search_opts(const ts_code *code, const ts_search_opts *o, int32_t widt
     if (!(o->rate > 0.0 && o->rate <= 1.0) || !(o->llr_scale > 0.0)) { set_error("rate / llr_scale out of range"); return TS_E_INVAL; }
     if (o->extract_mode != TS_EXTRACT_PATH && o->extract_mode != TS_EXTRACT_CRITICAL) { set_error("bad extract_mode"); return TS_E_INVAL; }
     if (o->mem != TS_MEM_HOST && o->mem != TS_MEM_DEVICE) { set_error("bad mem kind"); return TS_E_INVAL; }
+    if (o->layout < TS_LAYOUT_AUTO || o->layout > TS_LAYOUT_STREAMED) { set_error("bad layout"); return TS_E_INVAL; }
     if (width < 1 || width > kMaxWidth) { set_error("width must be 1..%d", kMaxWidth); return TS_E_INVAL; }
     if (code->dv_max > kDvMax) { set_error("variable degree %d above the sieve's limit %d", code->dv_max, kDvMax); return TS_E_INVAL; }
     return TS_OK;
@@ -119,7 +126,8 @@ int check_search_opts(const ts_code *code, const ts_search_opts *o, int32_t widt
 
 // Autotuner: times every candidate launch shape once on a probe of the job's own
 // patterns (candidate writing off) and keeps the fastest per (code, decoder,
-// iteration count).  Shapes only change the schedule, never the results.
+// iteration count, layout request).  Shapes only change the schedule, never the
+// results.
 static int tune_shape(ts_exec &ex, const std::vector<SearchPlan> &cands,
                       const SearchLaunch &base, int64_t P, SearchPlan *best) {
     int64_t probe = 0;
@@ -148,6 +156,15 @@ static int tune_shape(ts_exec &ex, const std::vector<SearchPlan> &cands,
     return TS_OK;
 }
 
+static bool same_shape(const SearchPlan &p, const SearchShape &s) {
+    return p.kind == s.kind && p.cpt == s.cpt && p.block == s.block;
+}
+
+static size_t scratch_bytes(const SearchPlan &p, int64_t P) {
+    if (p.kind != kPlanStreamed) return 0;
+    return (size_t)std::min<int64_t>(p.grid, std::max<int64_t>(P, 1)) * p.slot_bytes;
+}
+
 // Runs the search on device-resident patterns / outputs into `table`.  With
 // sieve = false no candidate is written (only k* and the iteration counts).
 int run_search(ts_exec &ex, ts_code *code, DevTable &table, const ts_search_opts *o,
@@ -157,19 +174,34 @@ int run_search(ts_exec &ex, ts_code *code, DevTable &table, const ts_search_opts
     std::vector<SearchPlan> shapes;
     int rc = plan_candidates(ctx, code, o->decoder, o->max_iter, &shapes);
     if (rc) return rc;
+    if (o->layout != TS_LAYOUT_AUTO) {
+        const int want = o->layout == TS_LAYOUT_REGISTER ? kPlanRegister : kPlanStreamed;
+        shapes.erase(std::remove_if(shapes.begin(), shapes.end(),
+                                    [&](const SearchPlan &p) { return p.kind != want; }),
+                     shapes.end());
+        if (shapes.empty()) {
+            set_error("the requested decoder layout does not fit this code");
+            return TS_E_INVAL;
+        }
+    }
     SearchPlan plan = shapes.front();
-    const int tune_key = o->decoder * 1000 + o->max_iter;
+    const int tune_key = (o->layout * 2 + o->decoder) * 1000 + o->max_iter;
     bool need_tune = false;
     {
         std::lock_guard<std::mutex> g(code->tune_mu);
         auto it = code->tuned.find(tune_key);
         if (it != code->tuned.end()) {
             for (const SearchPlan &p : shapes)
-                if (p.cpt == it->second.cpt) plan = p;
+                if (same_shape(p, it->second)) plan = p;
         } else {
             need_tune = shapes.size() > 1 && P >= 256;
         }
     }
+    size_t scr_bytes = scratch_bytes(plan, P);
+    if (need_tune)
+        for (const SearchPlan &p : shapes) scr_bytes = std::max(scr_bytes, scratch_bytes(p, P));
+    DBuf scratch(ex, scr_bytes);
+    if (scr_bytes && !scratch.p) { set_error("device allocation of the decoder scratch failed"); return TS_E_NOMEM; }
     const double s2 = sigma2_of(o->ebn0_db, o->rate);
     const double h = 2.0 / s2;
     const int q_base = sat127(std::lround(o->llr_scale * h));
@@ -211,6 +243,7 @@ int run_search(ts_exec &ex, ts_code *code, DevTable &table, const ts_search_opts
     a.counters = (unsigned long long *)(d_misc + 4);
     a.recs = recs.as<int>();
     a.rec_cap = (int)rec_cap;
+    a.gscr = scr_bytes ? scratch.as<unsigned char>() : nullptr;
 
     if (need_tune) {
         a.patterns = d_pat;
@@ -218,7 +251,9 @@ int run_search(ts_exec &ex, ts_code *code, DevTable &table, const ts_search_opts
         if (rc) return rc;
         std::lock_guard<std::mutex> g(code->tune_mu);
         SearchShape sh;
+        sh.kind = plan.kind;
         sh.cpt = plan.cpt;
+        sh.block = plan.block;
         code->tuned[tune_key] = sh;
         rc = launch_fill(s, d_misc, 0, 64);   // the probe's counters are not the job's
         if (rc) return rc;
@@ -285,6 +320,8 @@ int run_search(ts_exec &ex, ts_code *code, DevTable &table, const ts_search_opts
     ex.stats.candidates += cands;
     ex.stats.block_threads = plan.block;
     ex.stats.grid_blocks = (int)std::min<int64_t>(plan.grid, P);
+    ex.stats.layout = plan.kind == kPlanRegister ? TS_LAYOUT_REGISTER : TS_LAYOUT_STREAMED;
+    ex.stats.checks_per_thread = plan.cpt;
     if (err & 1) { set_error("pattern entry out of range"); return TS_E_INVAL; }
     if (err & 4) { set_error("TS table insert timed out"); return TS_E_DEVICE; }
     if (err & 8) { set_error("TS table full"); return TS_E_NOMEM; }
@@ -298,6 +335,7 @@ int check_is_opts(const ts_code *code, const int32_t *ts_bits, int32_t a, const 
     if (o->max_iter < 1 || o->max_iter > kMaxIter) { set_error("max_iter must be 1..%d", kMaxIter); return TS_E_INVAL; }
     if (!(o->rate > 0.0 && o->rate <= 1.0)) { set_error("rate out of range"); return TS_E_INVAL; }
     if (!std::isfinite(o->ebn0_db) || !std::isfinite(o->shift)) { set_error("Eb/N0 and shift must be finite"); return TS_E_INVAL; }
+    if (o->layout < TS_LAYOUT_AUTO || o->layout > TS_LAYOUT_STREAMED) { set_error("bad layout"); return TS_E_INVAL; }
     std::vector<int32_t> t(ts_bits, ts_bits + a);
     std::sort(t.begin(), t.end());
     for (int i = 0; i < a; ++i)
@@ -333,6 +371,7 @@ int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const 
         so.extract_mode = TS_EXTRACT_CRITICAL;
         so.collect_from_iter = -1;
         so.mem = TS_MEM_DEVICE;
+        so.layout = o->layout;
         DBuf outs(ex, 5 * 4);
         if (!outs.p) return TS_E_NOMEM;
         int32_t *d_out[5];
@@ -369,9 +408,15 @@ int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const 
     L.wf = d_wf.as<double>();
     L.queue = d_misc.as<int>();
     L.counters = (unsigned long long *)(d_misc.as<int>() + 4);
-    int grid = 0, block = 0;
+    SearchPlan plan;
+    rc = plan_is(ex.ctx, code, o->max_iter, o->layout, &plan);
+    if (rc) return rc;
+    const int grid = (int)std::min<int64_t>(plan.grid, K), block = plan.block;
+    DBuf scratch(ex, plan.kind == kPlanStreamed ? (size_t)grid * plan.slot_bytes : 0);
+    if (plan.kind == kPlanStreamed && !scratch.p) { set_error("device allocation of the decoder scratch failed"); return TS_E_NOMEM; }
+    L.gscr = plan.kind == kPlanStreamed ? scratch.as<unsigned char>() : nullptr;
     TSG_HIP(hipEventRecord(ex.ev[0], s));
-    rc = launch_is(ex, code, L, &grid, &block);
+    rc = launch_is(s, code, plan, L);
     if (rc) return rc;
     TSG_HIP(hipEventRecord(ex.ev[1], s));
     rc = launch_is_reduce(s, L.wf, L.fail, K, 0, 0.0, d_red.as<double>());
@@ -411,6 +456,8 @@ int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const 
     ex.stats.decode_launches += 1;
     ex.stats.block_threads = block;
     ex.stats.grid_blocks = grid;
+    ex.stats.layout = plan.kind == kPlanRegister ? TS_LAYOUT_REGISTER : TS_LAYOUT_STREAMED;
+    ex.stats.checks_per_thread = plan.cpt;
     return TS_OK;
 }
 

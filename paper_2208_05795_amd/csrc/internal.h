@@ -38,6 +38,12 @@ constexpr int kCapMax = 2 * kMaxAmax;  // |S u I| bound for sieving
 constexpr int kDvMax = 8;         // variable degree bound of the sieve kernel
 constexpr int kRecHdr = 8;        // candidate record header (ints)
 constexpr int kRecStride = kRecHdr + kCapMax;
+// Check-degree classes of the streamed-frame decoder: a check of degree d is
+// padded to the smallest class >= d; checks are sorted by degree so each class
+// is a contiguous range.  Codes of check degree above 24 use the classes
+// without 24 (degrees 17..32 pad to 32).
+constexpr int kGClasses[] = {3, 4, 6, 8, 12, 16, 24, 32};
+constexpr int kGMaxCls = 8;
 
 // Device-side description of a code, shared by all kernels.
 struct DevCode {
@@ -52,6 +58,15 @@ struct DevCode {
     const int *cn_tab;     // [dc_pad][m_tab] padded check neighbour table (-1 = pad)
     const int *vn_tab;     // [dv_pad][n_tab] padded variable -> edge table (-1 = pad)
     int dc_pad, m_tab, dv_pad, n_tab;
+    // streamed-frame layout: checks sorted by degree into classes; class q holds
+    // positions [g_c0[q], g_c0[q+1]) with message slot g_off[q] + j*g_stride[q] + (p - g_c0[q])
+    int g_ncls;
+    int g_dc[kGMaxCls];
+    int g_c0[kGMaxCls + 1];
+    int g_stride[kGMaxCls];
+    int g_off[kGMaxCls + 1];   // g_off[g_ncls] = total message slots
+    const int *g_cn;       // [slots] variable of each message slot (n = padding)
+    const int *g_vslot;    // [dv_pad][n_tab] message slot of each (variable, k) edge, -1 = pad
 };
 
 // Open-addressing TS table on the device, keyed by the canonical QC-orbit
@@ -70,7 +85,7 @@ struct DevTable {
 
 // A decoder launch shape picked by the autotuner.
 struct SearchShape {
-    int cpt = 0;
+    int kind = 0, cpt = 0, block = 0;
 };
 
 }  // namespace tsg
@@ -149,12 +164,16 @@ int collect_table(ts_exec &ex, const DevTable &t, std::vector<int32_t> &rec_host
 size_t table_bytes(int cap);
 
 // search (search_kernels.hip)
+enum PlanKind { kPlanRegister = 0, kPlanStreamed = 1 };
 struct SearchPlan {
+    int kind;       // kPlanRegister: messages in registers; kPlanStreamed: in global memory
     int block;      // threads per workgroup
-    int cpt;        // checks per thread
-    int dc;         // padded check degree of the kernel
+    int cpt;        // checks per thread (register kind)
+    int dc;         // padded check degree of the kernel (streamed: largest class)
     size_t lds;     // dynamic LDS bytes
     int grid;       // persistent workgroups
+    size_t slot_bytes;   // streamed: global scratch per workgroup
+    size_t hist_off;     // streamed: offset of the iteration history in a slot
 };
 
 struct SearchLaunch {
@@ -172,12 +191,15 @@ struct SearchLaunch {
     int *rec_count;
     unsigned long long *counters;   // [0] decodes, [1] iterations
     int *err;
+    unsigned char *gscr;            // streamed kind: grid x slot_bytes scratch
+    long long slot_bytes, hist_off;
 };
 
 int plan_search(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter, SearchPlan *plan);
 int plan_candidates(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter,
                     std::vector<SearchPlan> *out);
 int launch_search(hipStream_t s, const SearchPlan &plan, const SearchLaunch &a);
+size_t streamed_slot_bytes(const ts_code *c, int decoder, int max_iter, bool search, size_t *hist_off);
 int launch_sieve(ts_exec &ex, const DevCode &cd, const DevTable &t, const SearchLaunch &a,
                  int n_records);
 int launch_fill(hipStream_t s, int *p, int value, int64_t count);
@@ -195,8 +217,11 @@ struct IsLaunch {
     double *wf;             // [n_frames]
     int *queue;
     unsigned long long *counters;
+    unsigned char *gscr;    // streamed kind: grid x slot_bytes scratch
 };
-int launch_is(ts_exec &ex, const ts_code *c, const IsLaunch &a, int *grid_out, int *block_out);
+// IS launch shape (streamed kind: plan.slot_bytes of scratch per workgroup)
+int plan_is(ts_ctx *ctx, const ts_code *c, int max_iter, int layout, SearchPlan *plan);
+int launch_is(hipStream_t s, const ts_code *c, const SearchPlan &plan, const IsLaunch &a);
 // mode 0: out[0..2] = sum w, sum w^2, failures; mode 1: out[3] = sum (w - mean)^2
 int launch_is_reduce(hipStream_t s, const double *wf, const unsigned char *fail, int64_t n, int mode,
                      double mean, double *out);

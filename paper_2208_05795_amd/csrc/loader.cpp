@@ -176,11 +176,59 @@ int upload_code(ts_exec &ex, ts_code *c) {
     for (int v = 0; v < c->n; ++v)
         for (int64_t k = c->vptr[v]; k < c->vptr[v + 1]; ++k)
             vn[(size_t)(k - c->vptr[v]) * d.n_tab + v] = c->vedge[k];
+    // streamed layout: checks sorted (stably) by degree, each degree padded to
+    // its class; class q stores slot j of its checks contiguously
+    std::vector<int32_t> order(c->m);
+    for (int r = 0; r < c->m; ++r) order[r] = r;
+    auto deg = [&](int r) { return (int)(c->row_ptr[r + 1] - c->row_ptr[r]); };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return deg(x) < deg(y); });
+    const bool skip24 = c->dc_max > 24;
+    auto class_of = [skip24](int dg) {
+        for (int q = 0; q < kGMaxCls; ++q)
+            if (kGClasses[q] >= dg && !(skip24 && kGClasses[q] == 24)) return q;
+        return -1;
+    };
+    d.g_ncls = 0;
+    std::vector<int32_t> gcn, gvs((size_t)d.dv_pad * d.n_tab, -1);
+    if (c->dc_max <= kGClasses[kGMaxCls - 1]) {
+        std::vector<int32_t> edge_slot(c->e, -1);
+        int p = 0, off = 0;
+        while (p < c->m) {
+            const int q = class_of(deg(order[p]));
+            int p1 = p;
+            while (p1 < c->m && class_of(deg(order[p1])) == q) ++p1;
+            const int cnt = p1 - p, stride = (cnt + 63) / 64 * 64, dcq = kGClasses[q];
+            const int k = d.g_ncls++;
+            d.g_dc[k] = dcq;
+            d.g_c0[k] = p;
+            d.g_stride[k] = stride;
+            d.g_off[k] = off;
+            gcn.resize((size_t)off + (size_t)dcq * stride, c->n);
+            for (int i = p; i < p1; ++i) {
+                const int r = order[i];
+                for (int64_t e = c->row_ptr[r]; e < c->row_ptr[r + 1]; ++e) {
+                    const int j = (int)(e - c->row_ptr[r]);
+                    const int slot = off + j * stride + (i - p);
+                    gcn[slot] = c->col[e];
+                    edge_slot[e] = slot;
+                }
+            }
+            off += dcq * stride;
+            p = p1;
+        }
+        d.g_c0[d.g_ncls] = c->m;
+        d.g_off[d.g_ncls] = off;
+        for (int v = 0; v < c->n; ++v)
+            for (int64_t k = c->vptr[v]; k < c->vptr[v + 1]; ++k)
+                gvs[(size_t)(k - c->vptr[v]) * d.n_tab + v] = edge_slot[c->vedge[k]];
+    }
+    if (gcn.empty()) gcn.push_back(c->n);
     struct Up { const void *src; size_t bytes; const int **dst; } ups[] = {
         {rp32.data(), rp32.size() * 4, &d.row_ptr}, {c->col.data(), c->col.size() * 4, &d.col},
         {vp32.data(), vp32.size() * 4, &d.vptr},    {c->vchk.data(), c->vchk.size() * 4, &d.vchk},
         {c->vedge.data(), c->vedge.size() * 4, &d.vedge}, {cn.data(), cn.size() * 4, &d.cn_tab},
-        {vn.data(), vn.size() * 4, &d.vn_tab},
+        {vn.data(), vn.size() * 4, &d.vn_tab}, {gcn.data(), gcn.size() * 4, &d.g_cn},
+        {gvs.data(), gvs.size() * 4, &d.g_vslot},
     };
     for (auto &u : ups) {
         void *p = ex.dalloc(u.bytes ? u.bytes : 4);

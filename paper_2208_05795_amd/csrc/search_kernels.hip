@@ -28,6 +28,7 @@
 //     hardware exp2 / log2 / reciprocal and series at both ends; the exclusive
 //     sums come from prefix and suffix sums; messages are rounded to 2^-20.
 #include <climits>
+#include <type_traits>
 #include <cmath>
 
 #include "internal.h"
@@ -346,55 +347,15 @@ struct MaxBlockIs {
     static constexpr int value = DC * CPT <= 8 ? 1024 : 256;
 };
 
-template <class Rule, int DC, int CPT>
-__global__ __launch_bounds__((MaxBlock<DC, CPT>::value)) void k_search(SearchLaunch a, DevCode cd) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int n = cd.n, T = a.max_iter;
-    const Lds L = lds_layout(n, T, true);
-    const int np = L.np, W = L.W;
-    Frame F;
-    F.lam = (int *)(smem + L.lam);
-    F.app = (int *)(smem + L.app);
-    F.hist = (unsigned long long *)(smem + L.hist);
-    F.wsyn = (int *)(smem + L.wsyn);
-    F.pcnt = (int *)(smem + L.pcnt);
-    F.n = n;
-    F.np = np;
-    F.W = W;
-    F.T = T;
-    unsigned long long *imask = (unsigned long long *)(smem + L.imask);
-    int *sh = (int *)(smem + L.sh);
+// Common part of the impulse-search kernels: the pattern queue, the bisection on
+// the impulse amplitude, the candidate write-out and the per-pattern results.
+// Dec::decode(K) runs one decode of the current pattern (impulse bits in imask)
+// at amplitude index K; Dec::hist() is its iteration history of hard decisions.
+template <class Dec>
+__device__ __forceinline__ void search_patterns(const SearchLaunch &a, int n, int W, Dec &dec,
+                                                unsigned long long *imask, int *sh) {
     const int B = blockDim.x, tid = threadIdx.x;
-    const bool oms = Rule::kDummy == OmsRule::kDummy;
-
-    int nb[CPT][DC];
-    load_neighbours<DC, CPT>(cd, nb);
-    int c2v[CPT][DC];
     unsigned long long my_iters = 0, my_dec = 0;
-    const int lam_base = oms ? a.q_base : to_q20(a.h);
-
-#define TSG_DECODE(K, OUT)                                                                  \
-    do {                                                                                   \
-        __syncthreads();                                                                   \
-        const int li_ = oms ? q_impulse(a.q_base, (K))                                     \
-                            : to_q20(a.h * (1.0f - (float)(K) / (float)a.k_den));          \
-        for (int v = tid; v < np; v += B) {                                                \
-            int l_ = v == n ? Rule::kDummy : 0;                                            \
-            if (v < n) l_ = ((imask[v >> 6] >> (v & 63)) & 1ull) ? li_ : lam_base;          \
-            F.lam[v] = l_;                                                                 \
-            F.app[v] = l_;                                                                 \
-            F.app[np + v] = l_;                                                            \
-        }                                                                                  \
-        for (int i = tid; i < T + 2; i += B) {                                             \
-            F.wsyn[i] = 0;                                                                 \
-            F.pcnt[i] = 0;                                                                 \
-        }                                                                                  \
-        __syncthreads();                                                                   \
-        OUT = run_decode<Rule, DC, CPT>(F, nb, c2v, a.offset);                             \
-        my_iters += OUT.iters;                                                             \
-        my_dec += 1;                                                                       \
-    } while (0)
-
     for (;;) {
         __syncthreads();
         if (tid == 0) sh[0] = atomicAdd(a.queue, 1);
@@ -410,23 +371,26 @@ __global__ __launch_bounds__((MaxBlock<DC, CPT>::value)) void k_search(SearchLau
             else if (v >= 0) atomicOr(&imask[v >> 6], 1ull << (v & 63));
         }
         const int pg = a.pat_base + pl;
-        DecRes r;
-        TSG_DECODE(a.k_max, r);
+        DecRes r = dec.decode(a.k_max);
+        my_iters += r.iters;
+        my_dec += 1;
         int kc = -1, it_hi = 0, tm_hi = 0, it_lo = r.iters;
         if (r.fail) {
-            write_candidates(a, F.hist, imask, W, r.iters, pg, a.k_max);
+            write_candidates(a, dec.hist(), imask, W, r.iters, pg, a.k_max);
             int lo = 0, hi = a.k_max;
             it_hi = r.iters;
             tm_hi = r.tmin;
             it_lo = 1;   // D(0) is the noiseless decode: success at the first iteration
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
-                TSG_DECODE(mid, r);
+                r = dec.decode(mid);
+                my_iters += r.iters;
+                my_dec += 1;
                 if (r.fail) {
                     hi = mid;
                     it_hi = r.iters;
                     tm_hi = r.tmin;
-                    write_candidates(a, F.hist, imask, W, r.iters, pg, mid);
+                    write_candidates(a, dec.hist(), imask, W, r.iters, pg, mid);
                 } else {
                     lo = mid;
                     it_lo = r.iters;
@@ -442,11 +406,77 @@ __global__ __launch_bounds__((MaxBlock<DC, CPT>::value)) void k_search(SearchLau
             a.n_cand[pg] = 0;
         }
     }
-#undef TSG_DECODE
     if (tid == 0) {
         atomicAdd(&a.counters[0], my_dec);
         atomicAdd(&a.counters[1], my_iters);
     }
+}
+
+// Channel value of an impulse frame: impulse bits get the amplitude-K value,
+// all others the base value (Section III).
+template <class Rule>
+__device__ __forceinline__ int impulse_lambda(const SearchLaunch &a, int K) {
+    return Rule::kDummy == OmsRule::kDummy ? q_impulse(a.q_base, K)
+                                           : to_q20(a.h * (1.0f - (float)K / (float)a.k_den));
+}
+
+template <class Rule>
+__device__ __forceinline__ int base_lambda(const SearchLaunch &a) {
+    return Rule::kDummy == OmsRule::kDummy ? a.q_base : to_q20(a.h);
+}
+
+// Register-resident decoder of one workgroup: the neighbour lists and messages
+// of the checks a thread owns stay in its registers.
+template <class Rule, int DC, int CPT>
+struct RegSearchDec {
+    const SearchLaunch &a;
+    Frame F;
+    const unsigned long long *imask;
+    int nb[CPT][DC];
+    int c2v[CPT][DC];
+
+    __device__ __forceinline__ RegSearchDec(const SearchLaunch &a_) : a(a_) {}
+
+    __device__ __forceinline__ DecRes decode(int K) {
+        const int B = blockDim.x, tid = threadIdx.x, n = F.n, np = F.np;
+        const int li = impulse_lambda<Rule>(a, K), lb = base_lambda<Rule>(a);
+        __syncthreads();
+        for (int v = tid; v < np; v += B) {
+            int l = v == n ? Rule::kDummy : 0;
+            if (v < n) l = ((imask[v >> 6] >> (v & 63)) & 1ull) ? li : lb;
+            F.lam[v] = l;
+            F.app[v] = l;
+            F.app[np + v] = l;
+        }
+        for (int i = tid; i < F.T + 2; i += B) {
+            F.wsyn[i] = 0;
+            F.pcnt[i] = 0;
+        }
+        __syncthreads();
+        return run_decode<Rule, DC, CPT>(F, nb, c2v, a.offset);
+    }
+    __device__ __forceinline__ const unsigned long long *hist() const { return F.hist; }
+};
+
+template <class Rule, int DC, int CPT>
+__global__ __launch_bounds__((MaxBlock<DC, CPT>::value)) void k_search(SearchLaunch a, DevCode cd) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = cd.n, T = a.max_iter;
+    const Lds L = lds_layout(n, T, true);
+    RegSearchDec<Rule, DC, CPT> dec(a);
+    dec.F.lam = (int *)(smem + L.lam);
+    dec.F.app = (int *)(smem + L.app);
+    dec.F.hist = (unsigned long long *)(smem + L.hist);
+    dec.F.wsyn = (int *)(smem + L.wsyn);
+    dec.F.pcnt = (int *)(smem + L.pcnt);
+    dec.F.n = n;
+    dec.F.np = L.np;
+    dec.F.W = L.W;
+    dec.F.T = T;
+    unsigned long long *imask = (unsigned long long *)(smem + L.imask);
+    dec.imask = imask;
+    load_neighbours<DC, CPT>(cd, dec.nb);
+    search_patterns(a, n, L.W, dec, imask, (int *)(smem + L.sh));
 }
 
 // ---------------------------------------------------------------------------
@@ -484,7 +514,54 @@ struct IsDev {
     double *wf;
     int *queue;
     unsigned long long *counters;
+    unsigned char *gscr;   // streamed kind: per-workgroup scratch
+    long long slot_bytes, lam_off;
 };
+
+// Channel of IS frame `frame` (Section II, mean-shifted noise on the TS bits):
+// y_v = 1 - s [v in T] + sigma n_v with n_v from Philox4x32-10 at counter
+// (v >> 2, frame, stream) and Box-Muller, lambda_v = 2 y_v / sigma^2 in Q20.
+// put(v, lambda) stores the values; the normals of the TS bits go to tn.
+template <class Put>
+__device__ __forceinline__ void is_channel(const IsDev &a, int n, unsigned long long frame,
+                                           const int *tsl, double *tn, Put put) {
+    const int B = blockDim.x, tid = threadIdx.x;
+    const unsigned k0 = (unsigned)a.seed, k1 = (unsigned)(a.seed >> 32);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int g = tid; 4 * g < n; g += B) {
+        unsigned c[4] = {(unsigned)g, (unsigned)frame, (unsigned)(frame >> 32), a.stream};
+        philox4x32_10(c, k0, k1);
+        double u[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) u[i] = ((double)c[i] + 0.5) * 0x1p-32;
+        const double r0 = sqrt(-2.0 * log(u[0])), r1 = sqrt(-2.0 * log(u[2]));
+        double s0, c0, s1, c1;
+        sincos(two_pi * u[1], &s0, &c0);
+        sincos(two_pi * u[3], &s1, &c1);
+        const double nv[4] = {r0 * c0, r0 * s0, r1 * c1, r1 * s1};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int v = 4 * g + i;
+            if (v >= n) break;
+            int slot = -1;
+            for (int q = 0; q < a.a; ++q)
+                if (tsl[q] == v) slot = q;
+            const double y = 1.0 - (slot >= 0 ? a.shift : 0.0) + a.sigma * nv[i];
+            put(v, to_q20((float)(2.0 * y / a.sigma2)));
+            if (slot >= 0) tn[slot] = nv[i];
+        }
+    }
+}
+
+// Importance weight of a finished frame (thread 0):
+// w = exp(-a s^2 / (2 sigma^2) + (s / sigma) sum_{v in T} n_v), kept for failures.
+__device__ __forceinline__ void is_finish(const IsDev &a, int f, const DecRes &r, const double *tn) {
+    double st = 0.0;
+    for (int q = 0; q < a.a; ++q) st += tn[q];
+    const double w = exp(a.wconst + (a.shift / a.sigma) * st);
+    a.fail[f] = (unsigned char)r.fail;
+    a.wf[f] = r.fail ? w : 0.0;
+}
 
 template <int DC, int CPT>
 __global__ __launch_bounds__((MaxBlockIs<DC, CPT>::value)) void k_is(IsDev a, DevCode cd) {
@@ -512,41 +589,17 @@ __global__ __launch_bounds__((MaxBlockIs<DC, CPT>::value)) void k_is(IsDev a, De
     int c2v[CPT][DC];
     if (tid < kMaxWidth) tsl[tid] = tid < a.a ? a.ts[tid] : -1;
     unsigned long long my_iters = 0;
-    const unsigned k0 = (unsigned)a.seed, k1 = (unsigned)(a.seed >> 32);
-    const double two_pi = 6.283185307179586476925286766559;
     for (;;) {
         __syncthreads();
         if (tid == 0) sh[0] = atomicAdd(a.queue, 1);
         __syncthreads();
         const int f = sh[0];
         if ((long long)f >= a.n_frames) break;
-        const unsigned long long frame = a.frame_base + (unsigned long long)f;
-        for (int g = tid; 4 * g < n; g += B) {
-            unsigned c[4] = {(unsigned)g, (unsigned)frame, (unsigned)(frame >> 32), a.stream};
-            philox4x32_10(c, k0, k1);
-            double u[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) u[i] = ((double)c[i] + 0.5) * 0x1p-32;
-            const double r0 = sqrt(-2.0 * log(u[0])), r1 = sqrt(-2.0 * log(u[2]));
-            double s0, c0, s1, c1;
-            sincos(two_pi * u[1], &s0, &c0);
-            sincos(two_pi * u[3], &s1, &c1);
-            const double nv[4] = {r0 * c0, r0 * s0, r1 * c1, r1 * s1};
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int v = 4 * g + i;
-                if (v >= n) break;
-                int slot = -1;
-                for (int q = 0; q < a.a; ++q)
-                    if (tsl[q] == v) slot = q;
-                const double y = 1.0 - (slot >= 0 ? a.shift : 0.0) + a.sigma * nv[i];
-                const int l = to_q20((float)(2.0 * y / a.sigma2));
-                F.lam[v] = l;
-                F.app[v] = l;
-                F.app[np + v] = l;
-                if (slot >= 0) tn[slot] = nv[i];
-            }
-        }
+        is_channel(a, n, a.frame_base + (unsigned long long)f, tsl, tn, [&](int v, int l) {
+            F.lam[v] = l;
+            F.app[v] = l;
+            F.app[np + v] = l;
+        });
         for (int v = n + tid; v < np; v += B) {
             F.lam[v] = 0;
             F.app[v] = 0;
@@ -559,13 +612,7 @@ __global__ __launch_bounds__((MaxBlockIs<DC, CPT>::value)) void k_is(IsDev a, De
         __syncthreads();
         const DecRes r = run_decode<SpaRule, DC, CPT>(F, nb, c2v, 0);
         my_iters += r.iters;
-        if (tid == 0) {
-            double st = 0.0;
-            for (int q = 0; q < a.a; ++q) st += tn[q];
-            const double w = exp(a.wconst + (a.shift / a.sigma) * st);
-            a.fail[f] = (unsigned char)r.fail;
-            a.wf[f] = r.fail ? w : 0.0;
-        }
+        if (tid == 0) is_finish(a, f, r, tn);
     }
     if (tid == 0) atomicAdd(&a.counters[1], my_iters);
 }
@@ -620,6 +667,291 @@ __global__ void k_fill(int *p, int value, long long count) {
 }
 
 // ---------------------------------------------------------------------------
+// streamed frames: codes whose messages do not fit in registers
+// ---------------------------------------------------------------------------
+// One workgroup per frame as above, but the check-to-variable messages stream
+// through a per-workgroup scratch area in global memory, and the APP values are
+// rebuilt from them in a second pass per iteration instead of by atomics:
+//   check pass  (thread per check, checks sorted into degree classes): gather
+//               APP_{t-1} from LDS, take the syndrome bit of x_{t-1}, read the
+//               old messages, apply the check rule, write the new messages;
+//   variable pass (thread per variable, wave-contiguous): APP_t = lambda + sum
+//               of the variable's new messages, hard decision by ballot.
+// Messages are stored edge-major within a class (slot j of consecutive checks
+// adjacent), so both passes read and write them coalesced; for a QC code the
+// variable pass gathers from consecutive rows of each circulant.  The integer
+// arithmetic (int8 / Q20 messages, int32 sums) is that of the register-resident
+// decoder, so both give identical results.
+struct LdsG {
+    int np, W;
+    size_t app, imask, wsyn, pcnt, sh, cls, extra, total;
+};
+
+__host__ __device__ inline LdsG lds_layout_g(int n, int T) {
+    LdsG L;
+    L.np = (n + 1 + 63) & ~63;
+    L.W = L.np >> 6;
+    size_t o = 0;
+    L.app = o;
+    o += (size_t)L.np * 4;
+    o = (o + 15) & ~(size_t)15;
+    L.imask = o;
+    o += (size_t)L.W * 8;
+    L.wsyn = o;
+    o += (size_t)(T + 2) * 4;
+    L.pcnt = o;
+    o += (size_t)(T + 2) * 4;
+    L.sh = o;
+    o += 32 * 4;
+    L.cls = o;   // class table: dc, c0, stride, off
+    o += (size_t)(4 * kGMaxCls + 2) * 4;
+    o = (o + 15) & ~(size_t)15;
+    L.extra = o;
+    o += (size_t)kMaxWidth * 8 + (size_t)kMaxWidth * 4;
+    L.total = (o + 15) & ~(size_t)15;
+    return L;
+}
+
+struct GFrame {
+    int *app;                          // LDS [np]
+    const unsigned long long *imask;   // LDS impulse bits (search) or nullptr
+    const int *lam_g;                  // global channel values (IS) or nullptr
+    int lam_base, lam_imp;
+    void *msg;                         // global message slots of this workgroup
+    unsigned long long *hist;          // global [T][W] or nullptr
+    int *wsyn, *pcnt;                  // LDS
+    const int *cdc, *cc0, *cstr, *coff;   // LDS copy of the class table
+    int ncls, n, np, W, T;
+};
+
+__device__ __forceinline__ int g_lambda(const GFrame &F, int v) {
+    if (F.lam_g) return F.lam_g[v];
+    return ((F.imask[v >> 6] >> (v & 63)) & 1ull) ? F.lam_imp : F.lam_base;
+}
+
+// Check pass of one check (sorted position p, class q); returns the parity of
+// the hard decisions of APP_{t-1} on its variables.
+template <class Rule, int DC, class M>
+__device__ __forceinline__ int check_g(const DevCode &cd, const GFrame &F, int q, int p, int t,
+                                       int offset) {
+    const int stride = F.cstr[q];
+    const size_t base = (size_t)F.coff[q] + (size_t)(p - F.cc0[q]);
+    int nb[DC], val[DC], c2v[DC];
+#pragma unroll
+    for (int j = 0; j < DC; ++j) {
+        nb[j] = cd.g_cn[base + (size_t)j * stride];
+        val[j] = F.app[nb[j]];
+    }
+    int par = 0;
+#pragma unroll
+    for (int j = 0; j < DC; ++j) par ^= (val[j] < 0);
+    if (t <= F.T) {
+        M *msg = (M *)F.msg;
+#pragma unroll
+        for (int j = 0; j < DC; ++j) c2v[j] = t == 1 ? 0 : (int)msg[base + (size_t)j * stride];
+        Rule::template update<DC>(val, c2v, nb, F.n, offset);
+#pragma unroll
+        for (int j = 0; j < DC; ++j) msg[base + (size_t)j * stride] = (M)c2v[j];
+    }
+    return par;
+}
+
+// One decode of a streamed frame.  On entry APP (LDS) holds the channel values
+// (slot n: the padding value), wsyn/pcnt are zero, all threads passed a barrier.
+template <class Rule, int DCMAX, class M>
+__device__ DecRes run_decode_g(const DevCode &cd, const GFrame &F, int offset) {
+    const int n = F.n, W = F.W, T = F.T, mm = cd.m;
+    const int B = blockDim.x, NW = B >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const M *msg = (const M *)F.msg;
+    int iters = T, wmin = INT_MAX, tmin = 0;
+    for (int t = 1; t <= T + 1; ++t) {
+        int unsat = 0, q = 0;
+        for (int p = tid; p < mm; p += B) {
+            while (q + 1 < F.ncls && p >= F.cc0[q + 1]) ++q;
+            int par = 0;
+            switch (F.cdc[q]) {
+#define TSG_GCASE(D)                                                             \
+    case D:                                                                      \
+        if constexpr (D <= DCMAX && !(DCMAX == 32 && D == 24))                   \
+            par = check_g<Rule, D, M>(cd, F, q, p, t, offset);                   \
+        break;
+                TSG_GCASE(3) TSG_GCASE(4) TSG_GCASE(6) TSG_GCASE(8)
+                TSG_GCASE(12) TSG_GCASE(16) TSG_GCASE(24) TSG_GCASE(32)
+#undef TSG_GCASE
+                default: break;
+            }
+            unsat += par;
+        }
+        if (t >= 2) {
+            const int us = wave_sum(unsat);
+            if (lane == 0 && us) atomicAdd(&F.wsyn[t - 1], us);
+        }
+        __syncthreads();
+        if (t >= 2) {
+            const int w = F.wsyn[t - 1];
+            if (w < wmin) {
+                wmin = w;
+                tmin = t - 1;
+            }
+            if (w == 0) {
+                iters = t - 1;
+                break;
+            }
+        }
+        if (t > T) break;
+        int pc = 0;
+        for (int i = wid; i < W; i += NW) {
+            const int v = i * 64 + lane;
+            int x = 0;
+            if (v < n) {
+                int sum = g_lambda(F, v);
+                for (int k = 0; k < cd.dv_pad; ++k) {
+                    const int e = cd.g_vslot[(size_t)k * cd.n_tab + v];
+                    if (e >= 0) sum += (int)msg[e];
+                }
+                F.app[v] = sum;
+                x = sum < 0;
+            }
+            const unsigned long long mask = __ballot(x);
+            if (F.hist && lane == 0) F.hist[(size_t)(t - 1) * W + i] = mask;
+            pc += __popcll(mask);
+        }
+        if (lane == 0 && pc) atomicAdd(&F.pcnt[t], pc);
+        __syncthreads();
+    }
+    DecRes r;
+    r.iters = iters;
+    r.tmin = tmin;
+    r.fail = F.pcnt[iters] > 0;
+    return r;
+}
+
+__device__ __forceinline__ void g_load_classes(const DevCode &cd, unsigned char *smem, const LdsG &L,
+                                               GFrame &F) {
+    int *cls = (int *)(smem + L.cls);
+    const int tid = threadIdx.x;
+    if (tid < kGMaxCls) {
+        cls[tid] = cd.g_dc[tid];
+        cls[2 * kGMaxCls + 1 + tid] = cd.g_stride[tid];
+    }
+    if (tid < kGMaxCls + 1) {
+        cls[kGMaxCls + tid] = cd.g_c0[tid];
+        cls[3 * kGMaxCls + 1 + tid] = cd.g_off[tid];
+    }
+    F.cdc = cls;
+    F.cc0 = cls + kGMaxCls;
+    F.cstr = cls + 2 * kGMaxCls + 1;
+    F.coff = cls + 3 * kGMaxCls + 1;
+    F.ncls = cd.g_ncls;
+}
+
+template <class Rule, int DCMAX, class M>
+struct GSearchDec {
+    const SearchLaunch &a;
+    const DevCode &cd;
+    GFrame F;
+
+    __device__ __forceinline__ GSearchDec(const SearchLaunch &a_, const DevCode &cd_) : a(a_), cd(cd_) {}
+
+    __device__ __forceinline__ DecRes decode(int K) {
+        const int B = blockDim.x, tid = threadIdx.x, n = F.n;
+        F.lam_imp = impulse_lambda<Rule>(a, K);
+        __syncthreads();
+        for (int v = tid; v < F.np; v += B) F.app[v] = v < n ? g_lambda(F, v) : Rule::kDummy;
+        for (int i = tid; i < F.T + 2; i += B) {
+            F.wsyn[i] = 0;
+            F.pcnt[i] = 0;
+        }
+        __syncthreads();
+        return run_decode_g<Rule, DCMAX, M>(cd, F, a.offset);
+    }
+    __device__ __forceinline__ const unsigned long long *hist() const { return F.hist; }
+};
+
+// Workgroup bounds of the streamed kernels (the register budget follows).
+template <int DCMAX> struct MaxBlockG { static constexpr int value = DCMAX <= 16 ? 1024 : 512; };
+template <int DCMAX> struct MaxBlockGIs { static constexpr int value = 512; };
+
+template <class Rule, int DCMAX>
+__global__ __launch_bounds__((MaxBlockG<DCMAX>::value)) void k_search_g(SearchLaunch a, DevCode cd) {
+    typedef typename std::conditional<Rule::kDummy == OmsRule::kDummy, signed char, int>::type M;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = cd.n, T = a.max_iter;
+    const LdsG L = lds_layout_g(n, T);
+    GSearchDec<Rule, DCMAX, M> dec(a, cd);
+    GFrame &F = dec.F;
+    unsigned long long *imask = (unsigned long long *)(smem + L.imask);
+    unsigned char *slot = a.gscr + (size_t)blockIdx.x * a.slot_bytes;
+    F.app = (int *)(smem + L.app);
+    F.imask = imask;
+    F.lam_g = nullptr;
+    F.lam_base = base_lambda<Rule>(a);
+    F.lam_imp = F.lam_base;
+    F.msg = slot;
+    F.hist = (unsigned long long *)(slot + a.hist_off);
+    F.wsyn = (int *)(smem + L.wsyn);
+    F.pcnt = (int *)(smem + L.pcnt);
+    F.n = n;
+    F.np = L.np;
+    F.W = L.W;
+    F.T = T;
+    g_load_classes(cd, smem, L, F);
+    search_patterns(a, n, L.W, dec, imask, (int *)(smem + L.sh));
+}
+
+template <int DCMAX>
+__global__ __launch_bounds__((MaxBlockGIs<DCMAX>::value)) void k_is_g(IsDev a, DevCode cd) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = cd.n, T = a.max_iter;
+    const LdsG L = lds_layout_g(n, T);
+    const int np = L.np;
+    unsigned char *slot = a.gscr + (size_t)blockIdx.x * a.slot_bytes;
+    int *lam = (int *)(slot + a.lam_off);
+    GFrame F;
+    F.app = (int *)(smem + L.app);
+    F.imask = nullptr;
+    F.lam_g = lam;
+    F.lam_base = F.lam_imp = 0;
+    F.msg = slot;
+    F.hist = nullptr;
+    F.wsyn = (int *)(smem + L.wsyn);
+    F.pcnt = (int *)(smem + L.pcnt);
+    F.n = n;
+    F.np = np;
+    F.W = L.W;
+    F.T = T;
+    g_load_classes(cd, smem, L, F);
+    int *sh = (int *)(smem + L.sh);
+    double *tn = (double *)(smem + L.extra);
+    int *tsl = (int *)(tn + kMaxWidth);
+    const int B = blockDim.x, tid = threadIdx.x;
+    if (tid < kMaxWidth) tsl[tid] = tid < a.a ? a.ts[tid] : -1;
+    unsigned long long my_iters = 0;
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) sh[0] = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int f = sh[0];
+        if ((long long)f >= a.n_frames) break;
+        is_channel(a, n, a.frame_base + (unsigned long long)f, tsl, tn, [&](int v, int l) {
+            lam[v] = l;
+            F.app[v] = l;
+        });
+        for (int v = n + tid; v < np; v += B) F.app[v] = SpaRule::kDummy;
+        for (int i = tid; i < T + 2; i += B) {
+            F.wsyn[i] = 0;
+            F.pcnt[i] = 0;
+        }
+        __syncthreads();
+        const DecRes r = run_decode_g<SpaRule, DCMAX, int>(cd, F, 0);
+        my_iters += r.iters;
+        if (tid == 0) is_finish(a, f, r, tn);
+    }
+    if (tid == 0) atomicAdd(&a.counters[1], my_iters);
+}
+
+// ---------------------------------------------------------------------------
 // kernel table
 // ---------------------------------------------------------------------------
 typedef void (*SearchKernel)(SearchLaunch, DevCode);
@@ -641,9 +973,26 @@ const KEntry kTable[] = {
 };
 #undef TSG_K
 
+// streamed-frame kernels, by largest check-degree class
+struct GEntry {
+    int dcmax, max_block, is_max_block;
+    SearchKernel oms, spa;
+    IsKernel is;
+};
+#define TSG_G(D) \
+    {D, MaxBlockG<D>::value, MaxBlockGIs<D>::value, k_search_g<OmsRule, D>, k_search_g<SpaRule, D>, k_is_g<D>}
+const GEntry kGTable[] = {TSG_G(16), TSG_G(24), TSG_G(32)};
+#undef TSG_G
+
 const KEntry *find_kernel(int dc, int cpt) {
     for (const KEntry &k : kTable)
         if (k.dc == dc && k.cpt == cpt) return &k;
+    return nullptr;
+}
+
+const GEntry *find_g(int dcmax) {
+    for (const GEntry &g : kGTable)
+        if (g.dcmax == dcmax) return &g;
     return nullptr;
 }
 
@@ -655,57 +1004,82 @@ int padded_degree(const ts_code *c) {
     return 0;
 }
 
-// IS shape: the fewest checks per thread whose workgroup fits the IS kernel's bound.
-int pick_is_shape(const ts_code *c, int *dc_out, int *cpt_out, int *block_out) {
-    const int dc = padded_degree(c);
-    if (!dc) return TS_E_INVAL;
-    for (int cp : {1, 2, 4, 8}) {
-        const KEntry *k = find_kernel(dc, cp);
-        if (!k) continue;
-        const int b = ((c->m + cp - 1) / cp + 63) / 64 * 64;
-        if (b <= k->is_max_block) {
-            *dc_out = dc;
-            *cpt_out = cp;
-            *block_out = b;
-            return TS_OK;
-        }
+int streamed_dcmax(const ts_code *c) { return c->dc_max <= 16 ? 16 : (c->dc_max <= 24 ? 24 : 32); }
+
+// Streamed plans: every workgroup size up to the kernel's bound that fits.
+int add_streamed_plans(ts_ctx *ctx, const ts_code *c, bool search, int decoder, int max_iter,
+                       std::vector<SearchPlan> *out) {
+    const GEntry *g = find_g(streamed_dcmax(c));
+    const LdsG L = lds_layout_g(c->n, max_iter);
+    if (!g || L.total > ctx->lds_per_block) return TS_OK;
+    size_t aux = 0;
+    const size_t slot = streamed_slot_bytes(c, decoder, max_iter, search, &aux);
+    const void *kern = search ? (const void *)(decoder == TS_DEC_OMS_I8 ? g->oms : g->spa)
+                              : (const void *)g->is;
+    for (int block : {256, 512, 1024}) {
+        if (block > (search ? g->max_block : g->is_max_block)) continue;
+        int per_cu = 0;
+        TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, L.total));
+        if (per_cu < 1) continue;
+        SearchPlan p;
+        p.kind = kPlanStreamed;
+        p.block = block;
+        p.cpt = 0;
+        p.dc = g->dcmax;
+        p.lds = L.total;
+        p.grid = per_cu * ctx->num_cu;
+        p.slot_bytes = slot;
+        p.hist_off = aux;
+        out->push_back(p);
     }
-    set_error("code has too many checks (%d) for one workgroup at check degree %d", c->m, c->dc_max);
-    return TS_E_INVAL;
+    return TS_OK;
 }
 
 }  // namespace
 
+size_t streamed_slot_bytes(const ts_code *c, int decoder, int max_iter, bool search, size_t *aux_off) {
+    const size_t msg = (size_t)c->dev.g_off[c->dev.g_ncls] * (decoder == TS_DEC_OMS_I8 ? 1 : 4);
+    size_t o = (msg + 255) & ~(size_t)255;
+    *aux_off = o;
+    const LdsG L = lds_layout_g(c->n, max_iter);
+    o += search ? (size_t)max_iter * L.W * 8 : (size_t)L.np * 4;
+    return (o + 255) & ~(size_t)255;
+}
+
+// Launch shapes of the impulse search, register-resident ones first (fewest
+// checks per thread first), then streamed ones.
 int plan_candidates(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter,
                     std::vector<SearchPlan> *out) {
     out->clear();
     const int dc = padded_degree(c);
     if (!dc) return TS_E_INVAL;
     const Lds L = lds_layout(c->n, max_iter, true);
-    if (L.total > ctx->lds_per_block) {
-        set_error("code needs %zu bytes of LDS per workgroup, the device has %zu", L.total,
-                  ctx->lds_per_block);
-        return TS_E_INVAL;
+    if (L.total <= ctx->lds_per_block) {
+        for (int cp : {1, 2, 4, 8}) {
+            const KEntry *ke = find_kernel(dc, cp);
+            if (!ke) continue;
+            const int block = ((c->m + cp - 1) / cp + 63) / 64 * 64;
+            if (block > ke->max_block) continue;
+            SearchKernel kern = decoder == TS_DEC_OMS_I8 ? ke->oms : ke->spa;
+            int per_cu = 0;
+            TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, block, L.total));
+            if (per_cu < 1) continue;
+            SearchPlan p;
+            p.kind = kPlanRegister;
+            p.block = block;
+            p.cpt = cp;
+            p.dc = dc;
+            p.lds = L.total;
+            p.grid = per_cu * ctx->num_cu;
+            p.slot_bytes = 0;
+            p.hist_off = 0;
+            out->push_back(p);
+        }
     }
-    for (int cp : {1, 2, 4, 8}) {
-        const KEntry *ke = find_kernel(dc, cp);
-        if (!ke) continue;
-        const int block = ((c->m + cp - 1) / cp + 63) / 64 * 64;
-        if (block > ke->max_block) continue;
-        SearchKernel kern = decoder == TS_DEC_OMS_I8 ? ke->oms : ke->spa;
-        int per_cu = 0;
-        TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, block, L.total));
-        if (per_cu < 1) continue;
-        SearchPlan p;
-        p.block = block;
-        p.cpt = cp;
-        p.dc = dc;
-        p.lds = L.total;
-        p.grid = per_cu * ctx->num_cu;
-        out->push_back(p);
-    }
+    int rc = add_streamed_plans(ctx, c, true, decoder, max_iter, out);
+    if (rc) return rc;
     if (out->empty()) {
-        set_error("code has too many checks (%d) for one workgroup at check degree %d", c->m, c->dc_max);
+        set_error("code (n = %d) needs more LDS per workgroup than the device has", c->n);
         return TS_E_INVAL;
     }
     return TS_OK;
@@ -719,13 +1093,26 @@ int plan_search(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter, Search
     return TS_OK;
 }
 
-int launch_search(hipStream_t stream, const SearchPlan &plan, const SearchLaunch &a) {
-    const KEntry *ke = find_kernel(plan.dc, plan.cpt);
-    if (!ke) {
-        set_error("no kernel for dc %d cpt %d", plan.dc, plan.cpt);
+int launch_search(hipStream_t stream, const SearchPlan &plan, const SearchLaunch &a0) {
+    SearchKernel kern = nullptr;
+    SearchLaunch a = a0;
+    if (plan.kind == kPlanRegister) {
+        const KEntry *ke = find_kernel(plan.dc, plan.cpt);
+        if (ke) kern = a.decoder == TS_DEC_OMS_I8 ? ke->oms : ke->spa;
+    } else {
+        const GEntry *g = find_g(plan.dc);
+        if (g) kern = a.decoder == TS_DEC_OMS_I8 ? g->oms : g->spa;
+        if (!a.gscr) {
+            set_error("streamed launch without scratch");
+            return TS_E_INVAL;
+        }
+        a.slot_bytes = (long long)plan.slot_bytes;
+        a.hist_off = (long long)plan.hist_off;
+    }
+    if (!kern) {
+        set_error("no kernel for kind %d dc %d cpt %d", plan.kind, plan.dc, plan.cpt);
         return TS_E_INVAL;
     }
-    SearchKernel kern = a.decoder == TS_DEC_OMS_I8 ? ke->oms : ke->spa;
     const int grid = a.n_patterns < plan.grid ? a.n_patterns : plan.grid;
     if (grid <= 0) return TS_OK;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(plan.block), plan.lds, stream, a, *a.code);
@@ -743,25 +1130,66 @@ int launch_fill(hipStream_t stream, int *p, int value, int64_t count) {
     return TS_OK;
 }
 
-int launch_is(ts_exec &ex, const ts_code *c, const IsLaunch &a, int *grid_out, int *block_out) {
-    ts_ctx *ctx = ex.ctx;
-    int dc = 0, cpt = 0, block = 0;
-    int rc = pick_is_shape(c, &dc, &cpt, &block);
-    if (rc) return rc;
-    const Lds L = lds_layout(c->n, a.max_iter, false);
-    if (L.total > ctx->lds_per_block) {
-        set_error("code needs %zu bytes of LDS per workgroup, the device has %zu", L.total,
-                  ctx->lds_per_block);
+// IS launch shape: the register-resident kernel with the fewest checks per
+// thread that fits, else the streamed kernel at its largest workgroup.
+int plan_is(ts_ctx *ctx, const ts_code *c, int max_iter, int layout, SearchPlan *plan) {
+    const int dc = padded_degree(c);
+    if (!dc) return TS_E_INVAL;
+    const Lds L = lds_layout(c->n, max_iter, false);
+    if (L.total <= ctx->lds_per_block && layout != TS_LAYOUT_STREAMED) {
+        for (int cp : {1, 2, 4, 8}) {
+            const KEntry *k = find_kernel(dc, cp);
+            if (!k) continue;
+            const int b = ((c->m + cp - 1) / cp + 63) / 64 * 64;
+            if (b > k->is_max_block) continue;
+            int per_cu = 0;
+            TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k->is, b, L.total));
+            if (per_cu < 1) continue;
+            plan->kind = kPlanRegister;
+            plan->block = b;
+            plan->cpt = cp;
+            plan->dc = dc;
+            plan->lds = L.total;
+            plan->grid = per_cu * ctx->num_cu;
+            plan->slot_bytes = plan->hist_off = 0;
+            return TS_OK;
+        }
+    }
+    std::vector<SearchPlan> g;
+    if (layout != TS_LAYOUT_REGISTER) {
+        int rc = add_streamed_plans(ctx, c, false, TS_DEC_SPA_F32, max_iter, &g);
+        if (rc) return rc;
+    }
+    if (g.empty()) {
+        if (layout == TS_LAYOUT_REGISTER) {
+            set_error("the requested decoder layout does not fit this code");
+            return TS_E_INVAL;
+        }
+        set_error("code (n = %d) needs more LDS per workgroup than the device has", c->n);
         return TS_E_INVAL;
     }
-    IsKernel kern = find_kernel(dc, cpt)->is;
-    int per_cu = 0;
-    TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, block, L.total));
-    if (per_cu < 1) {
-        set_error("IS kernel does not fit on a compute unit");
+    *plan = g.back();
+    return TS_OK;
+}
+
+int launch_is(hipStream_t stream, const ts_code *c, const SearchPlan &plan, const IsLaunch &a) {
+    IsKernel kern = nullptr;
+    if (plan.kind == kPlanRegister) {
+        const KEntry *k = find_kernel(plan.dc, plan.cpt);
+        if (k) kern = k->is;
+    } else {
+        const GEntry *g = find_g(plan.dc);
+        if (g) kern = g->is;
+        if (!a.gscr) {
+            set_error("streamed launch without scratch");
+            return TS_E_INVAL;
+        }
+    }
+    if (!kern) {
+        set_error("no IS kernel for kind %d dc %d cpt %d", plan.kind, plan.dc, plan.cpt);
         return TS_E_INVAL;
     }
-    long long grid = (long long)per_cu * ctx->num_cu;
+    long long grid = plan.grid;
     if (grid > a.n_frames) grid = a.n_frames;
     IsDev d;
     d.max_iter = a.max_iter;
@@ -779,10 +1207,11 @@ int launch_is(ts_exec &ex, const ts_code *c, const IsLaunch &a, int *grid_out, i
     d.wf = a.wf;
     d.queue = a.queue;
     d.counters = a.counters;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(block), L.total, ex.stream, d, c->dev);
+    d.gscr = a.gscr;
+    d.slot_bytes = (long long)plan.slot_bytes;
+    d.lam_off = (long long)plan.hist_off;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(plan.block), plan.lds, stream, d, c->dev);
     TSG_HIP(hipGetLastError());
-    if (grid_out) *grid_out = (int)grid;
-    if (block_out) *block_out = block;
     return TS_OK;
 }
 

@@ -255,6 +255,9 @@ int ts_submit(ts_ctx *ctx, const ts_job_desc *d, uint64_t *job_id) {
         j->io = d->is;
         j->ts_bits.assign(d->ts_bits, d->ts_bits + d->a);
         j->est = (size_t)d->is.n_frames * 9 + (1 << 20);
+        SearchPlan ip;
+        if (plan_is(ctx, d->code, d->is.max_iter, d->is.layout, &ip) == TS_OK && ip.kind == kPlanStreamed)
+            j->est += (size_t)std::min<int64_t>(ip.grid, d->is.n_frames) * ip.slot_bytes;
     } else {
         delete j;
         set_error("unknown job kind %d", d->kind);
