@@ -278,6 +278,18 @@ int ts_job_outputs(ts_ctx *ctx, uint64_t job_id, ts_search_out *out, ts_record *
 /* Cancels a queued job at once; a running job finishes its kernels and is then
  * reported as cancelled with no results.  Thread-safe. */
 int ts_cancel(ts_ctx *ctx, uint64_t job_id);
+/* Runs jobs[n_jobs] (search and IS jobs on any codes of this context, as for
+ * ts_submit) as one batch: jobs whose decoder kernel shape is the same share
+ * ONE persistent launch whose workgroups take patterns / frames of all of them
+ * from a single queue; launches of different shapes overlap on side streams;
+ * nothing returns to the host until every decode is done.  Each job's results
+ * equal those of the same call run alone.  Synchronous and serialised with the
+ * other calls of the context.  On return the jobs are finished jobs of the
+ * serving store: read them with ts_poll / ts_job_outputs and free them with
+ * ts_release, using the ids written to job_ids[n_jobs].  Errors: TS_E_INVAL if
+ * any job fails validation (nothing runs), at most 4096 jobs. */
+int ts_run_batch(ts_ctx *ctx, const ts_job_desc *jobs, int32_t n_jobs, uint64_t *job_ids);
+
 /* Frees a finished or cancelled job's results; TS_E_BUSY while in flight. */
 int ts_release(ts_ctx *ctx, uint64_t job_id);
 

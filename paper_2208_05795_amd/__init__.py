@@ -116,11 +116,12 @@ class Context:
     def serve_start(self, slots: int = 4):
         _check(lib().ts_serve_start(self._h, slots))
 
-    def submit_search(self, code: "Code", patterns, decoder: int = DEC_OMS, max_iter: int = 20,
-                      oms_offset: int = 1, ebn0_db: float = 3.0, rate: Optional[float] = None,
-                      llr_scale: float = 4.0, k_max: int = 512, k_den: int = 16, a_max: int = 6,
-                      extract_mode: int = EXTRACT_PATH, collect_from_iter: int = -1,
-                      layout: int = 0) -> int:
+    @staticmethod
+    def _search_desc(code: "Code", patterns, decoder: int = DEC_OMS, max_iter: int = 20,
+                     oms_offset: int = 1, ebn0_db: float = 3.0, rate: Optional[float] = None,
+                     llr_scale: float = 4.0, k_max: int = 512, k_den: int = 16, a_max: int = 6,
+                     extract_mode: int = EXTRACT_PATH, collect_from_iter: int = -1,
+                     layout: int = 0):
         pats = _i32(patterns)
         if pats.ndim == 1:
             pats = pats.reshape(-1, 1)
@@ -131,13 +132,12 @@ class Context:
                                 k_den, a_max, extract_mode, collect_from_iter, A.TS_MEM_HOST,
                                 layout)
         d.patterns, d.n_patterns, d.width = pats.ctypes.data, pats.shape[0], pats.shape[1]
-        jid = C.c_uint64()
-        _check(lib().ts_submit(self._h, C.byref(d), C.byref(jid)))
-        return jid.value
+        return d, pats
 
-    def submit_is(self, code: "Code", ts_bits, ebn0_db: float, shift: float, n_frames: int,
-                  seed: int, frame_base: int = 0, stream: int = 0, max_iter: int = 50,
-                  rate: Optional[float] = None, layout: int = 0) -> int:
+    @staticmethod
+    def _is_desc(code: "Code", ts_bits, ebn0_db: float, shift: float, n_frames: int,
+                 seed: int, frame_base: int = 0, stream: int = 0, max_iter: int = 50,
+                 rate: Optional[float] = None, layout: int = 0):
         t = _i32(ts_bits)
         rate = (1.0 - code.m / code.n) if rate is None else rate
         d = A.JobDesc()
@@ -145,9 +145,44 @@ class Context:
         d.is_ = A.IsOpts(max_iter, ebn0_db, rate, shift, n_frames, seed, frame_base, stream,
                          layout)
         d.ts_bits, d.a = t.ctypes.data, t.size
+        return d, t
+
+    def submit_search(self, code: "Code", patterns, **kw) -> int:
+        """Queues a search job (arguments as Code.impulse_search); returns its id."""
+        d, keep = self._search_desc(code, patterns, **kw)
         jid = C.c_uint64()
         _check(lib().ts_submit(self._h, C.byref(d), C.byref(jid)))
         return jid.value
+
+    def submit_is(self, code: "Code", ts_bits, ebn0_db: float, shift: float, n_frames: int,
+                  seed: int, **kw) -> int:
+        """Queues an IS job (arguments as Code.is_estimate); returns its id."""
+        d, keep = self._is_desc(code, ts_bits, ebn0_db, shift, n_frames, seed, **kw)
+        jid = C.c_uint64()
+        _check(lib().ts_submit(self._h, C.byref(d), C.byref(jid)))
+        return jid.value
+
+    def run_batch(self, jobs) -> List[int]:
+        """Runs jobs as one batch (ts_run_batch).  jobs: ("search", code, patterns,
+        kwargs) or ("is", code, ts_bits, kwargs) tuples; kwargs as for
+        submit_search / submit_is.  Returns the job ids (finished jobs: read them
+        with poll / job_outputs, free them with release)."""
+        descs, keep = [], []
+        for kind, code, data, kw in jobs:
+            if kind == "search":
+                d, k = self._search_desc(code, data, **kw)
+            elif kind == "is":
+                kw = dict(kw)
+                d, k = self._is_desc(code, data, kw.pop("ebn0_db"), kw.pop("shift"),
+                                     kw.pop("n_frames"), kw.pop("seed"), **kw)
+            else:
+                raise ValueError(f"unknown job kind {kind!r}")
+            descs.append(d)
+            keep.append(k)
+        arr = (A.JobDesc * max(len(descs), 1))(*descs)
+        ids = (C.c_uint64 * max(len(descs), 1))()
+        _check(lib().ts_run_batch(self._h, arr, len(descs), ids))
+        return [int(ids[i]) for i in range(len(descs))]
 
     def poll(self, job_id: int, wait: bool = False) -> dict:
         info = A.JobInfo()

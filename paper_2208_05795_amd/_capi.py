@@ -112,6 +112,7 @@ PROTOTYPES = {
     "ts_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, C.POINTER(JobInfo)]),
     "ts_job_outputs": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(SearchOut), C.c_void_p,
                                  C.c_int64, C.c_void_p, C.c_int64]),
+    "ts_run_batch": (C.c_int, [C.c_void_p, C.POINTER(JobDesc), C.c_int32, C.POINTER(C.c_uint64)]),
     "ts_cancel": (C.c_int, [C.c_void_p, C.c_uint64]),
     "ts_release": (C.c_int, [C.c_void_p, C.c_uint64]),
 }

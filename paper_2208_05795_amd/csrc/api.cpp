@@ -58,6 +58,28 @@ void ts_exec::dfree(void *p) {
     else (void)hipFree(p);
 }
 
+int ts_exec::stage(const void *src, size_t bytes, void **dev, int *slot) {
+    if (bytes > kJobSlotBytes) {
+        tsg::set_error("job descriptors exceed %zu bytes", kJobSlotBytes);
+        return TS_E_INVAL;
+    }
+    const int i = job_next;
+    job_next = (job_next + 1) % kJobSlots;
+    if (job_used[i]) TSG_HIP(hipEventSynchronize(job_ev[i]));   // its last launch has run
+    std::memcpy(job_host + (size_t)i * kJobSlotBytes, src, bytes);
+    TSG_HIP(hipMemcpyAsync(job_dev + (size_t)i * kJobSlotBytes, job_host + (size_t)i * kJobSlotBytes,
+                           bytes, hipMemcpyHostToDevice, stream));
+    *dev = job_dev + (size_t)i * kJobSlotBytes;
+    *slot = i;
+    return TS_OK;
+}
+
+void ts_exec::staged(int slot) {
+    if (slot < 0) return;
+    (void)hipEventRecord(job_ev[slot], stream);
+    job_used[slot] = true;
+}
+
 namespace {
 
 // RAII device buffer from an executor
@@ -70,6 +92,10 @@ struct DBuf {
     DBuf &operator=(const DBuf &) = delete;
     template <class T> T *as() { return (T *)p; }
 };
+
+}  // namespace
+
+namespace tsg {
 
 double sigma2_of(double ebn0_db, double rate) { return 1.0 / (2.0 * rate * std::pow(10.0, ebn0_db / 10.0)); }
 
@@ -89,9 +115,24 @@ int first_iter(const ts_code *code, const ts_search_opts *o) {
     return t0 < 1 ? 1 : t0;
 }
 
-}  // namespace
-
-namespace tsg {
+// Search launch parameters of opts that do not depend on buffers.
+void fill_search_launch(const ts_code *code, const ts_search_opts *o, int t0, int32_t width,
+                        SearchLaunch *a) {
+    const double h = 2.0 / sigma2_of(o->ebn0_db, o->rate);
+    a->code = &code->dev;
+    a->decoder = o->decoder;
+    a->max_iter = o->max_iter;
+    a->offset = o->oms_offset;
+    a->q_base = sat127(std::lround(o->llr_scale * h));
+    a->k_max = o->k_max;
+    a->k_den = o->k_den;
+    a->h = (float)h;
+    a->t0 = t0;
+    a->cap = 2 * o->a_max;
+    a->a_max = o->a_max;
+    a->extract_mode = o->extract_mode;
+    a->width = width;
+}
 
 size_t search_bytes_estimate(const ts_code *code, const ts_search_opts *o, int64_t P, int32_t width) {
     const int64_t cap = rec_capacity(o, first_iter(code, o), P, true, nullptr);
@@ -142,7 +183,7 @@ static int tune_shape(ts_exec &ex, const std::vector<SearchPlan> &cands,
         int rc = launch_fill(ex.stream, a.queue, 0, 2);
         if (rc) return rc;
         TSG_HIP(hipEventRecord(ex.ev[0], ex.stream));
-        rc = launch_search(ex.stream, p, a);
+        rc = launch_search(ex, p, a);
         if (rc) return rc;
         TSG_HIP(hipEventRecord(ex.ev[1], ex.stream));
         TSG_HIP(hipStreamSynchronize(ex.stream));
@@ -165,6 +206,43 @@ static size_t scratch_bytes(const SearchPlan &p, int64_t P) {
     return (size_t)std::min<int64_t>(p.grid, std::max<int64_t>(P, 1)) * p.slot_bytes;
 }
 
+// Candidate shapes of a search (restricted to the requested layout) and the
+// one to use: the autotuner's earlier choice for (decoder, iterations, layout),
+// else the first; need_tune when there is no choice yet and a probe is worth it.
+static int select_shape(ts_ctx *ctx, ts_code *code, const ts_search_opts *o, int64_t P,
+                        std::vector<SearchPlan> *shapes, SearchPlan *plan, bool *need_tune) {
+    int rc = plan_candidates(ctx, code, o->decoder, o->max_iter, shapes);
+    if (rc) return rc;
+    if (o->layout != TS_LAYOUT_AUTO) {
+        const int want = o->layout == TS_LAYOUT_REGISTER ? kPlanRegister : kPlanStreamed;
+        shapes->erase(std::remove_if(shapes->begin(), shapes->end(),
+                                     [&](const SearchPlan &p) { return p.kind != want; }),
+                      shapes->end());
+        if (shapes->empty()) {
+            set_error("the requested decoder layout does not fit this code");
+            return TS_E_INVAL;
+        }
+    }
+    *plan = shapes->front();
+    *need_tune = false;
+    const int tune_key = (o->layout * 2 + o->decoder) * 1000 + o->max_iter;
+    std::lock_guard<std::mutex> g(code->tune_mu);
+    auto it = code->tuned.find(tune_key);
+    if (it != code->tuned.end()) {
+        for (const SearchPlan &p : *shapes)
+            if (same_shape(p, it->second)) *plan = p;
+    } else {
+        *need_tune = shapes->size() > 1 && P >= 256;
+    }
+    return TS_OK;
+}
+
+int plan_search_shape(ts_exec &ex, ts_code *code, const ts_search_opts *o, int64_t P, SearchPlan *plan) {
+    std::vector<SearchPlan> shapes;
+    bool need_tune = false;
+    return select_shape(ex.ctx, code, o, P, &shapes, plan, &need_tune);
+}
+
 // Runs the search on device-resident patterns / outputs into `table`.  With
 // sieve = false no candidate is written (only k* and the iteration counts).
 int run_search(ts_exec &ex, ts_code *code, DevTable &table, const ts_search_opts *o,
@@ -172,39 +250,16 @@ int run_search(ts_exec &ex, ts_code *code, DevTable &table, const ts_search_opts
     ts_ctx *ctx = ex.ctx;
     hipStream_t s = ex.stream;
     std::vector<SearchPlan> shapes;
-    int rc = plan_candidates(ctx, code, o->decoder, o->max_iter, &shapes);
-    if (rc) return rc;
-    if (o->layout != TS_LAYOUT_AUTO) {
-        const int want = o->layout == TS_LAYOUT_REGISTER ? kPlanRegister : kPlanStreamed;
-        shapes.erase(std::remove_if(shapes.begin(), shapes.end(),
-                                    [&](const SearchPlan &p) { return p.kind != want; }),
-                     shapes.end());
-        if (shapes.empty()) {
-            set_error("the requested decoder layout does not fit this code");
-            return TS_E_INVAL;
-        }
-    }
-    SearchPlan plan = shapes.front();
-    const int tune_key = (o->layout * 2 + o->decoder) * 1000 + o->max_iter;
+    SearchPlan plan;
     bool need_tune = false;
-    {
-        std::lock_guard<std::mutex> g(code->tune_mu);
-        auto it = code->tuned.find(tune_key);
-        if (it != code->tuned.end()) {
-            for (const SearchPlan &p : shapes)
-                if (same_shape(p, it->second)) plan = p;
-        } else {
-            need_tune = shapes.size() > 1 && P >= 256;
-        }
-    }
+    const int tune_key = (o->layout * 2 + o->decoder) * 1000 + o->max_iter;
+    int rc = select_shape(ctx, code, o, P, &shapes, &plan, &need_tune);
+    if (rc) return rc;
     size_t scr_bytes = scratch_bytes(plan, P);
     if (need_tune)
         for (const SearchPlan &p : shapes) scr_bytes = std::max(scr_bytes, scratch_bytes(p, P));
     DBuf scratch(ex, scr_bytes);
     if (scr_bytes && !scratch.p) { set_error("device allocation of the decoder scratch failed"); return TS_E_NOMEM; }
-    const double s2 = sigma2_of(o->ebn0_db, o->rate);
-    const double h = 2.0 / s2;
-    const int q_base = sat127(std::lround(o->llr_scale * h));
     int t0 = first_iter(code, o);
     if (!sieve) t0 = o->max_iter + 1;   // no iteration qualifies: nothing is written
 
@@ -219,19 +274,7 @@ int run_search(ts_exec &ex, ts_code *code, DevTable &table, const ts_search_opts
     if (!recs.p) { set_error("device allocation of the candidate buffer failed"); return TS_E_NOMEM; }
 
     SearchLaunch a{};
-    a.code = &code->dev;
-    a.decoder = o->decoder;
-    a.max_iter = o->max_iter;
-    a.offset = o->oms_offset;
-    a.q_base = q_base;
-    a.k_max = o->k_max;
-    a.k_den = o->k_den;
-    a.h = (float)h;
-    a.t0 = t0;
-    a.cap = 2 * o->a_max;
-    a.a_max = o->a_max;
-    a.extract_mode = o->extract_mode;
-    a.width = width;
+    fill_search_launch(code, o, t0, width, &a);
     a.k_crit = d_out[0];
     a.iters_crit = d_out[1];
     a.iters_lo = d_out[2];
@@ -273,7 +316,7 @@ int run_search(ts_exec &ex, ts_code *code, DevTable &table, const ts_search_opts
         a.n_patterns = (int)len;
         a.pat_base = (int)pos;
         TSG_HIP(hipEventRecord(ex.ev[0], s));
-        rc = launch_search(s, plan, a);
+        rc = launch_search(ex, plan, a);
         if (rc) return rc;
         TSG_HIP(hipEventRecord(ex.ev[1], s));
         TSG_HIP(hipMemcpyAsync(ex.pinned, d_misc, 16, hipMemcpyDeviceToHost, s));
@@ -329,6 +372,58 @@ int run_search(ts_exec &ex, ts_code *code, DevTable &table, const ts_search_opts
     return TS_OK;
 }
 
+// eps* of the noiseless SPA impulse on the whole set (device bits d_t), grid
+// 2^-10 up to 32: the default mean shift of the IS frames.
+int is_eps_shift(ts_exec &ex, ts_code *code, const int32_t *d_t, int32_t a, const ts_is_opts *o,
+                 double *shift) {
+    hipStream_t s = ex.stream;
+    ts_search_opts so{};
+    so.decoder = TS_DEC_SPA_F32;
+    so.max_iter = o->max_iter;
+    so.ebn0_db = o->ebn0_db;
+    so.rate = o->rate;
+    so.llr_scale = 4.0;
+    so.k_max = 32 * 1024;
+    so.k_den = 1024;
+    so.a_max = 1;
+    so.extract_mode = TS_EXTRACT_CRITICAL;
+    so.collect_from_iter = -1;
+    so.mem = TS_MEM_DEVICE;
+    so.layout = o->layout;
+    DBuf outs(ex, 5 * 4);
+    if (!outs.p) return TS_E_NOMEM;
+    int32_t *d_out[5];
+    for (int i = 0; i < 5; ++i) d_out[i] = outs.as<int32_t>() + i;
+    DevTable none{};
+    int rc = run_search(ex, code, none, &so, d_t, 1, a, d_out, false);
+    if (rc) return rc;
+    TSG_HIP(hipMemcpyAsync(ex.pinned, d_out[0], 4, hipMemcpyDeviceToHost, s));
+    TSG_HIP(hipStreamSynchronize(s));
+    const int32_t kc = ex.pinned[0];
+    if (kc < 0) {
+        set_error("the impulse on the whole set never fails; give a shift");
+        return TS_E_INVAL;
+    }
+    *shift = kc / 1024.0;
+    return TS_OK;
+}
+
+// IS estimate from the fixed-order sums red = {sum w, sum w^2, failures,
+// sum (w - p)^2} of K frames.
+void is_fill_result(const double red[4], int64_t K, double shift, ts_is_result *res) {
+    const double p = red[0] / (double)K;
+    const double var = red[3] / ((double)K * (double)(K - 1));
+    res->p_hat = p;
+    res->var = var;
+    res->ci_lo = p - 1.96 * std::sqrt(var);
+    res->ci_hi = p + 1.96 * std::sqrt(var);
+    res->sum_w = red[0];
+    res->sum_w2 = red[1];
+    res->n = K;
+    res->n_fail = (int64_t)std::llround(red[2]);
+    res->shift_used = shift;
+}
+
 int check_is_opts(const ts_code *code, const int32_t *ts_bits, int32_t a, const ts_is_opts *o) {
     if (a < 1 || a > kMaxWidth || !ts_bits) { set_error("TS size must be 1..%d", kMaxWidth); return TS_E_INVAL; }
     if (o->n_frames < 2 || o->n_frames > (1ll << 31) - 1) { set_error("n_frames must be 2..2^31-1"); return TS_E_INVAL; }
@@ -358,35 +453,8 @@ int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const 
     if (!d_t.p) return TS_E_NOMEM;
     TSG_HIP(hipMemcpyAsync(d_t.p, t.data(), a * 4, hipMemcpyHostToDevice, s));
     if (shift < 0.0) {
-        // eps* of the noiseless SPA impulse on the whole set, grid 2^-10 up to 32
-        ts_search_opts so{};
-        so.decoder = TS_DEC_SPA_F32;
-        so.max_iter = o->max_iter;
-        so.ebn0_db = o->ebn0_db;
-        so.rate = o->rate;
-        so.llr_scale = 4.0;
-        so.k_max = 32 * 1024;
-        so.k_den = 1024;
-        so.a_max = 1;
-        so.extract_mode = TS_EXTRACT_CRITICAL;
-        so.collect_from_iter = -1;
-        so.mem = TS_MEM_DEVICE;
-        so.layout = o->layout;
-        DBuf outs(ex, 5 * 4);
-        if (!outs.p) return TS_E_NOMEM;
-        int32_t *d_out[5];
-        for (int i = 0; i < 5; ++i) d_out[i] = outs.as<int32_t>() + i;
-        DevTable none{};
-        int rc = run_search(ex, code, none, &so, d_t.as<int32_t>(), 1, a, d_out, false);
+        const int rc = is_eps_shift(ex, code, d_t.as<int32_t>(), a, o, &shift);
         if (rc) return rc;
-        TSG_HIP(hipMemcpyAsync(ex.pinned, d_out[0], 4, hipMemcpyDeviceToHost, s));
-        TSG_HIP(hipStreamSynchronize(s));
-        const int32_t kc = ex.pinned[0];
-        if (kc < 0) {
-            set_error("the impulse on the whole set never fails; give a shift");
-            return TS_E_INVAL;
-        }
-        shift = kc / 1024.0;
     }
     const int64_t K = o->n_frames;
     DBuf d_fail(ex, (size_t)K), d_wf(ex, (size_t)K * 8), d_misc(ex, 64 * 4), d_red(ex, 8 * 8);
@@ -406,7 +474,6 @@ int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const 
     L.a = a;
     L.fail = d_fail.as<unsigned char>();
     L.wf = d_wf.as<double>();
-    L.queue = d_misc.as<int>();
     L.counters = (unsigned long long *)(d_misc.as<int>() + 4);
     SearchPlan plan;
     rc = plan_is(ex.ctx, code, o->max_iter, o->layout, &plan);
@@ -415,8 +482,17 @@ int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const 
     DBuf scratch(ex, plan.kind == kPlanStreamed ? (size_t)grid * plan.slot_bytes : 0);
     if (plan.kind == kPlanStreamed && !scratch.p) { set_error("device allocation of the decoder scratch failed"); return TS_E_NOMEM; }
     L.gscr = plan.kind == kPlanStreamed ? scratch.as<unsigned char>() : nullptr;
+    IsJob job{};
+    job.a = make_is_dev(L, plan);
+    job.cd = code->dev;
+    job.item0 = 0;
+    void *dj = nullptr;
+    int slot = -1;
+    rc = ex.stage(&job, sizeof(job), &dj, &slot);
+    if (rc) return rc;
     TSG_HIP(hipEventRecord(ex.ev[0], s));
-    rc = launch_is(s, code, plan, L);
+    rc = launch_is_jobs(s, plan, (const IsJob *)dj, 1, d_misc.as<int>(), K);
+    ex.staged(slot);
     if (rc) return rc;
     TSG_HIP(hipEventRecord(ex.ev[1], s));
     rc = launch_is_reduce(s, L.wf, L.fail, K, 0, 0.0, d_red.as<double>());
@@ -439,16 +515,7 @@ int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const 
     float ms = 0.0f, tot = 0.0f;
     TSG_HIP(hipEventElapsedTime(&ms, ex.ev[0], ex.ev[1]));
     TSG_HIP(hipEventElapsedTime(&tot, ex.ev[0], ex.ev[2]));
-    const double var = red[3] / ((double)K * (double)(K - 1));
-    res->p_hat = p;
-    res->var = var;
-    res->ci_lo = p - 1.96 * std::sqrt(var);
-    res->ci_hi = p + 1.96 * std::sqrt(var);
-    res->sum_w = red[0];
-    res->sum_w2 = red[1];
-    res->n = K;
-    res->n_fail = (int64_t)std::llround(red[2]);
-    res->shift_used = shift;
+    is_fill_result(red, K, shift, res);
     ex.stats.decode_ms += ms;
     ex.stats.total_ms += tot;
     ex.stats.decodes += K;
@@ -477,6 +544,10 @@ int exec_init(ts_exec &ex, ts_ctx *ctx, hipStream_t stream, bool stream_alloc) {
     ex.stream_alloc = stream_alloc;
     for (auto &e : ex.ev) TSG_HIP(hipEventCreate(&e));
     TSG_HIP(hipHostMalloc((void **)&ex.pinned, 64 * sizeof(int), hipHostMallocDefault));
+    for (auto &e : ex.job_ev) TSG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    TSG_HIP(hipHostMalloc((void **)&ex.job_host, ts_exec::kJobSlots * ts_exec::kJobSlotBytes,
+                          hipHostMallocDefault));
+    TSG_HIP(hipMalloc((void **)&ex.job_dev, ts_exec::kJobSlots * ts_exec::kJobSlotBytes));
     return TS_OK;
 }
 
@@ -484,7 +555,19 @@ void exec_fini(ts_exec &ex) {
     if (ex.stream) (void)hipStreamSynchronize(ex.stream);
     for (auto &e : ex.ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto &e : ex.job_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (int i = 0; i < ts_exec::kSide; ++i) {
+        if (ex.side[i]) {
+            (void)hipStreamSynchronize(ex.side[i]);
+            (void)hipStreamDestroy(ex.side[i]);
+        }
+        if (ex.side_ev[i]) (void)hipEventDestroy(ex.side_ev[i]);
+    }
+    if (ex.join_ev) (void)hipEventDestroy(ex.join_ev);
     if (ex.pinned) (void)hipHostFree(ex.pinned);
+    if (ex.job_host) (void)hipHostFree(ex.job_host);
+    if (ex.job_dev) (void)hipFree(ex.job_dev);
     if (ex.own_stream && ex.stream) (void)hipStreamDestroy(ex.stream);
     ex = ts_exec{};
 }

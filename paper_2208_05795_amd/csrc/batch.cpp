@@ -1,0 +1,421 @@
+// Batched execution of several search and IS jobs, possibly on different codes.
+//
+// Every job is planned as if run alone (the code's autotuned shape, else the
+// first that fits).  Jobs whose plans name the same kernel and a workgroup size
+// in the same power-of-two bucket form a group; a group runs as ONE persistent
+// launch whose workgroups pull items (patterns or IS frames) of all its jobs
+// from a single queue, so small jobs fill the device together and no launch
+// tail or host round trip separates them.  Groups go to the executor's side
+// streams and overlap.  After one synchronisation the per-job candidate sieves
+// and IS reductions run, each job with its own TS table, so every result is the
+// one the job gives alone (a job whose candidate buffer overflows is re-run
+// alone).  All device buffers of the batch come from a single allocation.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <tuple>
+
+#include "internal.h"
+
+namespace tsg {
+
+int plan_search_shape(ts_exec &ex, ts_code *code, const ts_search_opts *o, int64_t P, SearchPlan *plan);
+
+namespace {
+
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int bucket(int block) {
+    int b = 64;
+    while (b < block) b <<= 1;
+    return b;
+}
+
+struct SItem {
+    BatchJob *b;
+    SearchPlan plan;
+    int t0 = 0;
+    int64_t P = 0, rec_cap = 0;
+    size_t pat = 0, out = 0, recs = 0, misc = 0;   // arena offsets; misc in the zeroed area
+    int group = -1;
+    SearchLaunch a{};
+};
+
+struct IItem {
+    BatchJob *b;
+    SearchPlan plan;
+    double shift = 0.0;
+    int64_t K = 0;
+    size_t ts = 0, fail = 0, wf = 0, red = 0, misc = 0;
+    int group = -1;
+    IsLaunch L{};
+};
+
+struct Group {
+    bool search = true;
+    SearchPlan plan{};
+    std::vector<int> members;
+    size_t queue = 0, jobs = 0, scratch = 0, scratch_bytes = 0;
+    long long n_items = 0;
+    double work = 0.0;
+};
+
+int ensure_side(ts_exec &ex) {
+    for (int i = 0; i < ts_exec::kSide; ++i) {
+        if (!ex.side[i]) TSG_HIP(hipStreamCreateWithFlags(&ex.side[i], hipStreamNonBlocking));
+        if (!ex.side_ev[i]) TSG_HIP(hipEventCreateWithFlags(&ex.side_ev[i], hipEventDisableTiming));
+    }
+    if (!ex.join_ev) TSG_HIP(hipEventCreateWithFlags(&ex.join_ev, hipEventDisableTiming));
+    return TS_OK;
+}
+
+}  // namespace
+
+int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
+    ts_ctx *ctx = ex.ctx;
+    hipStream_t s = ex.stream;
+    int rc = ensure_side(ex);
+    if (rc) return rc;
+    std::vector<SItem> S;
+    std::vector<IItem> I;
+    // ---- plan every job -------------------------------------------------
+    for (BatchJob &b : jobs) {
+        b.status = TS_OK;
+        b.edge_updates = 0;
+        if (b.kind == TS_JOB_SEARCH) {
+            if (b.n_patterns == 0) {
+                for (int i = 0; i < 5; ++i) b.out[i].clear();
+                b.recs->clear();
+                b.bits->clear();
+                continue;
+            }
+            SItem it;
+            it.b = &b;
+            it.P = b.n_patterns;
+            rc = plan_search_shape(ex, b.code, &b.so, it.P, &it.plan);
+            if (rc) return rc;
+            it.t0 = first_iter(b.code, &b.so);
+            it.rec_cap = std::min<int64_t>(rec_capacity(&b.so, it.t0, it.P, true, nullptr), 2 * it.P + 4096);
+            S.push_back(it);
+        } else {
+            IItem it;
+            it.b = &b;
+            it.K = b.io.n_frames;
+            it.shift = b.io.shift;
+            rc = plan_is(ctx, b.code, b.io.max_iter, b.io.layout, &it.plan);
+            if (rc) return rc;
+            I.push_back(it);
+        }
+    }
+    // eps* shifts (a one-pattern search each) before the batch
+    for (IItem &it : I) {
+        if (it.shift >= 0.0) continue;
+        std::vector<int32_t> t(it.b->ts_bits, it.b->ts_bits + it.b->a);
+        std::sort(t.begin(), t.end());
+        int32_t *d_t = (int32_t *)ex.dalloc(kMaxWidth * 4);
+        if (!d_t) { set_error("device allocation failed"); return TS_E_NOMEM; }
+        TSG_HIP(hipMemcpyAsync(d_t, t.data(), t.size() * 4, hipMemcpyHostToDevice, s));
+        rc = is_eps_shift(ex, it.b->code, d_t, it.b->a, &it.b->io, &it.shift);
+        ex.dfree(d_t);
+        if (rc) return rc;
+    }
+    // ---- groups -----------------------------------------------------------
+    std::vector<Group> G;
+    std::map<std::tuple<int, int, int, int, int, int>, int> gid;
+    auto group_of = [&](bool search, const SearchPlan &p) {
+        const auto key = std::make_tuple(search ? 1 : 0, p.kind, p.dc, p.cpt, p.decoder, bucket(p.block));
+        auto f = gid.find(key);
+        if (f != gid.end()) {
+            Group &g = G[f->second];
+            g.plan.block = std::max(g.plan.block, p.block);
+            g.plan.lds = std::max(g.plan.lds, p.lds);
+            g.plan.slot_bytes = std::max(g.plan.slot_bytes, p.slot_bytes);
+            return f->second;
+        }
+        Group g;
+        g.search = search;
+        g.plan = p;
+        G.push_back(g);
+        gid[key] = (int)G.size() - 1;
+        return (int)G.size() - 1;
+    };
+    for (size_t i = 0; i < S.size(); ++i) {
+        S[i].group = group_of(true, S[i].plan);
+        Group &g = G[S[i].group];
+        g.members.push_back((int)i);
+        g.n_items += S[i].P;
+        g.work += (double)S[i].P * S[i].b->code->e;
+    }
+    for (size_t i = 0; i < I.size(); ++i) {
+        I[i].group = group_of(false, I[i].plan);
+        Group &g = G[I[i].group];
+        g.members.push_back((int)i);
+        g.n_items += I[i].K;
+        g.work += (double)I[i].K * I[i].b->code->e * 8.0;
+    }
+    for (Group &g : G) {
+        if (g.n_items > INT_MAX) { set_error("too many items in one batch group"); return TS_E_INVAL; }
+        rc = occupancy_grid(ctx, g.plan, g.plan.decoder, g.search, &g.plan.grid);
+        if (rc) return rc;
+        const long long grid = std::min<long long>(g.plan.grid, g.n_items);
+        g.scratch_bytes = g.plan.kind == kPlanStreamed ? (size_t)grid * g.plan.slot_bytes : 0;
+    }
+    // ---- one arena: zeroed counters first, then the buffers ---------------
+    // per job 8 ints: [0] candidate count, [1] error flags, [4..7] two 64-bit
+    // counters (decodes, iterations); per group one queue counter
+    constexpr size_t kMisc = 32;
+    size_t zero = 0;
+    for (SItem &it : S) { it.misc = zero; zero += kMisc; }
+    for (IItem &it : I) { it.misc = zero; zero += kMisc; }
+    for (Group &g : G) { g.queue = zero; zero += kMisc; }
+    size_t o = al(zero);
+    for (SItem &it : S) {
+        it.pat = o; o = al(o + (size_t)it.P * it.b->width * 4);
+        it.out = o; o = al(o + (size_t)it.P * 5 * 4);
+        it.recs = o; o = al(o + (size_t)it.rec_cap * kRecStride * 4);
+    }
+    for (IItem &it : I) {
+        it.ts = o; o = al(o + kMaxWidth * 4);
+        it.fail = o; o = al(o + (size_t)it.K);
+        it.wf = o; o = al(o + (size_t)it.K * 8);
+        it.red = o; o = al(o + 8 * 8);
+    }
+    for (Group &g : G) {
+        g.jobs = o;
+        o = al(o + g.members.size() * (g.search ? sizeof(SearchJob) : sizeof(IsJob)));
+        g.scratch = o;
+        o = al(o + g.scratch_bytes);
+    }
+    if (o == 0) return TS_OK;
+    unsigned char *arena = (unsigned char *)ex.dalloc(o);
+    if (!arena) { set_error("device allocation of %zu bytes for the batch failed", o); return TS_E_NOMEM; }
+    struct Free {
+        ts_exec &ex;
+        void *p;
+        ~Free() { ex.dfree(p); }
+    } arena_guard{ex, arena};
+    rc = launch_fill(s, (int *)arena, 0, (int64_t)(zero / 4));
+    if (rc) return rc;
+    // ---- inputs and job descriptors ----------------------------------------
+    // Host sources of the uploads stay alive until the synchronisation below:
+    // an asynchronous copy from pageable memory may read them after it returns.
+    std::vector<std::vector<int32_t>> host_ts(I.size());
+    std::vector<std::vector<unsigned char>> host_jobs(G.size());
+    for (SItem &it : S) {
+        TSG_HIP(hipMemcpyAsync(arena + it.pat, it.b->patterns, (size_t)it.P * it.b->width * 4,
+                               hipMemcpyHostToDevice, s));
+        SearchLaunch &a = it.a;
+        fill_search_launch(it.b->code, &it.b->so, it.t0, it.b->width, &a);
+        int32_t *out = (int32_t *)(arena + it.out);
+        a.k_crit = out;
+        a.iters_crit = out + it.P;
+        a.iters_lo = out + 2 * it.P;
+        a.tmin_crit = out + 3 * it.P;
+        a.n_cand = out + 4 * it.P;
+        a.patterns = (const int *)(arena + it.pat);
+        a.n_patterns = (int)it.P;
+        a.pat_base = 0;
+        int *misc = (int *)(arena + it.misc);
+        a.queue = nullptr;
+        a.rec_count = misc;
+        a.err = misc + 1;
+        a.counters = (unsigned long long *)(misc + 4);
+        a.recs = (int *)(arena + it.recs);
+        a.rec_cap = (int)it.rec_cap;
+        const Group &g = G[it.group];
+        a.gscr = g.scratch_bytes ? arena + g.scratch : nullptr;
+        a.slot_bytes = (long long)g.plan.slot_bytes;
+        a.hist_off = (long long)it.plan.hist_off;
+    }
+    for (size_t ii = 0; ii < I.size(); ++ii) {
+        IItem &it = I[ii];
+        std::vector<int32_t> &t = host_ts[ii];
+        t.assign(it.b->ts_bits, it.b->ts_bits + it.b->a);
+        std::sort(t.begin(), t.end());
+        TSG_HIP(hipMemcpyAsync(arena + it.ts, t.data(), t.size() * 4, hipMemcpyHostToDevice, s));
+        IsLaunch &L = it.L;
+        L.code = &it.b->code->dev;
+        L.max_iter = it.b->io.max_iter;
+        L.sigma2 = sigma2_of(it.b->io.ebn0_db, it.b->io.rate);
+        L.shift = it.shift;
+        L.n_frames = it.K;
+        L.seed = it.b->io.seed;
+        L.frame_base = it.b->io.frame_base;
+        L.stream = it.b->io.stream;
+        L.ts = (const int *)(arena + it.ts);
+        L.a = it.b->a;
+        L.fail = arena + it.fail;
+        L.wf = (double *)(arena + it.wf);
+        L.counters = (unsigned long long *)(arena + it.misc + 16);
+        const Group &g = G[it.group];
+        L.gscr = g.scratch_bytes ? arena + g.scratch : nullptr;
+    }
+    for (size_t gi = 0; gi < G.size(); ++gi) {
+        Group &g = G[gi];
+        std::vector<unsigned char> &hj = host_jobs[gi];
+        long long item0 = 0;
+        for (int m : g.members) {
+            if (g.search) {
+                SearchJob j{};
+                j.a = S[m].a;
+                j.cd = S[m].b->code->dev;
+                j.item0 = item0;
+                item0 += S[m].P;
+                hj.insert(hj.end(), (unsigned char *)&j, (unsigned char *)&j + sizeof(j));
+            } else {
+                IsJob j{};
+                j.a = make_is_dev(I[m].L, I[m].plan);
+                j.a.slot_bytes = (long long)g.plan.slot_bytes;
+                j.cd = I[m].b->code->dev;
+                j.item0 = item0;
+                item0 += I[m].K;
+                hj.insert(hj.end(), (unsigned char *)&j, (unsigned char *)&j + sizeof(j));
+            }
+        }
+        TSG_HIP(hipMemcpyAsync(arena + g.jobs, hj.data(), hj.size(), hipMemcpyHostToDevice, s));
+    }
+    TSG_HIP(hipStreamSynchronize(s));
+    // ---- launches: largest groups first, spread over the side streams ------
+    std::vector<int> order(G.size());
+    for (size_t i = 0; i < G.size(); ++i) order[i] = (int)i;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return G[x].work > G[y].work; });
+    TSG_HIP(hipEventRecord(ex.ev[0], s));
+    TSG_HIP(hipEventRecord(ex.join_ev, s));
+    int used = 0;
+    for (size_t k = 0; k < order.size(); ++k) {
+        const Group &g = G[order[k]];
+        const int si = (int)(k % ts_exec::kSide);
+        hipStream_t st = ex.side[si];
+        if ((int)k < ts_exec::kSide) TSG_HIP(hipStreamWaitEvent(st, ex.join_ev, 0));
+        int *queue = (int *)(arena + g.queue);
+        if (g.search)
+            rc = launch_search_jobs(st, g.plan, (const SearchJob *)(arena + g.jobs), (int)g.members.size(),
+                                    queue, g.n_items);
+        else
+            rc = launch_is_jobs(st, g.plan, (const IsJob *)(arena + g.jobs), (int)g.members.size(), queue,
+                                g.n_items);
+        if (rc) return rc;
+        used = std::max(used, si + 1);
+    }
+    for (int i = 0; i < used; ++i) {
+        TSG_HIP(hipEventRecord(ex.side_ev[i], ex.side[i]));
+        TSG_HIP(hipStreamWaitEvent(s, ex.side_ev[i], 0));
+    }
+    TSG_HIP(hipEventRecord(ex.ev[1], s));
+    std::vector<int> zh(zero / 4);
+    if (zero) TSG_HIP(hipMemcpyAsync(zh.data(), arena, zero, hipMemcpyDeviceToHost, s));
+    TSG_HIP(hipStreamSynchronize(s));
+    float dec_ms = 0.0f;
+    TSG_HIP(hipEventElapsedTime(&dec_ms, ex.ev[0], ex.ev[1]));
+    ex.stats.decode_ms += dec_ms;
+    ex.stats.decode_launches += (int)G.size();
+    // ---- per search job: sieve into its own table, read out -----------------
+    std::vector<SItem *> rerun;
+    std::vector<DevTable> tables(S.size());
+    int64_t cands = 0;
+    for (size_t i = 0; i < S.size(); ++i) {
+        SItem &it = S[i];
+        const int *misc = zh.data() + it.misc / 4;
+        unsigned long long cnt[2];
+        std::memcpy(cnt, misc + 4, 16);
+        it.b->edge_updates = (int64_t)cnt[1] * it.b->code->e;
+        ex.stats.decodes += (int64_t)cnt[0];
+        ex.stats.edge_updates += it.b->edge_updates;
+        if (misc[1] & 1) {
+            it.b->status = TS_E_INVAL;
+            it.b->err = "pattern entry out of range";
+            continue;
+        }
+        const int64_t nrec = misc[0];
+        if (nrec > it.rec_cap) {
+            rerun.push_back(&it);
+            continue;
+        }
+        it.b->recs->clear();
+        it.b->bits->clear();
+        if (nrec > 0) {   // a table sized for the job's candidates (the read-out is sorted)
+            int cap = 1024;
+            while (cap < 4 * nrec && cap < (1 << 30)) cap <<= 1;
+            rc = table_init(ex, tables[i], cap);
+            if (rc) return rc;
+            cands += nrec;
+            rc = table_grow_if_needed(ex, tables[i], 2 * nrec);
+            if (rc) return rc;
+            rc = launch_sieve(ex, it.b->code->dev, tables[i], it.a, (int)nrec);
+            if (rc) return rc;
+            ex.stats.extract_launches++;
+        }
+        for (int k = 0; k < 5; ++k) {
+            it.b->out[k].resize((size_t)it.P);
+            TSG_HIP(hipMemcpyAsync(it.b->out[k].data(), arena + it.out + (size_t)k * it.P * 4,
+                                   (size_t)it.P * 4, hipMemcpyDeviceToHost, s));
+        }
+    }
+    ex.stats.candidates += cands;
+    // ---- per IS job: fixed-order reductions ----------------------------------
+    std::vector<double> red(I.size() * 4);
+    for (IItem &it : I) {
+        rc = launch_is_reduce(s, it.L.wf, it.L.fail, it.K, 0, 0.0, (double *)(arena + it.red));
+        if (rc) return rc;
+    }
+    for (size_t i = 0; i < I.size(); ++i)
+        TSG_HIP(hipMemcpyAsync(&red[4 * i], arena + I[i].red, 32, hipMemcpyDeviceToHost, s));
+    TSG_HIP(hipStreamSynchronize(s));
+    for (size_t i = 0; i < I.size(); ++i) {
+        rc = launch_is_reduce(s, I[i].L.wf, I[i].L.fail, I[i].K, 1, red[4 * i] / (double)I[i].K,
+                              (double *)(arena + I[i].red));
+        if (rc) return rc;
+    }
+    std::vector<double> red2(I.size() * 4);
+    for (size_t i = 0; i < I.size(); ++i)
+        TSG_HIP(hipMemcpyAsync(&red2[4 * i], arena + I[i].red, 32, hipMemcpyDeviceToHost, s));
+    TSG_HIP(hipStreamSynchronize(s));
+    for (size_t i = 0; i < I.size(); ++i) {
+        IItem &it = I[i];
+        double r[4] = {red[4 * i], red[4 * i + 1], red[4 * i + 2], red2[4 * i + 3]};
+        is_fill_result(r, it.K, it.shift, it.b->is);
+        const int *misc = zh.data() + it.misc / 4;
+        unsigned long long cnt[2];
+        std::memcpy(cnt, misc + 4, 16);
+        it.b->edge_updates = (int64_t)cnt[1] * it.b->code->e;
+        ex.stats.decodes += it.K;
+        ex.stats.edge_updates += it.b->edge_updates;
+    }
+    // ---- TS read-out ------------------------------------------------------
+    for (size_t i = 0; i < S.size(); ++i) {
+        SItem &it = S[i];
+        if (tables[i].cap && it.b->status == TS_OK) {
+            rc = collect_table(ex, tables[i], *it.b->recs, *it.b->bits);
+            if (rc) return rc;
+        }
+        table_free(ex, tables[i]);
+    }
+    // ---- jobs whose candidates overflowed the batch buffer run alone ---------
+    for (SItem *it : rerun) {
+        int32_t *d_pat = (int32_t *)(arena + it->pat);
+        int32_t *out = (int32_t *)(arena + it->out);
+        int32_t *d_out[5] = {out, out + it->P, out + 2 * it->P, out + 3 * it->P, out + 4 * it->P};
+        DevTable t{};
+        ts_search_opts so = it->b->so;
+        so.mem = TS_MEM_DEVICE;
+        const int64_t eu0 = ex.stats.edge_updates;
+        rc = run_search(ex, it->b->code, t, &so, d_pat, it->P, it->b->width, d_out, true);
+        if (rc == TS_OK) {
+            for (int k = 0; k < 5; ++k) {
+                it->b->out[k].resize((size_t)it->P);
+                TSG_HIP(hipMemcpyAsync(it->b->out[k].data(), d_out[k], (size_t)it->P * 4,
+                                       hipMemcpyDeviceToHost, s));
+            }
+            TSG_HIP(hipStreamSynchronize(s));
+            rc = collect_table(ex, t, *it->b->recs, *it->b->bits);
+        }
+        it->b->edge_updates = ex.stats.edge_updates - eu0;
+        table_free(ex, t);
+        if (rc) return rc;
+    }
+    TSG_HIP(hipStreamSynchronize(s));
+    return TS_OK;
+}
+
+}  // namespace tsg

@@ -102,9 +102,27 @@ struct ts_exec {
     hipEvent_t ev[6] = {};
     int *pinned = nullptr;       // host staging for small device -> host reads
     ts_stats stats{};
+    // job descriptors: a ring of pinned host slots copied to device slots; a
+    // slot is reused once the event recorded after its launch has completed
+    static constexpr int kJobSlots = 8;
+    static constexpr size_t kJobSlotBytes = 64 * 1024;
+    unsigned char *job_host = nullptr;
+    unsigned char *job_dev = nullptr;
+    hipEvent_t job_ev[kJobSlots] = {};
+    bool job_used[kJobSlots] = {};
+    int job_next = 0;
+    // side streams (default priority) for the concurrent launches of a batch
+    static constexpr int kSide = 4;
+    hipStream_t side[kSide] = {};
+    hipEvent_t side_ev[kSide] = {};
+    hipEvent_t join_ev = nullptr;
 
     void *dalloc(size_t bytes);
     void dfree(void *p);
+    // copies bytes (<= kJobSlotBytes) of job descriptors into a free slot; the
+    // caller launches with *dev and then calls staged(slot)
+    int stage(const void *src, size_t bytes, void **dev, int *slot);
+    void staged(int slot);
 };
 
 namespace tsg {
@@ -167,6 +185,7 @@ size_t table_bytes(int cap);
 enum PlanKind { kPlanRegister = 0, kPlanStreamed = 1 };
 struct SearchPlan {
     int kind;       // kPlanRegister: messages in registers; kPlanStreamed: in global memory
+    int decoder;    // TS_DEC_* of the kernel (search plans)
     int block;      // threads per workgroup
     int cpt;        // checks per thread (register kind)
     int dc;         // padded check degree of the kernel (streamed: largest class)
@@ -198,11 +217,46 @@ struct SearchLaunch {
 int plan_search(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter, SearchPlan *plan);
 int plan_candidates(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter,
                     std::vector<SearchPlan> *out);
-int launch_search(hipStream_t s, const SearchPlan &plan, const SearchLaunch &a);
+int launch_search(ts_exec &ex, const SearchPlan &plan, const SearchLaunch &a);
 size_t streamed_slot_bytes(const ts_code *c, int decoder, int max_iter, bool search, size_t *hist_off);
 int launch_sieve(ts_exec &ex, const DevCode &cd, const DevTable &t, const SearchLaunch &a,
                  int n_records);
 int launch_fill(hipStream_t s, int *p, int value, int64_t count);
+
+// Several jobs in one persistent launch: items (patterns or IS frames) of job j
+// are the indices [item0, item0 + count) of the launch's queue.  Kernels copy the
+// descriptor of the job they work on into LDS (kJobLds bytes at offset 0,
+// followed by kShLds bytes of scratch words and then the frame).
+struct SearchJob {
+    SearchLaunch a;
+    DevCode cd;
+    long long item0;
+};
+
+struct IsDev {
+    int max_iter;
+    double sigma2, sigma, shift, wconst;   // wconst = -a s^2 / (2 sigma^2)
+    long long n_frames;
+    unsigned long long seed, frame_base;
+    unsigned stream;
+    const int *ts;
+    int a;
+    unsigned char *fail;
+    double *wf;
+    unsigned long long *counters;
+    unsigned char *gscr;   // streamed kind: per-workgroup scratch
+    long long slot_bytes, lam_off;
+};
+
+struct IsJob {
+    IsDev a;
+    DevCode cd;
+    long long item0;
+};
+
+constexpr size_t kJobLds = ((sizeof(SearchJob) > sizeof(IsJob) ? sizeof(SearchJob) : sizeof(IsJob)) + 15) & ~(size_t)15;
+constexpr size_t kShLds = 32 * 4;
+constexpr size_t kHdrLds = kJobLds + kShLds;
 
 // importance sampling
 struct IsLaunch {
@@ -215,18 +269,32 @@ struct IsLaunch {
     const int *ts; int a;
     unsigned char *fail;    // [n_frames]
     double *wf;             // [n_frames]
-    int *queue;
     unsigned long long *counters;
     unsigned char *gscr;    // streamed kind: grid x slot_bytes scratch
 };
 // IS launch shape (streamed kind: plan.slot_bytes of scratch per workgroup)
 int plan_is(ts_ctx *ctx, const ts_code *c, int max_iter, int layout, SearchPlan *plan);
-int launch_is(hipStream_t s, const ts_code *c, const SearchPlan &plan, const IsLaunch &a);
+IsDev make_is_dev(const IsLaunch &a, const SearchPlan &plan);
+// One persistent launch over the items of n_jobs device-resident jobs that share
+// the plan's kernel and workgroup size (plan.lds and plan.grid cover them all).
+int launch_search_jobs(hipStream_t s, const SearchPlan &plan, const SearchJob *d_jobs, int n_jobs,
+                       int *queue, long long n_items);
+int launch_is_jobs(hipStream_t s, const SearchPlan &plan, const IsJob *d_jobs, int n_jobs,
+                   int *queue, long long n_items);
+int occupancy_grid(ts_ctx *ctx, const SearchPlan &plan, int decoder, bool search, int *grid);
 // mode 0: out[0..2] = sum w, sum w^2, failures; mode 1: out[3] = sum (w - mean)^2
 int launch_is_reduce(hipStream_t s, const double *wf, const unsigned char *fail, int64_t n, int mode,
                      double mean, double *out);
 
 // api.cpp: the work of one search / IS call on an executor
+double sigma2_of(double ebn0_db, double rate);
+int first_iter(const ts_code *code, const ts_search_opts *o);
+int64_t rec_capacity(const ts_search_opts *o, int t0, int64_t P, bool sieve, int64_t *worst);
+void fill_search_launch(const ts_code *code, const ts_search_opts *o, int t0, int32_t width,
+                        SearchLaunch *a);
+int is_eps_shift(ts_exec &ex, ts_code *code, const int32_t *d_t, int32_t a, const ts_is_opts *o,
+                 double *shift);
+void is_fill_result(const double red[4], int64_t K, double shift, ts_is_result *res);
 int check_search_opts(const ts_code *code, const ts_search_opts *o, int32_t width);
 int run_search(ts_exec &ex, ts_code *code, DevTable &table, const ts_search_opts *o,
                const int32_t *d_pat, int64_t P, int32_t width, int32_t *const d_out[5], bool sieve);
@@ -234,6 +302,29 @@ int check_is_opts(const ts_code *code, const int32_t *ts_bits, int32_t a, const 
 int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const ts_is_opts *o,
            ts_is_result *res, uint8_t *fail_out);
 size_t search_bytes_estimate(const ts_code *code, const ts_search_opts *o, int64_t P, int32_t width);
+
+// batch.cpp: several search / IS jobs run as one batch on an executor.  Jobs
+// that share a kernel shape share one persistent launch; launches of different
+// shapes run on the executor's side streams.  Results are those of each job
+// run alone.
+struct BatchJob {
+    int kind = 0;                          // TS_JOB_SEARCH / TS_JOB_IS
+    ts_code *code = nullptr;
+    ts_search_opts so{};
+    const int32_t *patterns = nullptr;     // host [n_patterns][width]
+    int32_t n_patterns = 0, width = 0;
+    ts_is_opts io{};
+    const int32_t *ts_bits = nullptr;      // host [a]
+    int32_t a = 0;
+    // results
+    std::vector<int32_t> *out = nullptr;   // [5] per-pattern outputs (search)
+    std::vector<int32_t> *recs = nullptr, *bits = nullptr;
+    ts_is_result *is = nullptr;
+    int64_t edge_updates = 0;
+    int status = TS_OK;
+    std::string err;
+};
+int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs);
 
 // serve.cpp
 struct Server;

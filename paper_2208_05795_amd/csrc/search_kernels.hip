@@ -70,6 +70,21 @@ __device__ __forceinline__ float phi_fast(float x) {
     return u < 0.0625f ? small : big;
 }
 
+// A value every lane of the wave holds (read from the LDS job copy), moved to
+// scalar registers so that addresses derived from it stay scalar.
+template <class T>
+__device__ __forceinline__ T uni(T v) {
+    static_assert(sizeof(T) % 4 == 0, "32-bit words");
+    union {
+        T t;
+        int w[sizeof(T) / 4];
+    } u;
+    u.t = v;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) u.w[i] = __builtin_amdgcn_readfirstlane(u.w[i]);
+    return u.t;
+}
+
 struct OmsRule {
     static constexpr int kDummy = 127;   // padded edges read as a saturated positive message
     template <int DC>
@@ -137,7 +152,7 @@ struct SpaRule {
 // Shared-memory layout of a frame (byte offsets).
 struct Lds {
     int np, W, T;
-    size_t lam, app, hist, imask, wsyn, pcnt, sh, extra, total;
+    size_t lam, app, hist, imask, wsyn, pcnt, extra, total;
 };
 
 __host__ __device__ inline Lds lds_layout(int n, int T, bool with_hist) {
@@ -159,8 +174,6 @@ __host__ __device__ inline Lds lds_layout(int n, int T, bool with_hist) {
     o += (size_t)(T + 2) * 4;
     L.pcnt = o;
     o += (size_t)(T + 2) * 4;
-    L.sh = o;
-    o += 32 * 4;
     o = (o + 15) & ~(size_t)15;
     L.extra = o;   // IS: Philox normals of the TS bits (doubles) and the TS bits
     o += (size_t)kMaxWidth * 8 + (size_t)kMaxWidth * 4;
@@ -347,26 +360,73 @@ struct MaxBlockIs {
     static constexpr int value = DC * CPT <= 8 ? 1024 : 256;
 };
 
+// Multi-job launches.  Thread 0 pops the next item of the launch and finds its
+// job by binary search on the jobs' first items; a workgroup that moves on to
+// another job copies that job's descriptor into the LDS header and rebinds its
+// decoder (neighbour registers, frame layout).
+template <class Job>
+__device__ __forceinline__ void pop_item(const Job *jobs, int n_jobs, int *queue, int *sh) {
+    if (threadIdx.x == 0) {
+        const int it = atomicAdd(queue, 1);
+        int lo = 0, hi = n_jobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].item0 <= (long long)it) lo = mid;
+            else hi = mid - 1;
+        }
+        sh[0] = it;
+        sh[1] = lo;
+    }
+}
+
+template <class Job>
+__device__ __forceinline__ void load_job(const Job *jobs, int j, unsigned char *smem) {
+    const int *src = (const int *)(jobs + j);
+    int *dst = (int *)smem;
+    for (int i = threadIdx.x; i < (int)(sizeof(Job) / 4); i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+}
+
 // Common part of the impulse-search kernels: the pattern queue, the bisection on
 // the impulse amplitude, the candidate write-out and the per-pattern results.
-// Dec::decode(K) runs one decode of the current pattern (impulse bits in imask)
-// at amplitude index K; Dec::hist() is its iteration history of hard decisions.
+// Dec::decode(K) runs one decode of the current pattern (impulse bits in
+// Dec::imask) at amplitude index K; Dec::hist() is its history of hard decisions.
 template <class Dec>
-__device__ __forceinline__ void search_patterns(const SearchLaunch &a, int n, int W, Dec &dec,
-                                                unsigned long long *imask, int *sh) {
+__device__ __forceinline__ void search_jobs(const SearchJob *jobs, int n_jobs, int *queue,
+                                            long long n_items, Dec &dec, unsigned char *smem) {
     const int B = blockDim.x, tid = threadIdx.x;
+    const SearchJob &J = *(const SearchJob *)smem;
+    const SearchLaunch &a = J.a;
+    int *sh = (int *)(smem + kJobLds);
+    unsigned char *frame = smem + kHdrLds;
+    int cur = -1;
     unsigned long long my_iters = 0, my_dec = 0;
     for (;;) {
         __syncthreads();
-        if (tid == 0) sh[0] = atomicAdd(a.queue, 1);
+        pop_item(jobs, n_jobs, queue, sh);
         __syncthreads();
-        const int pl = sh[0];
-        if (pl >= a.n_patterns) break;
+        const int it = sh[0], j = sh[1];
+        if ((long long)it >= n_items) break;
+        if (j != cur) {
+            if (cur >= 0 && tid == 0) {
+                atomicAdd(&a.counters[0], my_dec);
+                atomicAdd(&a.counters[1], my_iters);
+            }
+            my_iters = my_dec = 0;
+            __syncthreads();
+            load_job(jobs, j, smem);
+            dec.bind(J, frame);
+            __syncthreads();
+            cur = j;
+        }
+        const int n = J.cd.n, W = dec.W;
+        unsigned long long *imask = dec.imask;
+        const int pl = it - (int)J.item0;
         for (int i = tid; i < W; i += B) imask[i] = 0ull;
-        if (tid < kMaxWidth) sh[1 + tid] = tid < a.width ? a.patterns[(size_t)pl * a.width + tid] : -1;
+        if (tid < kMaxWidth) sh[2 + tid] = tid < a.width ? a.patterns[(size_t)pl * a.width + tid] : -1;
         __syncthreads();
         if (tid < kMaxWidth) {
-            const int v = sh[1 + tid];
+            const int v = sh[2 + tid];
             if (v >= n || v < -1) atomicOr(a.err, 1);
             else if (v >= 0) atomicOr(&imask[v >> 6], 1ull << (v & 63));
         }
@@ -406,7 +466,7 @@ __device__ __forceinline__ void search_patterns(const SearchLaunch &a, int n, in
             a.n_cand[pg] = 0;
         }
     }
-    if (tid == 0) {
+    if (cur >= 0 && tid == 0) {
         atomicAdd(&a.counters[0], my_dec);
         atomicAdd(&a.counters[1], my_iters);
     }
@@ -429,17 +489,35 @@ __device__ __forceinline__ int base_lambda(const SearchLaunch &a) {
 // of the checks a thread owns stay in its registers.
 template <class Rule, int DC, int CPT>
 struct RegSearchDec {
-    const SearchLaunch &a;
+    const SearchLaunch *a;
     Frame F;
-    const unsigned long long *imask;
+    unsigned long long *imask;
+    int W, offset;
     int nb[CPT][DC];
     int c2v[CPT][DC];
 
-    __device__ __forceinline__ RegSearchDec(const SearchLaunch &a_) : a(a_) {}
+    __device__ __forceinline__ void bind(const SearchJob &J, unsigned char *frame) {
+        a = &J.a;
+        const int n = uni(J.cd.n), T = uni(J.a.max_iter);
+        const Lds L = lds_layout(n, T, true);
+        F.lam = (int *)(frame + L.lam);
+        F.app = (int *)(frame + L.app);
+        F.hist = (unsigned long long *)(frame + L.hist);
+        F.wsyn = (int *)(frame + L.wsyn);
+        F.pcnt = (int *)(frame + L.pcnt);
+        F.n = n;
+        F.np = L.np;
+        F.W = L.W;
+        F.T = T;
+        imask = (unsigned long long *)(frame + L.imask);
+        W = L.W;
+        offset = uni(J.a.offset);
+        load_neighbours<DC, CPT>(J.cd, nb);
+    }
 
     __device__ __forceinline__ DecRes decode(int K) {
         const int B = blockDim.x, tid = threadIdx.x, n = F.n, np = F.np;
-        const int li = impulse_lambda<Rule>(a, K), lb = base_lambda<Rule>(a);
+        const int li = impulse_lambda<Rule>(*a, K), lb = base_lambda<Rule>(*a);
         __syncthreads();
         for (int v = tid; v < np; v += B) {
             int l = v == n ? Rule::kDummy : 0;
@@ -453,30 +531,17 @@ struct RegSearchDec {
             F.pcnt[i] = 0;
         }
         __syncthreads();
-        return run_decode<Rule, DC, CPT>(F, nb, c2v, a.offset);
+        return run_decode<Rule, DC, CPT>(F, nb, c2v, offset);
     }
     __device__ __forceinline__ const unsigned long long *hist() const { return F.hist; }
 };
 
 template <class Rule, int DC, int CPT>
-__global__ __launch_bounds__((MaxBlock<DC, CPT>::value)) void k_search(SearchLaunch a, DevCode cd) {
+__global__ __launch_bounds__((MaxBlock<DC, CPT>::value)) void k_search(const SearchJob *jobs, int n_jobs,
+                                                                      int *queue, long long n_items) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int n = cd.n, T = a.max_iter;
-    const Lds L = lds_layout(n, T, true);
-    RegSearchDec<Rule, DC, CPT> dec(a);
-    dec.F.lam = (int *)(smem + L.lam);
-    dec.F.app = (int *)(smem + L.app);
-    dec.F.hist = (unsigned long long *)(smem + L.hist);
-    dec.F.wsyn = (int *)(smem + L.wsyn);
-    dec.F.pcnt = (int *)(smem + L.pcnt);
-    dec.F.n = n;
-    dec.F.np = L.np;
-    dec.F.W = L.W;
-    dec.F.T = T;
-    unsigned long long *imask = (unsigned long long *)(smem + L.imask);
-    dec.imask = imask;
-    load_neighbours<DC, CPT>(cd, dec.nb);
-    search_patterns(a, n, L.W, dec, imask, (int *)(smem + L.sh));
+    RegSearchDec<Rule, DC, CPT> dec;
+    search_jobs(jobs, n_jobs, queue, n_items, dec, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -502,35 +567,39 @@ __device__ __forceinline__ void philox4x32_10(unsigned c[4], unsigned k0, unsign
     }
 }
 
-struct IsDev {
-    int max_iter;
-    double sigma2, sigma, shift, wconst;   // wconst = -a s^2 / (2 sigma^2)
-    long long n_frames;
-    unsigned long long seed, frame_base;
-    unsigned stream;
-    const int *ts;
+// Channel parameters of the IS frames of one job (scalar copies).
+struct IsChan {
+    unsigned k0, k1, stream;
     int a;
-    unsigned char *fail;
-    double *wf;
-    int *queue;
-    unsigned long long *counters;
-    unsigned char *gscr;   // streamed kind: per-workgroup scratch
-    long long slot_bytes, lam_off;
+    double shift, sigma, sigma2;
+    unsigned long long frame_base;
 };
+
+__device__ __forceinline__ IsChan is_chan(const IsDev &d) {
+    IsChan c;
+    c.k0 = uni((unsigned)d.seed);
+    c.k1 = uni((unsigned)(d.seed >> 32));
+    c.stream = uni(d.stream);
+    c.a = uni(d.a);
+    c.shift = uni(d.shift);
+    c.sigma = uni(d.sigma);
+    c.sigma2 = uni(d.sigma2);
+    c.frame_base = uni(d.frame_base);
+    return c;
+}
 
 // Channel of IS frame `frame` (Section II, mean-shifted noise on the TS bits):
 // y_v = 1 - s [v in T] + sigma n_v with n_v from Philox4x32-10 at counter
 // (v >> 2, frame, stream) and Box-Muller, lambda_v = 2 y_v / sigma^2 in Q20.
 // put(v, lambda) stores the values; the normals of the TS bits go to tn.
 template <class Put>
-__device__ __forceinline__ void is_channel(const IsDev &a, int n, unsigned long long frame,
+__device__ __forceinline__ void is_channel(const IsChan &a, int n, unsigned long long frame,
                                            const int *tsl, double *tn, Put put) {
     const int B = blockDim.x, tid = threadIdx.x;
-    const unsigned k0 = (unsigned)a.seed, k1 = (unsigned)(a.seed >> 32);
     const double two_pi = 6.283185307179586476925286766559;
     for (int g = tid; 4 * g < n; g += B) {
         unsigned c[4] = {(unsigned)g, (unsigned)frame, (unsigned)(frame >> 32), a.stream};
-        philox4x32_10(c, k0, k1);
+        philox4x32_10(c, a.k0, a.k1);
         double u[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) u[i] = ((double)c[i] + 0.5) * 0x1p-32;
@@ -563,38 +632,72 @@ __device__ __forceinline__ void is_finish(const IsDev &a, int f, const DecRes &r
     a.wf[f] = r.fail ? w : 0.0;
 }
 
-template <int DC, int CPT>
-__global__ __launch_bounds__((MaxBlockIs<DC, CPT>::value)) void k_is(IsDev a, DevCode cd) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int n = cd.n, T = a.max_iter;
-    const Lds L = lds_layout(n, T, false);
-    const int np = L.np;
-    Frame F;
-    F.lam = (int *)(smem + L.lam);
-    F.app = (int *)(smem + L.app);
-    F.hist = nullptr;
-    F.wsyn = (int *)(smem + L.wsyn);
-    F.pcnt = (int *)(smem + L.pcnt);
-    F.n = n;
-    F.np = np;
-    F.W = L.W;
-    F.T = T;
-    int *sh = (int *)(smem + L.sh);
-    double *tn = (double *)(smem + L.extra);
-    int *tsl = (int *)(tn + kMaxWidth);
-    const int B = blockDim.x, tid = threadIdx.x;
-
-    int nb[CPT][DC];
-    load_neighbours<DC, CPT>(cd, nb);
-    int c2v[CPT][DC];
-    if (tid < kMaxWidth) tsl[tid] = tid < a.a ? a.ts[tid] : -1;
+// Common part of the IS kernels: the frame queue over the launch's jobs and
+// the per-frame weights.  Dec::decode_frame(f) builds frame f's channel and
+// decodes it; Dec::tn holds the normals of the TS bits.
+template <class Dec>
+__device__ __forceinline__ void is_jobs(const IsJob *jobs, int n_jobs, int *queue, long long n_items,
+                                        Dec &dec, unsigned char *smem) {
+    const int tid = threadIdx.x;
+    const IsJob &J = *(const IsJob *)smem;
+    int *sh = (int *)(smem + kJobLds);
+    unsigned char *frame = smem + kHdrLds;
+    int cur = -1;
     unsigned long long my_iters = 0;
     for (;;) {
         __syncthreads();
-        if (tid == 0) sh[0] = atomicAdd(a.queue, 1);
+        pop_item(jobs, n_jobs, queue, sh);
         __syncthreads();
-        const int f = sh[0];
-        if ((long long)f >= a.n_frames) break;
+        const int it = sh[0], j = sh[1];
+        if ((long long)it >= n_items) break;
+        if (j != cur) {
+            if (cur >= 0 && tid == 0) atomicAdd(&J.a.counters[1], my_iters);
+            my_iters = 0;
+            __syncthreads();
+            load_job(jobs, j, smem);
+            dec.bind(J, frame);
+            __syncthreads();
+            cur = j;
+        }
+        const int f = it - (int)J.item0;
+        const DecRes r = dec.decode_frame(f);
+        my_iters += r.iters;
+        if (tid == 0) is_finish(J.a, f, r, dec.tn);
+    }
+    if (cur >= 0 && tid == 0) atomicAdd(&J.a.counters[1], my_iters);
+}
+
+template <int DC, int CPT>
+struct RegIsDec {
+    IsChan a;
+    Frame F;
+    double *tn;
+    int *tsl;
+    int nb[CPT][DC];
+    int c2v[CPT][DC];
+
+    __device__ __forceinline__ void bind(const IsJob &J, unsigned char *frame) {
+        a = is_chan(J.a);
+        const int n = uni(J.cd.n), T = uni(J.a.max_iter);
+        const Lds L = lds_layout(n, T, false);
+        F.lam = (int *)(frame + L.lam);
+        F.app = (int *)(frame + L.app);
+        F.hist = nullptr;
+        F.wsyn = (int *)(frame + L.wsyn);
+        F.pcnt = (int *)(frame + L.pcnt);
+        F.n = n;
+        F.np = L.np;
+        F.W = L.W;
+        F.T = T;
+        tn = (double *)(frame + L.extra);
+        tsl = (int *)(tn + kMaxWidth);
+        const int tid = threadIdx.x;
+        if (tid < kMaxWidth) tsl[tid] = tid < J.a.a ? J.a.ts[tid] : -1;
+        load_neighbours<DC, CPT>(J.cd, nb);
+    }
+
+    __device__ __forceinline__ DecRes decode_frame(int f) {
+        const int B = blockDim.x, tid = threadIdx.x, n = F.n, np = F.np;
         is_channel(a, n, a.frame_base + (unsigned long long)f, tsl, tn, [&](int v, int l) {
             F.lam[v] = l;
             F.app[v] = l;
@@ -605,16 +708,21 @@ __global__ __launch_bounds__((MaxBlockIs<DC, CPT>::value)) void k_is(IsDev a, De
             F.app[v] = 0;
             F.app[np + v] = 0;
         }
-        for (int i = tid; i < T + 2; i += B) {
+        for (int i = tid; i < F.T + 2; i += B) {
             F.wsyn[i] = 0;
             F.pcnt[i] = 0;
         }
         __syncthreads();
-        const DecRes r = run_decode<SpaRule, DC, CPT>(F, nb, c2v, 0);
-        my_iters += r.iters;
-        if (tid == 0) is_finish(a, f, r, tn);
+        return run_decode<SpaRule, DC, CPT>(F, nb, c2v, 0);
     }
-    if (tid == 0) atomicAdd(&a.counters[1], my_iters);
+};
+
+template <int DC, int CPT>
+__global__ __launch_bounds__((MaxBlockIs<DC, CPT>::value)) void k_is(const IsJob *jobs, int n_jobs,
+                                                                    int *queue, long long n_items) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    RegIsDec<DC, CPT> dec;
+    is_jobs(jobs, n_jobs, queue, n_items, dec, smem);
 }
 
 // Fixed-order reduction of the per-frame values: thread t sums a contiguous
@@ -684,7 +792,7 @@ __global__ void k_fill(int *p, int value, long long count) {
 // decoder, so both give identical results.
 struct LdsG {
     int np, W;
-    size_t app, imask, wsyn, pcnt, sh, cls, extra, total;
+    size_t app, imask, wsyn, pcnt, cls, extra, total;
 };
 
 __host__ __device__ inline LdsG lds_layout_g(int n, int T) {
@@ -701,8 +809,6 @@ __host__ __device__ inline LdsG lds_layout_g(int n, int T) {
     o += (size_t)(T + 2) * 4;
     L.pcnt = o;
     o += (size_t)(T + 2) * 4;
-    L.sh = o;
-    o += 32 * 4;
     L.cls = o;   // class table: dc, c0, stride, off
     o += (size_t)(4 * kGMaxCls + 2) * 4;
     o = (o + 15) & ~(size_t)15;
@@ -721,7 +827,8 @@ struct GFrame {
     unsigned long long *hist;          // global [T][W] or nullptr
     int *wsyn, *pcnt;                  // LDS
     const int *cdc, *cc0, *cstr, *coff;   // LDS copy of the class table
-    int ncls, n, np, W, T;
+    const int *g_cn, *g_vslot;         // the code's slot tables
+    int ncls, n, np, W, T, m, dv_pad, n_tab;
 };
 
 __device__ __forceinline__ int g_lambda(const GFrame &F, int v) {
@@ -732,14 +839,13 @@ __device__ __forceinline__ int g_lambda(const GFrame &F, int v) {
 // Check pass of one check (sorted position p, class q); returns the parity of
 // the hard decisions of APP_{t-1} on its variables.
 template <class Rule, int DC, class M>
-__device__ __forceinline__ int check_g(const DevCode &cd, const GFrame &F, int q, int p, int t,
-                                       int offset) {
+__device__ __forceinline__ int check_g(const GFrame &F, int q, int p, int t, int offset) {
     const int stride = F.cstr[q];
     const size_t base = (size_t)F.coff[q] + (size_t)(p - F.cc0[q]);
     int nb[DC], val[DC], c2v[DC];
 #pragma unroll
     for (int j = 0; j < DC; ++j) {
-        nb[j] = cd.g_cn[base + (size_t)j * stride];
+        nb[j] = F.g_cn[base + (size_t)j * stride];
         val[j] = F.app[nb[j]];
     }
     int par = 0;
@@ -759,8 +865,8 @@ __device__ __forceinline__ int check_g(const DevCode &cd, const GFrame &F, int q
 // One decode of a streamed frame.  On entry APP (LDS) holds the channel values
 // (slot n: the padding value), wsyn/pcnt are zero, all threads passed a barrier.
 template <class Rule, int DCMAX, class M>
-__device__ DecRes run_decode_g(const DevCode &cd, const GFrame &F, int offset) {
-    const int n = F.n, W = F.W, T = F.T, mm = cd.m;
+__device__ DecRes run_decode_g(const GFrame &F, int offset) {
+    const int n = F.n, W = F.W, T = F.T, mm = F.m;
     const int B = blockDim.x, NW = B >> 6;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const M *msg = (const M *)F.msg;
@@ -774,7 +880,7 @@ __device__ DecRes run_decode_g(const DevCode &cd, const GFrame &F, int offset) {
 #define TSG_GCASE(D)                                                             \
     case D:                                                                      \
         if constexpr (D <= DCMAX && !(DCMAX == 32 && D == 24))                   \
-            par = check_g<Rule, D, M>(cd, F, q, p, t, offset);                   \
+            par = check_g<Rule, D, M>(F, q, p, t, offset);                       \
         break;
                 TSG_GCASE(3) TSG_GCASE(4) TSG_GCASE(6) TSG_GCASE(8)
                 TSG_GCASE(12) TSG_GCASE(16) TSG_GCASE(24) TSG_GCASE(32)
@@ -806,8 +912,8 @@ __device__ DecRes run_decode_g(const DevCode &cd, const GFrame &F, int offset) {
             int x = 0;
             if (v < n) {
                 int sum = g_lambda(F, v);
-                for (int k = 0; k < cd.dv_pad; ++k) {
-                    const int e = cd.g_vslot[(size_t)k * cd.n_tab + v];
+                for (int k = 0; k < F.dv_pad; ++k) {
+                    const int e = F.g_vslot[(size_t)k * F.n_tab + v];
                     if (e >= 0) sum += (int)msg[e];
                 }
                 F.app[v] = sum;
@@ -827,9 +933,14 @@ __device__ DecRes run_decode_g(const DevCode &cd, const GFrame &F, int offset) {
     return r;
 }
 
-__device__ __forceinline__ void g_load_classes(const DevCode &cd, unsigned char *smem, const LdsG &L,
-                                               GFrame &F) {
-    int *cls = (int *)(smem + L.cls);
+// Binds a streamed frame to a job: LDS regions, the workgroup's scratch slot,
+// the code's tables and an LDS copy of its class table.
+__device__ __forceinline__ void g_bind(const DevCode &cd, int T, unsigned char *frame,
+                                       unsigned char *slot, GFrame &F, LdsG &L) {
+    const int n = uni(cd.n);
+    T = uni(T);
+    L = lds_layout_g(n, T);
+    int *cls = (int *)(frame + L.cls);
     const int tid = threadIdx.x;
     if (tid < kGMaxCls) {
         cls[tid] = cd.g_dc[tid];
@@ -843,20 +954,46 @@ __device__ __forceinline__ void g_load_classes(const DevCode &cd, unsigned char 
     F.cc0 = cls + kGMaxCls;
     F.cstr = cls + 2 * kGMaxCls + 1;
     F.coff = cls + 3 * kGMaxCls + 1;
-    F.ncls = cd.g_ncls;
+    F.ncls = uni(cd.g_ncls);
+    F.g_cn = uni(cd.g_cn);
+    F.g_vslot = uni(cd.g_vslot);
+    F.m = uni(cd.m);
+    F.dv_pad = uni(cd.dv_pad);
+    F.n_tab = uni(cd.n_tab);
+    F.app = (int *)(frame + L.app);
+    F.wsyn = (int *)(frame + L.wsyn);
+    F.pcnt = (int *)(frame + L.pcnt);
+    F.msg = uni(slot);
+    F.n = n;
+    F.np = L.np;
+    F.W = L.W;
+    F.T = T;
 }
 
 template <class Rule, int DCMAX, class M>
 struct GSearchDec {
-    const SearchLaunch &a;
-    const DevCode &cd;
+    const SearchLaunch *a;
     GFrame F;
+    unsigned long long *imask;
+    int W;
 
-    __device__ __forceinline__ GSearchDec(const SearchLaunch &a_, const DevCode &cd_) : a(a_), cd(cd_) {}
+    __device__ __forceinline__ void bind(const SearchJob &J, unsigned char *frame) {
+        a = &J.a;
+        unsigned char *slot = J.a.gscr + (size_t)blockIdx.x * J.a.slot_bytes;
+        LdsG L;
+        g_bind(J.cd, J.a.max_iter, frame, slot, F, L);
+        imask = (unsigned long long *)(frame + L.imask);
+        W = L.W;
+        F.imask = imask;
+        F.lam_g = nullptr;
+        F.lam_base = base_lambda<Rule>(J.a);
+        F.lam_imp = F.lam_base;
+        F.hist = (unsigned long long *)(slot + J.a.hist_off);
+    }
 
     __device__ __forceinline__ DecRes decode(int K) {
         const int B = blockDim.x, tid = threadIdx.x, n = F.n;
-        F.lam_imp = impulse_lambda<Rule>(a, K);
+        F.lam_imp = impulse_lambda<Rule>(*a, K);
         __syncthreads();
         for (int v = tid; v < F.np; v += B) F.app[v] = v < n ? g_lambda(F, v) : Rule::kDummy;
         for (int i = tid; i < F.T + 2; i += B) {
@@ -864,7 +1001,7 @@ struct GSearchDec {
             F.pcnt[i] = 0;
         }
         __syncthreads();
-        return run_decode_g<Rule, DCMAX, M>(cd, F, a.offset);
+        return run_decode_g<Rule, DCMAX, M>(F, a->offset);
     }
     __device__ __forceinline__ const unsigned long long *hist() const { return F.hist; }
 };
@@ -874,88 +1011,69 @@ template <int DCMAX> struct MaxBlockG { static constexpr int value = DCMAX <= 16
 template <int DCMAX> struct MaxBlockGIs { static constexpr int value = 512; };
 
 template <class Rule, int DCMAX>
-__global__ __launch_bounds__((MaxBlockG<DCMAX>::value)) void k_search_g(SearchLaunch a, DevCode cd) {
+__global__ __launch_bounds__((MaxBlockG<DCMAX>::value)) void k_search_g(const SearchJob *jobs, int n_jobs,
+                                                                       int *queue, long long n_items) {
     typedef typename std::conditional<Rule::kDummy == OmsRule::kDummy, signed char, int>::type M;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int n = cd.n, T = a.max_iter;
-    const LdsG L = lds_layout_g(n, T);
-    GSearchDec<Rule, DCMAX, M> dec(a, cd);
-    GFrame &F = dec.F;
-    unsigned long long *imask = (unsigned long long *)(smem + L.imask);
-    unsigned char *slot = a.gscr + (size_t)blockIdx.x * a.slot_bytes;
-    F.app = (int *)(smem + L.app);
-    F.imask = imask;
-    F.lam_g = nullptr;
-    F.lam_base = base_lambda<Rule>(a);
-    F.lam_imp = F.lam_base;
-    F.msg = slot;
-    F.hist = (unsigned long long *)(slot + a.hist_off);
-    F.wsyn = (int *)(smem + L.wsyn);
-    F.pcnt = (int *)(smem + L.pcnt);
-    F.n = n;
-    F.np = L.np;
-    F.W = L.W;
-    F.T = T;
-    g_load_classes(cd, smem, L, F);
-    search_patterns(a, n, L.W, dec, imask, (int *)(smem + L.sh));
+    GSearchDec<Rule, DCMAX, M> dec;
+    search_jobs(jobs, n_jobs, queue, n_items, dec, smem);
 }
 
 template <int DCMAX>
-__global__ __launch_bounds__((MaxBlockGIs<DCMAX>::value)) void k_is_g(IsDev a, DevCode cd) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int n = cd.n, T = a.max_iter;
-    const LdsG L = lds_layout_g(n, T);
-    const int np = L.np;
-    unsigned char *slot = a.gscr + (size_t)blockIdx.x * a.slot_bytes;
-    int *lam = (int *)(slot + a.lam_off);
+struct GIsDec {
+    IsChan a;
     GFrame F;
-    F.app = (int *)(smem + L.app);
-    F.imask = nullptr;
-    F.lam_g = lam;
-    F.lam_base = F.lam_imp = 0;
-    F.msg = slot;
-    F.hist = nullptr;
-    F.wsyn = (int *)(smem + L.wsyn);
-    F.pcnt = (int *)(smem + L.pcnt);
-    F.n = n;
-    F.np = np;
-    F.W = L.W;
-    F.T = T;
-    g_load_classes(cd, smem, L, F);
-    int *sh = (int *)(smem + L.sh);
-    double *tn = (double *)(smem + L.extra);
-    int *tsl = (int *)(tn + kMaxWidth);
-    const int B = blockDim.x, tid = threadIdx.x;
-    if (tid < kMaxWidth) tsl[tid] = tid < a.a ? a.ts[tid] : -1;
-    unsigned long long my_iters = 0;
-    for (;;) {
-        __syncthreads();
-        if (tid == 0) sh[0] = atomicAdd(a.queue, 1);
-        __syncthreads();
-        const int f = sh[0];
-        if ((long long)f >= a.n_frames) break;
+    int *lam;
+    double *tn;
+    int *tsl;
+
+    __device__ __forceinline__ void bind(const IsJob &J, unsigned char *frame) {
+        a = is_chan(J.a);
+        unsigned char *slot = J.a.gscr + (size_t)blockIdx.x * J.a.slot_bytes;
+        LdsG L;
+        g_bind(J.cd, J.a.max_iter, frame, slot, F, L);
+        lam = uni((int *)(slot + J.a.lam_off));
+        F.imask = nullptr;
+        F.lam_g = lam;
+        F.lam_base = F.lam_imp = 0;
+        F.hist = nullptr;
+        tn = (double *)(frame + L.extra);
+        tsl = (int *)(tn + kMaxWidth);
+        const int tid = threadIdx.x;
+        if (tid < kMaxWidth) tsl[tid] = tid < J.a.a ? J.a.ts[tid] : -1;
+    }
+
+    __device__ __forceinline__ DecRes decode_frame(int f) {
+        const int B = blockDim.x, tid = threadIdx.x, n = F.n;
+        int *lm = lam;
+        int *app = F.app;
         is_channel(a, n, a.frame_base + (unsigned long long)f, tsl, tn, [&](int v, int l) {
-            lam[v] = l;
-            F.app[v] = l;
+            lm[v] = l;
+            app[v] = l;
         });
-        for (int v = n + tid; v < np; v += B) F.app[v] = SpaRule::kDummy;
-        for (int i = tid; i < T + 2; i += B) {
+        for (int v = n + tid; v < F.np; v += B) F.app[v] = SpaRule::kDummy;
+        for (int i = tid; i < F.T + 2; i += B) {
             F.wsyn[i] = 0;
             F.pcnt[i] = 0;
         }
         __syncthreads();
-        const DecRes r = run_decode_g<SpaRule, DCMAX, int>(cd, F, 0);
-        my_iters += r.iters;
-        if (tid == 0) is_finish(a, f, r, tn);
+        return run_decode_g<SpaRule, DCMAX, int>(F, 0);
     }
-    if (tid == 0) atomicAdd(&a.counters[1], my_iters);
+};
+
+template <int DCMAX>
+__global__ __launch_bounds__((MaxBlockGIs<DCMAX>::value)) void k_is_g(const IsJob *jobs, int n_jobs,
+                                                                     int *queue, long long n_items) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    GIsDec<DCMAX> dec;
+    is_jobs(jobs, n_jobs, queue, n_items, dec, smem);
 }
 
 // ---------------------------------------------------------------------------
 // kernel table
 // ---------------------------------------------------------------------------
-typedef void (*SearchKernel)(SearchLaunch, DevCode);
-typedef void (*IsKernel)(IsDev, DevCode);
+typedef void (*SearchKernel)(const SearchJob *, int, int *, long long);
+typedef void (*IsKernel)(const IsJob *, int, int *, long long);
 
 struct KEntry {
     int dc, cpt, max_block, is_max_block;
@@ -1010,8 +1128,8 @@ int streamed_dcmax(const ts_code *c) { return c->dc_max <= 16 ? 16 : (c->dc_max 
 int add_streamed_plans(ts_ctx *ctx, const ts_code *c, bool search, int decoder, int max_iter,
                        std::vector<SearchPlan> *out) {
     const GEntry *g = find_g(streamed_dcmax(c));
-    const LdsG L = lds_layout_g(c->n, max_iter);
-    if (!g || L.total > ctx->lds_per_block) return TS_OK;
+    const size_t lds = kHdrLds + lds_layout_g(c->n, max_iter).total;
+    if (!g || lds > ctx->lds_per_block) return TS_OK;
     size_t aux = 0;
     const size_t slot = streamed_slot_bytes(c, decoder, max_iter, search, &aux);
     const void *kern = search ? (const void *)(decoder == TS_DEC_OMS_I8 ? g->oms : g->spa)
@@ -1019,14 +1137,15 @@ int add_streamed_plans(ts_ctx *ctx, const ts_code *c, bool search, int decoder, 
     for (int block : {256, 512, 1024}) {
         if (block > (search ? g->max_block : g->is_max_block)) continue;
         int per_cu = 0;
-        TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, L.total));
+        TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds));
         if (per_cu < 1) continue;
         SearchPlan p;
         p.kind = kPlanStreamed;
+        p.decoder = decoder;
         p.block = block;
         p.cpt = 0;
         p.dc = g->dcmax;
-        p.lds = L.total;
+        p.lds = lds;
         p.grid = per_cu * ctx->num_cu;
         p.slot_bytes = slot;
         p.hist_off = aux;
@@ -1053,8 +1172,8 @@ int plan_candidates(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter,
     out->clear();
     const int dc = padded_degree(c);
     if (!dc) return TS_E_INVAL;
-    const Lds L = lds_layout(c->n, max_iter, true);
-    if (L.total <= ctx->lds_per_block) {
+    const size_t lds = kHdrLds + lds_layout(c->n, max_iter, true).total;
+    if (lds <= ctx->lds_per_block) {
         for (int cp : {1, 2, 4, 8}) {
             const KEntry *ke = find_kernel(dc, cp);
             if (!ke) continue;
@@ -1062,14 +1181,15 @@ int plan_candidates(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter,
             if (block > ke->max_block) continue;
             SearchKernel kern = decoder == TS_DEC_OMS_I8 ? ke->oms : ke->spa;
             int per_cu = 0;
-            TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, block, L.total));
+            TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, block, lds));
             if (per_cu < 1) continue;
             SearchPlan p;
             p.kind = kPlanRegister;
+            p.decoder = decoder;
             p.block = block;
             p.cpt = cp;
             p.dc = dc;
-            p.lds = L.total;
+            p.lds = lds;
             p.grid = per_cu * ctx->num_cu;
             p.slot_bytes = 0;
             p.hist_off = 0;
@@ -1093,31 +1213,102 @@ int plan_search(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter, Search
     return TS_OK;
 }
 
-int launch_search(hipStream_t stream, const SearchPlan &plan, const SearchLaunch &a0) {
-    SearchKernel kern = nullptr;
-    SearchLaunch a = a0;
+static SearchKernel search_kernel(const SearchPlan &plan, int decoder) {
     if (plan.kind == kPlanRegister) {
         const KEntry *ke = find_kernel(plan.dc, plan.cpt);
-        if (ke) kern = a.decoder == TS_DEC_OMS_I8 ? ke->oms : ke->spa;
-    } else {
-        const GEntry *g = find_g(plan.dc);
-        if (g) kern = a.decoder == TS_DEC_OMS_I8 ? g->oms : g->spa;
-        if (!a.gscr) {
-            set_error("streamed launch without scratch");
-            return TS_E_INVAL;
-        }
-        a.slot_bytes = (long long)plan.slot_bytes;
-        a.hist_off = (long long)plan.hist_off;
+        return ke ? (decoder == TS_DEC_OMS_I8 ? ke->oms : ke->spa) : nullptr;
     }
+    const GEntry *g = find_g(plan.dc);
+    return g ? (decoder == TS_DEC_OMS_I8 ? g->oms : g->spa) : nullptr;
+}
+
+static IsKernel is_kernel(const SearchPlan &plan) {
+    if (plan.kind == kPlanRegister) {
+        const KEntry *k = find_kernel(plan.dc, plan.cpt);
+        return k ? k->is : nullptr;
+    }
+    const GEntry *g = find_g(plan.dc);
+    return g ? g->is : nullptr;
+}
+
+int occupancy_grid(ts_ctx *ctx, const SearchPlan &plan, int decoder, bool search, int *grid) {
+    const void *kern = search ? (const void *)search_kernel(plan, decoder) : (const void *)is_kernel(plan);
     if (!kern) {
         set_error("no kernel for kind %d dc %d cpt %d", plan.kind, plan.dc, plan.cpt);
         return TS_E_INVAL;
     }
-    const int grid = a.n_patterns < plan.grid ? a.n_patterns : plan.grid;
-    if (grid <= 0) return TS_OK;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(plan.block), plan.lds, stream, a, *a.code);
+    int per_cu = 0;
+    TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, plan.block, plan.lds));
+    if (per_cu < 1) {
+        set_error("kernel does not fit on a compute unit (block %d, %zu bytes of LDS)", plan.block, plan.lds);
+        return TS_E_INVAL;
+    }
+    *grid = per_cu * ctx->num_cu;
+    return TS_OK;
+}
+
+int launch_search_jobs(hipStream_t stream, const SearchPlan &plan, const SearchJob *d_jobs, int n_jobs,
+                       int *queue, long long n_items) {
+    if (n_items <= 0 || n_jobs <= 0) return TS_OK;
+    if (n_items > INT_MAX) {
+        set_error("too many items in one launch");
+        return TS_E_INVAL;
+    }
+    SearchKernel kern = search_kernel(plan, plan.decoder);
+    if (!kern) {
+        set_error("no kernel for kind %d dc %d cpt %d", plan.kind, plan.dc, plan.cpt);
+        return TS_E_INVAL;
+    }
+    const long long grid = n_items < plan.grid ? n_items : plan.grid;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(plan.block), plan.lds, stream, d_jobs, n_jobs,
+                       queue, n_items);
     TSG_HIP(hipGetLastError());
     return TS_OK;
+}
+
+int launch_is_jobs(hipStream_t stream, const SearchPlan &plan, const IsJob *d_jobs, int n_jobs,
+                   int *queue, long long n_items) {
+    if (n_items <= 0 || n_jobs <= 0) return TS_OK;
+    if (n_items > INT_MAX) {
+        set_error("too many items in one launch");
+        return TS_E_INVAL;
+    }
+    IsKernel kern = is_kernel(plan);
+    if (!kern) {
+        set_error("no IS kernel for kind %d dc %d cpt %d", plan.kind, plan.dc, plan.cpt);
+        return TS_E_INVAL;
+    }
+    const long long grid = n_items < plan.grid ? n_items : plan.grid;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(plan.block), plan.lds, stream, d_jobs, n_jobs,
+                       queue, n_items);
+    TSG_HIP(hipGetLastError());
+    return TS_OK;
+}
+
+// One job: its descriptor goes through the executor's staging ring.
+int launch_search(ts_exec &ex, const SearchPlan &plan0, const SearchLaunch &a) {
+    SearchPlan plan = plan0;
+    plan.decoder = a.decoder;
+    SearchJob j{};
+    j.a = a;
+    j.cd = *a.code;
+    j.item0 = 0;
+    if (plan.kind == kPlanStreamed) {
+        if (!a.gscr) {
+            set_error("streamed launch without scratch");
+            return TS_E_INVAL;
+        }
+        j.a.slot_bytes = (long long)plan.slot_bytes;
+        j.a.hist_off = (long long)plan.hist_off;
+    }
+    if (a.n_patterns <= 0) return TS_OK;
+    void *dj = nullptr;
+    int slot = -1;
+    int rc = ex.stage(&j, sizeof(j), &dj, &slot);
+    if (rc) return rc;
+    rc = launch_search_jobs(ex.stream, plan, (const SearchJob *)dj, 1, a.queue, a.n_patterns);
+    ex.staged(slot);
+    return rc;
 }
 
 int launch_fill(hipStream_t stream, int *p, int value, int64_t count) {
@@ -1135,21 +1326,22 @@ int launch_fill(hipStream_t stream, int *p, int value, int64_t count) {
 int plan_is(ts_ctx *ctx, const ts_code *c, int max_iter, int layout, SearchPlan *plan) {
     const int dc = padded_degree(c);
     if (!dc) return TS_E_INVAL;
-    const Lds L = lds_layout(c->n, max_iter, false);
-    if (L.total <= ctx->lds_per_block && layout != TS_LAYOUT_STREAMED) {
+    const size_t lds = kHdrLds + lds_layout(c->n, max_iter, false).total;
+    if (lds <= ctx->lds_per_block && layout != TS_LAYOUT_STREAMED) {
         for (int cp : {1, 2, 4, 8}) {
             const KEntry *k = find_kernel(dc, cp);
             if (!k) continue;
             const int b = ((c->m + cp - 1) / cp + 63) / 64 * 64;
             if (b > k->is_max_block) continue;
             int per_cu = 0;
-            TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k->is, b, L.total));
+            TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k->is, b, lds));
             if (per_cu < 1) continue;
             plan->kind = kPlanRegister;
+            plan->decoder = TS_DEC_SPA_F32;
             plan->block = b;
             plan->cpt = cp;
             plan->dc = dc;
-            plan->lds = L.total;
+            plan->lds = lds;
             plan->grid = per_cu * ctx->num_cu;
             plan->slot_bytes = plan->hist_off = 0;
             return TS_OK;
@@ -1172,26 +1364,8 @@ int plan_is(ts_ctx *ctx, const ts_code *c, int max_iter, int layout, SearchPlan 
     return TS_OK;
 }
 
-int launch_is(hipStream_t stream, const ts_code *c, const SearchPlan &plan, const IsLaunch &a) {
-    IsKernel kern = nullptr;
-    if (plan.kind == kPlanRegister) {
-        const KEntry *k = find_kernel(plan.dc, plan.cpt);
-        if (k) kern = k->is;
-    } else {
-        const GEntry *g = find_g(plan.dc);
-        if (g) kern = g->is;
-        if (!a.gscr) {
-            set_error("streamed launch without scratch");
-            return TS_E_INVAL;
-        }
-    }
-    if (!kern) {
-        set_error("no IS kernel for kind %d dc %d cpt %d", plan.kind, plan.dc, plan.cpt);
-        return TS_E_INVAL;
-    }
-    long long grid = plan.grid;
-    if (grid > a.n_frames) grid = a.n_frames;
-    IsDev d;
+IsDev make_is_dev(const IsLaunch &a, const SearchPlan &plan) {
+    IsDev d{};
     d.max_iter = a.max_iter;
     d.sigma2 = a.sigma2;
     d.sigma = std::sqrt(a.sigma2);
@@ -1205,14 +1379,11 @@ int launch_is(hipStream_t stream, const ts_code *c, const SearchPlan &plan, cons
     d.a = a.a;
     d.fail = a.fail;
     d.wf = a.wf;
-    d.queue = a.queue;
     d.counters = a.counters;
     d.gscr = a.gscr;
     d.slot_bytes = (long long)plan.slot_bytes;
     d.lam_off = (long long)plan.hist_off;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(plan.block), plan.lds, stream, d, c->dev);
-    TSG_HIP(hipGetLastError());
-    return TS_OK;
+    return d;
 }
 
 int launch_is_reduce(hipStream_t stream, const double *wf, const unsigned char *fail, int64_t n, int mode,

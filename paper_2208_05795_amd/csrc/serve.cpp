@@ -56,6 +56,8 @@ struct Server {
 
 namespace {
 
+void run_jobs(ts_exec &ex, std::vector<Job *> &js);
+
 int run_job(ts_exec &ex, Job *j) {
     ex.stats = ts_stats{};
     if (j->kind == TS_JOB_IS) {
@@ -104,42 +106,54 @@ int run_job(ts_exec &ex, Job *j) {
     return rc;
 }
 
+// A worker takes the first queued job that fits in what the running batches
+// leave of the budget, together with every further queued job that fits beside
+// it (first fit, up to kMaxBatch), and runs them as one batch.  Jobs that arrive
+// meanwhile go to the next free worker, whose batch overlaps on the device.
+constexpr int kMaxBatch = 32;
+
 void worker_main(Server *s, ts_exec *ex) {
     (void)hipSetDevice(s->ctx->device);
     for (;;) {
-        Job *j = nullptr;
+        std::vector<Job *> js;
+        size_t est = 0;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             for (;;) {
                 if (s->stop) return;
-                auto it = std::find_if(s->queue.begin(), s->queue.end(), [&](Job *q) {
-                    return s->in_use + q->est <= s->budget;
-                });
-                if (it != s->queue.end()) {
-                    j = *it;
-                    s->queue.erase(it);
-                    break;
+                for (auto it = s->queue.begin(); it != s->queue.end() && (int)js.size() < kMaxBatch;) {
+                    if (s->in_use + est + (*it)->est <= s->budget) {
+                        est += (*it)->est;
+                        js.push_back(*it);
+                        it = s->queue.erase(it);
+                    } else {
+                        ++it;
+                    }
                 }
+                if (!js.empty()) break;
                 s->cv_work.wait(lk);
             }
-            s->in_use += j->est;
-            j->state = TS_JOB_RUNNING;
-            j->t_start = now_ms();
+            s->in_use += est;
+            const double t = now_ms();
+            for (Job *j : js) {
+                j->state = TS_JOB_RUNNING;
+                j->t_start = t;
+            }
         }
-        clear_error();
-        const int rc = run_job(*ex, j);
+        run_jobs(*ex, js);
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            s->in_use -= j->est;
-            j->t_end = now_ms();
-            j->code->jobs_in_flight--;
-            if (j->cancel_req) {
-                j->state = TS_JOB_CANCELLED;
-                j->status = TS_E_CANCELLED;
-            } else {
-                j->state = TS_JOB_DONE;
-                j->status = rc;
-                if (rc != TS_OK) j->err = last_error_copy();
+            s->in_use -= est;
+            const double t = now_ms();
+            for (Job *j : js) {
+                j->t_end = t;
+                j->code->jobs_in_flight--;
+                if (j->cancel_req) {
+                    j->state = TS_JOB_CANCELLED;
+                    j->status = TS_E_CANCELLED;
+                } else {
+                    j->state = TS_JOB_DONE;
+                }
             }
         }
         s->cv_done.notify_all();
@@ -182,6 +196,88 @@ int server_get(ts_ctx *ctx, int slots, Server **out) {
 Job *find_job(Server *s, uint64_t id) {
     auto it = s->jobs.find(id);
     return it == s->jobs.end() ? nullptr : it->second;
+}
+
+// Validates a job description and copies its inputs.
+int make_job(ts_ctx *ctx, const ts_job_desc *d, Job **out) {
+    if (!d->code) { set_error("null code"); return TS_E_INVAL; }
+    if (d->code->ctx != ctx) { set_error("code belongs to another context"); return TS_E_STATE; }
+    Job *j = new Job();
+    j->kind = d->kind;
+    j->code = d->code;
+    if (d->kind == TS_JOB_SEARCH) {
+        int rc = check_search_opts(d->code, &d->search, d->width);
+        if (rc) { delete j; return rc; }
+        if (d->search.mem != TS_MEM_HOST) { delete j; set_error("submitted jobs take host arrays"); return TS_E_INVAL; }
+        if (d->n_patterns < 0 || (d->n_patterns > 0 && !d->patterns)) { delete j; set_error("bad patterns"); return TS_E_INVAL; }
+        const size_t cnt = (size_t)d->n_patterns * d->width;
+        for (size_t i = 0; i < cnt; ++i)
+            if (d->patterns[i] < -1 || d->patterns[i] >= d->code->n) {
+                delete j;
+                set_error("pattern entry %d out of range", d->patterns[i]);
+                return TS_E_INVAL;
+            }
+        j->so = d->search;
+        j->patterns.assign(d->patterns, d->patterns + cnt);
+        j->n_patterns = d->n_patterns;
+        j->width = d->width;
+        j->est = search_bytes_estimate(d->code, &d->search, d->n_patterns, d->width) * 5 / 4;
+    } else if (d->kind == TS_JOB_IS) {
+        int rc = check_is_opts(d->code, d->ts_bits, d->a, &d->is);
+        if (rc) { delete j; return rc; }
+        j->io = d->is;
+        j->ts_bits.assign(d->ts_bits, d->ts_bits + d->a);
+        j->est = (size_t)d->is.n_frames * 9 + (1 << 20);
+        SearchPlan ip;
+        if (plan_is(ctx, d->code, d->is.max_iter, d->is.layout, &ip) == TS_OK && ip.kind == kPlanStreamed)
+            j->est += (size_t)std::min<int64_t>(ip.grid, d->is.n_frames) * ip.slot_bytes;
+    } else {
+        delete j;
+        set_error("unknown job kind %d", d->kind);
+        return TS_E_INVAL;
+    }
+    *out = j;
+    return TS_OK;
+}
+
+BatchJob batch_view(Job *j) {
+    BatchJob b;
+    b.kind = j->kind;
+    b.code = j->code;
+    b.so = j->so;
+    b.patterns = j->patterns.data();
+    b.n_patterns = j->n_patterns;
+    b.width = j->width;
+    b.io = j->io;
+    b.ts_bits = j->ts_bits.data();
+    b.a = (int32_t)j->ts_bits.size();
+    b.out = j->out;
+    b.recs = &j->recs;
+    b.bits = &j->bits;
+    b.is = &j->is;
+    return b;
+}
+
+// Runs jobs as one batch; each job's status and results are filled in.
+void run_jobs(ts_exec &ex, std::vector<Job *> &js) {
+    if (js.size() == 1) {
+        clear_error();
+        const int rc = run_job(ex, js[0]);
+        js[0]->status = rc;
+        if (rc != TS_OK) js[0]->err = last_error_copy();
+        return;
+    }
+    std::vector<BatchJob> v;
+    for (Job *j : js) v.push_back(batch_view(j));
+    ex.stats = ts_stats{};
+    clear_error();
+    const int rc = run_batch(ex, v);
+    const std::string err = rc != TS_OK ? last_error_copy() : std::string();
+    for (size_t i = 0; i < js.size(); ++i) {
+        js[i]->edge_updates = v[i].edge_updates;
+        js[i]->status = rc != TS_OK ? rc : v[i].status;
+        js[i]->err = rc != TS_OK ? err : v[i].err;
+    }
 }
 
 }  // namespace
@@ -227,42 +323,10 @@ int ts_serve_start(ts_ctx *ctx, int32_t slots) {
 
 int ts_submit(ts_ctx *ctx, const ts_job_desc *d, uint64_t *job_id) {
     clear_error();
-    if (!ctx || !d || !job_id || !d->code) { set_error("null argument"); return TS_E_INVAL; }
-    if (d->code->ctx != ctx) { set_error("code belongs to another context"); return TS_E_STATE; }
-    Job *j = new Job();
-    j->kind = d->kind;
-    j->code = d->code;
-    if (d->kind == TS_JOB_SEARCH) {
-        int rc = check_search_opts(d->code, &d->search, d->width);
-        if (rc) { delete j; return rc; }
-        if (d->search.mem != TS_MEM_HOST) { delete j; set_error("submitted jobs take host arrays"); return TS_E_INVAL; }
-        if (d->n_patterns < 0 || (d->n_patterns > 0 && !d->patterns)) { delete j; set_error("bad patterns"); return TS_E_INVAL; }
-        const size_t cnt = (size_t)d->n_patterns * d->width;
-        for (size_t i = 0; i < cnt; ++i)
-            if (d->patterns[i] < -1 || d->patterns[i] >= d->code->n) {
-                delete j;
-                set_error("pattern entry %d out of range", d->patterns[i]);
-                return TS_E_INVAL;
-            }
-        j->so = d->search;
-        j->patterns.assign(d->patterns, d->patterns + cnt);
-        j->n_patterns = d->n_patterns;
-        j->width = d->width;
-        j->est = search_bytes_estimate(d->code, &d->search, d->n_patterns, d->width) * 5 / 4;
-    } else if (d->kind == TS_JOB_IS) {
-        int rc = check_is_opts(d->code, d->ts_bits, d->a, &d->is);
-        if (rc) { delete j; return rc; }
-        j->io = d->is;
-        j->ts_bits.assign(d->ts_bits, d->ts_bits + d->a);
-        j->est = (size_t)d->is.n_frames * 9 + (1 << 20);
-        SearchPlan ip;
-        if (plan_is(ctx, d->code, d->is.max_iter, d->is.layout, &ip) == TS_OK && ip.kind == kPlanStreamed)
-            j->est += (size_t)std::min<int64_t>(ip.grid, d->is.n_frames) * ip.slot_bytes;
-    } else {
-        delete j;
-        set_error("unknown job kind %d", d->kind);
-        return TS_E_INVAL;
-    }
+    if (!ctx || !d || !job_id) { set_error("null argument"); return TS_E_INVAL; }
+    Job *j = nullptr;
+    int rc0 = make_job(ctx, d, &j);
+    if (rc0) return rc0;
     Server *s = nullptr;
     int rc = server_get(ctx, 4, &s);
     if (rc) { delete j; return rc; }
@@ -281,6 +345,51 @@ int ts_submit(ts_ctx *ctx, const ts_job_desc *d, uint64_t *job_id) {
         *job_id = j->id;
     }
     s->cv_work.notify_one();
+    return TS_OK;
+}
+
+int ts_run_batch(ts_ctx *ctx, const ts_job_desc *jobs, int32_t n_jobs, uint64_t *job_ids) {
+    clear_error();
+    if (!ctx || n_jobs < 0 || (n_jobs > 0 && (!jobs || !job_ids))) { set_error("bad arguments"); return TS_E_INVAL; }
+    if (n_jobs > 4096) { set_error("at most 4096 jobs per batch"); return TS_E_INVAL; }
+    std::vector<Job *> js;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        Job *j = nullptr;
+        const int rc = make_job(ctx, &jobs[i], &j);
+        if (rc) {
+            for (Job *q : js) delete q;
+            return rc;
+        }
+        js.push_back(j);
+    }
+    Server *s = nullptr;
+    int rc = server_get(ctx, 4, &s);
+    if (rc) {
+        for (Job *q : js) delete q;
+        return rc;
+    }
+    const double t0 = now_ms();
+    {
+        std::lock_guard<std::recursive_mutex> g(ctx->mu);
+        for (Job *j : js) {
+            j->t_submit = j->t_start = t0;
+            j->state = TS_JOB_RUNNING;
+        }
+        if (!js.empty()) run_jobs(ctx->main, js);
+    }
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        const double t1 = now_ms();
+        for (int32_t i = 0; i < n_jobs; ++i) {
+            Job *j = js[i];
+            j->t_end = t1;
+            j->state = TS_JOB_DONE;
+            j->id = s->next_id++;
+            s->jobs[j->id] = j;
+            job_ids[i] = j->id;
+        }
+    }
+    s->cv_done.notify_all();
     return TS_OK;
 }
 
