@@ -8,6 +8,19 @@ bisecting the impulse amplitude and sieving/deduplicating TS up to a = 12; then
 importance sampling (float32 SPA, 50 iterations, 3 dB) of the four most harmful
 TS found, 10^4 frames each.  Inputs are resident on the device before timing.
 
+Beside it, with their own figures in the same JSON line:
+  batched  - 64 QC codes of uneven size (bases 3x6/4x8/3x12/4x24, Z 16..384,
+             N 96..9216), each with 4096 impulse patterns (OMS-i8, 20 it.) and
+             16384 IS frames (SPA-f32, 50 it., 3 dB, s = 1 on the shortest cycle
+             through variable 0): every job alone versus all 128 in one batch
+             (ts_run_batch), results checked identical;
+  served   - a Poisson stream (20 jobs/s) of search and IS jobs on 46x68-base QC
+             codes (N up to 25.7k), 10^3..10^5 frames each (log-uniform),
+             through ts_submit: p50/p99 latency and edge-updates/s;
+  qc2640   - the (2640,1320) girth-8 QC stand-in: every tree-path triple
+             searched with SPA, then IS of the 16 most harmful TS at 2/3/4/5 dB,
+             10^5 frames each.
+
 Prints one JSON line.  The metric is edge-updates per second (one edge x one
 frame x one executed iteration), with TS found per second beside it.
 """
@@ -50,6 +63,13 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=20.0)
     p.add_argument("--calib-copy", action="store_true",
                    help="copy 1 GiB once before timing (reference for HBM byte counters)")
+    p.add_argument("--no-batch", action="store_true")
+    p.add_argument("--no-serve", action="store_true")
+    p.add_argument("--no-qc2640", action="store_true")
+    p.add_argument("--only", choices=["batch", "serve", "qc2640"],
+                   help="run only this section (profiling aid); prints its JSON object")
+    p.add_argument("--serve-seconds", type=float, default=10.0)
+    p.add_argument("--serve-rate", type=float, default=20.0)
     return p.parse_args()
 
 
@@ -63,6 +83,13 @@ def main():
 
     import paper_2208_05795_amd as tsg
     import workloads
+
+    if args.only:
+        fn = {"batch": lambda: bench_batch(tsg),
+              "serve": lambda: bench_serve(tsg, args.serve_seconds, args.serve_rate),
+              "qc2640": lambda: bench_qc2640(tsg)}[args.only]
+        print(json.dumps({args.only: fn()}), flush=True)
+        return
 
     code = workloads.peg1008_code()
     ctx = tsg.Context(0)
@@ -162,10 +189,285 @@ def main():
         "phases": phases,
         "roofline": roofline,
     }
+    ctx.close()
+    del pats
+    if not args.no_batch:
+        line["batched"] = bench_batch(tsg)
+    if not args.no_serve:
+        line["served"] = bench_serve(tsg, args.serve_seconds, args.serve_rate)
+    if not args.no_qc2640:
+        line["qc2640"] = bench_qc2640(tsg)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(code, pats_host, args.cpu_seconds)
-    ctx.close()
     print(json.dumps(line), flush=True)
+
+
+def _say(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def var_checks(rp, col, n):
+    """Checks of every variable, from the check-major CSR."""
+    import numpy as np
+    m = len(rp) - 1
+    rows = np.repeat(np.arange(m), np.diff(rp))
+    order = np.argsort(col, kind="stable")
+    vptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(vptr, col.astype(np.int64) + 1, 1)
+    return np.cumsum(vptr), rows[order]
+
+
+def shortest_cycle_vns(graph, v0):
+    """Variables of a shortest Tanner-graph cycle through variable v0 (BFS with
+    one branch label per neighbouring check of v0).  graph = (rp, col, vptr,
+    vchk, n)."""
+    rp, col, vptr, vchk, n = graph
+    parent = {v0: -1}
+    branch = {v0: -1}
+    dist = {v0: 0}
+    frontier = [v0]
+    best = None
+    while frontier and best is None:
+        nxt = []
+        for u in frontier:
+            if u < n:
+                nbrs = [int(c) + n for c in vchk[vptr[u]:vptr[u + 1]]]
+            else:
+                nbrs = [int(v) for v in col[rp[u - n]:rp[u - n + 1]]]
+            for w in nbrs:
+                if w == parent[u]:
+                    continue
+                if w in dist:
+                    if branch[w] != branch[u] and w != v0 and u != v0:
+                        L = dist[u] + dist[w] + 1
+                        if best is None or L < best[0]:
+                            best = (L, u, w)
+                    continue
+                dist[w] = dist[u] + 1
+                parent[w] = u
+                branch[w] = w if u == v0 else branch[u]
+                nxt.append(w)
+        frontier = nxt
+    if best is None:
+        return [v0]
+    _, u, w = best
+    vs = set()
+    for x in (u, w):
+        while x != -1:
+            if x < n:
+                vs.add(x)
+            x = parent[x]
+    return sorted(vs)
+
+
+def sample_pairs(graph, count, rng):
+    """count impulse pairs (u, w) at Tanner distance 2: u uniform, then one of its
+    checks, then another variable of that check."""
+    import numpy as np
+    rp, col, vptr, vchk, n = graph
+    u = rng.integers(0, n, size=count)
+    deg_u = vptr[u + 1] - vptr[u]
+    c = vchk[vptr[u] + (rng.random(count) * deg_u).astype(np.int64)]
+    deg_c = rp[c + 1] - rp[c]
+    k = (rng.random(count) * deg_c).astype(np.int64)
+    w = col[rp[c] + k]
+    w = np.where(w == u, col[rp[c] + (k + 1) % deg_c], w)   # the next variable of the check
+    out = np.stack([np.minimum(u, w), np.maximum(u, w)], axis=1).astype(np.int32)
+    return np.ascontiguousarray(out)
+
+
+def _job_results(ctx, ids, jobs):
+    out = []
+    for (kind, _, _, _), jid in zip(jobs, ids):
+        info = ctx.poll(jid, wait=True)
+        if info["status"] != 0:
+            raise RuntimeError(f"job {jid} failed: {info.get('error')}")
+        if kind == "search":
+            o = ctx.job_outputs(jid, arrays=True)
+            out.append(("search", o["k_crit"], (o["ts_recs"], o["ts_bits"]), info["edge_updates"]))
+        else:
+            out.append(("is", info["is"]["p_hat"], info["is"]["n_fail"], info["edge_updates"]))
+        ctx.release(jid)
+    return out
+
+
+def bench_batch(tsg):
+    """64 uneven QC codes: every job alone, then all of them as one batch."""
+    import numpy as np
+    import workloads
+    codes = workloads.batch_codes()
+    rng = np.random.default_rng(4)
+    ctx = tsg.Context(0)
+    loaded = [ctx.load_code(c) for c in codes]
+    jobs = []
+    for i, (c, g) in enumerate(zip(codes, loaded)):
+        pats = np.full((4096, 2), -1, dtype=np.int32)
+        k = min(c.n, 4096)
+        pats[:k, 0] = np.arange(k)
+        if k < 4096:
+            pairs = g.make_patterns(tsg.PAT_PAIRS)
+            sel = np.sort(rng.choice(len(pairs), 4096 - k, replace=False))
+            pats[k:] = pairs[sel]
+        rp, col = g.csr()
+        bits = shortest_cycle_vns((rp, col) + var_checks(rp, col, c.n) + (c.n,), 0)
+        jobs.append(("search", g, pats, dict(a_max=12)))
+        jobs.append(("is", g, bits, dict(ebn0_db=3.0, shift=1.0, n_frames=16384, seed=40 + i,
+                                         max_iter=50)))
+
+    def plain():
+        res = []
+        for kind, g, data, kw in jobs:
+            if kind == "search":
+                g.reset_ts()
+                r = g.impulse_search(data, **kw)
+                res.append(("search", r["k_crit"], g.collect_arrays(), r["stats"]["edge_updates"]))
+            else:
+                kw = dict(kw)
+                r = g.is_estimate(data, kw.pop("ebn0_db"), kw.pop("shift"), kw.pop("n_frames"),
+                                  kw.pop("seed"), **kw)
+                res.append(("is", r["p_hat"], r["n_fail"], r["stats"]["edge_updates"]))
+        return res
+
+    def batched():
+        ids = ctx.run_batch(jobs)
+        st = ctx.stats()
+        return _job_results(ctx, ids, jobs), st
+
+    _say("batched: warm-up (autotunes every code)")
+    plain()
+    batched()
+    t0 = time.perf_counter()
+    ref = plain()
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    got, st = batched()
+    t_batch = time.perf_counter() - t0
+    def same_job(a, b):
+        if a[0] != b[0] or a[3] != b[3]:
+            return False
+        if a[0] == "is":
+            return a[1] == b[1] and a[2] == b[2]
+        return (np.array_equal(a[1], b[1]) and np.array_equal(a[2][0], b[2][0])
+                and np.array_equal(a[2][1], b[2][1]))
+    same = all(same_job(a, b) for a, b in zip(ref, got))
+    eu = sum(r[3] for r in ref)
+    ts = sum(len(r[2][0]) for r in ref if r[0] == "search")
+    ctx.close()
+    return {"workload": "64 QC codes, bases 3x6/4x8/3x12/4x24, Z 16..384 (seed 4); per code 4096 "
+                        "impulse patterns OMS-i8 20it + 16384 IS frames SPA-f32 50it at 3 dB",
+            "jobs": len(jobs), "edge_updates": eu, "ts_found": ts,
+            "plain": {"seconds": t_plain, "edge_updates_per_s": eu / t_plain,
+                      "ts_found_per_s": ts / t_plain},
+            "batched": {"seconds": t_batch, "edge_updates_per_s": eu / t_batch,
+                        "ts_found_per_s": ts / t_batch, "decode_launches": st["decode_launches"]},
+            "speedup": t_plain / t_batch, "results_identical": bool(same)}
+
+
+def bench_serve(tsg, seconds, rate):
+    """Poisson arrivals of search and IS jobs on the 46x68-base code pool."""
+    import numpy as np
+    import workloads
+    pool = workloads.serving_pool()
+    rng = np.random.default_rng(5)
+    ctx = tsg.Context(0, torch_stream=False, torch_alloc=False)
+    loaded = [ctx.load_code(c) for c in pool]
+    graphs = []
+    for c, g in zip(pool, loaded):
+        rp, col = g.csr()
+        graphs.append((rp, col) + var_checks(rp, col, c.n) + (c.n,))
+    t, arrivals = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > seconds:
+            break
+        arrivals.append(t)
+    jobs = []
+    for ta in arrivals:
+        ci = int(rng.integers(0, len(pool)))
+        frames = int(round(10 ** rng.uniform(3, 5)))
+        c, g = pool[ci], loaded[ci]
+        if rng.random() < 0.5:
+            jobs.append((ta, "search", g, sample_pairs(graphs[ci], frames, rng), dict(a_max=12)))
+        else:
+            v0 = int(rng.integers(0, c.n))
+            bits = shortest_cycle_vns(graphs[ci], v0)[:16]
+            jobs.append((ta, "is", g, bits, dict(ebn0_db=float(rng.integers(2, 6)), shift=1.0,
+                                                 n_frames=frames, seed=int(rng.integers(1 << 30)),
+                                                 max_iter=50)))
+    ctx.serve_start(4)
+    _say(f"served: warm-up on {len(pool)} codes")
+    warm = [ctx.submit_search(g, sample_pairs(graphs[i], 512, rng), a_max=12)
+            for i, g in enumerate(loaded)]
+    for jid in warm:
+        ctx.poll(jid, wait=True)
+        ctx.release(jid)
+    _say(f"served: {len(jobs)} jobs over {seconds:.0f} s")
+    ids = []
+    t0 = time.perf_counter()
+    for ta, kind, g, data, kw in jobs:
+        now = time.perf_counter() - t0
+        if ta > now:
+            time.sleep(ta - now)
+        if kind == "search":
+            ids.append(ctx.submit_search(g, data, **kw))
+        else:
+            kw = dict(kw)
+            ids.append(ctx.submit_is(g, data, kw.pop("ebn0_db"), kw.pop("shift"), kw.pop("n_frames"),
+                                     kw.pop("seed"), **kw))
+    infos = [ctx.poll(j, wait=True) for j in ids]
+    wall = time.perf_counter() - t0
+    bad = [i for i in infos if i["status"] != 0]
+    for j in ids:
+        ctx.release(j)
+    ctx.close()
+    lat = np.array([i["end_ms"] - i["submit_ms"] for i in infos])
+    eu = sum(i["edge_updates"] for i in infos)
+    span = (max(i["end_ms"] for i in infos) - min(i["submit_ms"] for i in infos)) * 1e-3
+    return {"workload": f"Poisson {rate:g} jobs/s for {seconds:g} s, 46x68-base QC pool of 32 "
+                        "(N up to 25.7k), 50/50 search (OMS-i8 20it) / IS (SPA-f32 50it, 2..5 dB), "
+                        "10^3..10^5 frames log-uniform, 4 worker slots",
+            "jobs": len(ids), "failed": len(bad),
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "max": float(lat.max())},
+            "edge_updates": eu, "edge_updates_per_s": eu / span, "seconds": span,
+            "wall_s": wall}
+
+
+def bench_qc2640(tsg):
+    """QC-2640: SPA search over every tree-path triple, then IS of the 16 most
+    harmful TS at 2, 3, 4, 5 dB with 10^5 frames each (shift eps*)."""
+    import workloads
+    ctx = tsg.Context(0)
+    g = ctx.load_code(workloads.qc2640_code())
+    pats = g.make_patterns(tsg.PAT_TRIPLES)
+    kw = dict(decoder=tsg.DEC_SPA, max_iter=50, ebn0_db=3.0, k_max=32 * 1024, k_den=1024, a_max=12)
+    g.impulse_search(pats[:4096], **kw)   # warm-up / autotune
+    g.reset_ts()
+    t0 = time.perf_counter()
+    r = g.impulse_search(pats, **kw)
+    ts = g.collect()
+    t_search = time.perf_counter() - t0
+    eu_search = r["stats"]["edge_updates"]
+    fer = {}
+    eu_is = 0
+    t0 = time.perf_counter()
+    for snr in (2.0, 3.0, 4.0, 5.0):
+        rows = []
+        for i, t in enumerate(ts[:16]):
+            o = g.is_estimate(list(t.bits), snr, -1.0, 100000, seed=3, stream=(int(snr) << 16) | i)
+            eu_is += o["stats"]["edge_updates"]
+            rows.append({"a": t.a, "b": t.b, "orbit": t.orbit, "p_hat": o["p_hat"],
+                         "ci": [o["ci_lo"], o["ci_hi"]]})
+        fer[f"{snr:g}dB"] = {"union_bound": sum(x["orbit"] * x["p_hat"] for x in rows),
+                             "ts": rows[:4]}
+    t_is = time.perf_counter() - t0
+    ctx.close()
+    return {"workload": "QC (3,6) N=2640 Z=440 girth 8 (seed 3): SPA-f32 50it search over "
+                        f"{len(pats)} triples, then IS of the top 16 TS x 4 SNRs x 1e5 frames",
+            "ts_found": len(ts), "search": {"seconds": t_search, "edge_updates": eu_search,
+                                            "edge_updates_per_s": eu_search / t_search},
+            "is": {"seconds": t_is, "edge_updates": eu_is, "edge_updates_per_s": eu_is / t_is,
+                   "fer": fer}}
 
 
 def cpu_baseline(code, pats, seconds):

@@ -64,6 +64,18 @@ class TsRecord:
     bits: Tuple[int, ...]
 
 
+# numpy view of ts_record: a, b, orbit, first_pattern, k_crit, reserved, bits_off
+_REC_DTYPE = np.dtype([("a", np.int32), ("b", np.int32), ("orbit", np.int32),
+                       ("first_pattern", np.int32), ("k_crit", np.int32), ("reserved", np.int32),
+                       ("bits_off", np.int64)])
+
+
+def _ts_records(recs: np.ndarray, bits: np.ndarray) -> List[TsRecord]:
+    return [TsRecord(int(r["a"]), int(r["b"]), int(r["orbit"]), int(r["first_pattern"]),
+                     int(r["k_crit"]), tuple(int(x) for x in bits[r["bits_off"]:r["bits_off"] + r["a"]]))
+            for r in recs]
+
+
 class Context:
     """A device, a stream and an allocator.  By default the stream and the
     allocator are torch's (current stream, caching allocator)."""
@@ -193,7 +205,10 @@ class Context:
             out["error"] = lib().ts_last_error().decode(errors="replace")
         return out
 
-    def job_outputs(self, job_id: int) -> dict:
+    def job_outputs(self, job_id: int, arrays: bool = False) -> dict:
+        """Per-pattern outputs and the TS of a finished search job.  arrays=True
+        gives the TS as a record array ("ts_recs", fields of ts_record) and the
+        concatenated bits ("ts_bits"); otherwise "ts" is a list of TsRecord."""
         info = self.poll(job_id)
         P = info["n_patterns"]
         res = {k: np.zeros(P, dtype=np.int32)
@@ -201,13 +216,14 @@ class Context:
         out = A.SearchOut(*(res[k].ctypes.data for k in
                             ("k_crit", "iters_crit", "iters_lo", "tmin_crit", "n_cand")))
         n, nb = info["n_ts"], info["n_bits"]
-        recs = (A.Record * max(n, 1))()
+        recs = np.zeros(max(n, 1), dtype=_REC_DTYPE)
         bits = np.zeros(max(nb, 1), dtype=np.int32)
-        _check(lib().ts_job_outputs(self._h, job_id, C.byref(out), recs, n, bits.ctypes.data, nb))
-        res["ts"] = [TsRecord(recs[i].a, recs[i].b, recs[i].orbit, recs[i].first_pattern,
-                              recs[i].k_crit,
-                              tuple(int(x) for x in bits[recs[i].bits_off:recs[i].bits_off + recs[i].a]))
-                     for i in range(n)]
+        _check(lib().ts_job_outputs(self._h, job_id, C.byref(out), recs.ctypes.data, n,
+                                    bits.ctypes.data, nb))
+        if arrays:
+            res["ts_recs"], res["ts_bits"] = recs[:n], bits[:nb]
+        else:
+            res["ts"] = _ts_records(recs[:n], bits)
         return res
 
     def cancel(self, job_id: int):
@@ -332,20 +348,21 @@ class Code:
         res["stats"] = self.ctx.stats()
         return res
 
-    def collect(self) -> List[TsRecord]:
+    def collect_arrays(self):
+        """The code's TS table in order: a record array (fields of ts_record) and
+        the concatenated bits of the sets."""
         L = lib()
         n, nb = C.c_int64(), C.c_int64()
         _check(L.ts_collect(self.ctx.handle, self._h, None, 0, C.byref(n), None, 0, C.byref(nb)))
-        recs = (A.Record * max(n.value, 1))()
+        recs = np.zeros(max(n.value, 1), dtype=_REC_DTYPE)
         bits = np.zeros(max(nb.value, 1), dtype=np.int32)
-        _check(L.ts_collect(self.ctx.handle, self._h, recs, n.value, C.byref(n),
+        _check(L.ts_collect(self.ctx.handle, self._h, recs.ctypes.data, n.value, C.byref(n),
                             bits.ctypes.data, nb.value, C.byref(nb)))
-        out = []
-        for i in range(n.value):
-            r = recs[i]
-            out.append(TsRecord(r.a, r.b, r.orbit, r.first_pattern, r.k_crit,
-                                tuple(int(x) for x in bits[r.bits_off:r.bits_off + r.a])))
-        return out
+        return recs[:n.value], bits[:nb.value]
+
+    def collect(self) -> List[TsRecord]:
+        recs, bits = self.collect_arrays()
+        return _ts_records(recs, bits)
 
     def reset_ts(self):
         _check(lib().ts_reset_ts(self.ctx.handle, self._h))

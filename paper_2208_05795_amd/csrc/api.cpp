@@ -237,6 +237,32 @@ static int select_shape(ts_ctx *ctx, ts_code *code, const ts_search_opts *o, int
     return TS_OK;
 }
 
+static int is_tune_key(int max_iter, int layout) { return 500000 + layout * 1000 + max_iter; }
+
+// IS counterpart of select_shape.
+static int select_is_shape(ts_ctx *ctx, ts_code *code, int max_iter, int layout, int64_t K,
+                           std::vector<SearchPlan> *shapes, SearchPlan *plan, bool *need_tune) {
+    int rc = plan_is_candidates(ctx, code, max_iter, layout, shapes);
+    if (rc) return rc;
+    *plan = shapes->front();
+    *need_tune = false;
+    std::lock_guard<std::mutex> g(code->tune_mu);
+    auto it = code->tuned.find(is_tune_key(max_iter, layout));
+    if (it != code->tuned.end()) {
+        for (const SearchPlan &p : *shapes)
+            if (same_shape(p, it->second)) *plan = p;
+    } else {
+        *need_tune = shapes->size() > 1 && K >= 1024;
+    }
+    return TS_OK;
+}
+
+int plan_is_shape(ts_exec &ex, ts_code *code, int max_iter, int layout, SearchPlan *plan) {
+    std::vector<SearchPlan> shapes;
+    bool need_tune = false;
+    return select_is_shape(ex.ctx, code, max_iter, layout, 0, &shapes, plan, &need_tune);
+}
+
 int plan_search_shape(ts_exec &ex, ts_code *code, const ts_search_opts *o, int64_t P, SearchPlan *plan) {
     std::vector<SearchPlan> shapes;
     bool need_tune = false;
@@ -475,26 +501,69 @@ int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const 
     L.fail = d_fail.as<unsigned char>();
     L.wf = d_wf.as<double>();
     L.counters = (unsigned long long *)(d_misc.as<int>() + 4);
+    std::vector<SearchPlan> shapes;
     SearchPlan plan;
-    rc = plan_is(ex.ctx, code, o->max_iter, o->layout, &plan);
+    bool need_tune = false;
+    rc = select_is_shape(ex.ctx, code, o->max_iter, o->layout, K, &shapes, &plan, &need_tune);
     if (rc) return rc;
+    size_t scr = 0;
+    for (const SearchPlan &p : need_tune ? shapes : std::vector<SearchPlan>{plan})
+        if (p.kind == kPlanStreamed) scr = std::max(scr, (size_t)std::min<int64_t>(p.grid, K) * p.slot_bytes);
+    DBuf scratch(ex, scr);
+    if (scr && !scratch.p) { set_error("device allocation of the decoder scratch failed"); return TS_E_NOMEM; }
+    L.gscr = scr ? scratch.as<unsigned char>() : nullptr;
+    // one IS launch of `frames` frames with shape p; ms_out: its duration
+    auto launch = [&](const SearchPlan &p, int64_t frames, float *ms_out) -> int {
+        IsJob job{};
+        job.a = make_is_dev(L, p);
+        job.cd = code->dev;
+        job.item0 = 0;
+        void *dj = nullptr;
+        int slot = -1;
+        int r = ex.stage(&job, sizeof(job), &dj, &slot);
+        if (r) return r;
+        TSG_HIP(hipEventRecord(ex.ev[0], s));
+        r = launch_is_jobs(s, p, (const IsJob *)dj, 1, d_misc.as<int>(), frames);
+        ex.staged(slot);
+        if (r) return r;
+        TSG_HIP(hipEventRecord(ex.ev[1], s));
+        if (ms_out) {
+            TSG_HIP(hipStreamSynchronize(s));
+            TSG_HIP(hipEventElapsedTime(ms_out, ex.ev[0], ex.ev[1]));
+        }
+        return TS_OK;
+    };
+    if (need_tune) {
+        // Autotuner: every shape once on the job's first frames; the fastest is
+        // kept for (code, iterations, layout request).  Frames only depend on
+        // their Philox counters, so the real run below recomputes them exactly.
+        int64_t probe = 0;
+        for (const SearchPlan &p : shapes) probe = std::max<int64_t>(probe, 2 * (int64_t)p.grid);
+        probe = std::min(probe, K);
+        float best = 0.0f;
+        for (const SearchPlan &p : shapes) {
+            rc = launch_fill(s, d_misc.as<int>(), 0, 64);
+            if (rc) return rc;
+            float ms = 0.0f;
+            rc = launch(p, probe, &ms);
+            if (rc) return rc;
+            if (best == 0.0f || ms < best) {
+                best = ms;
+                plan = p;
+            }
+        }
+        std::lock_guard<std::mutex> g(code->tune_mu);
+        SearchShape sh;
+        sh.kind = plan.kind;
+        sh.cpt = plan.cpt;
+        sh.block = plan.block;
+        code->tuned[is_tune_key(o->max_iter, o->layout)] = sh;
+        rc = launch_fill(s, d_misc.as<int>(), 0, 64);
+        if (rc) return rc;
+    }
     const int grid = (int)std::min<int64_t>(plan.grid, K), block = plan.block;
-    DBuf scratch(ex, plan.kind == kPlanStreamed ? (size_t)grid * plan.slot_bytes : 0);
-    if (plan.kind == kPlanStreamed && !scratch.p) { set_error("device allocation of the decoder scratch failed"); return TS_E_NOMEM; }
-    L.gscr = plan.kind == kPlanStreamed ? scratch.as<unsigned char>() : nullptr;
-    IsJob job{};
-    job.a = make_is_dev(L, plan);
-    job.cd = code->dev;
-    job.item0 = 0;
-    void *dj = nullptr;
-    int slot = -1;
-    rc = ex.stage(&job, sizeof(job), &dj, &slot);
+    rc = launch(plan, K, nullptr);
     if (rc) return rc;
-    TSG_HIP(hipEventRecord(ex.ev[0], s));
-    rc = launch_is_jobs(s, plan, (const IsJob *)dj, 1, d_misc.as<int>(), K);
-    ex.staged(slot);
-    if (rc) return rc;
-    TSG_HIP(hipEventRecord(ex.ev[1], s));
     rc = launch_is_reduce(s, L.wf, L.fail, K, 0, 0.0, d_red.as<double>());
     if (rc) return rc;
     double red[4];

@@ -103,7 +103,7 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
             it.b = &b;
             it.K = b.io.n_frames;
             it.shift = b.io.shift;
-            rc = plan_is(ctx, b.code, b.io.max_iter, b.io.layout, &it.plan);
+            rc = plan_is_shape(ex, b.code, b.io.max_iter, b.io.layout, &it.plan);
             if (rc) return rc;
             I.push_back(it);
         }

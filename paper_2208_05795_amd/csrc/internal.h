@@ -274,6 +274,10 @@ struct IsLaunch {
 };
 // IS launch shape (streamed kind: plan.slot_bytes of scratch per workgroup)
 int plan_is(ts_ctx *ctx, const ts_code *c, int max_iter, int layout, SearchPlan *plan);
+int plan_is_candidates(ts_ctx *ctx, const ts_code *c, int max_iter, int layout,
+                       std::vector<SearchPlan> *out);
+// the IS shape to use: the autotuner's earlier choice, else the first candidate
+int plan_is_shape(ts_exec &ex, ts_code *code, int max_iter, int layout, SearchPlan *plan);
 IsDev make_is_dev(const IsLaunch &a, const SearchPlan &plan);
 // One persistent launch over the items of n_jobs device-resident jobs that share
 // the plan's kernel and workgroup size (plan.lds and plan.grid cover them all).

@@ -352,12 +352,11 @@ __device__ void write_candidates(const SearchLaunch &a, const unsigned long long
 // Workgroup bound of a shape: small register footprints allow 1024 threads.
 template <int DC, int CPT>
 struct MaxBlock {
-    static constexpr int value = DC * CPT <= 16 ? 1024 : 256;
+    static constexpr int value = DC * CPT <= 16 ? 1024 : (DC * CPT <= 48 ? 512 : 256);
 };
-// The IS kernel also keeps the Philox state and the weight accumulators live.
 template <int DC, int CPT>
 struct MaxBlockIs {
-    static constexpr int value = DC * CPT <= 8 ? 1024 : 256;
+    static constexpr int value = DC * CPT <= 12 ? 1024 : (DC * CPT <= 48 ? 512 : 256);
 };
 
 // Multi-job launches.  Thread 0 pops the next item of the launch and finds its
@@ -571,7 +570,7 @@ __device__ __forceinline__ void philox4x32_10(unsigned c[4], unsigned k0, unsign
 struct IsChan {
     unsigned k0, k1, stream;
     int a;
-    double shift, sigma, sigma2;
+    float shift, sigma, two_over_s2;
     unsigned long long frame_base;
 };
 
@@ -581,52 +580,55 @@ __device__ __forceinline__ IsChan is_chan(const IsDev &d) {
     c.k1 = uni((unsigned)(d.seed >> 32));
     c.stream = uni(d.stream);
     c.a = uni(d.a);
-    c.shift = uni(d.shift);
-    c.sigma = uni(d.sigma);
-    c.sigma2 = uni(d.sigma2);
+    c.shift = uni((float)d.shift);
+    c.sigma = uni((float)d.sigma);
+    c.two_over_s2 = uni((float)(2.0 / d.sigma2));
     c.frame_base = uni(d.frame_base);
     return c;
 }
 
 // Channel of IS frame `frame` (Section II, mean-shifted noise on the TS bits):
 // y_v = 1 - s [v in T] + sigma n_v with n_v from Philox4x32-10 at counter
-// (v >> 2, frame, stream) and Box-Muller, lambda_v = 2 y_v / sigma^2 in Q20.
-// put(v, lambda) stores the values; the normals of the TS bits go to tn.
+// (v >> 2, frame, stream) and Box-Muller on u = (x + 0.5) 2^-32, in float32
+// (the channel values are then rounded to the Q20 grid, 2^-20, far coarser than
+// the float32 error of the normals), lambda_v = 2 y_v / sigma^2.  put(v, lambda)
+// stores the values; the normals of the TS bits go to tn.
 template <class Put>
 __device__ __forceinline__ void is_channel(const IsChan &a, int n, unsigned long long frame,
-                                           const int *tsl, double *tn, Put put) {
+                                           const int *tsl, float *tn, Put put) {
     const int B = blockDim.x, tid = threadIdx.x;
-    const double two_pi = 6.283185307179586476925286766559;
+    const float two_pi = 6.2831853071795865f;
     for (int g = tid; 4 * g < n; g += B) {
         unsigned c[4] = {(unsigned)g, (unsigned)frame, (unsigned)(frame >> 32), a.stream};
         philox4x32_10(c, a.k0, a.k1);
-        double u[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) u[i] = ((double)c[i] + 0.5) * 0x1p-32;
-        const double r0 = sqrt(-2.0 * log(u[0])), r1 = sqrt(-2.0 * log(u[2]));
-        double s0, c0, s1, c1;
-        sincos(two_pi * u[1], &s0, &c0);
-        sincos(two_pi * u[3], &s1, &c1);
-        const double nv[4] = {r0 * c0, r0 * s0, r1 * c1, r1 * s1};
+        for (int h = 0; h < 2; ++h) {
+            const float u0 = ((float)c[2 * h] + 0.5f) * 0x1p-32f;
+            const float u1 = ((float)c[2 * h + 1] + 0.5f) * 0x1p-32f;
+            const float r = sqrtf(-2.0f * logf(u0));
+            float sn, cs;
+            sincosf(two_pi * u1, &sn, &cs);
+            const float nv[2] = {r * cs, r * sn};
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int v = 4 * g + i;
-            if (v >= n) break;
-            int slot = -1;
-            for (int q = 0; q < a.a; ++q)
-                if (tsl[q] == v) slot = q;
-            const double y = 1.0 - (slot >= 0 ? a.shift : 0.0) + a.sigma * nv[i];
-            put(v, to_q20((float)(2.0 * y / a.sigma2)));
-            if (slot >= 0) tn[slot] = nv[i];
+            for (int i = 0; i < 2; ++i) {
+                const int v = 4 * g + 2 * h + i;
+                if (v >= n) break;
+                int slot = -1;
+                for (int q = 0; q < a.a; ++q)
+                    if (tsl[q] == v) slot = q;
+                const float y = 1.0f - (slot >= 0 ? a.shift : 0.0f) + a.sigma * nv[i];
+                put(v, to_q20(y * a.two_over_s2));
+                if (slot >= 0) tn[slot] = nv[i];
+            }
         }
     }
 }
 
 // Importance weight of a finished frame (thread 0):
 // w = exp(-a s^2 / (2 sigma^2) + (s / sigma) sum_{v in T} n_v), kept for failures.
-__device__ __forceinline__ void is_finish(const IsDev &a, int f, const DecRes &r, const double *tn) {
+__device__ __forceinline__ void is_finish(const IsDev &a, int f, const DecRes &r, const float *tn) {
     double st = 0.0;
-    for (int q = 0; q < a.a; ++q) st += tn[q];
+    for (int q = 0; q < a.a; ++q) st += (double)tn[q];
     const double w = exp(a.wconst + (a.shift / a.sigma) * st);
     a.fail[f] = (unsigned char)r.fail;
     a.wf[f] = r.fail ? w : 0.0;
@@ -671,7 +673,7 @@ template <int DC, int CPT>
 struct RegIsDec {
     IsChan a;
     Frame F;
-    double *tn;
+    float *tn;
     int *tsl;
     int nb[CPT][DC];
     int c2v[CPT][DC];
@@ -689,7 +691,7 @@ struct RegIsDec {
         F.np = L.np;
         F.W = L.W;
         F.T = T;
-        tn = (double *)(frame + L.extra);
+        tn = (float *)(frame + L.extra);
         tsl = (int *)(tn + kMaxWidth);
         const int tid = threadIdx.x;
         if (tid < kMaxWidth) tsl[tid] = tid < J.a.a ? J.a.ts[tid] : -1;
@@ -1024,7 +1026,7 @@ struct GIsDec {
     IsChan a;
     GFrame F;
     int *lam;
-    double *tn;
+    float *tn;
     int *tsl;
 
     __device__ __forceinline__ void bind(const IsJob &J, unsigned char *frame) {
@@ -1037,7 +1039,7 @@ struct GIsDec {
         F.lam_g = lam;
         F.lam_base = F.lam_imp = 0;
         F.hist = nullptr;
-        tn = (double *)(frame + L.extra);
+        tn = (float *)(frame + L.extra);
         tsl = (int *)(tn + kMaxWidth);
         const int tid = threadIdx.x;
         if (tid < kMaxWidth) tsl[tid] = tid < J.a.a ? J.a.ts[tid] : -1;
@@ -1321,9 +1323,12 @@ int launch_fill(hipStream_t stream, int *p, int value, int64_t count) {
     return TS_OK;
 }
 
-// IS launch shape: the register-resident kernel with the fewest checks per
-// thread that fits, else the streamed kernel at its largest workgroup.
-int plan_is(ts_ctx *ctx, const ts_code *c, int max_iter, int layout, SearchPlan *plan) {
+// IS launch shapes: every register-resident shape that fits (fewest checks per
+// thread first), then the streamed kernel at each workgroup size; restricted to
+// the requested layout.
+int plan_is_candidates(ts_ctx *ctx, const ts_code *c, int max_iter, int layout,
+                       std::vector<SearchPlan> *out) {
+    out->clear();
     const int dc = padded_degree(c);
     if (!dc) return TS_E_INVAL;
     const size_t lds = kHdrLds + lds_layout(c->n, max_iter, false).total;
@@ -1336,31 +1341,36 @@ int plan_is(ts_ctx *ctx, const ts_code *c, int max_iter, int layout, SearchPlan 
             int per_cu = 0;
             TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k->is, b, lds));
             if (per_cu < 1) continue;
-            plan->kind = kPlanRegister;
-            plan->decoder = TS_DEC_SPA_F32;
-            plan->block = b;
-            plan->cpt = cp;
-            plan->dc = dc;
-            plan->lds = lds;
-            plan->grid = per_cu * ctx->num_cu;
-            plan->slot_bytes = plan->hist_off = 0;
-            return TS_OK;
+            SearchPlan p;
+            p.kind = kPlanRegister;
+            p.decoder = TS_DEC_SPA_F32;
+            p.block = b;
+            p.cpt = cp;
+            p.dc = dc;
+            p.lds = lds;
+            p.grid = per_cu * ctx->num_cu;
+            p.slot_bytes = p.hist_off = 0;
+            out->push_back(p);
         }
     }
-    std::vector<SearchPlan> g;
     if (layout != TS_LAYOUT_REGISTER) {
-        int rc = add_streamed_plans(ctx, c, false, TS_DEC_SPA_F32, max_iter, &g);
+        const int rc = add_streamed_plans(ctx, c, false, TS_DEC_SPA_F32, max_iter, out);
         if (rc) return rc;
     }
-    if (g.empty()) {
-        if (layout == TS_LAYOUT_REGISTER) {
-            set_error("the requested decoder layout does not fit this code");
-            return TS_E_INVAL;
-        }
-        set_error("code (n = %d) needs more LDS per workgroup than the device has", c->n);
+    if (out->empty()) {
+        set_error(layout == TS_LAYOUT_AUTO ? "code (n = %d) needs more LDS per workgroup than the device has"
+                                           : "the requested decoder layout does not fit this code (n = %d)",
+                  c->n);
         return TS_E_INVAL;
     }
-    *plan = g.back();
+    return TS_OK;
+}
+
+int plan_is(ts_ctx *ctx, const ts_code *c, int max_iter, int layout, SearchPlan *plan) {
+    std::vector<SearchPlan> v;
+    const int rc = plan_is_candidates(ctx, c, max_iter, layout, &v);
+    if (rc) return rc;
+    *plan = v.front();
     return TS_OK;
 }
 

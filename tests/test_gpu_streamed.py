@@ -196,8 +196,8 @@ def test_serving_code_is_vs_oracle(ctx, oracle_mod, pool):
 def test_wide_check_code_vs_oracle(ctx, oracle_mod):
     """A 4x24-base code with more checks than a register workgroup holds."""
     import paper_2208_05795_amd as tsg
-    codes = [c for c in workloads.batch_codes() if c.mb == 4 and c.nb == 24 and c.m > 512]
-    code = min(codes, key=lambda c: c.n)
+    codes = [c for c in workloads.batch_codes() if c.mb == 4 and c.nb == 24]
+    code = max(codes, key=lambda c: c.m)
     oc = oracle_mod.OCode(code)
     pats = _sample(oracle_mod.patterns(oc, 2), 24, 33)
     _say(f"{code.name} (n={code.n}, m={code.m}, dc=24) OMS vs oracle")

@@ -91,3 +91,12 @@ def test_python_binding_raises_without_gpu(libpath):
         tsg.Context(0)
     with pytest.raises(tsg.TsgError):
         tsg.Context(0, torch_stream=False, torch_alloc=False)
+
+
+def test_record_dtype_matches_header():
+    """The numpy view used by the array read-out has ts_record's layout."""
+    import paper_2208_05795_amd as tsg
+    from paper_2208_05795_amd import _capi as A
+    assert tsg._REC_DTYPE.itemsize == ctypes.sizeof(A.Record)
+    for f, _ in A.Record._fields_:
+        assert tsg._REC_DTYPE.fields[f][1] == getattr(A.Record, f).offset, f
