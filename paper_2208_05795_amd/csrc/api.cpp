@@ -564,14 +564,15 @@ int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const 
     const int grid = (int)std::min<int64_t>(plan.grid, K), block = plan.block;
     rc = launch(plan, K, nullptr);
     if (rc) return rc;
-    rc = launch_is_reduce(s, L.wf, L.fail, K, 0, 0.0, d_red.as<double>());
+    const IsDev dres = make_is_dev(L, plan);
+    rc = launch_is_reduce(s, dres, L.wf, L.fail, K, 0, 0.0, d_red.as<double>());
     if (rc) return rc;
     double red[4];
     TSG_HIP(hipMemcpyAsync(ex.pinned, d_red.p, 32, hipMemcpyDeviceToHost, s));
     TSG_HIP(hipStreamSynchronize(s));
     std::memcpy(red, ex.pinned, 32);
     const double p = red[0] / (double)K;
-    rc = launch_is_reduce(s, L.wf, L.fail, K, 1, p, d_red.as<double>());
+    rc = launch_is_reduce(s, dres, L.wf, L.fail, K, 1, p, d_red.as<double>());
     if (rc) return rc;
     TSG_HIP(hipMemcpyAsync(ex.pinned, d_red.p, 32, hipMemcpyDeviceToHost, s));
     TSG_HIP(hipMemcpyAsync(ex.pinned + 8, d_misc.as<int>() + 4, 16, hipMemcpyDeviceToHost, s));

@@ -356,15 +356,16 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
     // ---- per IS job: fixed-order reductions ----------------------------------
     std::vector<double> red(I.size() * 4);
     for (IItem &it : I) {
-        rc = launch_is_reduce(s, it.L.wf, it.L.fail, it.K, 0, 0.0, (double *)(arena + it.red));
+        rc = launch_is_reduce(s, make_is_dev(it.L, it.plan), it.L.wf, it.L.fail, it.K, 0, 0.0,
+                              (double *)(arena + it.red));
         if (rc) return rc;
     }
     for (size_t i = 0; i < I.size(); ++i)
         TSG_HIP(hipMemcpyAsync(&red[4 * i], arena + I[i].red, 32, hipMemcpyDeviceToHost, s));
     TSG_HIP(hipStreamSynchronize(s));
     for (size_t i = 0; i < I.size(); ++i) {
-        rc = launch_is_reduce(s, I[i].L.wf, I[i].L.fail, I[i].K, 1, red[4 * i] / (double)I[i].K,
-                              (double *)(arena + I[i].red));
+        rc = launch_is_reduce(s, make_is_dev(I[i].L, I[i].plan), I[i].L.wf, I[i].L.fail, I[i].K, 1,
+                              red[4 * i] / (double)I[i].K, (double *)(arena + I[i].red));
         if (rc) return rc;
     }
     std::vector<double> red2(I.size() * 4);

@@ -356,7 +356,7 @@ struct MaxBlock {
 };
 template <int DC, int CPT>
 struct MaxBlockIs {
-    static constexpr int value = DC * CPT <= 12 ? 1024 : (DC * CPT <= 48 ? 512 : 256);
+    static constexpr int value = MaxBlock<DC, CPT>::value;
 };
 
 // Multi-job launches.  Thread 0 pops the next item of the launch and finds its
@@ -624,14 +624,13 @@ __device__ __forceinline__ void is_channel(const IsChan &a, int n, unsigned long
     }
 }
 
-// Importance weight of a finished frame (thread 0):
-// w = exp(-a s^2 / (2 sigma^2) + (s / sigma) sum_{v in T} n_v), kept for failures.
+// A finished frame (thread 0): its failure flag and the sum of the normals of
+// its TS bits, from which the reduction forms the importance weight.
 __device__ __forceinline__ void is_finish(const IsDev &a, int f, const DecRes &r, const float *tn) {
     double st = 0.0;
     for (int q = 0; q < a.a; ++q) st += (double)tn[q];
-    const double w = exp(a.wconst + (a.shift / a.sigma) * st);
     a.fail[f] = (unsigned char)r.fail;
-    a.wf[f] = r.fail ? w : 0.0;
+    a.wf[f] = st;
 }
 
 // Common part of the IS kernels: the frame queue over the launch's jobs and
@@ -727,19 +726,21 @@ __global__ __launch_bounds__((MaxBlockIs<DC, CPT>::value)) void k_is(const IsJob
     is_jobs(jobs, n_jobs, queue, n_items, dec, smem);
 }
 
-// Fixed-order reduction of the per-frame values: thread t sums a contiguous
-// range in frame order, then a fixed binary tree combines the threads.
+// Fixed-order reduction over the frames of the importance weights
+// w_f = [frame f failed] exp(-a s^2 / (2 sigma^2) + (s / sigma) sum_{v in T} n_v)
+// (wf holds the sums of the TS-bit normals): thread t sums a contiguous range in
+// frame order, then a fixed binary tree combines the threads.
 // mode 0: out = {sum w, sum w^2, failures}; mode 1: out[3] = sum (w - mean)^2.
 __global__ __launch_bounds__(1024) void k_is_reduce(const double *wf, const unsigned char *fail,
-                                                     long long n, int mode, double mean,
-                                                     double *out) {
+                                                     long long n, int mode, double mean, double wconst,
+                                                     double coef, double *out) {
     __shared__ double s0[1024], s1[1024], s2[1024];
     const int t = threadIdx.x, B = blockDim.x;
     const long long per = (n + B - 1) / B;
     const long long lo = (long long)t * per, hi = lo + per < n ? lo + per : n;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     for (long long i = lo; i < hi; ++i) {
-        const double w = wf[i];
+        const double w = fail[i] ? exp(wconst + coef * wf[i]) : 0.0;
         if (mode == 0) {
             a0 += w;
             a1 += w * w;
@@ -1010,7 +1011,7 @@ struct GSearchDec {
 
 // Workgroup bounds of the streamed kernels (the register budget follows).
 template <int DCMAX> struct MaxBlockG { static constexpr int value = DCMAX <= 16 ? 1024 : 512; };
-template <int DCMAX> struct MaxBlockGIs { static constexpr int value = 512; };
+template <int DCMAX> struct MaxBlockGIs { static constexpr int value = MaxBlockG<DCMAX>::value; };
 
 template <class Rule, int DCMAX>
 __global__ __launch_bounds__((MaxBlockG<DCMAX>::value)) void k_search_g(const SearchJob *jobs, int n_jobs,
@@ -1396,10 +1397,10 @@ IsDev make_is_dev(const IsLaunch &a, const SearchPlan &plan) {
     return d;
 }
 
-int launch_is_reduce(hipStream_t stream, const double *wf, const unsigned char *fail, int64_t n, int mode,
-                     double mean, double *out) {
+int launch_is_reduce(hipStream_t stream, const IsDev &d, const double *wf, const unsigned char *fail,
+                     int64_t n, int mode, double mean, double *out) {
     hipLaunchKernelGGL(k_is_reduce, dim3(1), dim3(1024), 0, stream, wf, fail, (long long)n, mode,
-                       mean, out);
+                       mean, d.wconst, d.shift / d.sigma, out);
     TSG_HIP(hipGetLastError());
     return TS_OK;
 }
