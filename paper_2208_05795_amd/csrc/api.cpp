@@ -483,8 +483,9 @@ int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const 
         if (rc) return rc;
     }
     const int64_t K = o->n_frames;
-    DBuf d_fail(ex, (size_t)K), d_wf(ex, (size_t)K * 8), d_misc(ex, 64 * 4), d_red(ex, 8 * 8);
-    if (!d_fail.p || !d_wf.p || !d_misc.p || !d_red.p) { set_error("device allocation failed"); return TS_E_NOMEM; }
+    DBuf d_fail(ex, (size_t)K), d_wf(ex, (size_t)K * 8), d_misc(ex, 64 * 4), d_red(ex, 8 * 8),
+        d_part(ex, (size_t)is_reduce_parts(K) * 3 * 8);
+    if (!d_fail.p || !d_wf.p || !d_misc.p || !d_red.p || !d_part.p) { set_error("device allocation failed"); return TS_E_NOMEM; }
     int rc = launch_fill(s, d_misc.as<int>(), 0, 64);
     if (rc) return rc;
     IsLaunch L{};
@@ -565,14 +566,14 @@ int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const 
     rc = launch(plan, K, nullptr);
     if (rc) return rc;
     const IsDev dres = make_is_dev(L, plan);
-    rc = launch_is_reduce(s, dres, L.wf, L.fail, K, 0, 0.0, d_red.as<double>());
+    rc = launch_is_reduce(s, dres, L.wf, L.fail, K, 0, 0.0, d_red.as<double>(), d_part.as<double>());
     if (rc) return rc;
     double red[4];
     TSG_HIP(hipMemcpyAsync(ex.pinned, d_red.p, 32, hipMemcpyDeviceToHost, s));
     TSG_HIP(hipStreamSynchronize(s));
     std::memcpy(red, ex.pinned, 32);
     const double p = red[0] / (double)K;
-    rc = launch_is_reduce(s, dres, L.wf, L.fail, K, 1, p, d_red.as<double>());
+    rc = launch_is_reduce(s, dres, L.wf, L.fail, K, 1, p, d_red.as<double>(), d_part.as<double>());
     if (rc) return rc;
     TSG_HIP(hipMemcpyAsync(ex.pinned, d_red.p, 32, hipMemcpyDeviceToHost, s));
     TSG_HIP(hipMemcpyAsync(ex.pinned + 8, d_misc.as<int>() + 4, 16, hipMemcpyDeviceToHost, s));

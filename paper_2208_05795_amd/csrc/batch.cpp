@@ -47,7 +47,7 @@ struct IItem {
     SearchPlan plan;
     double shift = 0.0;
     int64_t K = 0;
-    size_t ts = 0, fail = 0, wf = 0, red = 0, misc = 0;
+    size_t ts = 0, fail = 0, wf = 0, red = 0, part = 0, misc = 0;
     int group = -1;
     IsLaunch L{};
 };
@@ -180,6 +180,7 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
         it.fail = o; o = al(o + (size_t)it.K);
         it.wf = o; o = al(o + (size_t)it.K * 8);
         it.red = o; o = al(o + 8 * 8);
+        it.part = o; o = al(o + (size_t)is_reduce_parts(it.K) * 3 * 8);
     }
     for (Group &g : G) {
         g.jobs = o;
@@ -357,7 +358,7 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
     std::vector<double> red(I.size() * 4);
     for (IItem &it : I) {
         rc = launch_is_reduce(s, make_is_dev(it.L, it.plan), it.L.wf, it.L.fail, it.K, 0, 0.0,
-                              (double *)(arena + it.red));
+                              (double *)(arena + it.red), (double *)(arena + it.part));
         if (rc) return rc;
     }
     for (size_t i = 0; i < I.size(); ++i)
@@ -365,7 +366,8 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
     TSG_HIP(hipStreamSynchronize(s));
     for (size_t i = 0; i < I.size(); ++i) {
         rc = launch_is_reduce(s, make_is_dev(I[i].L, I[i].plan), I[i].L.wf, I[i].L.fail, I[i].K, 1,
-                              red[4 * i] / (double)I[i].K, (double *)(arena + I[i].red));
+                              red[4 * i] / (double)I[i].K, (double *)(arena + I[i].red),
+                              (double *)(arena + I[i].part));
         if (rc) return rc;
     }
     std::vector<double> red2(I.size() * 4);

@@ -288,9 +288,10 @@ int launch_is_jobs(hipStream_t s, const SearchPlan &plan, const IsJob *d_jobs, i
 int occupancy_grid(ts_ctx *ctx, const SearchPlan &plan, int decoder, bool search, int *grid);
 // Reduction of the weights of n IS frames of job d (wf: sums of the TS-bit
 // normals).  mode 0: out[0..2] = sum w, sum w^2, failures; mode 1: out[3] =
-// sum (w - mean)^2.
+// sum (w - mean)^2.  part: device scratch of 3 * is_reduce_parts(n) doubles.
+int is_reduce_parts(int64_t n);
 int launch_is_reduce(hipStream_t s, const IsDev &d, const double *wf, const unsigned char *fail,
-                     int64_t n, int mode, double mean, double *out);
+                     int64_t n, int mode, double mean, double *out, double *part);
 
 // api.cpp: the work of one search / IS call on an executor
 double sigma2_of(double ebn0_db, double rate);

@@ -728,16 +728,35 @@ __global__ __launch_bounds__((MaxBlockIs<DC, CPT>::value)) void k_is(const IsJob
 
 // Fixed-order reduction over the frames of the importance weights
 // w_f = [frame f failed] exp(-a s^2 / (2 sigma^2) + (s / sigma) sum_{v in T} n_v)
-// (wf holds the sums of the TS-bit normals): thread t sums a contiguous range in
-// frame order, then a fixed binary tree combines the threads.
+// (wf holds the sums of the TS-bit normals).  Stage 1: workgroup g takes the
+// contiguous frame range of chunk g, each thread a contiguous sub-range in frame
+// order, combined by a fixed binary tree into part[g].  Stage 2: one workgroup
+// combines the parts the same way.  The order depends on n only.
 // mode 0: out = {sum w, sum w^2, failures}; mode 1: out[3] = sum (w - mean)^2.
-__global__ __launch_bounds__(1024) void k_is_reduce(const double *wf, const unsigned char *fail,
-                                                     long long n, int mode, double mean, double wconst,
-                                                     double coef, double *out) {
-    __shared__ double s0[1024], s1[1024], s2[1024];
-    const int t = threadIdx.x, B = blockDim.x;
-    const long long per = (n + B - 1) / B;
-    const long long lo = (long long)t * per, hi = lo + per < n ? lo + per : n;
+constexpr int kRedThreads = 256;
+constexpr long long kRedChunk = 16384;   // frames per stage-1 workgroup
+
+__device__ __forceinline__ void red_tree(double *s0, double *s1, double *s2, int t) {
+    __syncthreads();
+    for (int h = kRedThreads / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            s0[t] += s0[t + h];
+            s1[t] += s1[t + h];
+            s2[t] += s2[t + h];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_is_reduce(const double *wf, const unsigned char *fail,
+                                                          long long n, int mode, double mean,
+                                                          double wconst, double coef, double *part) {
+    __shared__ double s0[kRedThreads], s1[kRedThreads], s2[kRedThreads];
+    const int t = threadIdx.x;
+    const long long c0 = (long long)blockIdx.x * kRedChunk;
+    const long long c1 = c0 + kRedChunk < n ? c0 + kRedChunk : n;
+    const long long per = (kRedChunk + kRedThreads - 1) / kRedThreads;
+    const long long lo = c0 + (long long)t * per, hi = lo + per < c1 ? lo + per : c1;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     for (long long i = lo; i < hi; ++i) {
         const double w = fail[i] ? exp(wconst + coef * wf[i]) : 0.0;
@@ -752,15 +771,30 @@ __global__ __launch_bounds__(1024) void k_is_reduce(const double *wf, const unsi
     s0[t] = a0;
     s1[t] = a1;
     s2[t] = a2;
-    __syncthreads();
-    for (int h = B / 2; h > 0; h >>= 1) {
-        if (t < h) {
-            s0[t] += s0[t + h];
-            s1[t] += s1[t + h];
-            s2[t] += s2[t + h];
-        }
-        __syncthreads();
+    red_tree(s0, s1, s2, t);
+    if (t == 0) {
+        part[3 * blockIdx.x] = s0[0];
+        part[3 * blockIdx.x + 1] = s1[0];
+        part[3 * blockIdx.x + 2] = s2[0];
     }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_is_reduce_final(const double *part, int n_parts, int mode,
+                                                                double *out) {
+    __shared__ double s0[kRedThreads], s1[kRedThreads], s2[kRedThreads];
+    const int t = threadIdx.x;
+    const int per = (n_parts + kRedThreads - 1) / kRedThreads;
+    const int lo = t * per, hi = lo + per < n_parts ? lo + per : n_parts;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int i = lo; i < hi; ++i) {
+        a0 += part[3 * i];
+        a1 += part[3 * i + 1];
+        a2 += part[3 * i + 2];
+    }
+    s0[t] = a0;
+    s1[t] = a1;
+    s2[t] = a2;
+    red_tree(s0, s1, s2, t);
     if (t == 0) {
         if (mode == 0) {
             out[0] = s0[0];
@@ -1397,10 +1431,20 @@ IsDev make_is_dev(const IsLaunch &a, const SearchPlan &plan) {
     return d;
 }
 
+int is_reduce_parts(int64_t n) { return (int)((n + kRedChunk - 1) / kRedChunk); }
+
 int launch_is_reduce(hipStream_t stream, const IsDev &d, const double *wf, const unsigned char *fail,
-                     int64_t n, int mode, double mean, double *out) {
-    hipLaunchKernelGGL(k_is_reduce, dim3(1), dim3(1024), 0, stream, wf, fail, (long long)n, mode,
-                       mean, d.wconst, d.shift / d.sigma, out);
+                     int64_t n, int mode, double mean, double *out, double *part) {
+    const int np = is_reduce_parts(n);
+    if (np < 1) {
+        set_error("empty reduction");
+        return TS_E_INVAL;
+    }
+    hipLaunchKernelGGL(k_is_reduce, dim3(np), dim3(kRedThreads), 0, stream, wf, fail, (long long)n, mode,
+                       mean, d.wconst, d.shift / d.sigma, part);
+    TSG_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_is_reduce_final, dim3(1), dim3(kRedThreads), 0, stream, (const double *)part, np,
+                       mode, out);
     TSG_HIP(hipGetLastError());
     return TS_OK;
 }
