@@ -18,8 +18,9 @@ Beside it, with their own figures in the same JSON line:
              codes (N up to 25.7k), 10^3..10^5 frames each (log-uniform),
              through ts_submit: p50/p99 latency and edge-updates/s;
   qc2640   - the (2640,1320) girth-8 QC stand-in: every tree-path triple
-             searched with SPA, then IS of the 16 most harmful TS at 2/3/4/5 dB,
-             10^5 frames each.
+             searched with SPA, and one triple per orbit of the circulant shift
+             (same TS); then the union bound over the 16 most harmful TS at
+             2/3/4/5 dB, 10^5 IS frames each.
 
 Prints one JSON line.  The metric is edge-updates per second (one edge x one
 frame x one executed iteration), with TS found per second beside it.
@@ -434,40 +435,52 @@ def bench_serve(tsg, seconds, rate):
 
 
 def bench_qc2640(tsg):
-    """QC-2640: SPA search over every tree-path triple, then IS of the 16 most
-    harmful TS at 2, 3, 4, 5 dB with 10^5 frames each (shift eps*)."""
+    """QC-2640: SPA search over every tree-path triple and over one triple per
+    orbit of the circulant shift (same TS), then the union bound over the 16
+    most harmful TS at 2, 3, 4, 5 dB with 10^5 IS frames each (shift eps*)."""
+    import numpy as np
     import workloads
     ctx = tsg.Context(0)
     g = ctx.load_code(workloads.qc2640_code())
     pats = g.make_patterns(tsg.PAT_TRIPLES)
+    reps = g.make_patterns(tsg.PAT_TRIPLES | tsg.PAT_QC_ORBITS)
     kw = dict(decoder=tsg.DEC_SPA, max_iter=50, ebn0_db=3.0, k_max=32 * 1024, k_den=1024, a_max=12)
     g.impulse_search(pats[:4096], **kw)   # warm-up / autotune
+    g.impulse_search(reps, **kw)
     g.reset_ts()
     t0 = time.perf_counter()
     r = g.impulse_search(pats, **kw)
-    ts = g.collect()
+    recs, _ = g.collect_arrays()
     t_search = time.perf_counter() - t0
     eu_search = r["stats"]["edge_updates"]
-    fer = {}
-    eu_is = 0
+    g.reset_ts()
     t0 = time.perf_counter()
-    for snr in (2.0, 3.0, 4.0, 5.0):
-        rows = []
-        for i, t in enumerate(ts[:16]):
-            o = g.is_estimate(list(t.bits), snr, -1.0, 100000, seed=3, stream=(int(snr) << 16) | i)
-            eu_is += o["stats"]["edge_updates"]
-            rows.append({"a": t.a, "b": t.b, "orbit": t.orbit, "p_hat": o["p_hat"],
-                         "ci": [o["ci_lo"], o["ci_hi"]]})
-        fer[f"{snr:g}dB"] = {"union_bound": sum(x["orbit"] * x["p_hat"] for x in rows),
-                             "ts": rows[:4]}
-    t_is = time.perf_counter() - t0
+    rr = g.impulse_search(reps, **kw)
+    recs_r, _ = g.collect_arrays()
+    t_reduced = time.perf_counter() - t0
+    same = bool(np.array_equal(recs[["a", "b", "orbit", "k_crit"]], recs_r[["a", "b", "orbit", "k_crit"]]))
+    spectrum = g.spectrum(a_max=12, b_max=12, by_orbit=False)
+    n_ts = min(16, len(recs_r))
+    snrs = [2.0, 3.0, 4.0, 5.0]
+    t0 = time.perf_counter()
+    ub = g.union_bound(n_ts, snrs, 100000, seed=3, shift=-1.0, per_ts=True)
+    t_ub = time.perf_counter() - t0
+    eu_ub = ub["stats"]["edge_updates"]
     ctx.close()
+    cells = {f"{a},{b}": int(spectrum[a, b]) for a in range(spectrum.shape[0])
+             for b in range(spectrum.shape[1]) if spectrum[a, b]}
     return {"workload": "QC (3,6) N=2640 Z=440 girth 8 (seed 3): SPA-f32 50it search over "
-                        f"{len(pats)} triples, then IS of the top 16 TS x 4 SNRs x 1e5 frames",
-            "ts_found": len(ts), "search": {"seconds": t_search, "edge_updates": eu_search,
-                                            "edge_updates_per_s": eu_search / t_search},
-            "is": {"seconds": t_is, "edge_updates": eu_is, "edge_updates_per_s": eu_is / t_is,
-                   "fer": fer}}
+                        f"{len(pats)} triples and over the {len(reps)} orbit representatives, then the "
+                        f"union bound over the top {n_ts} TS x 4 SNRs x 1e5 IS frames",
+            "ts_found": int(len(recs)), "spectrum_all_sets": cells,
+            "search": {"seconds": t_search, "edge_updates": eu_search,
+                       "edge_updates_per_s": eu_search / t_search},
+            "search_orbit_reduced": {"patterns": int(len(reps)), "seconds": t_reduced,
+                                     "edge_updates": rr["stats"]["edge_updates"],
+                                     "speedup": t_search / t_reduced, "same_ts": same},
+            "union_bound": {"seconds": t_ub, "edge_updates": eu_ub, "edge_updates_per_s": eu_ub / t_ub,
+                            "fer": {f"{p['ebn0_db']:g}dB": {"fer": p["fer"], "ci": [p["ci_lo"], p["ci_hi"]]}
+                                    for p in ub["points"]}}}
 
 
 def cpu_baseline(code, pats, seconds):

@@ -110,10 +110,18 @@ int ts_free_code(ts_ctx *ctx, ts_code *code);
 #define TS_PAT_SINGLES 1   /* every variable alone (width 1) */
 #define TS_PAT_PAIRS 2     /* every pair at Tanner distance 2 or 4 (width 2) */
 #define TS_PAT_TRIPLES 3   /* every {v1,v2,v3} on a tree path v1-c-v2-c'-v3, c != c' (width 3) */
+/* OR-ed into the kind for a QC code: one pattern per orbit of the circulant
+ * shift v = jz + c -> jz + (c + t) mod z (the automorphism of Section II), namely
+ * the one equal to its canonical form (the lexicographically smallest sorted
+ * image).  The family lists are unions of whole orbits and the decoders commute
+ * with the shift, so searching the reduced list finds the same canonical TS with
+ * the same k*; only first_pattern indexes the shorter list.  About z-fold
+ * fewer patterns.  TS_E_INVAL for a code loaded in CSR form. */
+#define TS_PAT_QC_ORBITS 0x100
 
-/* Writes the sorted pattern list of one family (row-major, width = kind) to the
- * host array out when cap (in patterns) allows; *n_out = number of patterns.
- * Returns TS_E_TRUNC when cap is too small (out untouched). */
+/* Writes the sorted pattern list of one family (row-major, width = kind & 0xff)
+ * to the host array out when cap (in patterns) allows; *n_out = number of
+ * patterns.  Returns TS_E_TRUNC when cap is too small (out untouched). */
 int ts_make_patterns(ts_ctx *ctx, const ts_code *code, int32_t kind, int32_t *out,
                      int64_t cap, int64_t *n_out);
 
@@ -219,6 +227,44 @@ typedef struct {
  * array [n_frames]) receives each frame's failure flag. */
 int ts_is_estimate(ts_ctx *ctx, ts_code *code, const int32_t *ts_bits, int32_t a,
                    const ts_is_opts *opts, ts_is_result *res, uint8_t *fail_out);
+
+/* ---- TS spectrum and union bound (Section III; Tables III and IV) -------- */
+
+/* The code's TS table counted by (a, b): counts[a * (b_max + 1) + b] for
+ * 0 <= a <= a_max, 0 <= b <= b_max (caller-owned, overwritten), each canonical
+ * TS counted once (by_orbit != 0, one per QC orbit) or with its orbit size
+ * (by_orbit == 0, every set of the code).  Sets beyond the bounds are not
+ * counted.  Errors: TS_E_INVAL (a_max outside 1..16, b_max outside 0..1024). */
+int ts_spectrum(ts_ctx *ctx, const ts_code *code, int32_t a_max, int32_t b_max, int32_t by_orbit,
+                int64_t *counts);
+
+typedef struct {
+    int32_t n_ts;            /* the first n_ts sets of the code's TS table, in its order */
+    int32_t n_snr;
+    const double *ebn0_db;   /* [n_snr] host array */
+    int32_t max_iter;        /* SPA iterations */
+    double rate;             /* design rate for sigma */
+    double shift;            /* IS mean shift; < 0: eps* of each set (ts_is_estimate) */
+    int64_t n_frames;        /* frames per (set, SNR), >= 2 */
+    uint64_t seed;           /* Philox key; stream tag of (set t, SNR i) = (i << 16) | t */
+    int32_t layout;          /* TS_LAYOUT_* */
+} ts_ub_opts;
+
+typedef struct {
+    double ebn0_db;
+    double fer;              /* sum over the sets of orbit x P_hat */
+    double var;              /* sum over the sets of orbit^2 x Var(P_hat) */
+    double ci_lo, ci_hi;     /* fer -+ 1.96 sqrt(var) */
+} ts_ub_point;
+
+/* Union bound on the frame error rate of the code's decoder (Section III):
+ * FER(SNR) ~ sum over the canonical sets T of orbit(T) x P_T(SNR), each P_T an
+ * importance-sampling estimate as in ts_is_estimate.  All n_ts x n_snr
+ * estimates run as one batch.  out[n_snr] receives the bound per SNR; per_ts,
+ * if not NULL, [n_snr][n_ts] the individual estimates.  Errors: TS_E_INVAL
+ * (fewer than n_ts sets in the table, n_ts x n_snr > 4096, bad options). */
+int ts_union_bound(ts_ctx *ctx, ts_code *code, const ts_ub_opts *opts, ts_ub_point *out,
+                   ts_is_result *per_ts);
 
 /* ---- serving: continuous batching of submitted jobs ------------------------ */
 

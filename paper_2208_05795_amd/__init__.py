@@ -18,10 +18,11 @@ from . import _capi as A
 
 __all__ = ["Context", "Code", "TsRecord", "TsgError", "DEC_OMS", "DEC_SPA",
            "PAT_SINGLES", "PAT_PAIRS", "PAT_TRIPLES", "EXTRACT_PATH", "EXTRACT_CRITICAL",
-           "LAYOUT_AUTO", "LAYOUT_REGISTER", "LAYOUT_STREAMED"]
+           "LAYOUT_AUTO", "LAYOUT_REGISTER", "LAYOUT_STREAMED", "PAT_QC_ORBITS"]
 
 DEC_OMS, DEC_SPA = A.TS_DEC_OMS_I8, A.TS_DEC_SPA_F32
 PAT_SINGLES, PAT_PAIRS, PAT_TRIPLES = A.TS_PAT_SINGLES, A.TS_PAT_PAIRS, A.TS_PAT_TRIPLES
+PAT_QC_ORBITS = A.TS_PAT_QC_ORBITS
 EXTRACT_PATH, EXTRACT_CRITICAL = A.TS_EXTRACT_PATH, A.TS_EXTRACT_CRITICAL
 LAYOUT_AUTO, LAYOUT_REGISTER, LAYOUT_STREAMED = A.TS_LAYOUT_AUTO, A.TS_LAYOUT_REGISTER, A.TS_LAYOUT_STREAMED
 
@@ -295,7 +296,7 @@ class Code:
     def make_patterns(self, kind: int) -> np.ndarray:
         n = C.c_int64()
         _check(lib().ts_make_patterns(self.ctx.handle, self._h, kind, None, 0, C.byref(n)))
-        out = np.zeros((n.value, kind), dtype=np.int32)
+        out = np.zeros((n.value, kind & 0xff), dtype=np.int32)
         _check(lib().ts_make_patterns(self.ctx.handle, self._h, kind, out.ctypes.data,
                                       n.value, C.byref(n)))
         return out
@@ -363,6 +364,32 @@ class Code:
     def collect(self) -> List[TsRecord]:
         recs, bits = self.collect_arrays()
         return _ts_records(recs, bits)
+
+    def spectrum(self, a_max: int = 12, b_max: int = 16, by_orbit: bool = True) -> np.ndarray:
+        """counts[a, b] of the TS table (ts_spectrum): canonical sets, or every set
+        (orbit-weighted) when by_orbit is False."""
+        out = np.zeros((a_max + 1, b_max + 1), dtype=np.int64)
+        _check(lib().ts_spectrum(self.ctx.handle, self._h, a_max, b_max, int(by_orbit),
+                                 out.ctypes.data))
+        return out
+
+    def union_bound(self, n_ts: int, ebn0_db, n_frames: int, seed: int, shift: float = -1.0,
+                    max_iter: int = 50, rate: Optional[float] = None, layout: int = 0,
+                    per_ts: bool = False) -> dict:
+        """FER ~ sum over the first n_ts sets of the TS table of orbit x P_hat
+        (ts_union_bound), one IS batch over all (set, SNR) pairs."""
+        snr = np.ascontiguousarray(np.asarray(ebn0_db, dtype=np.float64).reshape(-1))
+        rate = (1.0 - self.m / self.n) if rate is None else rate
+        o = A.UbOpts(n_ts, snr.size, snr.ctypes.data, max_iter, rate, shift, n_frames, seed, layout)
+        pts = (A.UbPoint * snr.size)()
+        rs = (A.IsResult * (snr.size * n_ts))() if per_ts else None
+        _check(lib().ts_union_bound(self.ctx.handle, self._h, C.byref(o), pts, rs))
+        out = {"points": [{f: getattr(p, f) for f, _ in A.UbPoint._fields_} for p in pts]}
+        if per_ts:
+            out["per_ts"] = [[{f: getattr(rs[i * n_ts + t], f) for f, _ in A.IsResult._fields_}
+                              for t in range(n_ts)] for i in range(snr.size)]
+        out["stats"] = self.ctx.stats()
+        return out
 
     def reset_ts(self):
         _check(lib().ts_reset_ts(self.ctx.handle, self._h))

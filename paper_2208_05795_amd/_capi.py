@@ -13,6 +13,7 @@ TS_DEC_OMS_I8, TS_DEC_SPA_F32 = 0, 1
 TS_EXTRACT_PATH, TS_EXTRACT_CRITICAL = 0, 1
 TS_MEM_HOST, TS_MEM_DEVICE = 0, 1
 TS_LAYOUT_AUTO, TS_LAYOUT_REGISTER, TS_LAYOUT_STREAMED = 0, 1, 2
+TS_PAT_QC_ORBITS = 0x100
 TS_JOB_SEARCH, TS_JOB_IS = 1, 2
 TS_JOB_QUEUED, TS_JOB_RUNNING, TS_JOB_DONE, TS_JOB_CANCELLED = 0, 1, 2, 3
 
@@ -67,6 +68,17 @@ class IsResult(C.Structure):
                 ("n", C.c_int64), ("n_fail", C.c_int64), ("shift_used", C.c_double)]
 
 
+class UbOpts(C.Structure):
+    _fields_ = [("n_ts", C.c_int32), ("n_snr", C.c_int32), ("ebn0_db", C.c_void_p),
+                ("max_iter", C.c_int32), ("rate", C.c_double), ("shift", C.c_double),
+                ("n_frames", C.c_int64), ("seed", C.c_uint64), ("layout", C.c_int32)]
+
+
+class UbPoint(C.Structure):
+    _fields_ = [("ebn0_db", C.c_double), ("fer", C.c_double), ("var", C.c_double),
+                ("ci_lo", C.c_double), ("ci_hi", C.c_double)]
+
+
 class JobDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("code", C.c_void_p), ("search", SearchOpts),
                 ("patterns", C.c_void_p), ("n_patterns", C.c_int32), ("width", C.c_int32),
@@ -107,6 +119,8 @@ PROTOTYPES = {
     "ts_is_estimate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                  C.POINTER(IsOpts), C.POINTER(IsResult), C.c_void_p]),
     "ts_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
+    "ts_spectrum": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]),
+    "ts_union_bound": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(UbOpts), C.c_void_p, C.c_void_p]),
     "ts_serve_start": (C.c_int, [C.c_void_p, C.c_int32]),
     "ts_submit": (C.c_int, [C.c_void_p, C.POINTER(JobDesc), C.POINTER(C.c_uint64)]),
     "ts_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, C.POINTER(JobInfo)]),

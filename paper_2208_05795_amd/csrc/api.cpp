@@ -772,7 +772,11 @@ int ts_make_patterns(ts_ctx *ctx, const ts_code *code, int32_t kind, int32_t *ou
     clear_error();
     if (!ctx || !code || !n_out || (cap > 0 && !out)) { set_error("null argument"); return TS_E_INVAL; }
     const int64_t n = make_patterns(code, kind, nullptr, 0);
-    if (n < 0) { set_error("unknown pattern kind %d", kind); return TS_E_INVAL; }
+    if (n < 0) {
+        set_error((kind & TS_PAT_QC_ORBITS) && code->z <= 0 ? "orbit reduction needs a code in QC form"
+                                                            : "unknown pattern kind %d", kind);
+        return TS_E_INVAL;
+    }
     *n_out = n;
     if (cap < n) {
         if (cap > 0) set_error("pattern buffer holds %lld, need %lld", (long long)cap, (long long)n);

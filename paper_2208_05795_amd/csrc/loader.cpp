@@ -5,6 +5,7 @@
 // column (r+s) mod z; block (i,j) with exponent s joins check i*z+r to variable
 // j*z+(r+s) mod z, and exponent -1 is the zero block.
 #include <algorithm>
+#include <climits>
 #include <array>
 #include <cstring>
 #include <queue>
@@ -241,10 +242,55 @@ int upload_code(ts_exec &ex, ts_code *c) {
     return TS_OK;
 }
 
+namespace {
+
+// Canonical form of a variable set under the QC shift v = jz + c -> jz + (c+t)
+// mod z: the lexicographically smallest sorted image.  Its first element is an
+// image of an element of the lowest block column at offset 0, so only the shifts
+// that map such an element to offset 0 can produce it.
+void canon_set(const int32_t *p, int k, int z, std::vector<int32_t> &best, std::vector<int32_t> &tmp) {
+    int jmin = INT32_MAX;
+    for (int i = 0; i < k; ++i) jmin = std::min(jmin, p[i] / z);
+    best.assign(p, p + k);
+    std::sort(best.begin(), best.end());
+    bool have = false;
+    for (int i = 0; i < k; ++i) {
+        if (p[i] / z != jmin) continue;
+        const int t = (z - p[i] % z) % z;
+        tmp.resize(k);
+        for (int q = 0; q < k; ++q) tmp[q] = (p[q] / z) * z + (p[q] % z + t) % z;
+        std::sort(tmp.begin(), tmp.end());
+        if (!have || tmp < best) {
+            best = tmp;
+            have = true;
+        }
+    }
+}
+
+}  // namespace
+
 // Impulse pattern families drawn from the depth-3 impulse tree of Section III
 // (VN1-CN1-VN2-CN2-VN3): single roots, pairs of variables at Tanner distance 2
-// or 4, and the variable sets of tree paths v1-c-v2-c'-v3 with c != c'.
+// or 4, and the variable sets of tree paths v1-c-v2-c'-v3 with c != c'.  With
+// TS_PAT_QC_ORBITS only the patterns equal to their canonical QC form.
 int64_t make_patterns(const ts_code *c, int kind, int32_t *out, int64_t cap) {
+    if (kind & TS_PAT_QC_ORBITS) {
+        const int base = kind & 0xff;
+        if (c->z <= 0 || base < 1 || base > 3 || (kind & ~(0xff | TS_PAT_QC_ORBITS))) return -1;
+        const int64_t n = make_patterns(c, base, nullptr, 0);
+        std::vector<int32_t> all((size_t)n * base);
+        make_patterns(c, base, all.data(), n);
+        std::vector<int32_t> best, tmp;
+        int64_t cnt = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t *p = all.data() + i * base;   // sorted ascending
+            canon_set(p, base, c->z, best, tmp);
+            if (!std::equal(best.begin(), best.end(), p)) continue;
+            if (cnt < cap) std::memcpy(out + cnt * base, p, base * 4);
+            ++cnt;
+        }
+        return cnt;
+    }
     const int n = c->n;
     auto checks_of = [&](int v, auto &&f) {
         for (int64_t p = c->vptr[v]; p < c->vptr[v + 1]; ++p) f(c->vchk[p]);

@@ -49,7 +49,8 @@ def test_struct_sizes_match_header(libpath, tmp_path):
     structs = {"ts_ctx_opts": A.CtxOpts, "ts_code_desc": A.CodeDesc, "ts_code_info_t": A.CodeInfo,
                "ts_search_opts": A.SearchOpts, "ts_search_out": A.SearchOut, "ts_record": A.Record,
                "ts_is_opts": A.IsOpts, "ts_is_result": A.IsResult, "ts_stats": A.Stats,
-               "ts_job_desc": A.JobDesc, "ts_job_info": A.JobInfo}
+               "ts_job_desc": A.JobDesc, "ts_job_info": A.JobInfo, "ts_ub_opts": A.UbOpts,
+               "ts_ub_point": A.UbPoint}
     cname_of = {"is_": "is"}   # Python field names that are keywords
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "tsgpu.h"', "int main(void){"]
     for cname, py in structs.items():
