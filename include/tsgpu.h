@@ -228,6 +228,19 @@ typedef struct {
 int ts_is_estimate(ts_ctx *ctx, ts_code *code, const int32_t *ts_bits, int32_t a,
                    const ts_is_opts *opts, ts_is_result *res, uint8_t *fail_out);
 
+/* ---- cycle / EMD spectrum (Section II, Table II) ------------------------- */
+
+/* Simple cycles of length 4..max_len of a QC code through the position-0
+ * variable of every block column, found by walking exponent chains on the base
+ * matrix (a walk closes when its alternating shift sum is 0 mod z, Section II),
+ * bucketed by length and EMD (the number of (cycle variable, check) incidences
+ * whose check meets the cycle in exactly one variable):
+ * out[(len / 2) * (emd_max + 1) + emd] (caller-owned, overwritten) counts
+ * (cycle, position-0 variable) incidences, so an orbit of cycles of length 2l
+ * adds l.  EMD above emd_max is counted at emd_max.  Host computation.
+ * Errors: TS_E_INVAL (CSR-form code, max_len not even in 4..16). */
+int ts_cycle_emd(ts_ctx *ctx, const ts_code *code, int32_t max_len, int32_t emd_max, int64_t *out);
+
 /* ---- TS spectrum and union bound (Section III; Tables III and IV) -------- */
 
 /* The code's TS table counted by (a, b): counts[a * (b_max + 1) + b] for

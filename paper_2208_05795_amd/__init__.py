@@ -365,6 +365,13 @@ class Code:
         recs, bits = self.collect_arrays()
         return _ts_records(recs, bits)
 
+    def cycle_emd(self, max_len: int = 8, emd_max: int = 32) -> np.ndarray:
+        """counts[len // 2, emd] of simple cycles through the position-0 variable of
+        each block column (ts_cycle_emd); an orbit of 2l-cycles adds l."""
+        out = np.zeros((max_len // 2 + 1, emd_max + 1), dtype=np.int64)
+        _check(lib().ts_cycle_emd(self.ctx.handle, self._h, max_len, emd_max, out.ctypes.data))
+        return out
+
     def spectrum(self, a_max: int = 12, b_max: int = 16, by_orbit: bool = True) -> np.ndarray:
         """counts[a, b] of the TS table (ts_spectrum): canonical sets, or every set
         (orbit-weighted) when by_orbit is False."""

@@ -119,6 +119,7 @@ PROTOTYPES = {
     "ts_is_estimate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                  C.POINTER(IsOpts), C.POINTER(IsResult), C.c_void_p]),
     "ts_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
+    "ts_cycle_emd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     "ts_spectrum": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]),
     "ts_union_bound": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(UbOpts), C.c_void_p, C.c_void_p]),
     "ts_serve_start": (C.c_int, [C.c_void_p, C.c_int32]),

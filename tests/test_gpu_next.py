@@ -8,6 +8,8 @@ spectrum in the form of Tables III/IV, and the union bound on the FER.
 * The spectrum equals the counts of the oracle's TS list (bit-exact search).
 * The union bound equals sum over sets of orbit x P_hat with the oracle's
   estimates of the same Philox frames, within 2% or the oracle's CI.
+* The cycle / EMD spectrum walked on the base matrix reproduces Table II for
+  Code 1 and equals the oracle's expanded-graph enumeration on other codes.
 """
 import numpy as np
 import pytest
@@ -134,4 +136,58 @@ def test_union_bound_validation(ctx, tiny):
     g.reset_ts()
     with pytest.raises(tsg.TsgError):   # empty table
         g.union_bound(1, [3.0], 100, seed=1)
+    g.free()
+
+
+def _table2():
+    import os
+    out = {}
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "table2_code1_emd.txt")) as f:
+        for line in f:
+            line = line.split("#", 1)[0].split()
+            if line:
+                L, emd, cnt = (int(x) for x in line)
+                out[(L, emd)] = cnt
+    return out
+
+
+def test_cycle_emd_table2(ctx):
+    """The library's chain walk reproduces Table II (Code 1, Table V): 4- and
+    6-cycles exactly; 8-cycles at EMD 3..7 (Table II counts exponent chains,
+    so its 8,2 entry is the girth-4 chain walked twice and its 8,8 entry rounds
+    5380.5 orbits)."""
+    g = ctx.load_code(workloads.table5_code1())
+    out = g.cycle_emd(max_len=8, emd_max=16)
+    tab = _table2()
+    for L in (4, 6):
+        half = L // 2
+        got = {emd: out[half, emd] / half for emd in range(out.shape[1]) if out[half, emd]}
+        want = {emd: float(cnt) for (l, emd), cnt in tab.items() if l == L}
+        assert got == want, (L, got, want)
+    got8 = {emd: out[4, emd] / 4 for emd in range(out.shape[1]) if out[4, emd]}
+    for emd in range(3, 8):
+        assert got8.get(emd, 0) == tab[(8, emd)], emd
+    assert got8.get(2, 0) == 0 and got8[8] == 5380.5
+    _say(f"Table II reproduced: {int(out.sum())} cycle incidences up to length 8")
+    g.free()
+
+
+@pytest.mark.parametrize("name,max_len", [("tiny", 8), ("qc2640", 10), ("batch", 8)])
+def test_cycle_emd_matches_oracle(ctx, oracle_mod, name, max_len):
+    code = {"tiny": workloads.tiny_code, "qc2640": workloads.qc2640_code,
+            "batch": lambda: workloads.batch_codes()[3]}[name]()
+    oc = oracle_mod.OCode(code)
+    want, _, _ = oracle_mod.cycle_emd(oc, max_len=max_len, emd_max=24)
+    g = ctx.load_code(code)
+    got = g.cycle_emd(max_len=max_len, emd_max=24)
+    assert np.array_equal(got, want)
+    g.free()
+
+
+def test_cycle_emd_rejects_csr(ctx):
+    import paper_2208_05795_amd as tsg
+    g = ctx.load_code(workloads.peg1008_code())
+    with pytest.raises(tsg.TsgError):
+        g.cycle_emd()
     g.free()
