@@ -18,7 +18,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 PAT_SINGLES, PAT_PAIRS, PAT_TRIPLES = 1, 2, 3
-DEC_OMS, DEC_SPA = 0, 1
+DEC_OMS, DEC_SPA, DEC_LNMS = 0, 1, 2
 EXTRACT_PATH, EXTRACT_CRITICAL = 0, 1
 
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
@@ -81,6 +81,11 @@ def lib():
     L.or_decode_spa.argtypes = [vp, _f64p, C.c_int, vp, vp, vp]
     L.or_decode_oms_ex.restype = DecResult
     L.or_decode_oms_ex.argtypes = [vp, _i32p, C.c_int, C.c_int, vp, vp, vp]
+    L.or_decode_lnms.restype = DecResult
+    L.or_decode_lnms.argtypes = [vp, _i32p, C.c_int, vp, vp, vp]
+    L.or_layers.argtypes = [vp, _i32p]
+    L.or_q4_base.argtypes = [C.c_double, C.c_double, C.c_double]
+    L.or_q4_impulse.argtypes = [C.c_int, C.c_int]
     L.or_decode_spa_ex.restype = DecResult
     L.or_decode_spa_ex.argtypes = [vp, _f64p, C.c_int, vp, vp, vp, C.c_int]
     L.or_patterns.restype = C.c_int64
@@ -174,6 +179,35 @@ def decode_oms(oc: OCode, q_llr, max_iter: int = 20, offset: int = 1, hist: bool
     if hist:
         out["hist"] = hb[:r.iters]
     return out
+
+
+def decode_lnms(oc: OCode, q_llr, max_iter: int = 20, hist: bool = False):
+    """Quantised normalised layered min-sum (4-bit channel / c2v, 6-bit v2c / APP)."""
+    q = _i32(q_llr)
+    hb = np.zeros((max_iter, oc.n), dtype=np.uint8) if hist else None
+    sy = np.zeros(max_iter, dtype=np.int32)
+    app = np.zeros(oc.n, dtype=np.int32)
+    r = lib().or_decode_lnms(oc.handle, q, max_iter, hb.ctypes.data if hist else None,
+                             sy.ctypes.data, app.ctypes.data)
+    out = dict(fail=r.fail, iters=r.iters, tmin=r.tmin, wmin=r.wmin, synd=sy[:r.iters], app=app)
+    if hist:
+        out["hist"] = hb[:r.iters]
+    return out
+
+
+def layers(oc: OCode) -> Tuple[int, np.ndarray]:
+    """Layer of every check in the layered schedule, and the number of layers."""
+    lay = np.zeros(max(oc.m, 1), dtype=np.int32)
+    n = lib().or_layers(oc.handle, lay)
+    return n, lay[:oc.m]
+
+
+def q4_base(ebn0_db: float, rate: float, scale: float = 1.0) -> int:
+    return lib().or_q4_base(ebn0_db, rate, scale)
+
+
+def q4_impulse(qb: int, k: int) -> int:
+    return lib().or_q4_impulse(qb, k)
 
 
 def decode_spa(oc: OCode, llr, max_iter: int = 50, hist: bool = False, early_stop: bool = True):

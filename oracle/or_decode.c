@@ -158,6 +158,106 @@ or_dec_result or_decode_spa_ex(const or_code *c, const double *llr, int max_iter
     return res;
 }
 
+/* ---- quantised normalised layered min-sum (Section III, Fig. 2) ---------- */
+/* Reading of the paper's "quantized normalized layered min-sum, 4/4/6 bits":
+ * channel values and check-to-variable messages on 4 bits ([-7, 7]),
+ * variable-to-check messages and APP values on 6 bits ([-31, 31]); the check
+ * rule scales the min-sum magnitude by 3/4 (rounded down); the layers are the
+ * block rows of a QC code, otherwise the checks in index order each put in the
+ * first layer that holds none of its variables. */
+
+static int sat7(int x) { return x > 7 ? 7 : (x < -7 ? -7 : x); }
+static int sat31(int x) { return x > 31 ? 31 : (x < -31 ? -31 : x); }
+
+int or_layers(const or_code *c, int32_t *layer) {
+    if (c->z > 0) {
+        for (int r = 0; r < c->m; r++) layer[r] = r / c->z;
+        return c->mb;
+    }
+    /* owner[v * cap + L] = 1 if layer L holds a check of variable v */
+    int n_layers = 0, cap = 64;
+    uint8_t *owner = calloc((size_t)c->n * cap, 1);
+    for (int r = 0; r < c->m; r++) {
+        int L = 0;
+        for (;; L++) {
+            if (L >= cap) { free(owner); return -1; }
+            int clash = 0;
+            for (int64_t k = c->row_ptr[r]; k < c->row_ptr[r + 1] && !clash; k++)
+                clash = owner[(size_t)c->col[k] * cap + L];
+            if (!clash) break;
+        }
+        layer[r] = L;
+        for (int64_t k = c->row_ptr[r]; k < c->row_ptr[r + 1]; k++)
+            owner[(size_t)c->col[k] * cap + L] = 1;
+        if (L + 1 > n_layers) n_layers = L + 1;
+    }
+    free(owner);
+    return n_layers;
+}
+
+or_dec_result or_decode_lnms(const or_code *c, const int32_t *q_llr, int max_iter, uint8_t *hist,
+                             int32_t *synd, int32_t *app_out) {
+    or_dec_result res = {0, 0, 0, 0};
+    int32_t *layer = malloc(sizeof(int32_t) * (size_t)(c->m > 0 ? c->m : 1));
+    int n_layers = or_layers(c, layer);
+    int32_t *c2v = calloc((size_t)c->e, sizeof(int32_t));
+    int32_t *v2c = malloc(sizeof(int32_t) * (size_t)c->e);
+    int32_t *app = malloc(sizeof(int32_t) * (size_t)c->n);
+    uint8_t *x = malloc((size_t)c->n);
+    for (int v = 0; v < c->n; v++) app[v] = sat7(q_llr[v]);
+    int wbest = -1, t;
+    for (t = 1; t <= max_iter; t++) {
+        for (int L = 0; L < n_layers; L++)
+            for (int r = 0; r < c->m; r++) {
+                if (layer[r] != L) continue;
+                for (int64_t k = c->row_ptr[r]; k < c->row_ptr[r + 1]; k++)
+                    v2c[k] = sat31(app[c->col[k]] - c2v[k]);
+                /* each edge from the other edges of the check */
+                for (int64_t k = c->row_ptr[r]; k < c->row_ptr[r + 1]; k++) {
+                    int sign = 1, mn = 1 << 30;
+                    for (int64_t k2 = c->row_ptr[r]; k2 < c->row_ptr[r + 1]; k2++) {
+                        if (k2 == k) continue;
+                        if (v2c[k2] < 0) sign = -sign;
+                        int a = abs(v2c[k2]);
+                        if (a < mn) mn = a;
+                    }
+                    c2v[k] = sign * sat7((3 * mn) / 4);
+                }
+                for (int64_t k = c->row_ptr[r]; k < c->row_ptr[r + 1]; k++)
+                    app[c->col[k]] = sat31(v2c[k] + c2v[k]);
+            }
+        for (int v = 0; v < c->n; v++) x[v] = (uint8_t)(app[v] < 0);
+        int w = syndrome_weight(c, x);
+        if (hist) memcpy(hist + (size_t)(t - 1) * c->n, x, (size_t)c->n);
+        if (synd) synd[t - 1] = w;
+        if (wbest < 0 || w < wbest) { wbest = w; res.tmin = t; }
+        if (w == 0) break;
+    }
+    res.iters = t > max_iter ? max_iter : t;
+    res.wmin = wbest;
+    res.fail = 0;
+    for (int v = 0; v < c->n; v++) res.fail |= x[v];
+    if (app_out) memcpy(app_out, app, sizeof(int32_t) * (size_t)c->n);
+    free(layer);
+    free(c2v);
+    free(v2c);
+    free(app);
+    free(x);
+    return res;
+}
+
+int or_q4_base(double ebn0_db, double rate, double scale) {
+    double h = 2.0 / or_sigma2(ebn0_db, rate);
+    return sat7((int)lround(scale * h));
+}
+
+int or_q4_impulse(int q_base, int k) {
+    long n = (long)q_base * (16 - k);
+    long mag = (labs(n) + 8) / 16;
+    long q = n < 0 ? -mag : mag;
+    return sat7((int)(q > 1000 ? 1000 : (q < -1000 ? -1000 : q)));
+}
+
 /* ---- channel values ------------------------------------------------------ */
 
 double or_sigma2(double ebn0_db, double rate) {

@@ -171,6 +171,12 @@ static or_dec_result decode_at(worker *w, const int32_t *pat, int width, int k,
             if (pat[i] >= 0) w->q[pat[i]] = or_q_impulse(w->q_base, k);
         return or_decode_oms(c, w->q, w->o->max_iter, w->o->oms_offset, hist, NULL);
     }
+    if (w->o->decoder == OR_DEC_LNMS) {
+        for (int v = 0; v < c->n; v++) w->q[v] = w->q_base;
+        for (int i = 0; i < width; i++)
+            if (pat[i] >= 0) w->q[pat[i]] = or_q4_impulse(w->q_base, k);
+        return or_decode_lnms(c, w->q, w->o->max_iter, hist, NULL, NULL);
+    }
     double eps = (double)k / (double)w->o->k_den;
     for (int v = 0; v < c->n; v++) w->llr[v] = w->h;
     for (int i = 0; i < width; i++)
@@ -243,7 +249,8 @@ int or_search(const or_code *c, const or_search_opts *o, const int32_t *patterns
         memset(&w, 0, sizeof(w));
         w.c = c;
         w.o = o;
-        w.q_base = or_q_base(o->ebn0_db, o->rate, o->llr_scale);
+        w.q_base = o->decoder == OR_DEC_LNMS ? or_q4_base(o->ebn0_db, o->rate, o->llr_scale)
+                                             : or_q_base(o->ebn0_db, o->rate, o->llr_scale);
         w.h = 2.0 / or_sigma2(o->ebn0_db, o->rate);
         w.t0 = t0;
         w.cap = 2 * o->a_max;

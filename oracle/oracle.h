@@ -85,6 +85,22 @@ or_dec_result or_decode_spa_ex(const or_code *c, const double *llr, int max_iter
                                uint8_t *hist, int32_t *synd, double *app_out,
                                int early_stop);
 
+/* Quantised normalised layered min-sum (Section III, Fig. 2; the 4/4/6-bit
+ * reading): channel values and check-to-variable messages in [-7, 7],
+ * variable-to-check messages and APP values in [-31, 31], check magnitude =
+ * floor(3/4 min), layers processed in order with immediate APP updates.
+ * q_llr[n] are 4-bit channel values (saturated on entry). */
+or_dec_result or_decode_lnms(const or_code *c, const int32_t *q_llr, int max_iter, uint8_t *hist,
+                             int32_t *synd, int32_t *app_out);
+/* Layers of that schedule: block rows of a QC code; otherwise each check, in
+ * index order, in the first layer holding none of its variables.  layer[m];
+ * returns the number of layers (-1 if more than 64). */
+int or_layers(const or_code *c, int32_t *layer);
+/* 4-bit channel values: sat7(round_half_away(scale h)); impulse bits
+ * sat7(round_half_away(q_base (16 - k) / 16)). */
+int or_q4_base(double ebn0_db, double rate, double scale);
+int or_q4_impulse(int q_base, int k);
+
 /* ---- impulse patterns (Section III, impulse tree of Fig. 3) --------------- */
 #define OR_PAT_SINGLES 1  /* every variable alone */
 #define OR_PAT_PAIRS 2    /* every pair at Tanner distance 2 or 4 */
@@ -108,10 +124,11 @@ int or_canon(const or_code *c, const int32_t *set, int k, int32_t *out, int32_t 
 /* ---- impulse search with bisection (Section III) ------------------------- */
 #define OR_DEC_OMS 0
 #define OR_DEC_SPA 1
+#define OR_DEC_LNMS 2     /* quantised normalised layered min-sum (k_den = 16) */
 #define OR_EXTRACT_PATH 0
 #define OR_EXTRACT_CRITICAL 1
 typedef struct {
-    int32_t decoder;           /* OR_DEC_OMS / OR_DEC_SPA */
+    int32_t decoder;           /* OR_DEC_OMS / OR_DEC_SPA / OR_DEC_LNMS */
     int32_t max_iter;
     int32_t oms_offset;        /* beta */
     double ebn0_db, rate;

@@ -125,3 +125,67 @@ def test_decode_stops_on_nonzero_codeword_is_failure(oracle_mod, tiny, tiny_sear
     r = oracle_mod.decode_oms(oc, q, 20, 1, hist=True)
     assert r["fail"] == 1 and r["synd"][-1] == 0
     assert set(np.nonzero(r["hist"][-1])[0]) == set(cw)
+
+
+# ---- quantised normalised layered min-sum (4/4/6 bits) -----------------------
+
+def test_lnms_noiseless_tiny_by_hand(oracle_mod, tiny):
+    """Every variable of the tiny 3x6 code lies in one check of each block row
+    (layer).  With channel value 4 everywhere: layer 0 sends floor(3*4/4) = 3
+    (APP 7), layer 1 floor(3*7/4) = 5 (APP 12), layer 2 sat7(floor(3*12/4) = 9)
+    = 7 (APP 19); the syndrome is 0 after the first iteration."""
+    c, oc = tiny
+    n_layers, lay = oracle_mod.layers(oc)
+    assert n_layers == 3 and list(lay) == [r // c.z for r in range(c.m)]
+    r = oracle_mod.decode_lnms(oc, np.full(oc.n, 4), max_iter=20)
+    assert r["iters"] == 1 and r["fail"] == 0
+    assert (r["app"] == 19).all()
+
+
+def test_lnms_two_layers_by_hand(oracle_mod):
+    """Checks {0,1,2} and {2,3,4} share variable 2, so they form two layers.
+    Channel (4, 4, -3, 4, 4): layer 0 sends -floor(3*3/4) = -2 to variables 0
+    and 1 (APP 2, 2) and +floor(3*4/4) = 3 to variable 2 (APP 0); layer 1 reads
+    v2c 0 from variable 2, sends it +3 (APP 3) and, through the zero (sign +),
+    +0 to variables 3 and 4 (APP 4, 4).  Channel (7, 7, -7, 7, 7): layer 0 gives
+    APP (2, 2, -2); layer 1 sends +5 to variable 2 (APP 3) and -floor(3*2/4) =
+    -1 to variables 3 and 4 (APP 6, 6)."""
+    oc = oracle_mod.OCode(workloads.csr_code(5, 2, [0, 3, 6], [0, 1, 2, 2, 3, 4]))
+    n_layers, lay = oracle_mod.layers(oc)
+    assert n_layers == 2 and list(lay) == [0, 1]
+    r = oracle_mod.decode_lnms(oc, [4, 4, -3, 4, 4], max_iter=1)
+    assert list(r["app"]) == [2, 2, 3, 4, 4] and r["iters"] == 1 and r["fail"] == 0
+    r = oracle_mod.decode_lnms(oc, [7, 7, -7, 7, 7], max_iter=1)
+    assert list(r["app"]) == [2, 2, 3, 6, 6]
+    # channel values are 4-bit: out-of-range inputs saturate on entry
+    r = oracle_mod.decode_lnms(oc, [100, 100, -100, 100, 100], max_iter=1)
+    assert list(r["app"]) == [2, 2, 3, 6, 6]
+
+
+def test_lnms_layers_and_ranges(oracle_mod):
+    """Greedy layers of a CSR code: each layer's checks touch disjoint
+    variables, and every check sits in the lowest layer free of its variables
+    at its turn.  APP values stay within 6 bits."""
+    code = workloads.peg1008_code()
+    oc = oracle_mod.OCode(code)
+    n_layers, lay = oracle_mod.layers(oc)
+    rp, col = oc.csr()
+    owner = {}
+    for r in range(oc.m):
+        vs = col[rp[r]:rp[r + 1]]
+        free = next(L for L in range(n_layers + 1) if all((int(v), L) not in owner for v in vs))
+        assert lay[r] == free
+        for v in vs:
+            owner[(int(v), int(lay[r]))] = r
+    assert n_layers == max(lay) + 1
+    rng = np.random.default_rng(5)
+    q = rng.integers(-7, 8, size=oc.n)
+    r = oracle_mod.decode_lnms(oc, q, max_iter=20)
+    assert np.abs(r["app"]).max() <= 31
+
+
+def test_lnms_channel_values(oracle_mod):
+    qb = oracle_mod.q4_base(3.0, 0.5, 1.0)
+    assert qb == 4   # round(3.99)
+    assert [oracle_mod.q4_impulse(qb, k) for k in (0, 4, 8, 16, 32, 64, 512)] == [4, 3, 2, 0, -4, -7, -7]
+    assert oracle_mod.q4_base(3.0, 0.5, 4.0) == 7   # saturated

@@ -195,3 +195,31 @@ def test_spa_search_small(oracle_mod, tiny):
     assert res["decodes"] == int((kc < 0).sum()) + 16 * int((kc >= 0).sum())
     for r in res["ts"]:
         assert oracle_mod.count_b(oc, r.bits) == r.b
+
+
+def test_lnms_search_consistent(oracle_mod, tiny):
+    """Layered min-sum search: re-decoding at k* fails and at k*-1 succeeds,
+    every emitted set recounts, and the search commutes with the QC shift."""
+    c, oc = tiny
+    pats = oracle_mod.pattern_list(oc, [1, 2])
+    kw = dict(decoder=oracle_mod.DEC_LNMS, llr_scale=1.0, a_max=6)
+    res = oracle_mod.search(oc, pats, **kw)
+    kc = res["k_crit"]
+    fails = kc >= 0
+    assert fails.any()
+    qb = oracle_mod.q4_base(3.0, 0.5, 1.0)
+    rng = np.random.default_rng(4)
+    for p in rng.choice(np.nonzero(fails)[0], 25, replace=False):
+        for k, want in ((kc[p], 1), (kc[p] - 1, 0)):
+            q = np.full(oc.n, qb)
+            for v in pats[p]:
+                if v >= 0:
+                    q[v] = oracle_mod.q4_impulse(qb, int(k))
+            assert oracle_mod.decode_lnms(oc, q, 20)["fail"] == want
+    for r in res["ts"]:
+        assert oracle_mod.count_b(oc, r.bits) == r.b
+        assert tuple(oracle_mod.tree(oc, r.bits)) == r.bits
+    sp = np.where(pats >= 0, (pats // c.z) * c.z + (pats % c.z + 5) % c.z, -1).astype(np.int32)
+    r2 = oracle_mod.search(oc, sp, **kw)
+    assert (r2["k_crit"] == kc).all()
+    assert [x.bits for x in r2["ts"]] == [x.bits for x in res["ts"]]
