@@ -129,6 +129,13 @@ int ts_make_patterns(ts_ctx *ctx, const ts_code *code, int32_t kind, int32_t *ou
 
 #define TS_DEC_OMS_I8 0     /* offset min-sum, saturating int8 messages */
 #define TS_DEC_SPA_F32 1    /* sum-product, float32 */
+/* quantised normalised layered min-sum (Section III, Fig. 2): channel values
+ * and check-to-variable messages on 4 bits ([-7, 7]; llr_scale sets the
+ * channel scale, q = sat7(round(llr_scale h))), variable-to-check messages and
+ * APP values on 6 bits ([-31, 31]), check magnitude floor(3/4 min), layers =
+ * block rows of a QC code, else checks in index order each in the first layer
+ * holding none of its variables; k_den must be 16.  Register layout only. */
+#define TS_DEC_LNMS_Q4 2
 #define TS_EXTRACT_PATH 0      /* candidates from every failing decode of the bisection */
 #define TS_EXTRACT_CRITICAL 1  /* candidates from the decode at k* only */
 #define TS_MEM_HOST 0

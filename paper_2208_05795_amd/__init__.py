@@ -16,11 +16,11 @@ import numpy as np
 
 from . import _capi as A
 
-__all__ = ["Context", "Code", "TsRecord", "TsgError", "DEC_OMS", "DEC_SPA",
+__all__ = ["DEC_LNMS", "Context", "Code", "TsRecord", "TsgError", "DEC_OMS", "DEC_SPA",
            "PAT_SINGLES", "PAT_PAIRS", "PAT_TRIPLES", "EXTRACT_PATH", "EXTRACT_CRITICAL",
            "LAYOUT_AUTO", "LAYOUT_REGISTER", "LAYOUT_STREAMED", "PAT_QC_ORBITS"]
 
-DEC_OMS, DEC_SPA = A.TS_DEC_OMS_I8, A.TS_DEC_SPA_F32
+DEC_OMS, DEC_SPA, DEC_LNMS = A.TS_DEC_OMS_I8, A.TS_DEC_SPA_F32, A.TS_DEC_LNMS_Q4
 PAT_SINGLES, PAT_PAIRS, PAT_TRIPLES = A.TS_PAT_SINGLES, A.TS_PAT_PAIRS, A.TS_PAT_TRIPLES
 PAT_QC_ORBITS = A.TS_PAT_QC_ORBITS
 EXTRACT_PATH, EXTRACT_CRITICAL = A.TS_EXTRACT_PATH, A.TS_EXTRACT_CRITICAL

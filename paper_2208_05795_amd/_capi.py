@@ -9,7 +9,7 @@ TS_OK, TS_E_INVAL, TS_E_NOMEM, TS_E_DEVICE, TS_E_STATE, TS_E_BUSY, TS_E_TRUNC, T
     0, -1, -2, -3, -4, -5, -6, -7
 TS_CODE_CSR, TS_CODE_QC = 1, 2
 TS_PAT_SINGLES, TS_PAT_PAIRS, TS_PAT_TRIPLES = 1, 2, 3
-TS_DEC_OMS_I8, TS_DEC_SPA_F32 = 0, 1
+TS_DEC_OMS_I8, TS_DEC_SPA_F32, TS_DEC_LNMS_Q4 = 0, 1, 2
 TS_EXTRACT_PATH, TS_EXTRACT_CRITICAL = 0, 1
 TS_MEM_HOST, TS_MEM_DEVICE = 0, 1
 TS_LAYOUT_AUTO, TS_LAYOUT_REGISTER, TS_LAYOUT_STREAMED = 0, 1, 2

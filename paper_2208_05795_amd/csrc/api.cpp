@@ -123,7 +123,8 @@ void fill_search_launch(const ts_code *code, const ts_search_opts *o, int t0, in
     a->decoder = o->decoder;
     a->max_iter = o->max_iter;
     a->offset = o->oms_offset;
-    a->q_base = sat127(std::lround(o->llr_scale * h));
+    const long q = std::lround(o->llr_scale * h);
+    a->q_base = o->decoder == TS_DEC_LNMS_Q4 ? (int)(q > 7 ? 7 : (q < -7 ? -7 : q)) : sat127(q);
     a->k_max = o->k_max;
     a->k_den = o->k_den;
     a->h = (float)h;
@@ -146,14 +147,18 @@ size_t search_bytes_estimate(const ts_code *code, const ts_search_opts *o, int64
 }
 
 int check_search_opts(const ts_code *code, const ts_search_opts *o, int32_t width) {
-    if (o->decoder != TS_DEC_OMS_I8 && o->decoder != TS_DEC_SPA_F32) {
+    if (o->decoder != TS_DEC_OMS_I8 && o->decoder != TS_DEC_SPA_F32 && o->decoder != TS_DEC_LNMS_Q4) {
         set_error("unknown decoder %d", o->decoder);
+        return TS_E_INVAL;
+    }
+    if (o->decoder == TS_DEC_LNMS_Q4 && code->dev.n_layers == 0) {
+        set_error("the code needs more than 64 layers for the layered decoder");
         return TS_E_INVAL;
     }
     if (o->max_iter < 1 || o->max_iter > kMaxIter) { set_error("max_iter must be 1..%d", kMaxIter); return TS_E_INVAL; }
     if (o->a_max < 1 || o->a_max > kMaxAmax) { set_error("a_max must be 1..%d", kMaxAmax); return TS_E_INVAL; }
     if (o->k_max < 1 || o->k_max > (1 << 24)) { set_error("k_max must be 1..2^24"); return TS_E_INVAL; }
-    if (o->decoder == TS_DEC_OMS_I8 && o->k_den != 16) { set_error("the int8 decoder uses k_den = 16"); return TS_E_INVAL; }
+    if (o->decoder != TS_DEC_SPA_F32 && o->k_den != 16) { set_error("the integer decoders use k_den = 16"); return TS_E_INVAL; }
     if (o->k_den < 1) { set_error("k_den must be positive"); return TS_E_INVAL; }
     if (o->oms_offset < 0 || o->oms_offset > 127) { set_error("oms_offset must be 0..127"); return TS_E_INVAL; }
     if (!(o->rate > 0.0 && o->rate <= 1.0) || !(o->llr_scale > 0.0)) { set_error("rate / llr_scale out of range"); return TS_E_INVAL; }

@@ -67,6 +67,9 @@ struct DevCode {
     int g_off[kGMaxCls + 1];   // g_off[g_ncls] = total message slots
     const int *g_cn;       // [slots] variable of each message slot (n = padding)
     const int *g_vslot;    // [dv_pad][n_tab] message slot of each (variable, k) edge, -1 = pad
+    // layered schedule: layer of every check, number of layers (0 = none fits)
+    const int *lay_of;
+    int n_layers;
 };
 
 // Open-addressing TS table on the device, keyed by the canonical QC-orbit

@@ -224,12 +224,33 @@ int upload_code(ts_exec &ex, ts_code *c) {
                 gvs[(size_t)(k - c->vptr[v]) * d.n_tab + v] = edge_slot[c->vedge[k]];
     }
     if (gcn.empty()) gcn.push_back(c->n);
+    // layered schedule: block rows of a QC code; otherwise each check, in index
+    // order, goes to the lowest layer none of whose checks shares a variable
+    std::vector<int32_t> lay((size_t)std::max(c->m, 1), 0);
+    d.n_layers = 0;
+    if (c->z > 0) {
+        for (int r = 0; r < c->m; ++r) lay[r] = r / c->z;
+        d.n_layers = c->mb;
+    } else {
+        std::vector<uint64_t> busy((size_t)c->n, 0);   // bit L: variable has a check in layer L
+        bool ok = true;
+        for (int r = 0; r < c->m && ok; ++r) {
+            uint64_t taken = 0;
+            for (int64_t e = c->row_ptr[r]; e < c->row_ptr[r + 1]; ++e) taken |= busy[c->col[e]];
+            if (~taken == 0) { ok = false; break; }
+            const int L = __builtin_ctzll(~taken);
+            lay[r] = L;
+            for (int64_t e = c->row_ptr[r]; e < c->row_ptr[r + 1]; ++e) busy[c->col[e]] |= 1ull << L;
+            d.n_layers = std::max(d.n_layers, L + 1);
+        }
+        if (!ok) d.n_layers = 0;   // more than 64 layers: the layered decoder is not offered
+    }
     struct Up { const void *src; size_t bytes; const int **dst; } ups[] = {
         {rp32.data(), rp32.size() * 4, &d.row_ptr}, {c->col.data(), c->col.size() * 4, &d.col},
         {vp32.data(), vp32.size() * 4, &d.vptr},    {c->vchk.data(), c->vchk.size() * 4, &d.vchk},
         {c->vedge.data(), c->vedge.size() * 4, &d.vedge}, {cn.data(), cn.size() * 4, &d.cn_tab},
         {vn.data(), vn.size() * 4, &d.vn_tab}, {gcn.data(), gcn.size() * 4, &d.g_cn},
-        {gvs.data(), gvs.size() * 4, &d.g_vslot},
+        {gvs.data(), gvs.size() * 4, &d.g_vslot}, {lay.data(), lay.size() * 4, &d.lay_of},
     };
     for (auto &u : ups) {
         void *p = ex.dalloc(u.bytes ? u.bytes : 4);

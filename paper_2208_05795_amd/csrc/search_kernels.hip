@@ -149,6 +149,26 @@ struct SpaRule {
     }
 };
 
+// Quantised normalised layered min-sum (4-bit channel values and
+// check-to-variable messages, 6-bit variable-to-check messages and APP values,
+// magnitude floor(3/4 min)); the update is applied layer by layer in
+// run_decode_l.  Padded edges read as a saturated positive message.
+struct LnmsRule {
+    static constexpr int kDummy = 31;
+};
+
+__device__ __forceinline__ int sat7(int x) { return x > 7 ? 7 : (x < -7 ? -7 : x); }
+__device__ __forceinline__ int sat31(int x) { return x > 31 ? 31 : (x < -31 ? -31 : x); }
+
+__device__ __forceinline__ int q4_impulse(int qb, int k) {
+    // round_half_away(qb * (16 - k) / 16), saturated to [-7, 7]
+    const long long nv = (long long)qb * (16 - k);
+    const long long mag = ((nv < 0 ? -nv : nv) + 8) >> 4;
+    long long q = nv < 0 ? -mag : mag;
+    q = q > 7 ? 7 : (q < -7 ? -7 : q);
+    return (int)q;
+}
+
 // Shared-memory layout of a frame (byte offsets).
 struct Lds {
     int np, W, T;
@@ -475,13 +495,14 @@ __device__ __forceinline__ void search_jobs(const SearchJob *jobs, int n_jobs, i
 // all others the base value (Section III).
 template <class Rule>
 __device__ __forceinline__ int impulse_lambda(const SearchLaunch &a, int K) {
-    return Rule::kDummy == OmsRule::kDummy ? q_impulse(a.q_base, K)
-                                           : to_q20(a.h * (1.0f - (float)K / (float)a.k_den));
+    if (std::is_same<Rule, OmsRule>::value) return q_impulse(a.q_base, K);
+    if (std::is_same<Rule, LnmsRule>::value) return q4_impulse(a.q_base, K);
+    return to_q20(a.h * (1.0f - (float)K / (float)a.k_den));
 }
 
 template <class Rule>
 __device__ __forceinline__ int base_lambda(const SearchLaunch &a) {
-    return Rule::kDummy == OmsRule::kDummy ? a.q_base : to_q20(a.h);
+    return std::is_same<Rule, SpaRule>::value ? to_q20(a.h) : a.q_base;
 }
 
 // Register-resident decoder of one workgroup: the neighbour lists and messages
@@ -540,6 +561,157 @@ __global__ __launch_bounds__((MaxBlock<DC, CPT>::value)) void k_search(const Sea
                                                                       int *queue, long long n_items) {
     extern __shared__ __align__(16) unsigned char smem[];
     RegSearchDec<Rule, DC, CPT> dec;
+    search_jobs(jobs, n_jobs, queue, n_items, dec, smem);
+}
+
+// One layered decode (register layout).  On entry APP slot 0 (LDS) holds the
+// channel values (slot n: the padding value), wsyn/pcnt are zero and all
+// threads have passed a barrier.  Per iteration the layers run in order, one
+// barrier each: the checks of a layer touch disjoint variables, so each writes
+// its variables' APP values in place.  Then the hard decision x_t, its
+// syndrome and history, and the stop test.
+template <int DC, int CPT>
+__device__ __forceinline__ DecRes run_decode_l(const Frame &F, const int (&nb)[CPT][DC],
+                                               const int (&lay)[CPT], int n_layers,
+                                               int (&c2v)[CPT][DC]) {
+    const int n = F.n, W = F.W, T = F.T;
+    const int B = blockDim.x, NW = B >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    int *A = F.app;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+#pragma unroll
+        for (int j = 0; j < DC; ++j) c2v[c][j] = 0;
+    int iters = T, wmin = INT_MAX, tmin = 0;
+    for (int t = 1; t <= T; ++t) {
+        for (int L = 0; L < n_layers; ++L) {
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                if (lay[c] != L) continue;
+                int v2[DC];
+                int mn1 = 31, mn2 = 31, idx = 0, sgn = 0;
+#pragma unroll
+                for (int j = 0; j < DC; ++j) {
+                    int x = sat31(A[nb[c][j]] - c2v[c][j]);
+                    if (nb[c][j] == n) x = 31;
+                    v2[j] = x;
+                    const int ax = x < 0 ? -x : x;
+                    sgn ^= (x < 0);
+                    if (ax < mn1) {
+                        mn2 = mn1;
+                        mn1 = ax;
+                        idx = j;
+                    } else if (ax < mn2) {
+                        mn2 = ax;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < DC; ++j) {
+                    const int mag = sat7((3 * (j == idx ? mn2 : mn1)) >> 2);
+                    const int m = (sgn ^ (v2[j] < 0)) ? -mag : mag;
+                    c2v[c][j] = m;
+                    if (nb[c][j] != n) A[nb[c][j]] = sat31(v2[j] + m);
+                }
+            }
+            __syncthreads();
+        }
+        int unsat = 0;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            if (lay[c] < 0) continue;
+            int par = 0;
+#pragma unroll
+            for (int j = 0; j < DC; ++j)
+                if (nb[c][j] != n) par ^= (A[nb[c][j]] < 0);
+            unsat += par;
+        }
+        const int us = wave_sum(unsat);
+        if (lane == 0 && us) atomicAdd(&F.wsyn[t], us);
+        int pc = 0;
+        for (int i = wid; i < W; i += NW) {
+            const int v = i * 64 + lane;
+            const unsigned long long mask = __ballot((v < n) && (A[v] < 0));
+            if (F.hist && lane == 0) F.hist[(size_t)(t - 1) * W + i] = mask;
+            pc += __popcll(mask);
+        }
+        if (lane == 0 && pc) atomicAdd(&F.pcnt[t], pc);
+        __syncthreads();
+        const int w = F.wsyn[t];
+        if (w < wmin) {
+            wmin = w;
+            tmin = t;
+        }
+        if (w == 0) {
+            iters = t;
+            break;
+        }
+    }
+    DecRes r;
+    r.iters = iters;
+    r.tmin = tmin;
+    r.fail = F.pcnt[iters] > 0;
+    return r;
+}
+
+template <int DC, int CPT>
+struct LayDec {
+    const SearchLaunch *a;
+    Frame F;
+    unsigned long long *imask;
+    int W, n_layers;
+    int nb[CPT][DC];
+    int lay[CPT];
+    int c2v[CPT][DC];
+
+    __device__ __forceinline__ void bind(const SearchJob &J, unsigned char *frame) {
+        a = &J.a;
+        const int n = uni(J.cd.n), T = uni(J.a.max_iter);
+        const Lds L = lds_layout(n, T, true);
+        F.lam = (int *)(frame + L.lam);
+        F.app = (int *)(frame + L.app);
+        F.hist = (unsigned long long *)(frame + L.hist);
+        F.wsyn = (int *)(frame + L.wsyn);
+        F.pcnt = (int *)(frame + L.pcnt);
+        F.n = n;
+        F.np = L.np;
+        F.W = L.W;
+        F.T = T;
+        imask = (unsigned long long *)(frame + L.imask);
+        W = L.W;
+        n_layers = uni(J.cd.n_layers);
+        load_neighbours<DC, CPT>(J.cd, nb);
+        const int B = blockDim.x, tid = threadIdx.x, m = uni(J.cd.m);
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int chk = tid + c * B;
+            lay[c] = chk < m ? J.cd.lay_of[chk] : -1;
+        }
+    }
+
+    __device__ __forceinline__ DecRes decode(int K) {
+        const int B = blockDim.x, tid = threadIdx.x, n = F.n, np = F.np;
+        const int li = impulse_lambda<LnmsRule>(*a, K), lb = base_lambda<LnmsRule>(*a);
+        __syncthreads();
+        for (int v = tid; v < np; v += B) {
+            int l = v == n ? LnmsRule::kDummy : 0;
+            if (v < n) l = ((imask[v >> 6] >> (v & 63)) & 1ull) ? li : lb;
+            F.app[v] = l;
+        }
+        for (int i = tid; i < F.T + 2; i += B) {
+            F.wsyn[i] = 0;
+            F.pcnt[i] = 0;
+        }
+        __syncthreads();
+        return run_decode_l<DC, CPT>(F, nb, lay, n_layers, c2v);
+    }
+    __device__ __forceinline__ const unsigned long long *hist() const { return F.hist; }
+};
+
+template <int DC, int CPT>
+__global__ __launch_bounds__((MaxBlock<DC, CPT>::value)) void k_search_l(const SearchJob *jobs, int n_jobs,
+                                                                        int *queue, long long n_items) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    LayDec<DC, CPT> dec;
     search_jobs(jobs, n_jobs, queue, n_items, dec, smem);
 }
 
@@ -1114,13 +1286,13 @@ typedef void (*IsKernel)(const IsJob *, int, int *, long long);
 
 struct KEntry {
     int dc, cpt, max_block, is_max_block;
-    SearchKernel oms, spa;
+    SearchKernel oms, spa, lnms;
     IsKernel is;
 };
 
 #define TSG_K(DC, CPT)                                                                \
     {DC, CPT, MaxBlock<DC, CPT>::value, MaxBlockIs<DC, CPT>::value, k_search<OmsRule, DC, CPT>, \
-     k_search<SpaRule, DC, CPT>, k_is<DC, CPT>}
+     k_search<SpaRule, DC, CPT>, k_search_l<DC, CPT>, k_is<DC, CPT>}
 const KEntry kTable[] = {
     TSG_K(6, 1),  TSG_K(6, 2),  TSG_K(6, 4),  TSG_K(6, 8),  TSG_K(8, 1),  TSG_K(8, 2),
     TSG_K(8, 4),  TSG_K(8, 8),  TSG_K(12, 1), TSG_K(12, 2), TSG_K(12, 4), TSG_K(16, 1),
@@ -1216,7 +1388,7 @@ int plan_candidates(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter,
             if (!ke) continue;
             const int block = ((c->m + cp - 1) / cp + 63) / 64 * 64;
             if (block > ke->max_block) continue;
-            SearchKernel kern = decoder == TS_DEC_OMS_I8 ? ke->oms : ke->spa;
+            SearchKernel kern = decoder == TS_DEC_OMS_I8 ? ke->oms : (decoder == TS_DEC_SPA_F32 ? ke->spa : ke->lnms);
             int per_cu = 0;
             TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, block, lds));
             if (per_cu < 1) continue;
@@ -1233,10 +1405,14 @@ int plan_candidates(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter,
             out->push_back(p);
         }
     }
-    int rc = add_streamed_plans(ctx, c, true, decoder, max_iter, out);
-    if (rc) return rc;
+    if (decoder != TS_DEC_LNMS_Q4) {   // the layered decoder has the register layout only
+        int rc = add_streamed_plans(ctx, c, true, decoder, max_iter, out);
+        if (rc) return rc;
+    }
     if (out->empty()) {
-        set_error("code (n = %d) needs more LDS per workgroup than the device has", c->n);
+        set_error(decoder == TS_DEC_LNMS_Q4 ? "the layered decoder needs a register shape; none fits this code"
+                                            : "code (n = %d) needs more LDS per workgroup than the device has",
+                  c->n);
         return TS_E_INVAL;
     }
     return TS_OK;
@@ -1253,8 +1429,10 @@ int plan_search(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter, Search
 static SearchKernel search_kernel(const SearchPlan &plan, int decoder) {
     if (plan.kind == kPlanRegister) {
         const KEntry *ke = find_kernel(plan.dc, plan.cpt);
-        return ke ? (decoder == TS_DEC_OMS_I8 ? ke->oms : ke->spa) : nullptr;
+        if (!ke) return nullptr;
+        return decoder == TS_DEC_OMS_I8 ? ke->oms : (decoder == TS_DEC_SPA_F32 ? ke->spa : ke->lnms);
     }
+    if (decoder == TS_DEC_LNMS_Q4) return nullptr;
     const GEntry *g = find_g(plan.dc);
     return g ? (decoder == TS_DEC_OMS_I8 ? g->oms : g->spa) : nullptr;
 }
