@@ -67,7 +67,8 @@ def parse():
     p.add_argument("--no-batch", action="store_true")
     p.add_argument("--no-serve", action="store_true")
     p.add_argument("--no-qc2640", action="store_true")
-    p.add_argument("--only", choices=["batch", "serve", "qc2640"],
+    p.add_argument("--no-layered", action="store_true")
+    p.add_argument("--only", choices=["batch", "serve", "qc2640", "layered"],
                    help="run only this section (profiling aid); prints its JSON object")
     p.add_argument("--serve-seconds", type=float, default=10.0)
     p.add_argument("--serve-rate", type=float, default=20.0)
@@ -88,7 +89,8 @@ def main():
     if args.only:
         fn = {"batch": lambda: bench_batch(tsg),
               "serve": lambda: bench_serve(tsg, args.serve_seconds, args.serve_rate),
-              "qc2640": lambda: bench_qc2640(tsg)}[args.only]
+              "qc2640": lambda: bench_qc2640(tsg),
+              "layered": lambda: bench_layered(tsg)}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
 
@@ -198,6 +200,8 @@ def main():
         line["served"] = bench_serve(tsg, args.serve_seconds, args.serve_rate)
     if not args.no_qc2640:
         line["qc2640"] = bench_qc2640(tsg)
+    if not args.no_layered:
+        line["layered"] = bench_layered(tsg)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(code, pats_host, args.cpu_seconds)
     print(json.dumps(line), flush=True)
@@ -481,6 +485,40 @@ def bench_qc2640(tsg):
             "union_bound": {"seconds": t_ub, "edge_updates": eu_ub, "edge_updates_per_s": eu_ub / t_ub,
                             "fer": {f"{p['ebn0_db']:g}dB": {"fer": p["fer"], "ci": [p["ci_lo"], p["ci_hi"]]}
                                     for p in ub["points"]}}}
+
+
+def bench_layered(tsg):
+    """The quantised normalised layered min-sum (4/4/6 bits, 20 iterations, the
+    decoder of Fig. 2) as the impulse-search decoder: the whole PEG-1008 list
+    (greedy layers) and every QC-2640 triple (block-row layers), at 3 dB with
+    the channel at full scale and at 0.3 x scale (where impulses fail)."""
+    import workloads
+    out = {}
+    for name, fn, kinds in (("peg1008", workloads.peg1008_code,
+                             [tsg.PAT_SINGLES, tsg.PAT_PAIRS, tsg.PAT_TRIPLES]),
+                            ("qc2640", workloads.qc2640_code, [tsg.PAT_TRIPLES])):
+        ctx = tsg.Context(0)
+        g = ctx.load_code(fn())
+        pats = g.pattern_list(kinds)
+        for scale in (1.0, 0.3):
+            kw = dict(decoder=tsg.DEC_LNMS, max_iter=20, ebn0_db=3.0, llr_scale=scale, k_max=512,
+                      k_den=16, a_max=12)
+            g.impulse_search(pats[:4096], **kw)   # warm-up / autotune
+            g.reset_ts()
+            t0 = time.perf_counter()
+            r = g.impulse_search(pats, **kw)
+            recs, _ = g.collect_arrays()
+            dt = time.perf_counter() - t0
+            st = r["stats"]
+            out[f"{name}_x{scale:g}"] = {
+                "patterns": int(len(pats)), "layers": int(g.info["n_layers"]),
+                "seconds": dt, "edge_updates": st["edge_updates"],
+                "edge_updates_per_s": st["edge_updates"] / dt,
+                "kernel_edge_updates_per_s": st["edge_updates"] / (st["decode_ms"] * 1e-3),
+                "failing_patterns": int((r["k_crit"] >= 0).sum()), "ts_found": int(len(recs)),
+                "shape": {"layout": st["layout"], "checks_per_thread": st["checks_per_thread"]}}
+        ctx.close()
+    return out
 
 
 def cpu_baseline(code, pats, seconds):

@@ -99,6 +99,10 @@ typedef struct {
     int32_t girth;      /* 0 = cycle-free */
     int32_t z;          /* circulant size, 0 for CSR codes */
     int32_t dv_max, dc_max;
+    int32_t n_layers;   /* layers of the layered min-sum schedule: the block rows
+                         * of a QC code, else the greedy variable-disjoint
+                         * colouring of the checks; 0 = more than 64 layers
+                         * (TS_DEC_LNMS_Q4 is then rejected) */
 } ts_code_info_t;
 int ts_code_info(const ts_code *code, ts_code_info_t *out);
 /* Check-major CSR of the expanded H (host arrays row_ptr[m+1], col[e]). */

@@ -34,7 +34,8 @@ class CodeDesc(C.Structure):
 
 class CodeInfo(C.Structure):
     _fields_ = [("n", C.c_int32), ("m", C.c_int32), ("e", C.c_int64), ("girth", C.c_int32),
-                ("z", C.c_int32), ("dv_max", C.c_int32), ("dc_max", C.c_int32)]
+                ("z", C.c_int32), ("dv_max", C.c_int32), ("dc_max", C.c_int32),
+                ("n_layers", C.c_int32)]
 
 
 class SearchOpts(C.Structure):

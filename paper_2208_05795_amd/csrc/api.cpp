@@ -761,6 +761,7 @@ int ts_code_info(const ts_code *code, ts_code_info_t *out) {
     out->z = code->z;
     out->dv_max = code->dv_max;
     out->dc_max = code->dc_max;
+    out->n_layers = code->dev.n_layers;
     return TS_OK;
 }
 

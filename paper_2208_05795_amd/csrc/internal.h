@@ -67,8 +67,12 @@ struct DevCode {
     int g_off[kGMaxCls + 1];   // g_off[g_ncls] = total message slots
     const int *g_cn;       // [slots] variable of each message slot (n = padding)
     const int *g_vslot;    // [dv_pad][n_tab] message slot of each (variable, k) edge, -1 = pad
-    // layered schedule: layer of every check, number of layers (0 = none fits)
+    // layered schedule: the checks ordered by layer (stable), so that a layer is a
+    // contiguous range of positions; lay_of[p] = layer at position p
+    // (non-decreasing), cn_lay[j][p] = cn_tab[j][check at p]; n_layers = 0 when
+    // no schedule of at most 64 layers exists
     const int *lay_of;
+    const int *cn_lay;     // [dc_pad][m_tab]
     int n_layers;
 };
 

@@ -245,12 +245,23 @@ int upload_code(ts_exec &ex, ts_code *c) {
         }
         if (!ok) d.n_layers = 0;   // more than 64 layers: the layered decoder is not offered
     }
+    // layer-major check order: a wavefront's lanes then hold checks of one layer,
+    // so each layer's update runs on few wavefronts instead of all of them
+    std::vector<int32_t> lorder(c->m);
+    for (int r = 0; r < c->m; ++r) lorder[r] = r;
+    std::stable_sort(lorder.begin(), lorder.end(), [&](int x, int y) { return lay[x] < lay[y]; });
+    std::vector<int32_t> lay_pos((size_t)std::max(c->m, 1), 0), cnl((size_t)d.dc_pad * d.m_tab, -1);
+    for (int p = 0; p < c->m; ++p) {
+        lay_pos[p] = lay[lorder[p]];
+        for (int j = 0; j < d.dc_pad; ++j) cnl[(size_t)j * d.m_tab + p] = cn[(size_t)j * d.m_tab + lorder[p]];
+    }
     struct Up { const void *src; size_t bytes; const int **dst; } ups[] = {
         {rp32.data(), rp32.size() * 4, &d.row_ptr}, {c->col.data(), c->col.size() * 4, &d.col},
         {vp32.data(), vp32.size() * 4, &d.vptr},    {c->vchk.data(), c->vchk.size() * 4, &d.vchk},
         {c->vedge.data(), c->vedge.size() * 4, &d.vedge}, {cn.data(), cn.size() * 4, &d.cn_tab},
         {vn.data(), vn.size() * 4, &d.vn_tab}, {gcn.data(), gcn.size() * 4, &d.g_cn},
-        {gvs.data(), gvs.size() * 4, &d.g_vslot}, {lay.data(), lay.size() * 4, &d.lay_of},
+        {gvs.data(), gvs.size() * 4, &d.g_vslot}, {lay_pos.data(), lay_pos.size() * 4, &d.lay_of},
+        {cnl.data(), cnl.size() * 4, &d.cn_lay},
     };
     for (auto &u : ups) {
         void *p = ex.dalloc(u.bytes ? u.bytes : 4);

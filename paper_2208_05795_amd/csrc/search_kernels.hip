@@ -213,15 +213,17 @@ struct DecRes {
 };
 
 template <int DC, int CPT>
-__device__ __forceinline__ void load_neighbours(const DevCode &cd, int (&nb)[CPT][DC]) {
+__device__ __forceinline__ void load_neighbours(const DevCode &cd, int (&nb)[CPT][DC],
+                                                const int *tab = nullptr) {
     const int B = blockDim.x, tid = threadIdx.x;
+    if (!tab) tab = cd.cn_tab;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
         const int chk = tid + c * B;
 #pragma unroll
         for (int j = 0; j < DC; ++j) {
             int v = -1;
-            if (chk < cd.m && j < cd.dc_pad) v = cd.cn_tab[(size_t)j * cd.m_tab + chk];
+            if (chk < cd.m && j < cd.dc_pad) v = tab[(size_t)j * cd.m_tab + chk];
             nb[c][j] = v < 0 ? cd.n : v;
         }
     }
@@ -679,7 +681,7 @@ struct LayDec {
         imask = (unsigned long long *)(frame + L.imask);
         W = L.W;
         n_layers = uni(J.cd.n_layers);
-        load_neighbours<DC, CPT>(J.cd, nb);
+        load_neighbours<DC, CPT>(J.cd, nb, J.cd.cn_lay);   // positions in layer order
         const int B = blockDim.x, tid = threadIdx.x, m = uni(J.cd.m);
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {

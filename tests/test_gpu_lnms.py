@@ -73,3 +73,13 @@ def test_lnms_rejects_bad_options(ctx):
         g.impulse_search(np.array([[0]], dtype=np.int32), decoder=tsg.DEC_LNMS, llr_scale=1.0,
                          layout=tsg.LAYOUT_STREAMED)
     g.free()
+
+
+@pytest.mark.parametrize("name", ["tiny", "peg1008", "qc2640"])
+def test_layer_count_matches_oracle(ctx, oracle_mod, name):
+    code = {"tiny": workloads.tiny_code, "peg1008": workloads.peg1008_code,
+            "qc2640": workloads.qc2640_code}[name]()
+    n_layers, _ = oracle_mod.layers(oracle_mod.OCode(code))
+    g = ctx.load_code(code)
+    assert g.info["n_layers"] == n_layers
+    g.free()
