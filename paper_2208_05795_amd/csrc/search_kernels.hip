@@ -25,8 +25,9 @@
 //   sum-product (float32 arithmetic on Q20 fixed-point APP / messages):
 //     c2v' = sign-product * phi(sum_{others} phi(min(|v2c|, 30))),
 //     phi(x) = ln((1 + e^-x) / (1 - e^-x)) at max(x, 2^-20), evaluated with the
-//     hardware exp2 / log2 / reciprocal and series at both ends; the exclusive
-//     sums come from prefix and suffix sums; messages are rounded to 2^-20.
+//     hardware exp2 / log2 / reciprocal, with a series at the end where each of
+//     the two evaluations needs one (phi_in, phi_out_q); the exclusive sums
+//     come from prefix and suffix sums; messages are rounded to 2^-20.
 #include <climits>
 #include <type_traits>
 #include <cmath>
@@ -38,7 +39,6 @@ namespace tsg {
 namespace {
 
 constexpr float kQ = 1048576.0f;        // Q20 scale of the sum-product APP values
-constexpr float kQinv = 1.0f / 1048576.0f;
 constexpr float kLamMax = 1024.0f;      // |lambda| bound of the Q20 format
 
 __device__ __forceinline__ int q_impulse(int qb, int k) {
@@ -55,19 +55,39 @@ __device__ __forceinline__ int to_q20(float l) {
     return __float2int_rn(l * kQ);
 }
 
-// phi(x) = -ln tanh(x/2) = ln((1+u)/(1-u)), u = e^-x, for x >= 0.
-__device__ __forceinline__ float phi_fast(float x) {
+// phi(x) = -ln tanh(x/2) = ln((1+u)/(1-u)), u = e^-x, for x >= 0, in two
+// forms, each accurate where its result matters.
+//
+// phi_in: phi of a variable-to-check magnitude |d| (Q20), clamped to
+// [2^-20, 30].  Small results must keep their relative accuracy (their sum
+// over a check can be tiny, and phi of a tiny sum is large), so below
+// u = 1/16 the series 2(u + u^3/3 + u^5/5) replaces the logarithm.  Large
+// results (x -> 0, where 1 - u cancels) need no care: such a term enters the
+// other edges' sums S >= phi_in, where |phi'(S)| <= 2 e^-S ~ x, which
+// cancels the 2^-24 / x relative error of 1 - u.
+__device__ __forceinline__ float phi_in(int d) {
+    constexpr float kL2eQ = -1.4426950408889634f / 1048576.0f;   // -log2(e) 2^-20
+    const float e = fminf(fmaxf(fabsf((float)d) * kL2eQ, -30.0f * 1.4426950408889634f),
+                          -0x1p-20f * 1.4426950408889634f);
+    const float u = __builtin_amdgcn_exp2f(e);
+    const float r = (1.0f + u) * __builtin_amdgcn_rcpf(1.0f - u);
+    const float big = __builtin_amdgcn_logf(r) * 0.69314718055994531f;
+    const float u2 = u * u;
+    const float small = u * (2.0f + u2 * (0.66666667f + u2 * 0.4f));
+    return u < 0.0625f ? small : big;
+}
+
+// phi_out: Q20 check-to-variable magnitude phi(S) x 2^20 of an exclusive sum
+// S >= 0 (before rounding).  Large results need 1 - e^-S without
+// cancellation: a Taylor series below S = 1/8.  Small results need only the
+// absolute accuracy of the logarithm (about 1e-7, below the 2^-20 step).
+__device__ __forceinline__ float phi_out_q(float x) {
     x = fmaxf(x, 0x1p-20f);
     const float u = __builtin_amdgcn_exp2f(-x * 1.4426950408889634f);
-    // 1 - e^-x: Taylor series below 1/8, direct difference above
     const float ser = x * (1.0f - x * (0.5f - x * (0.16666667f - x * (0.041666668f - x * 0.0083333333f))));
     const float den = x < 0.125f ? ser : 1.0f - u;
     const float r = (1.0f + u) * __builtin_amdgcn_rcpf(den);
-    const float big = __builtin_amdgcn_logf(r) * 0.69314718055994531f;
-    // small u: ln((1+u)/(1-u)) = 2 (u + u^3/3 + u^5/5 + ...)
-    const float u2 = u * u;
-    const float small = 2.0f * u * (1.0f + u2 * (0.33333334f + u2 * 0.2f));
-    return u < 0.0625f ? small : big;
+    return __builtin_amdgcn_logf(r) * (0.69314718055994531f * 1048576.0f);
 }
 
 // A value every lane of the wave holds (read from the LDS job copy), moved to
@@ -118,21 +138,22 @@ struct OmsRule {
 };
 
 struct SpaRule {
-    static constexpr int kDummy = 0;
+    // Padded edges read APP = 2^30 (Q20, far above any real message): their
+    // v2c stays positive and clamps to 30, so they add phi(30) ~ 1.9e-13 to the
+    // check's sums (below the 2^-20 step of the results) and no sign, without
+    // a per-edge test.  Real APP values stay below 2^30 + 2^27 in magnitude.
+    static constexpr int kDummy = 1 << 30;
     template <int DC>
     __device__ static __forceinline__ void update(const int (&val)[DC], int (&c2v)[DC],
-                                                  const int (&nb)[DC], int pad_id, int) {
+                                                  const int (&)[DC], int, int) {
         float ph[DC];
-        int neg[DC];
-        int sgn = 0;
+        int d[DC];
+        int sx = 0;   // sign bit = parity of the negative v2c messages
 #pragma unroll
         for (int j = 0; j < DC; ++j) {
-            const int d = val[j] - c2v[j];
-            const bool pad = nb[j] == pad_id;
-            neg[j] = (d < 0) & !pad;
-            sgn ^= neg[j];
-            const float ax = fminf(fabsf((float)d * kQinv), 30.0f);
-            ph[j] = pad ? 0.0f : phi_fast(ax);
+            d[j] = val[j] - c2v[j];
+            sx ^= d[j];
+            ph[j] = phi_in(d[j]);
         }
         float pre[DC + 1], suf[DC + 1];
         pre[0] = 0.0f;
@@ -143,8 +164,11 @@ struct SpaRule {
         for (int j = DC - 1; j >= 0; --j) suf[j] = suf[j + 1] + ph[j];
 #pragma unroll
         for (int j = 0; j < DC; ++j) {
-            const int q = __float2int_rn(phi_fast(pre[j] + suf[j + 1]) * kQ);
-            c2v[j] = (sgn ^ neg[j]) ? -q : q;
+            // sign of the other edges' product applied to the float before the
+            // (sign-symmetric) rounding to Q20
+            const float f = phi_out_q(pre[j] + suf[j + 1]);
+            const int sb = (sx ^ d[j]) & (int)0x80000000u;
+            c2v[j] = __float2int_rn(__int_as_float(__float_as_int(f) ^ sb));
         }
     }
 };
@@ -879,9 +903,9 @@ struct RegIsDec {
             F.app[np + v] = l;
         });
         for (int v = n + tid; v < np; v += B) {
-            F.lam[v] = 0;
-            F.app[v] = 0;
-            F.app[np + v] = 0;
+            F.lam[v] = SpaRule::kDummy;
+            F.app[v] = SpaRule::kDummy;
+            F.app[np + v] = SpaRule::kDummy;
         }
         for (int i = tid; i < F.T + 2; i += B) {
             F.wsyn[i] = 0;
