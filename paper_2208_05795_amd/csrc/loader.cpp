@@ -154,6 +154,63 @@ int build_code(const ts_code_desc *d, ts_code *c) {
     return TS_OK;
 }
 
+namespace {
+
+// Order of each check's edges in the device neighbour tables: slot j of check
+// r holds edge ord[row_ptr[r] + j].  The lanes of a wavefront own 64
+// consecutive checks, and the APP gather (and atomic add) of slot j touches
+// one LDS word per lane; words in one bank serialise.  The order within a
+// check is free for the decoders (min-sum does not depend on it; the
+// sum-product sums follow it in every layout alike), so a local search swaps
+// two edges of a check while that lowers the sum over slots of the squared
+// bank loads, counted over 64 banks per wavefront and over 32 banks per
+// half-wavefront.
+std::vector<int64_t> edge_order(const ts_code *c) {
+    std::vector<int64_t> ord((size_t)c->e);
+    for (int64_t k = 0; k < c->e; ++k) ord[k] = k;
+    const int dmax = c->dc_max;
+    std::vector<int> c64((size_t)dmax * 64), c32((size_t)2 * dmax * 32);
+    for (int g0 = 0; g0 < c->m; g0 += 64) {
+        const int g1 = std::min(c->m, g0 + 64);
+        std::fill(c64.begin(), c64.end(), 0);
+        std::fill(c32.begin(), c32.end(), 0);
+        for (int r = g0; r < g1; ++r) {
+            const int h = (r - g0) >> 5;
+            for (int64_t k = c->row_ptr[r]; k < c->row_ptr[r + 1]; ++k) {
+                const int j = (int)(k - c->row_ptr[r]), v = c->col[ord[k]];
+                c64[(size_t)j * 64 + (v & 63)]++;
+                c32[((size_t)h * dmax + j) * 32 + (v & 31)]++;
+            }
+        }
+        for (int pass = 0; pass < 8; ++pass) {
+            bool moved = false;
+            for (int r = g0; r < g1; ++r) {
+                const int h = (r - g0) >> 5, d = (int)(c->row_ptr[r + 1] - c->row_ptr[r]);
+                int64_t *o = ord.data() + c->row_ptr[r];
+                for (int j1 = 0; j1 < d; ++j1)
+                    for (int j2 = j1 + 1; j2 < d; ++j2) {
+                        const int a = c->col[o[j1]], b = c->col[o[j2]];
+                        int *p1 = &c64[(size_t)j1 * 64], *p2 = &c64[(size_t)j2 * 64];
+                        int *q1 = &c32[((size_t)h * dmax + j1) * 32], *q2 = &c32[((size_t)h * dmax + j2) * 32];
+                        const int a6 = a & 63, b6 = b & 63, a5 = a & 31, b5 = b & 31;
+                        int delta = 0;
+                        if (a6 != b6) delta += 2 * (p1[b6] - p1[a6] + p2[a6] - p2[b6]) + 4;
+                        if (a5 != b5) delta += 2 * (q1[b5] - q1[a5] + q2[a5] - q2[b5]) + 4;
+                        if (delta >= 0) continue;
+                        p1[a6]--, p1[b6]++, p2[b6]--, p2[a6]++;
+                        q1[a5]--, q1[b5]++, q2[b5]--, q2[a5]++;
+                        std::swap(o[j1], o[j2]);
+                        moved = true;
+                    }
+            }
+            if (!moved) break;
+        }
+    }
+    return ord;
+}
+
+}  // namespace
+
 int upload_code(ts_exec &ex, ts_code *c) {
     DevCode &d = c->dev;
     d.n = c->n;
@@ -171,9 +228,10 @@ int upload_code(ts_exec &ex, ts_code *c) {
     std::vector<int32_t> rp32(c->row_ptr.begin(), c->row_ptr.end());
     std::vector<int32_t> vp32(c->vptr.begin(), c->vptr.end());
     std::vector<int32_t> cn((size_t)d.dc_pad * d.m_tab, -1), vn((size_t)d.dv_pad * d.n_tab, -1);
+    const std::vector<int64_t> ord = edge_order(c);
     for (int r = 0; r < c->m; ++r)
         for (int64_t k = c->row_ptr[r]; k < c->row_ptr[r + 1]; ++k)
-            cn[(size_t)(k - c->row_ptr[r]) * d.m_tab + r] = c->col[k];
+            cn[(size_t)(k - c->row_ptr[r]) * d.m_tab + r] = c->col[ord[k]];
     for (int v = 0; v < c->n; ++v)
         for (int64_t k = c->vptr[v]; k < c->vptr[v + 1]; ++k)
             vn[(size_t)(k - c->vptr[v]) * d.n_tab + v] = c->vedge[k];
@@ -210,8 +268,8 @@ int upload_code(ts_exec &ex, ts_code *c) {
                 for (int64_t e = c->row_ptr[r]; e < c->row_ptr[r + 1]; ++e) {
                     const int j = (int)(e - c->row_ptr[r]);
                     const int slot = off + j * stride + (i - p);
-                    gcn[slot] = c->col[e];
-                    edge_slot[e] = slot;
+                    gcn[slot] = c->col[ord[e]];
+                    edge_slot[ord[e]] = slot;
                 }
             }
             off += dcq * stride;
