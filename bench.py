@@ -143,6 +143,8 @@ def main():
     eu = sum(r["oms"]["edge_updates"] + r["spa"]["edge_updates"] + r["is"]["edge_updates"]
              for r in recs)
     ts_found = sum(r["ts_oms"] + r["ts_spa"] for r in recs)
+    cands = sum(r["oms"]["candidates"] + r["spa"]["candidates"] for r in recs)
+    lds_peak = ctx.probe_lds()
     last = recs[-1]
     phases = {
         "oms_search": {"edge_updates": last["oms"]["edge_updates"],
@@ -165,6 +167,11 @@ def main():
     eu_per_launch = dk["edge_updates"] / max(dk["decode_launches"], 1)
     achieved = VALU_SLOTS_PER_EU[dom] * eu_per_launch / launch_s / 1e12
     hbm_equiv = BYTES_PER_EU[dom] * eu_per_launch / launch_s / 1e9
+    # LDS bytes per edge-update of the register layout: the APP gather (4) and
+    # the atomic add (read + write, 8) per edge, and per variable the channel
+    # read, the next APP buffer's initialisation and the hard-decision read
+    # (12) spread over its edges
+    lds_bpe = 12.0 + 12.0 * code.n / c.e
     roofline = {
         "bound": "alu", "kernel": f"k_search<{'SpaRule' if dom == 'spa' else 'OmsRule'}>",
         "achieved": round(achieved, 2), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TFLOP/s",
@@ -176,6 +183,10 @@ def main():
         "hbm_equivalent": {"bytes_per_edge_update": BYTES_PER_EU[dom],
                            "achieved_GBs": round(hbm_equiv, 1),
                            "frac_of_peak": round(hbm_equiv / HBM_PEAK_GBS, 4)},
+        "lds": {"bytes_per_edge_update": round(lds_bpe, 3),
+                "achieved_GBs": round(lds_bpe * eu_per_launch / launch_s / 1e9, 1),
+                "peak_GBs_measured": round(lds_peak / 1e9, 1),
+                "frac_of_measured_peak": round(lds_bpe * eu_per_launch / launch_s / lds_peak, 4)},
     }
     line = {
         "metric": "BP edge-updates/s (TS search + IS, one job)",
@@ -189,6 +200,7 @@ def main():
                                "OMS-i8 20it + SPA-f32 50it, a_max 12, 3 dB, + IS top-4 TS",
                    "patterns": int(P), "is_frames_per_ts": args.is_frames},
         "ts_found_per_s": ts_found / wall,
+        "candidates_per_s": cands / wall,
         "phases": phases,
         "roofline": roofline,
     }
@@ -203,7 +215,9 @@ def main():
     if not args.no_layered:
         line["layered"] = bench_layered(tsg)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(code, pats_host, args.cpu_seconds)
+        mix = {"oms": last["oms"]["edge_updates"], "spa": last["spa"]["edge_updates"],
+               "is": last["is"]["edge_updates"]}
+        line["cpu_baseline"] = cpu_baseline(code, pats_host, args.cpu_seconds, mix)
     print(json.dumps(line), flush=True)
 
 
@@ -368,51 +382,56 @@ def bench_batch(tsg):
             "speedup": t_plain / t_batch, "results_identical": bool(same)}
 
 
-def bench_serve(tsg, seconds, rate):
-    """Poisson arrivals of search and IS jobs on the 46x68-base code pool."""
-    import numpy as np
-    import workloads
-    pool = workloads.serving_pool()
-    rng = np.random.default_rng(5)
-    ctx = tsg.Context(0, torch_stream=False, torch_alloc=False)
-    loaded = [ctx.load_code(c) for c in pool]
-    graphs = []
-    for c, g in zip(pool, loaded):
-        rp, col = g.csr()
-        graphs.append((rp, col) + var_checks(rp, col, c.n) + (c.n,))
-    t, arrivals = 0.0, []
+def _serve_stream(pool, graphs, rng, seconds, rate):
+    """Poisson arrivals over [0, seconds): (arrival, kind, code index, data, kwargs)."""
+    t, jobs = 0.0, []
     while True:
         t += rng.exponential(1.0 / rate)
         if t > seconds:
             break
-        arrivals.append(t)
-    jobs = []
-    for ta in arrivals:
         ci = int(rng.integers(0, len(pool)))
         frames = int(round(10 ** rng.uniform(3, 5)))
-        c, g = pool[ci], loaded[ci]
+        c = pool[ci]
         if rng.random() < 0.5:
-            jobs.append((ta, "search", g, sample_pairs(graphs[ci], frames, rng), dict(a_max=12)))
+            jobs.append((t, "search", ci, sample_pairs(graphs[ci], frames, rng), dict(a_max=12)))
         else:
             v0 = int(rng.integers(0, c.n))
             bits = shortest_cycle_vns(graphs[ci], v0)[:16]
-            jobs.append((ta, "is", g, bits, dict(ebn0_db=float(rng.integers(2, 6)), shift=1.0,
+            jobs.append((t, "is", ci, bits, dict(ebn0_db=float(rng.integers(2, 6)), shift=1.0,
                                                  n_frames=frames, seed=int(rng.integers(1 << 30)),
                                                  max_iter=50)))
+    return jobs
+
+
+def _warm(loaded, graphs, jobs):
+    """Runs one small search and one small IS estimate per code the jobs use,
+    so that the autotuner's probes (cached per code) fall outside the timing."""
+    import numpy as np
+    rng = np.random.default_rng(9)
+    skw = next(j[4] for j in jobs if j[1] == "search")
+    for ci in sorted({j[2] for j in jobs}):
+        g = loaded[ci]
+        # sizes at which a plain call tunes (256 patterns, 1024 frames)
+        g.impulse_search(sample_pairs(graphs[ci], 512, rng), **skw)
+        g.reset_ts()
+        g.is_estimate(shortest_cycle_vns(graphs[ci], 0)[:16], 3.0, 1.0, 2048, seed=1, max_iter=50)
+
+
+def _serve_run(tsg, pool, graphs, jobs, budget, paced):
+    """Runs the jobs through the serving loop (4 worker slots) on a fresh
+    context; paced = submit at the arrival times, else all at once."""
+    import numpy as np
+    ctx = tsg.Context(0, torch_stream=False, torch_alloc=False, hbm_budget_bytes=budget)
+    loaded = [ctx.load_code(c) for c in pool]
+    _warm(loaded, graphs, jobs)
     ctx.serve_start(4)
-    _say(f"served: warm-up on {len(pool)} codes")
-    warm = [ctx.submit_search(g, sample_pairs(graphs[i], 512, rng), a_max=12)
-            for i, g in enumerate(loaded)]
-    for jid in warm:
-        ctx.poll(jid, wait=True)
-        ctx.release(jid)
-    _say(f"served: {len(jobs)} jobs over {seconds:.0f} s")
     ids = []
     t0 = time.perf_counter()
-    for ta, kind, g, data, kw in jobs:
+    for ta, kind, ci, data, kw in jobs:
         now = time.perf_counter() - t0
-        if ta > now:
+        if paced and ta > now:
             time.sleep(ta - now)
+        g = loaded[ci]
         if kind == "search":
             ids.append(ctx.submit_search(g, data, **kw))
         else:
@@ -421,21 +440,78 @@ def bench_serve(tsg, seconds, rate):
                                      kw.pop("seed"), **kw))
     infos = [ctx.poll(j, wait=True) for j in ids]
     wall = time.perf_counter() - t0
-    bad = [i for i in infos if i["status"] != 0]
     for j in ids:
         ctx.release(j)
     ctx.close()
     lat = np.array([i["end_ms"] - i["submit_ms"] for i in infos])
     eu = sum(i["edge_updates"] for i in infos)
     span = (max(i["end_ms"] for i in infos) - min(i["submit_ms"] for i in infos)) * 1e-3
-    return {"workload": f"Poisson {rate:g} jobs/s for {seconds:g} s, 46x68-base QC pool of 32 "
-                        "(N up to 25.7k), 50/50 search (OMS-i8 20it) / IS (SPA-f32 50it, 2..5 dB), "
-                        "10^3..10^5 frames log-uniform, 4 worker slots",
-            "jobs": len(ids), "failed": len(bad),
+    return {"jobs": len(ids), "failed": sum(1 for i in infos if i["status"] != 0),
             "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                            "max": float(lat.max())},
-            "edge_updates": eu, "edge_updates_per_s": eu / span, "seconds": span,
-            "wall_s": wall}
+            "edge_updates": int(eu), "edge_updates_per_s": eu / span, "seconds": span, "wall_s": wall}
+
+
+def _plain_run(tsg, pool, graphs, jobs):
+    """The same jobs one after another through the plain per-job calls."""
+    import numpy as np
+    ctx = tsg.Context(0, torch_stream=False, torch_alloc=False)
+    loaded = [ctx.load_code(c) for c in pool]
+    _warm(loaded, graphs, jobs)
+    eu = 0
+    t0 = time.perf_counter()
+    for _, kind, ci, data, kw in jobs:
+        g = loaded[ci]
+        if kind == "search":
+            g.reset_ts()
+            r = g.impulse_search(data, **kw)
+            g.collect_arrays()
+        else:
+            kw = dict(kw)
+            r = g.is_estimate(data, kw.pop("ebn0_db"), kw.pop("shift"), kw.pop("n_frames"),
+                              kw.pop("seed"), **kw)
+        eu += r["stats"]["edge_updates"]
+    wall = time.perf_counter() - t0
+    ctx.close()
+    return {"edge_updates": int(eu), "seconds": wall, "edge_updates_per_s": eu / wall}
+
+
+def bench_serve(tsg, seconds, rate, stress_seconds=5.0):
+    """Poisson arrivals of search and IS jobs on the 46x68-base code pool:
+    the paced stream under a 32 GiB HBM budget (latency), the same jobs all
+    submitted at once (capacity) and one after another through the plain
+    per-job calls, and a short paced stream under a 1 GiB budget (admission
+    stress)."""
+    import numpy as np
+    import workloads
+    pool = workloads.serving_pool()
+    rng = np.random.default_rng(5)
+    graphs = []
+    ctx = tsg.Context(0, torch_stream=False, torch_alloc=False)
+    for c in pool:   # the expanded graphs, from the library's loader
+        g = ctx.load_code(c)
+        rp, col = g.csr()
+        graphs.append((rp, col) + var_checks(rp, col, c.n) + (c.n,))
+    ctx.close()
+    jobs = _serve_stream(pool, graphs, rng, seconds, rate)
+    _say(f"served: {len(jobs)} jobs paced over {seconds:.0f} s")
+    paced = _serve_run(tsg, pool, graphs, jobs, 32 << 30, True)
+    _say("served: the same jobs submitted at once")
+    burst = _serve_run(tsg, pool, graphs, jobs, 32 << 30, False)
+    _say("plain: the same jobs one after another")
+    plain = _plain_run(tsg, pool, graphs, jobs)
+    stress_jobs = _serve_stream(pool, graphs, np.random.default_rng(55), stress_seconds, rate)
+    _say(f"served: {len(stress_jobs)} jobs paced over {stress_seconds:.0f} s under a 1 GiB budget")
+    stress = _serve_run(tsg, pool, graphs, stress_jobs, 1 << 30, True)
+    out = {"workload": f"Poisson {rate:g} jobs/s for {seconds:g} s, 46x68-base QC pool of 32 "
+                       "(N up to 25.7k), 50/50 search (OMS-i8 20it) / IS (SPA-f32 50it, 2..5 dB), "
+                       "10^3..10^5 frames log-uniform, 4 worker slots, 32 GiB HBM budget"}
+    out.update(paced)
+    out["all_at_once"] = burst
+    out["plain_sequential"] = plain
+    out["served_vs_plain"] = burst["edge_updates_per_s"] / plain["edge_updates_per_s"]
+    out["stress_1GiB"] = stress
+    return out
 
 
 def bench_qc2640(tsg):
@@ -521,9 +597,24 @@ def bench_layered(tsg):
     return out
 
 
-def cpu_baseline(code, pats, seconds):
-    """The oracle (plain C, OpenMP over patterns) on a bounded sample of the same
-    workload: the first patterns of a fixed shuffle, OMS then SPA."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(code, pats, seconds, mix):
+    """The oracle (plain C, OpenMP over patterns / frames) on bounded samples of
+    the same workload, on all host threads: OMS and SPA searches over the first
+    patterns of a fixed shuffle, and IS frames (SPA, 3 dB, shift 1.5) of the
+    shortest cycle through variable 0.  The reported rate is that of the GPU
+    step's mix: edge-updates of the step / the oracle's time for each leg's
+    share.  A single-thread SPA sample is reported beside it."""
     import numpy as np
 
     import oracle
@@ -531,33 +622,50 @@ def cpu_baseline(code, pats, seconds):
     rng = np.random.default_rng(0)
     order = rng.permutation(len(pats))
     threads = os.cpu_count() or 1
-    eu = 0
-    t_used = 0.0
-    n_oms = n_spa = 0
-    # OMS sample, then SPA sample, each about half of the time budget
-    for dec, kw in (("oms", dict(decoder=oracle.DEC_OMS, max_iter=20, k_max=512, k_den=16)),
-                    ("spa", dict(decoder=oracle.DEC_SPA, max_iter=50, k_max=32 * 1024,
-                                 k_den=1024))):
-        take = 256 if dec == "oms" else 16
-        pos = 0
-        t_phase = 0.0
-        while t_phase < seconds / 2 and pos < len(pats):
+    legs = {}
+
+    def search_leg(kw, take, budget, nthreads):
+        pos, t_used, eu = 0, 0.0, 0
+        while t_used < budget and pos < len(pats):
             sel = np.ascontiguousarray(pats[order[pos:pos + take]])
             t0 = time.perf_counter()
-            r = oracle.search(oc, sel, a_max=12, threads=threads, **kw)
-            dt = time.perf_counter() - t0
-            t_phase += dt
+            r = oracle.search(oc, sel, a_max=12, threads=nthreads, **kw)
+            t_used += time.perf_counter() - t0
             eu += r["edge_updates"]
             pos += len(sel)
             take *= 2
-        t_used += t_phase
-        if dec == "oms":
-            n_oms = pos
-        else:
-            n_spa = pos
-    return {"value": eu / t_used, "unit": "edge-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_oms} OMS + {n_spa} SPA patterns of the same list (fixed shuffle), "
-                      f"{t_used:.1f} s"}
+        return {"patterns": pos, "seconds": t_used, "edge_updates_per_s": eu / t_used}
+
+    legs["oms"] = search_leg(dict(decoder=oracle.DEC_OMS, max_iter=20, k_max=512, k_den=16),
+                             256, 0.25 * seconds, threads)
+    # the oracle spreads patterns over its threads in chunks: give each thread several
+    legs["spa"] = search_leg(dict(decoder=oracle.DEC_SPA, max_iter=50, k_max=32 * 1024, k_den=1024),
+                             8 * threads, 0.35 * seconds, threads)
+    rp, col = oc.csr()
+    graph = (rp, col) + var_checks(rp, col, code.n) + (code.n,)
+    bits = shortest_cycle_vns(graph, 0)
+    frames, t_used, eu = 256, 0.0, 0
+    n_frames = 0
+    while t_used < 0.2 * seconds:
+        t0 = time.perf_counter()
+        r = oracle.is_estimate(oc, bits, 3.0, 1.5, frames, seed=7, frame_base=n_frames,
+                               threads=threads)
+        t_used += time.perf_counter() - t0
+        eu += r["edge_updates"]
+        n_frames += frames
+        frames *= 2
+    legs["is"] = {"frames": n_frames, "seconds": t_used, "edge_updates_per_s": eu / t_used}
+    single = search_leg(dict(decoder=oracle.DEC_SPA, max_iter=50, k_max=32 * 1024, k_den=1024),
+                        2, 0.2 * seconds, 1)
+    t_step = sum(mix[k] / legs[k]["edge_updates_per_s"] for k in legs)
+    used = sum(l["seconds"] for l in legs.values()) + single["seconds"]
+    return {"value": sum(mix.values()) / t_step, "unit": "edge-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{legs['oms']['patterns']} OMS + {legs['spa']['patterns']} SPA patterns of the "
+                      f"same list (fixed shuffle) and {legs['is']['frames']} IS frames, {used:.1f} s; "
+                      "value = the GPU step's edge-updates over the oracle's time for each leg's share",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "legs": legs, "single_thread_spa": single}
 
 
 if __name__ == "__main__":

@@ -103,6 +103,9 @@ typedef struct {
                          * of a QC code, else the greedy variable-disjoint
                          * colouring of the checks; 0 = more than 64 layers
                          * (TS_DEC_LNMS_Q4 is then rejected) */
+    int32_t streamed_qc;   /* 1: the streamed-frame decoder of this QC code derives
+                            * its neighbour and message-slot indices from the
+                            * circulant shifts instead of reading index tables */
 } ts_code_info_t;
 int ts_code_info(const ts_code *code, ts_code_info_t *out);
 /* Check-major CSR of the expanded H (host arrays row_ptr[m+1], col[e]). */
@@ -380,6 +383,14 @@ typedef struct {
     int32_t checks_per_thread;   /* register layout: checks per thread */
 } ts_stats;
 int ts_get_stats(ts_ctx *ctx, ts_stats *out);
+
+/* Measurement aid (not a step of the paper's method): the device's LDS read
+ * bandwidth in bytes/s, the best of three timed launches of a kernel whose
+ * workgroups (20 per compute unit, 32 KB of LDS each) read their LDS with
+ * bank-conflict-free 16-byte loads.  Runs on the context's stream and waits
+ * for it; allocates and frees a small device buffer.  TS_E_INVAL on null
+ * arguments, TS_E_DEVICE / TS_E_NOMEM on runtime failures. */
+int ts_probe_lds(ts_ctx *ctx, double *bytes_per_s);
 
 #ifdef __cplusplus
 }

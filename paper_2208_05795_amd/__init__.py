@@ -238,6 +238,12 @@ class Context:
         _check(lib().ts_get_stats(self._h, C.byref(s)))
         return {f: getattr(s, f) for f, _ in A.Stats._fields_}
 
+    def probe_lds(self) -> float:
+        """LDS read bandwidth of the device in bytes/s (measurement aid)."""
+        v = C.c_double()
+        _check(lib().ts_probe_lds(self._h, C.byref(v)))
+        return v.value
+
     def close(self):
         if getattr(self, "_h", None):
             for c in list(self._codes):

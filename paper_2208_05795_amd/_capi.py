@@ -35,7 +35,7 @@ class CodeDesc(C.Structure):
 class CodeInfo(C.Structure):
     _fields_ = [("n", C.c_int32), ("m", C.c_int32), ("e", C.c_int64), ("girth", C.c_int32),
                 ("z", C.c_int32), ("dv_max", C.c_int32), ("dc_max", C.c_int32),
-                ("n_layers", C.c_int32)]
+                ("n_layers", C.c_int32), ("streamed_qc", C.c_int32)]
 
 
 class SearchOpts(C.Structure):
@@ -120,6 +120,7 @@ PROTOTYPES = {
     "ts_is_estimate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                  C.POINTER(IsOpts), C.POINTER(IsResult), C.c_void_p]),
     "ts_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
+    "ts_probe_lds": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "ts_cycle_emd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     "ts_spectrum": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]),
     "ts_union_bound": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(UbOpts), C.c_void_p, C.c_void_p]),

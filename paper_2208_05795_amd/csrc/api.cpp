@@ -262,6 +262,50 @@ static int select_is_shape(ts_ctx *ctx, ts_code *code, int max_iter, int layout,
     return TS_OK;
 }
 
+// Batches plan every job with its code's cached shape.  A job whose code has
+// none yet for the job's (decoder, iterations, layout), and which is as large
+// as a plain call that would tune (256 patterns / 1024 frames), first runs the
+// plain call on a probe of its own patterns or frames (at most 8192; results
+// discarded, statistics restored), which tunes and caches the shape.
+int tune_for_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
+    const ts_stats keep = ex.stats;
+    hipStream_t s = ex.stream;
+    int rc = TS_OK;
+    for (BatchJob &b : jobs) {
+        ts_code *code = b.code;
+        if (b.kind == TS_JOB_SEARCH) {
+            if (b.n_patterns < 256) continue;
+            {
+                std::lock_guard<std::mutex> g(code->tune_mu);
+                if (code->tuned.count((b.so.layout * 2 + b.so.decoder) * 1000 + b.so.max_iter)) continue;
+            }
+            const int64_t P = std::min<int64_t>(b.n_patterns, 8192);
+            DBuf d_pat(ex, (size_t)P * b.width * 4), d_out(ex, (size_t)5 * P * 4);
+            if (!d_pat.p || !d_out.p) { rc = TS_E_NOMEM; break; }
+            TSG_HIP(hipMemcpyAsync(d_pat.p, b.patterns, (size_t)P * b.width * 4, hipMemcpyHostToDevice, s));
+            int32_t *outs[5];
+            for (int i = 0; i < 5; ++i) outs[i] = d_out.as<int32_t>() + (size_t)i * P;
+            DevTable none{};
+            rc = run_search(ex, code, none, &b.so, d_pat.as<int32_t>(), P, b.width, outs, false);
+        } else {
+            if (b.io.n_frames < 1024) continue;
+            {
+                std::lock_guard<std::mutex> g(code->tune_mu);
+                if (code->tuned.count(is_tune_key(b.io.max_iter, b.io.layout))) continue;
+            }
+            ts_is_opts io = b.io;
+            io.n_frames = std::min<int64_t>(io.n_frames, 8192);
+            if (io.shift < 0.0) io.shift = 1.0;   // no eps* search for a timing probe
+            ts_is_result res{};
+            rc = run_is(ex, code, b.ts_bits, b.a, &io, &res, nullptr);
+        }
+        if (rc) break;
+    }
+    TSG_HIP(hipStreamSynchronize(s));
+    ex.stats = keep;
+    return rc;
+}
+
 int plan_is_shape(ts_exec &ex, ts_code *code, int max_iter, int layout, SearchPlan *plan) {
     std::vector<SearchPlan> shapes;
     bool need_tune = false;
@@ -762,6 +806,7 @@ int ts_code_info(const ts_code *code, ts_code_info_t *out) {
     out->dv_max = code->dv_max;
     out->dc_max = code->dc_max;
     out->n_layers = code->dev.n_layers;
+    out->streamed_qc = code->dev.q_ok;
     return TS_OK;
 }
 

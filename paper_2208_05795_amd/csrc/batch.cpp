@@ -1,8 +1,9 @@
 // Batched execution of several search and IS jobs, possibly on different codes.
 //
 // Every job is planned as if run alone (the code's autotuned shape, else the
-// first that fits).  Jobs whose plans name the same kernel and a workgroup size
-// in the same power-of-two bucket form a group; a group runs as ONE persistent
+// first that fits).  Jobs whose plans name the same kernel, a workgroup size in
+// the same power-of-two bucket and frames that fit the same number of times
+// into a CU's LDS form a group; a group runs as ONE persistent
 // launch whose workgroups pull items (patterns or IS frames) of all its jobs
 // from a single queue, so small jobs fill the device together and no launch
 // tail or host round trip separates them.  Groups go to the executor's side
@@ -77,6 +78,8 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
     hipStream_t s = ex.stream;
     int rc = ensure_side(ex);
     if (rc) return rc;
+    rc = tune_for_batch(ex, jobs);
+    if (rc) return rc;
     std::vector<SItem> S;
     std::vector<IItem> I;
     // ---- plan every job -------------------------------------------------
@@ -122,9 +125,13 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
     }
     // ---- groups -----------------------------------------------------------
     std::vector<Group> G;
-    std::map<std::tuple<int, int, int, int, int, int>, int> gid;
+    std::map<std::tuple<int, int, int, int, int, int, int>, int> gid;
     auto group_of = [&](bool search, const SearchPlan &p) {
-        const auto key = std::make_tuple(search ? 1 : 0, p.kind, p.dc, p.cpt, p.decoder, bucket(p.block));
+        // a group takes the largest LDS frame of its jobs: only jobs whose frames
+        // fit the same number of times into a CU's LDS share one, so that no job
+        // loses occupancy to a larger code's frame
+        const int lds_fit = (int)(ctx->lds_per_block / std::max<size_t>(p.lds, 1));
+        const auto key = std::make_tuple(search ? 1 : 0, p.kind, p.dc, p.cpt, p.decoder, bucket(p.block), lds_fit);
         auto f = gid.find(key);
         if (f != gid.end()) {
             Group &g = G[f->second];

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <condition_variable>
 #include <cstdint>
@@ -43,6 +44,7 @@ constexpr int kRecStride = kRecHdr + kCapMax;
 // is a contiguous range.  Codes of check degree above 24 use the classes
 // without 24 (degrees 17..32 pad to 32).
 constexpr int kGClasses[] = {3, 4, 6, 8, 12, 16, 24, 32};
+constexpr int kQTabMaxBytes = 16 * 1024;   // LDS budget of the QC index tables
 constexpr int kGMaxCls = 8;
 
 // Device-side description of a code, shared by all kernels.
@@ -67,6 +69,17 @@ struct DevCode {
     int g_off[kGMaxCls + 1];   // g_off[g_ncls] = total message slots
     const int *g_cn;       // [slots] variable of each message slot (n = padding)
     const int *g_vslot;    // [dv_pad][n_tab] message slot of each (variable, k) edge, -1 = pad
+    // streamed layout of a QC code: the same indices computed from per-circulant
+    // tables (qc_neighbour / qc_slot) instead of read from g_cn / g_vslot.  q_ok
+    // is set only after the loader has checked every computed index against
+    // those tables.  q_tab holds int pairs: [mb][q_dc] (j z or -1, shift) per
+    // (block row, neighbour slot), then [nb][q_dv] (slot base or -1, shift) per
+    // (block column, k-th check); q_rowpos[p] = (block row << 16) | row of the
+    // check at sorted position p.
+    int q_ok, q_dc, q_dv, q_bytes, q_var_off;   // q_var_off: ints before the column part
+    float q_inv_z;
+    const int *q_tab;
+    const int *q_rowpos;
     // layered schedule: the checks ordered by layer (stable), so that a layer is a
     // contiguous range of positions; lay_of[p] = layer at position p
     // (non-decreasing), cn_lay[j][p] = cn_tab[j][check at p]; n_layers = 0 when
@@ -75,6 +88,57 @@ struct DevCode {
     const int *cn_lay;     // [dc_pad][m_tab]
     int n_layers;
 };
+
+// LDS layout of a streamed frame (host and device).
+struct LdsG {
+    int np, W;
+    size_t app, imask, wsyn, pcnt, cls, qtab, extra, total;
+};
+
+// qbytes: size of the QC index tables copied to LDS (0 = read g_cn / g_vslot)
+__host__ __device__ inline LdsG lds_layout_g(int n, int T, int qbytes) {
+    LdsG L;
+    L.np = (n + 1 + 63) & ~63;
+    L.W = L.np >> 6;
+    size_t o = 0;
+    L.app = o;
+    o += (size_t)L.np * 4;
+    o = (o + 15) & ~(size_t)15;
+    L.imask = o;
+    o += (size_t)L.W * 8;
+    L.wsyn = o;
+    o += (size_t)(T + 2) * 4;
+    L.pcnt = o;
+    o += (size_t)(T + 2) * 4;
+    L.cls = o;   // class table: dc, c0, stride, off
+    o += (size_t)(4 * kGMaxCls + 2) * 4;
+    o = (o + 15) & ~(size_t)15;
+    L.qtab = o;
+    o += (size_t)qbytes;
+    o = (o + 15) & ~(size_t)15;
+    L.extra = o;
+    o += (size_t)kMaxWidth * 8 + (size_t)kMaxWidth * 4;
+    L.total = (o + 15) & ~(size_t)15;
+    return L;
+}
+
+// Variable of neighbour slot j of check (i, r) of a QC code, from its table
+// pair e = (j z, shift) of block row i (j z < 0: padding, returns n).
+__host__ __device__ inline int qc_neighbour(const int *e, int r, int z, int n) {
+    if (e[0] < 0) return n;
+    int c = r + e[1];
+    if (c >= z) c -= z;
+    return e[0] + c;
+}
+
+// Message slot of the k-th edge of variable (j, c) of a QC code, from the pair
+// e = (slot base, shift) of (block column j, k) (slot base < 0: padding, -1).
+__host__ __device__ inline int qc_slot(const int *e, int c, int z) {
+    if (e[0] < 0) return -1;
+    int r = c - e[1];
+    if (r < 0) r += z;
+    return e[0] + r;
+}
 
 // Open-addressing TS table on the device, keyed by the canonical QC-orbit
 // representative; the full key is compared on every hash match.
@@ -339,6 +403,7 @@ struct BatchJob {
     std::string err;
 };
 int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs);
+int tune_for_batch(ts_exec &ex, std::vector<BatchJob> &jobs);   // api.cpp
 
 // serve.cpp
 struct Server;

@@ -168,6 +168,10 @@ namespace {
 std::vector<int64_t> edge_order(const ts_code *c) {
     std::vector<int64_t> ord((size_t)c->e);
     for (int64_t k = 0; k < c->e; ++k) ord[k] = k;
+    // a QC code keeps its natural order: consecutive rows of a circulant already
+    // gather consecutive words, and the streamed layout derives its indices
+    // from the block structure
+    if (c->z > 0) return ord;
     const int dmax = c->dc_max;
     std::vector<int> c64((size_t)dmax * 64), c32((size_t)2 * dmax * 32);
     for (int g0 = 0; g0 < c->m; g0 += 64) {
@@ -282,6 +286,80 @@ int upload_code(ts_exec &ex, ts_code *c) {
                 gvs[(size_t)(k - c->vptr[v]) * d.n_tab + v] = edge_slot[c->vedge[k]];
     }
     if (gcn.empty()) gcn.push_back(c->n);
+    // QC code: the streamed indices from per-circulant tables (block row i,
+    // neighbour slot j -> (j z, shift); block column j, k-th check -> (slot base,
+    // shift)), switched on only once every computed index equals the table
+    // entry it replaces
+    d.q_ok = 0;
+    std::vector<int32_t> qtab, qrow;
+    if (c->z > 0 && d.g_ncls > 0 && c->z < (1 << 16) && c->mb < (1 << 15)) {
+        const int z = c->z, mb = c->mb, nb = c->nb;
+        std::vector<int> S((size_t)mb * nb, -1);   // shifts, read off row 0 of each block row
+        for (int i = 0; i < mb; ++i)
+            for (int64_t e = c->row_ptr[(size_t)i * z]; e < c->row_ptr[(size_t)i * z + 1]; ++e)
+                S[(size_t)i * nb + c->col[e] / z] = c->col[e] % z;
+        const int qdc = d.g_dc[d.g_ncls - 1], qdv = d.dv_pad;
+        std::vector<int> pos_of((size_t)c->m);
+        for (int p = 0; p < c->m; ++p) pos_of[order[p]] = p;
+        const size_t vb = 2 * (size_t)mb * qdc;
+        qtab.assign(vb + 2 * (size_t)nb * qdv, -1);
+        bool ok = true;
+        for (int i = 0; i < mb; ++i) {
+            int jj = 0;
+            for (int j = 0; j < nb; ++j)
+                if (S[(size_t)i * nb + j] >= 0) {
+                    if (jj >= qdc) { ok = false; break; }
+                    qtab[2 * ((size_t)i * qdc + jj)] = j * z;
+                    qtab[2 * ((size_t)i * qdc + jj) + 1] = S[(size_t)i * nb + j];
+                    ++jj;
+                }
+        }
+        for (int j = 0; j < nb && ok; ++j) {
+            int kk = 0;
+            for (int i = 0; i < mb; ++i) {
+                if (S[(size_t)i * nb + j] < 0) continue;
+                if (kk >= qdv) { ok = false; break; }
+                int jp = 0;   // slot of column j among the nonzero blocks of row i
+                for (int j2 = 0; j2 < j; ++j2) jp += S[(size_t)i * nb + j2] >= 0;
+                const int P0 = pos_of[(size_t)i * z];
+                int q = 0;
+                while (q + 1 < d.g_ncls && P0 >= d.g_c0[q + 1]) ++q;
+                qtab[vb + 2 * ((size_t)j * qdv + kk)] = d.g_off[q] + jp * d.g_stride[q] + (P0 - d.g_c0[q]);
+                qtab[vb + 2 * ((size_t)j * qdv + kk) + 1] = S[(size_t)i * nb + j];
+                ++kk;
+            }
+        }
+        qrow.resize((size_t)c->m);
+        for (int p = 0; p < c->m; ++p) qrow[p] = ((order[p] / z) << 16) | (order[p] % z);
+        for (int q = 0; q < d.g_ncls && ok; ++q)
+            for (int p = d.g_c0[q]; p < d.g_c0[q + 1] && ok; ++p) {
+                const int i = qrow[p] >> 16, r = qrow[p] & 0xffff;
+                for (int j = 0; j < d.g_dc[q] && ok; ++j) {
+                    const int v = qc_neighbour(&qtab[2 * ((size_t)i * qdc + j)], r, z, c->n);
+                    ok = v == gcn[(size_t)d.g_off[q] + (size_t)j * d.g_stride[q] + (p - d.g_c0[q])];
+                }
+            }
+        for (int v = 0; v < c->n && ok; ++v) {
+            const int jc = v / z, cc = v % z;
+            for (int k = 0; k < qdv && ok; ++k)
+                ok = qc_slot(&qtab[vb + 2 * ((size_t)jc * qdv + k)], cc, z) == gvs[(size_t)k * d.n_tab + v];
+        }
+        // the tables must not cost a code its streamed frame at any iteration count
+        const int qb = (int)(qtab.size() * 4);
+        const size_t lim = ex.ctx ? ex.ctx->lds_per_block : 0;
+        const bool fits = kHdrLds + lds_layout_g(c->n, kMaxIter, qb).total <= lim ||
+                          kHdrLds + lds_layout_g(c->n, kMaxIter, 0).total > lim;
+        if (ok && fits && qb <= kQTabMaxBytes) {
+            d.q_ok = 1;
+            d.q_dc = qdc;
+            d.q_dv = qdv;
+            d.q_bytes = (int)(qtab.size() * 4);
+            d.q_var_off = (int)vb;
+            d.q_inv_z = 1.0f / (float)z;
+        }
+    }
+    if (qtab.empty()) qtab.push_back(-1);
+    if (qrow.empty()) qrow.push_back(0);
     // layered schedule: block rows of a QC code; otherwise each check, in index
     // order, goes to the lowest layer none of whose checks shares a variable
     std::vector<int32_t> lay((size_t)std::max(c->m, 1), 0);
@@ -320,6 +398,7 @@ int upload_code(ts_exec &ex, ts_code *c) {
         {vn.data(), vn.size() * 4, &d.vn_tab}, {gcn.data(), gcn.size() * 4, &d.g_cn},
         {gvs.data(), gvs.size() * 4, &d.g_vslot}, {lay_pos.data(), lay_pos.size() * 4, &d.lay_of},
         {cnl.data(), cnl.size() * 4, &d.cn_lay},
+        {qtab.data(), qtab.size() * 4, &d.q_tab}, {qrow.data(), qrow.size() * 4, &d.q_rowpos},
     };
     for (auto &u : ups) {
         void *p = ex.dalloc(u.bytes ? u.bytes : 4);

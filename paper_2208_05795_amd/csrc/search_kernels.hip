@@ -1025,34 +1025,6 @@ __global__ void k_fill(int *p, int value, long long count) {
 // variable pass gathers from consecutive rows of each circulant.  The integer
 // arithmetic (int8 / Q20 messages, int32 sums) is that of the register-resident
 // decoder, so both give identical results.
-struct LdsG {
-    int np, W;
-    size_t app, imask, wsyn, pcnt, cls, extra, total;
-};
-
-__host__ __device__ inline LdsG lds_layout_g(int n, int T) {
-    LdsG L;
-    L.np = (n + 1 + 63) & ~63;
-    L.W = L.np >> 6;
-    size_t o = 0;
-    L.app = o;
-    o += (size_t)L.np * 4;
-    o = (o + 15) & ~(size_t)15;
-    L.imask = o;
-    o += (size_t)L.W * 8;
-    L.wsyn = o;
-    o += (size_t)(T + 2) * 4;
-    L.pcnt = o;
-    o += (size_t)(T + 2) * 4;
-    L.cls = o;   // class table: dc, c0, stride, off
-    o += (size_t)(4 * kGMaxCls + 2) * 4;
-    o = (o + 15) & ~(size_t)15;
-    L.extra = o;
-    o += (size_t)kMaxWidth * 8 + (size_t)kMaxWidth * 4;
-    L.total = (o + 15) & ~(size_t)15;
-    return L;
-}
-
 struct GFrame {
     int *app;                          // LDS [np]
     const unsigned long long *imask;   // LDS impulse bits (search) or nullptr
@@ -1064,6 +1036,10 @@ struct GFrame {
     const int *cdc, *cc0, *cstr, *coff;   // LDS copy of the class table
     const int *g_cn, *g_vslot;         // the code's slot tables
     int ncls, n, np, W, T, m, dv_pad, n_tab;
+    // QC codes: indices computed from the LDS copy of the per-circulant tables
+    const int *qtab, *rowpos;
+    int qc, qdc, qdv, qvar, z;
+    float inv_z;
 };
 
 __device__ __forceinline__ int g_lambda(const GFrame &F, int v) {
@@ -1078,11 +1054,17 @@ __device__ __forceinline__ int check_g(const GFrame &F, int q, int p, int t, int
     const int stride = F.cstr[q];
     const size_t base = (size_t)F.coff[q] + (size_t)(p - F.cc0[q]);
     int nb[DC], val[DC], c2v[DC];
+    if (F.qc) {
+        const int rp = F.rowpos[p];
+        const int *e = F.qtab + 2 * (rp >> 16) * F.qdc;
 #pragma unroll
-    for (int j = 0; j < DC; ++j) {
-        nb[j] = F.g_cn[base + (size_t)j * stride];
-        val[j] = F.app[nb[j]];
+        for (int j = 0; j < DC; ++j) nb[j] = qc_neighbour(e + 2 * j, rp & 0xffff, F.z, F.n);
+    } else {
+#pragma unroll
+        for (int j = 0; j < DC; ++j) nb[j] = F.g_cn[base + (size_t)j * stride];
     }
+#pragma unroll
+    for (int j = 0; j < DC; ++j) val[j] = F.app[nb[j]];
     int par = 0;
 #pragma unroll
     for (int j = 0; j < DC; ++j) par ^= (val[j] < 0);
@@ -1147,9 +1129,22 @@ __device__ DecRes run_decode_g(const GFrame &F, int offset) {
             int x = 0;
             if (v < n) {
                 int sum = g_lambda(F, v);
-                for (int k = 0; k < F.dv_pad; ++k) {
-                    const int e = F.g_vslot[(size_t)k * F.n_tab + v];
-                    if (e >= 0) sum += (int)msg[e];
+                if (F.qc) {
+                    // block column by a float estimate of v / z, corrected to exact
+                    int jc = (int)((float)v * F.inv_z);
+                    if (jc * F.z > v) --jc;
+                    else if ((jc + 1) * F.z <= v) ++jc;
+                    const int cc = v - jc * F.z;
+                    const int *e = F.qtab + F.qvar + 2 * jc * F.qdv;
+                    for (int k = 0; k < F.qdv; ++k) {
+                        const int s = qc_slot(e + 2 * k, cc, F.z);
+                        if (s >= 0) sum += (int)msg[s];
+                    }
+                } else {
+                    for (int k = 0; k < F.dv_pad; ++k) {
+                        const int e = F.g_vslot[(size_t)k * F.n_tab + v];
+                        if (e >= 0) sum += (int)msg[e];
+                    }
                 }
                 F.app[v] = sum;
                 x = sum < 0;
@@ -1174,7 +1169,8 @@ __device__ __forceinline__ void g_bind(const DevCode &cd, int T, unsigned char *
                                        unsigned char *slot, GFrame &F, LdsG &L) {
     const int n = uni(cd.n);
     T = uni(T);
-    L = lds_layout_g(n, T);
+    const int qc = uni(cd.q_ok);
+    L = lds_layout_g(n, T, qc ? uni(cd.q_bytes) : 0);
     int *cls = (int *)(frame + L.cls);
     const int tid = threadIdx.x;
     if (tid < kGMaxCls) {
@@ -1203,6 +1199,22 @@ __device__ __forceinline__ void g_bind(const DevCode &cd, int T, unsigned char *
     F.np = L.np;
     F.W = L.W;
     F.T = T;
+    F.qc = qc;
+    F.qtab = nullptr;
+    F.rowpos = nullptr;
+    if (qc) {
+        int *qt = (int *)(frame + L.qtab);
+        const int words = uni(cd.q_bytes) >> 2;
+        const int *src = uni(cd.q_tab);
+        for (int i = tid; i < words; i += blockDim.x) qt[i] = src[i];
+        F.qtab = qt;
+        F.rowpos = uni(cd.q_rowpos);
+        F.qdc = uni(cd.q_dc);
+        F.qdv = uni(cd.q_dv);
+        F.qvar = uni(cd.q_var_off);
+        F.z = uni(cd.z);
+        F.inv_z = uni(cd.q_inv_z);
+    }
 }
 
 template <class Rule, int DCMAX, class M>
@@ -1363,7 +1375,7 @@ int streamed_dcmax(const ts_code *c) { return c->dc_max <= 16 ? 16 : (c->dc_max 
 int add_streamed_plans(ts_ctx *ctx, const ts_code *c, bool search, int decoder, int max_iter,
                        std::vector<SearchPlan> *out) {
     const GEntry *g = find_g(streamed_dcmax(c));
-    const size_t lds = kHdrLds + lds_layout_g(c->n, max_iter).total;
+    const size_t lds = kHdrLds + lds_layout_g(c->n, max_iter, c->dev.q_ok ? c->dev.q_bytes : 0).total;
     if (!g || lds > ctx->lds_per_block) return TS_OK;
     size_t aux = 0;
     const size_t slot = streamed_slot_bytes(c, decoder, max_iter, search, &aux);
@@ -1395,7 +1407,7 @@ size_t streamed_slot_bytes(const ts_code *c, int decoder, int max_iter, bool sea
     const size_t msg = (size_t)c->dev.g_off[c->dev.g_ncls] * (decoder == TS_DEC_OMS_I8 ? 1 : 4);
     size_t o = (msg + 255) & ~(size_t)255;
     *aux_off = o;
-    const LdsG L = lds_layout_g(c->n, max_iter);
+    const LdsG L = lds_layout_g(c->n, max_iter, c->dev.q_ok ? c->dev.q_bytes : 0);
     o += search ? (size_t)max_iter * L.W * 8 : (size_t)L.np * 4;
     return (o + 255) & ~(size_t)255;
 }

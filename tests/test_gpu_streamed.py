@@ -94,9 +94,10 @@ def test_layouts_identical_spa(ctx, oracle_mod, name):
     g.free()
 
 
-def test_layouts_identical_is(ctx, oracle_mod):
+@pytest.mark.parametrize("name", ["peg1008", "qc2640"])
+def test_layouts_identical_is(ctx, oracle_mod, name):
     import paper_2208_05795_amd as tsg
-    code = workloads.peg1008_code()
+    code = {"peg1008": workloads.peg1008_code, "qc2640": workloads.qc2640_code}[name]()
     g = ctx.load_code(code)
     bits = [int(x) for x in g.csr()[1][:4]]   # the variables of check 0 (a 4-subset)
     res = [g.is_estimate(bits, 1.0, 2.0, 3000, seed=5, stream=2, want_fail=True, layout=lay)
@@ -106,10 +107,23 @@ def test_layouts_identical_is(ctx, oracle_mod):
     assert np.array_equal(res[0]["fail"], res[1]["fail"])
     for f in ("p_hat", "var", "sum_w", "sum_w2", "n_fail"):
         assert res[0][f] == res[1][f], f
-    _say(f"IS register vs streamed identical: p {res[0]['p_hat']:.4e}, "
+    _say(f"{name} IS register vs streamed identical: p {res[0]['p_hat']:.4e}, "
          f"{int(res[0]['n_fail'])} failures")
     assert res[0]["n_fail"] > 0
     g.free()
+
+
+def test_qc_index_path(ctx):
+    """The streamed decoder of a QC code computes its indices from the
+    circulant tables (switched on by the loader only after every computed index
+    matched the index tables); a CSR code keeps the tables."""
+    pool = sorted(workloads.serving_pool(), key=lambda c: c.n)
+    wide = [c for c in workloads.batch_codes() if c.mb == 4 and c.nb == 24][0]
+    for code, want in ((workloads.peg1008_code(), 0), (workloads.tiny_code(), 1),
+                       (workloads.qc2640_code(), 1), (pool[0], 1), (pool[-1], 1), (wide, 1)):
+        g = ctx.load_code(code)
+        assert g.info["streamed_qc"] == want, code.name
+        g.free()
 
 
 @pytest.fixture(scope="module")
