@@ -582,8 +582,27 @@ struct RegSearchDec {
     __device__ __forceinline__ const unsigned long long *hist() const { return F.hist; }
 };
 
+// Waves per SIMD the register allocator is asked to fit (1 = no request): one
+// step above the natural occupancy of the sum-product shapes for which the few
+// registers this frees are spilled only outside the decode loop (checked on
+// the generated code; the other shapes would spill inside it).
 template <class Rule, int DC, int CPT>
-__global__ __launch_bounds__((MaxBlock<DC, CPT>::value)) void k_search(const SearchJob *jobs, int n_jobs,
+struct SearchWaves {
+    static constexpr int value =
+        !std::is_same<Rule, SpaRule>::value ? 1
+        : (DC == 6 && CPT == 1) ? 7 : (DC == 6 && CPT == 2) ? 6 : (DC == 6 && CPT == 4) ? 4
+        : (DC == 8 && CPT == 1) ? 6 : (DC == 8 && CPT == 2) ? 5 : (DC == 12 && CPT == 2) ? 4 : 1;
+};
+template <int DC, int CPT>
+struct IsWaves {
+    static constexpr int value = (DC == 6 && CPT == 1) ? 8 : (DC == 6 && CPT == 2) ? 6
+                                 : (DC == 8 && CPT == 1) ? 7 : (DC == 8 && CPT == 2) ? 5
+                                 : (DC == 12 && CPT == 1) ? 5 : 1;
+};
+
+template <class Rule, int DC, int CPT>
+__global__ __launch_bounds__((MaxBlock<DC, CPT>::value))
+__attribute__((amdgpu_waves_per_eu(SearchWaves<Rule, DC, CPT>::value))) void k_search(const SearchJob *jobs, int n_jobs,
                                                                       int *queue, long long n_items) {
     extern __shared__ __align__(16) unsigned char smem[];
     RegSearchDec<Rule, DC, CPT> dec;
@@ -917,7 +936,8 @@ struct RegIsDec {
 };
 
 template <int DC, int CPT>
-__global__ __launch_bounds__((MaxBlockIs<DC, CPT>::value)) void k_is(const IsJob *jobs, int n_jobs,
+__global__ __launch_bounds__((MaxBlockIs<DC, CPT>::value))
+__attribute__((amdgpu_waves_per_eu(IsWaves<DC, CPT>::value))) void k_is(const IsJob *jobs, int n_jobs,
                                                                     int *queue, long long n_items) {
     extern __shared__ __align__(16) unsigned char smem[];
     RegIsDec<DC, CPT> dec;
