@@ -34,14 +34,18 @@ namespace {
 constexpr int kSetMax = kCapMax + kMaxAmax;
 constexpr int kWaves = 4;          // wavefronts per workgroup of the sieve kernel
 constexpr int kWtab = 128;         // LDS hash slots for the TS(U) additions
+constexpr int kHtab = 512;         // LDS check map (more slots than a set has incidences)
+static_assert(kHtab > kSetMax * kDvMax, "the check map must hold every incidence");
 
 struct WaveLds {
     int U[kCapMax];
     int X[kSetMax];
     int alive[kSetMax];
     int inc[kSetMax * kDvMax];
-    int cnt[kSetMax * kDvMax];
+    int isl[kSetMax * kDvMax];   // check-map slot of each incidence's check
     int comp[kCapMax];
+    int hkey[kHtab];             // check map: check id (-1 = empty) ...
+    int hval[kHtab];             // ... and its count (Tree) or component (TS)
     int wtab[kWtab];
     int wlist[kWtab];
     int S[kSetMax];
@@ -77,6 +81,36 @@ __device__ unsigned long long set_hash(const int *key, int a) {
     return h ? h : 1ull;
 }
 
+// Per-wave check map in LDS (open addressing; it never holds more checks than
+// it has slots, so probes end).
+__device__ __forceinline__ unsigned check_hash(int c) { return ((unsigned)c * 2654435761u) >> 23; }
+
+__device__ void check_map_clear(WaveLds &w) {
+    for (int i = lane_id(); i < kHtab; i += 64) w.hkey[i] = -1;
+}
+
+// slot of check c, inserted if absent (lanes may insert concurrently)
+__device__ int check_map_slot(WaveLds &w, int c) {
+    unsigned s = check_hash(c);
+    for (;;) {
+        const int old = atomicCAS(&w.hkey[s], -1, c);
+        if (old == -1 || old == c) return (int)s;
+        s = (s + 1) & (kHtab - 1);
+    }
+}
+
+// slot of check c, or -1 (no concurrent inserts)
+__device__ int check_map_find(const WaveLds &w, int c) {
+    unsigned s = check_hash(c);
+    for (int p = 0; p < kHtab; ++p) {
+        const int k = w.hkey[s];
+        if (k == c) return (int)s;
+        if (k == -1) return -1;
+        s = (s + 1) & (kHtab - 1);
+    }
+    return -1;
+}
+
 // Builds the incidence list of X[0..k) (check of each variable/degree slot).
 __device__ void build_incidences(const DevCode &cd, WaveLds &w, int k) {
     const int dv = cd.dv_max;
@@ -90,28 +124,30 @@ __device__ void build_incidences(const DevCode &cd, WaveLds &w, int k) {
 }
 
 // Tree(X[0..k)): survivors written sorted to out, returns their number; *b gets
-// the number of odd-degree checks of the survivors' induced subgraph.
+// the number of odd-degree checks of the survivors' induced subgraph.  Each
+// peeling round counts, per check, its surviving variables in the check map,
+// then drops every variable with fewer than two checks counted twice or more.
 __device__ int wave_tree(const DevCode &cd, WaveLds &w, int k, int *out, int *b) {
     const int lane = lane_id(), dv = cd.dv_max, L = k * dv;
     build_incidences(cd, w, k);
+    check_map_clear(w);
     if (lane < k) w.alive[lane] = 1;
     wave_sync();
+    for (int idx = lane; idx < L; idx += 64) w.isl[idx] = w.inc[idx] >= 0 ? check_map_slot(w, w.inc[idx]) : -1;
+    wave_sync();
     for (;;) {
-        for (int idx = lane; idx < L; idx += 64) {
-            const int c = w.inc[idx];
-            int cnt = 0;
-            if (c >= 0 && w.alive[idx / dv])
-                for (int i = 0; i < k; ++i) {
-                    if (!w.alive[i]) continue;
-                    for (int d = 0; d < dv; ++d) cnt += w.inc[i * dv + d] == c;
-                }
-            w.cnt[idx] = cnt;
-        }
+        for (int i = lane; i < kHtab; i += 64) w.hval[i] = 0;
+        wave_sync();
+        for (int idx = lane; idx < L; idx += 64)
+            if (w.isl[idx] >= 0 && w.alive[idx / dv]) atomicAdd(&w.hval[w.isl[idx]], 1);
         wave_sync();
         int drop = 0;
         if (lane < k && w.alive[lane]) {
             int strong = 0;
-            for (int d = 0; d < dv; ++d) strong += w.cnt[lane * dv + d] >= 2;
+            for (int d = 0; d < dv; ++d) {
+                const int sl = w.isl[lane * dv + d];
+                strong += sl >= 0 && w.hval[sl] >= 2;
+            }
             drop = strong < 2;
         }
         if (!__any(drop)) break;
@@ -121,15 +157,9 @@ __device__ int wave_tree(const DevCode &cd, WaveLds &w, int k, int *out, int *b)
     const int keep = lane < k ? w.alive[lane] : 0;
     const unsigned long long mask = __ballot(keep);
     if (keep) out[__popcll(mask & ((1ull << lane) - 1ull))] = w.X[lane];
+    // the final counts are those of the survivors: odd ones are the odd checks
     int odd = 0;
-    for (int idx = lane; idx < L; idx += 64) {
-        const int c = w.inc[idx];
-        if (c < 0 || !w.alive[idx / dv] || !(w.cnt[idx] & 1)) continue;
-        bool first = true;
-        for (int j = 0; j < idx && first; ++j)
-            if (w.inc[j] == c && w.alive[j / dv]) first = false;
-        odd += first;
-    }
+    for (int i = lane; i < kHtab; i += 64) odd += w.hkey[i] >= 0 && (w.hval[i] & 1);
     *b = wave_sum(odd);
     wave_sync();
     return __popcll(mask);
@@ -169,35 +199,50 @@ __device__ int wave_ts_additions(const DevCode &cd, WaveLds &w, int u, int a_max
     }
     if (lane < u) w.comp[lane] = comp;
     for (int i = lane; i < kWtab; i += 64) w.wtab[i] = -1;
+    check_map_clear(w);
     if (lane == 0) w.misc[0] = 0;
     wave_sync();
-    for (int idx = 0; idx < L; ++idx) {
+    // check map: every check of U -> its component (U variables that share a
+    // check are in one component, so concurrent writers agree)
+    for (int idx = lane; idx < L; idx += 64) {
         const int c = w.inc[idx];
-        if (c < 0) continue;
-        const int r0 = cd.row_ptr[c], deg = cd.row_ptr[c + 1] - r0;
-        for (int q = lane; q < deg; q += 64) {
-            const int v = cd.col[r0 + q];
+        if (c >= 0) w.hval[check_map_slot(w, c)] = w.comp[idx / dv];
+    }
+    wave_sync();
+    // every (incidence, neighbour) pair: dcp lanes per incidence, 64 / dcp
+    // incidences per round
+    const int dcp = cd.dc_max <= 8 ? 8 : (cd.dc_max <= 16 ? 16 : (cd.dc_max <= 32 ? 32 : 64));
+    for (int base = 0; base < L; base += 64 / dcp) {
+        const int idx = base + lane / dcp, q = lane & (dcp - 1);
+        const int c = idx < L ? w.inc[idx] : -1;
+        int v = -1;
+        if (c >= 0) {
+            const int r0 = cd.row_ptr[c], deg = cd.row_ptr[c + 1] - r0;
+            if (q < deg) v = cd.col[r0 + q];
+        }
+        if (v >= 0) {
             int lo = 0, hi = u;   // binary search in the sorted U
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
                 if (w.U[mid] < v) lo = mid + 1;
                 else hi = mid;
             }
-            if (lo < u && w.U[lo] == v) continue;
+            if (lo < u && w.U[lo] == v) v = -1;
+        }
+        bool hit = false;
+        if (v >= 0) {
             int comps[kDvMax];
             const int vlo = cd.vptr[v], vdeg = cd.vptr[v + 1] - vlo;
-            bool hit = false;
             for (int d = 0; d < vdeg && !hit; ++d) {
-                const int c2 = cd.vchk[vlo + d];
-                int cp = -1;
-                for (int j = 0; j < L; ++j)
-                    if (w.inc[j] == c2) { cp = w.comp[j / dv]; break; }
+                const int sl = check_map_find(w, cd.vchk[vlo + d]);
+                const int cp = sl >= 0 ? w.hval[sl] : -1;
                 comps[d] = cp;
                 if (cp >= 0)
                     for (int d2 = 0; d2 < d; ++d2)
                         if (comps[d2] == cp) { hit = true; break; }
             }
-            if (!hit) continue;
+        }
+        if (hit) {
             unsigned slot = ((unsigned)v * 2654435761u) & (kWtab - 1);
             for (int p = 0; p < kWtab; ++p) {
                 const int old = atomicCAS(&w.wtab[slot], -1, v);
