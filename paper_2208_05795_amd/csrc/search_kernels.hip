@@ -56,36 +56,38 @@ __device__ __forceinline__ int to_q20(float l) {
 }
 
 // phi(x) = -ln tanh(x/2) = ln((1+u)/(1-u)), u = e^-x, for x >= 0, in two
-// forms, each accurate where its result matters.
+// forms, each accurate where its result matters.  The check's phi terms and
+// their sums are kept in log2 units (phi / ln 2), which the hardware exp2 and
+// log2 take and give without conversion.
 //
-// phi_in: phi of a variable-to-check magnitude |d| (Q20), clamped to
+// phi_in: phi / ln 2 of a variable-to-check magnitude |d| (Q20), clamped to
 // [2^-20, 30].  Small results must keep their relative accuracy (their sum
 // over a check can be tiny, and phi of a tiny sum is large), so below
-// u = 1/16 the series 2(u + u^3/3 + u^5/5) replaces the logarithm.  Large
-// results (x -> 0, where 1 - u cancels) need no care: such a term enters the
-// other edges' sums S >= phi_in, where |phi'(S)| <= 2 e^-S ~ x, which
-// cancels the 2^-24 / x relative error of 1 - u.
+// u = 1/16 the series 2(u + u^3/3 + u^5/5) / ln 2 replaces the logarithm.
+// Large results (x -> 0, where 1 - u cancels) need no care: such a term
+// enters the other edges' sums S >= phi_in, where |phi'(S)| <= 2 e^-S ~ x,
+// which cancels the 2^-24 / x relative error of 1 - u.
 __device__ __forceinline__ float phi_in(int d) {
     constexpr float kL2eQ = -1.4426950408889634f / 1048576.0f;   // -log2(e) 2^-20
-    const float e = fminf(fmaxf(fabsf((float)d) * kL2eQ, -30.0f * 1.4426950408889634f),
-                          -0x1p-20f * 1.4426950408889634f);
+    const float e = __builtin_amdgcn_fmed3f(fabsf((float)d) * kL2eQ, -30.0f * 1.4426950408889634f,
+                                            -0x1p-20f * 1.4426950408889634f);
     const float u = __builtin_amdgcn_exp2f(e);
-    const float r = (1.0f + u) * __builtin_amdgcn_rcpf(1.0f - u);
-    const float big = __builtin_amdgcn_logf(r) * 0.69314718055994531f;
+    const float big = __builtin_amdgcn_logf((1.0f + u) * __builtin_amdgcn_rcpf(1.0f - u));
     const float u2 = u * u;
-    const float small = u * (2.0f + u2 * (0.66666667f + u2 * 0.4f));
+    const float small = u * (2.8853901f + u2 * (0.96179669f + u2 * 0.57707802f));
     return u < 0.0625f ? small : big;
 }
 
 // phi_out: Q20 check-to-variable magnitude phi(S) x 2^20 of an exclusive sum
-// S >= 0 (before rounding).  Large results need 1 - e^-S without
-// cancellation: a Taylor series below S = 1/8.  Small results need only the
-// absolute accuracy of the logarithm (about 1e-7, below the 2^-20 step).
-__device__ __forceinline__ float phi_out_q(float x) {
-    x = fmaxf(x, 0x1p-20f);
-    const float u = __builtin_amdgcn_exp2f(-x * 1.4426950408889634f);
-    const float ser = x * (1.0f - x * (0.5f - x * (0.16666667f - x * (0.041666668f - x * 0.0083333333f))));
-    const float den = x < 0.125f ? ser : 1.0f - u;
+// given in log2 units, y = S / ln 2 >= 0 (before rounding).  Large results
+// need 1 - e^-S without cancellation: its Taylor series in y below
+// S = 1/8.  Small results need only the absolute accuracy of the logarithm
+// (about 1e-7, below the 2^-20 step).
+__device__ __forceinline__ float phi_out_q(float y) {
+    y = fmaxf(y, 1.3758612e-06f);   // S >= 2^-20
+    const float u = __builtin_amdgcn_exp2f(-y);
+    const float ser = y * (0.69314718f - y * (0.24022651f - y * (0.055504109f - y * (0.0096181291f - y * 0.0013333558f))));
+    const float den = y < 0.18033688f ? ser : 1.0f - u;
     const float r = (1.0f + u) * __builtin_amdgcn_rcpf(den);
     return __builtin_amdgcn_logf(r) * (0.69314718055994531f * 1048576.0f);
 }
