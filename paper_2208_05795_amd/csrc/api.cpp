@@ -174,6 +174,11 @@ int check_search_opts(const ts_code *code, const ts_search_opts *o, int32_t widt
 // patterns (candidate writing off) and keeps the fastest per (code, decoder,
 // iteration count, layout request).  Shapes only change the schedule, never the
 // results.
+// Autotuner score of a probe time: a streamed shape must beat a register one
+// by 10%, since in batches its message traffic meets other launches in L2 and
+// the MALL (probes run alone) while register frames stay on chip.
+static float tune_score(const SearchPlan &p, float ms) { return p.kind == kPlanStreamed ? 1.1f * ms : ms; }
+
 static int tune_shape(ts_exec &ex, const std::vector<SearchPlan> &cands,
                       const SearchLaunch &base, int64_t P, SearchPlan *best) {
     int64_t probe = 0;
@@ -181,21 +186,26 @@ static int tune_shape(ts_exec &ex, const std::vector<SearchPlan> &cands,
     probe = std::min(probe, P);
     float best_ms = 0.0f;
     for (const SearchPlan &p : cands) {
-        SearchLaunch a = base;
-        a.t0 = a.max_iter + 1;   // no candidate is written while timing
-        a.n_patterns = (int)probe;
-        a.pat_base = 0;
-        int rc = launch_fill(ex.stream, a.queue, 0, 2);
-        if (rc) return rc;
-        TSG_HIP(hipEventRecord(ex.ev[0], ex.stream));
-        rc = launch_search(ex, p, a);
-        if (rc) return rc;
-        TSG_HIP(hipEventRecord(ex.ev[1], ex.stream));
-        TSG_HIP(hipStreamSynchronize(ex.stream));
-        float ms = 0.0f;
-        TSG_HIP(hipEventElapsedTime(&ms, ex.ev[0], ex.ev[1]));
-        if (best_ms == 0.0f || ms < best_ms) {
-            best_ms = ms;
+        float ms_min = 0.0f;
+        for (int rep = 0; rep < 2; ++rep) {   // the faster of two timings
+            SearchLaunch a = base;
+            a.t0 = a.max_iter + 1;   // no candidate is written while timing
+            a.n_patterns = (int)probe;
+            a.pat_base = 0;
+            int rc = launch_fill(ex.stream, a.queue, 0, 2);
+            if (rc) return rc;
+            TSG_HIP(hipEventRecord(ex.ev[0], ex.stream));
+            rc = launch_search(ex, p, a);
+            if (rc) return rc;
+            TSG_HIP(hipEventRecord(ex.ev[1], ex.stream));
+            TSG_HIP(hipStreamSynchronize(ex.stream));
+            float ms = 0.0f;
+            TSG_HIP(hipEventElapsedTime(&ms, ex.ev[0], ex.ev[1]));
+            if (rep == 0 || ms < ms_min) ms_min = ms;
+        }
+        const float score = tune_score(p, ms_min);
+        if (best_ms == 0.0f || score < best_ms) {
+            best_ms = score;
             *best = p;
         }
     }
@@ -584,7 +594,7 @@ int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const 
         return TS_OK;
     };
     if (need_tune) {
-        // Autotuner: every shape once on the job's first frames; the fastest is
+        // Autotuner: every shape twice on the job's first frames; the best is
         // kept for (code, iterations, layout request).  Frames only depend on
         // their Philox counters, so the real run below recomputes them exactly.
         int64_t probe = 0;
@@ -592,13 +602,18 @@ int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const 
         probe = std::min(probe, K);
         float best = 0.0f;
         for (const SearchPlan &p : shapes) {
-            rc = launch_fill(s, d_misc.as<int>(), 0, 64);
-            if (rc) return rc;
-            float ms = 0.0f;
-            rc = launch(p, probe, &ms);
-            if (rc) return rc;
-            if (best == 0.0f || ms < best) {
-                best = ms;
+            float ms_min = 0.0f;
+            for (int rep = 0; rep < 2; ++rep) {   // the faster of two timings
+                rc = launch_fill(s, d_misc.as<int>(), 0, 64);
+                if (rc) return rc;
+                float ms = 0.0f;
+                rc = launch(p, probe, &ms);
+                if (rc) return rc;
+                if (rep == 0 || ms < ms_min) ms_min = ms;
+            }
+            const float score = tune_score(p, ms_min);
+            if (best == 0.0f || score < best) {
+                best = score;
                 plan = p;
             }
         }

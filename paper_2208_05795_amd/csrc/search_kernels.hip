@@ -67,15 +67,21 @@ __device__ __forceinline__ int to_q20(float l) {
 // Large results (x -> 0, where 1 - u cancels) need no care: such a term
 // enters the other edges' sums S >= phi_in, where |phi'(S)| <= 2 e^-S ~ x,
 // which cancels the 2^-24 / x relative error of 1 - u.
-__device__ __forceinline__ float phi_in(int d) {
+// u = e^-x of the clamped magnitude of d (Q20), then phi_in from u in its two
+// regimes: below u = 1/16 the series (exp2 only), above it the logarithm.
+__device__ __forceinline__ float phi_in_u(int d) {
     constexpr float kL2eQ = -1.4426950408889634f / 1048576.0f;   // -log2(e) 2^-20
-    const float e = __builtin_amdgcn_fmed3f(fabsf((float)d) * kL2eQ, -30.0f * 1.4426950408889634f,
-                                            -0x1p-20f * 1.4426950408889634f);
-    const float u = __builtin_amdgcn_exp2f(e);
-    const float big = __builtin_amdgcn_logf((1.0f + u) * __builtin_amdgcn_rcpf(1.0f - u));
+    return __builtin_amdgcn_exp2f(__builtin_amdgcn_fmed3f(fabsf((float)d) * kL2eQ,
+                                                          -30.0f * 1.4426950408889634f,
+                                                          -0x1p-20f * 1.4426950408889634f));
+}
+constexpr float kPhiSmallU = 0.0625f;
+__device__ __forceinline__ float phi_in_small(float u) {
     const float u2 = u * u;
-    const float small = u * (2.8853901f + u2 * (0.96179669f + u2 * 0.57707802f));
-    return u < 0.0625f ? small : big;
+    return u * (2.8853901f + u2 * (0.96179669f + u2 * 0.57707802f));
+}
+__device__ __forceinline__ float phi_in_big(float u) {
+    return __builtin_amdgcn_logf((1.0f + u) * __builtin_amdgcn_rcpf(1.0f - u));
 }
 
 // phi_out: Q20 check-to-variable magnitude phi(S) x 2^20 of an exclusive sum
@@ -83,13 +89,20 @@ __device__ __forceinline__ float phi_in(int d) {
 // need 1 - e^-S without cancellation: its Taylor series in y below
 // S = 1/8.  Small results need only the absolute accuracy of the logarithm
 // (about 1e-7, below the 2^-20 step).
+constexpr float kPhiYMin = 1.3758612e-06f;   // S >= 2^-20
+constexpr float kPhiYSeries = 0.18033688f;   // S < 1/8
+__device__ __forceinline__ float phi_out_q_den(float y, float den) {
+    const float u = __builtin_amdgcn_exp2f(-y);
+    return __builtin_amdgcn_logf((1.0f + u) * __builtin_amdgcn_rcpf(den)) * (0.69314718055994531f * 1048576.0f);
+}
+__device__ __forceinline__ float phi_out_q_plain(float y) {   // y >= kPhiYSeries
+    return phi_out_q_den(y, 1.0f - __builtin_amdgcn_exp2f(-y));
+}
 __device__ __forceinline__ float phi_out_q(float y) {
-    y = fmaxf(y, 1.3758612e-06f);   // S >= 2^-20
     const float u = __builtin_amdgcn_exp2f(-y);
     const float ser = y * (0.69314718f - y * (0.24022651f - y * (0.055504109f - y * (0.0096181291f - y * 0.0013333558f))));
-    const float den = y < 0.18033688f ? ser : 1.0f - u;
-    const float r = (1.0f + u) * __builtin_amdgcn_rcpf(den);
-    return __builtin_amdgcn_logf(r) * (0.69314718055994531f * 1048576.0f);
+    const float den = y < kPhiYSeries ? ser : 1.0f - u;
+    return __builtin_amdgcn_logf((1.0f + u) * __builtin_amdgcn_rcpf(den)) * (0.69314718055994531f * 1048576.0f);
 }
 
 // A value every lane of the wave holds (read from the LDS job copy), moved to
@@ -147,33 +160,87 @@ struct SpaRule {
     static constexpr int kDummy = 1 << 30;
     template <int DC>
     __device__ static __forceinline__ void update(const int (&val)[DC], int (&c2v)[DC],
-                                                  const int (&)[DC], int, int) {
+                                                  const int (&nb)[DC], int pad, int off) {
+        update_impl<DC, true>(val, c2v, nb, pad, off);
+    }
+    template <int DC, bool kShortcuts>
+    __device__ static __forceinline__ void update_impl(const int (&val)[DC], int (&c2v)[DC],
+                                                       const int (&)[DC], int, int) {
         float ph[DC];
         int d[DC];
         int sx = 0;   // sign bit = parity of the negative v2c messages
+        // Wavefront-uniform shortcuts (impulse frames, kShortcuts): where every
+        // lane is in one regime, the other regime's arithmetic (whose result
+        // the selection would drop) is skipped.  The values are those of the
+        // general form.  The input one (u recomputed on the rare mixed path, so
+        // as to hold no extra registers) pays off up to a dozen edges per
+        // check; wider checks are rarely in one regime on every lane.
+        if constexpr (kShortcuts && DC <= 12) {
+            bool small = true;
 #pragma unroll
-        for (int j = 0; j < DC; ++j) {
-            d[j] = val[j] - c2v[j];
-            sx ^= d[j];
-            ph[j] = phi_in(d[j]);
+            for (int j = 0; j < DC; ++j) {
+                d[j] = val[j] - c2v[j];
+                sx ^= d[j];
+                const float u = phi_in_u(d[j]);
+                ph[j] = phi_in_small(u);
+                small &= u < kPhiSmallU;
+            }
+            if (!__all(small)) {
+#pragma unroll
+                for (int j = 0; j < DC; ++j) {
+                    const float u = phi_in_u(d[j]);
+                    if (!(u < kPhiSmallU)) ph[j] = phi_in_big(u);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < DC; ++j) {
+                d[j] = val[j] - c2v[j];
+                sx ^= d[j];
+                const float u = phi_in_u(d[j]);
+                ph[j] = u < kPhiSmallU ? phi_in_small(u) : phi_in_big(u);
+            }
         }
-        float pre[DC + 1], suf[DC + 1];
-        pre[0] = 0.0f;
-        suf[DC] = 0.0f;
+        // exclusive sums from prefix and suffix sums (no cancellation)
+        float pre[DC], suf[DC];
+        pre[1] = ph[0];
 #pragma unroll
-        for (int j = 0; j < DC; ++j) pre[j + 1] = pre[j] + ph[j];
+        for (int j = 1; j + 1 < DC; ++j) pre[j + 1] = pre[j] + ph[j];
+        suf[DC - 1] = ph[DC - 1];
 #pragma unroll
-        for (int j = DC - 1; j >= 0; --j) suf[j] = suf[j + 1] + ph[j];
+        for (int j = DC - 2; j >= 1; --j) suf[j] = suf[j + 1] + ph[j];
+        auto excl = [&](int j) { return j == 0 ? suf[1] : (j == DC - 1 ? pre[DC - 1] : pre[j] + suf[j + 1]); };
+        bool plain = kShortcuts;
+        if constexpr (kShortcuts) {
 #pragma unroll
-        for (int j = 0; j < DC; ++j) {
-            // sign of the other edges' product applied to the float before the
-            // (sign-symmetric) rounding to Q20
-            const float f = phi_out_q(pre[j] + suf[j + 1]);
+            for (int j = 0; j < DC; ++j) plain &= excl(j) >= kPhiYSeries;
+        }
+        // sign of the other edges' product applied to the float before the
+        // (sign-symmetric) rounding to Q20
+        auto put = [&](int j, float f) {
             const int sb = (sx ^ d[j]) & (int)0x80000000u;
             c2v[j] = __float2int_rn(__int_as_float(__float_as_int(f) ^ sb));
+        };
+        if (kShortcuts && __all(plain)) {
+#pragma unroll
+            for (int j = 0; j < DC; ++j) put(j, phi_out_q_plain(excl(j)));
+        } else {
+#pragma unroll
+            for (int j = 0; j < DC; ++j) put(j, phi_out_q(fmaxf(excl(j), kPhiYMin)));
         }
     }
 };
+// The sum-product rule of the noisy IS frames: the same values, without the
+// shortcuts (their channel values leave few checks in one regime, and the
+// extra paths cost the IS kernels more than they save).
+struct SpaIsRule : SpaRule {
+    template <int DC>
+    __device__ static __forceinline__ void update(const int (&val)[DC], int (&c2v)[DC],
+                                                  const int (&nb)[DC], int pad, int off) {
+        update_impl<DC, false>(val, c2v, nb, pad, off);
+    }
+};
+
 
 // Quantised normalised layered min-sum (4-bit channel values and
 // check-to-variable messages, 6-bit variable-to-check messages and APP values,
@@ -933,7 +1000,7 @@ struct RegIsDec {
             F.pcnt[i] = 0;
         }
         __syncthreads();
-        return run_decode<SpaRule, DC, CPT>(F, nb, c2v, 0);
+        return run_decode<SpaIsRule, DC, CPT>(F, nb, c2v, 0);
     }
 };
 
@@ -1326,7 +1393,7 @@ struct GIsDec {
             F.pcnt[i] = 0;
         }
         __syncthreads();
-        return run_decode_g<SpaRule, DCMAX, int>(F, 0);
+        return run_decode_g<SpaIsRule, DCMAX, int>(F, 0);
     }
 };
 
