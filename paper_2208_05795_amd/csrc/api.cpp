@@ -276,13 +276,14 @@ static int select_is_shape(ts_ctx *ctx, ts_code *code, int max_iter, int layout,
 // none yet for the job's (decoder, iterations, layout), and which is as large
 // as a plain call that would tune (256 patterns / 1024 frames), first runs the
 // plain call on a probe of its own patterns or frames (at most 8192; results
-// discarded, statistics restored), which tunes and caches the shape.
+// discarded, statistics restored), which tunes and caches the shape.  Never
+// fails: a probe that cannot run leaves the code untuned.
 int tune_for_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
     const ts_stats keep = ex.stats;
     hipStream_t s = ex.stream;
-    int rc = TS_OK;
     for (BatchJob &b : jobs) {
         ts_code *code = b.code;
+        int rc = TS_OK;
         if (b.kind == TS_JOB_SEARCH) {
             if (b.n_patterns < 256) continue;
             {
@@ -291,8 +292,9 @@ int tune_for_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
             }
             const int64_t P = std::min<int64_t>(b.n_patterns, 8192);
             DBuf d_pat(ex, (size_t)P * b.width * 4), d_out(ex, (size_t)5 * P * 4);
-            if (!d_pat.p || !d_out.p) { rc = TS_E_NOMEM; break; }
-            TSG_HIP(hipMemcpyAsync(d_pat.p, b.patterns, (size_t)P * b.width * 4, hipMemcpyHostToDevice, s));
+            if (!d_pat.p || !d_out.p) continue;
+            if (hipMemcpyAsync(d_pat.p, b.patterns, (size_t)P * b.width * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+                continue;
             int32_t *outs[5];
             for (int i = 0; i < 5; ++i) outs[i] = d_out.as<int32_t>() + (size_t)i * P;
             DevTable none{};
@@ -309,11 +311,13 @@ int tune_for_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
             ts_is_result res{};
             rc = run_is(ex, code, b.ts_bits, b.a, &io, &res, nullptr);
         }
-        if (rc) break;
+        // tuning is an optimisation: a probe that fails (the batch reports the
+        // job's own error) leaves the code untuned
+        if (rc) clear_error();
     }
-    TSG_HIP(hipStreamSynchronize(s));
+    (void)hipStreamSynchronize(s);
     ex.stats = keep;
-    return rc;
+    return TS_OK;
 }
 
 int plan_is_shape(ts_exec &ex, ts_code *code, int max_iter, int layout, SearchPlan *plan) {
