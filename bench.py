@@ -554,7 +554,8 @@ def bench_qc2640(tsg):
                         f"union bound over the top {n_ts} TS x 4 SNRs x 1e5 IS frames",
             "ts_found": int(len(recs)), "spectrum_all_sets": cells,
             "search": {"seconds": t_search, "edge_updates": eu_search,
-                       "edge_updates_per_s": eu_search / t_search},
+                       "edge_updates_per_s": eu_search / t_search,
+                       "hbm_equivalent_frac": BYTES_PER_EU["spa"] * eu_search / t_search / (HBM_PEAK_GBS * 1e9)},
             "search_orbit_reduced": {"patterns": int(len(reps)), "seconds": t_reduced,
                                      "edge_updates": rr["stats"]["edge_updates"],
                                      "speedup": t_search / t_reduced, "same_ts": same},
@@ -618,6 +619,7 @@ def cpu_baseline(code, pats, seconds, mix):
     import numpy as np
 
     import oracle
+    import workloads
     oc = oracle.OCode(code)
     rng = np.random.default_rng(0)
     order = rng.permutation(len(pats))
@@ -655,6 +657,22 @@ def cpu_baseline(code, pats, seconds, mix):
         n_frames += frames
         frames *= 2
     legs["is"] = {"frames": n_frames, "seconds": t_used, "edge_updates_per_s": eu / t_used}
+    # beside the mix: IS frames on the QC-2640 code (its shortest cycle through
+    # variable 0, 3 dB, shift 1.5), a counter-addressed subset of the same
+    # Philox frames the device draws
+    qc = workloads.qc2640_code()
+    oq = oracle.OCode(qc)
+    rq, cq = oq.csr()
+    qbits = shortest_cycle_vns((rq, cq) + var_checks(rq, cq, qc.n) + (qc.n,), 0)
+    frames, t_q, eu_q, nq = 256, 0.0, 0, 0
+    while t_q < 0.1 * seconds:
+        t0 = time.perf_counter()
+        r = oracle.is_estimate(oq, qbits, 3.0, 1.5, frames, seed=3, frame_base=nq, threads=threads)
+        t_q += time.perf_counter() - t0
+        eu_q += r["edge_updates"]
+        nq += frames
+        frames *= 2
+    qc_is = {"frames": nq, "seconds": t_q, "edge_updates_per_s": eu_q / t_q}
     single = search_leg(dict(decoder=oracle.DEC_SPA, max_iter=50, k_max=32 * 1024, k_den=1024),
                         2, 0.2 * seconds, 1)
     t_step = sum(mix[k] / legs[k]["edge_updates_per_s"] for k in legs)
@@ -665,7 +683,7 @@ def cpu_baseline(code, pats, seconds, mix):
                       f"same list (fixed shuffle) and {legs['is']['frames']} IS frames, {used:.1f} s; "
                       "value = the GPU step's edge-updates over the oracle's time for each leg's share",
             "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
-            "legs": legs, "single_thread_spa": single}
+            "legs": legs, "single_thread_spa": single, "qc2640_is": qc_is}
 
 
 if __name__ == "__main__":
