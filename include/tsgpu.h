@@ -154,7 +154,15 @@ int ts_make_patterns(ts_ctx *ctx, const ts_code *code, int32_t kind, int32_t *ou
  * integers, so results do not depend on the layout. */
 #define TS_LAYOUT_AUTO 0       /* autotuned among the layouts and shapes that fit */
 #define TS_LAYOUT_REGISTER 1
-#define TS_LAYOUT_STREAMED 2
+#define TS_LAYOUT_STREAMED 2   /* either streamed variant (autotuned) */
+/* The streamed layout's two variants, forced: GATHER rebuilds each APP sum in
+ * a variable pass that reads the variable's messages back; ACCUM adds the
+ * messages into a second LDS array with integer atomics during the check pass
+ * (8 bytes of LDS per variable instead of 4; n up to about 19k).  Statistics
+ * report both as TS_LAYOUT_STREAMED, with checks_per_thread = 0 (GATHER) or 1
+ * (ACCUM). */
+#define TS_LAYOUT_STREAMED_GATHER 3
+#define TS_LAYOUT_STREAMED_ACCUM 4
 
 typedef struct {
     int32_t decoder;           /* TS_DEC_* */

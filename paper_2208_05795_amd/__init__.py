@@ -18,13 +18,15 @@ from . import _capi as A
 
 __all__ = ["DEC_LNMS", "Context", "Code", "TsRecord", "TsgError", "DEC_OMS", "DEC_SPA",
            "PAT_SINGLES", "PAT_PAIRS", "PAT_TRIPLES", "EXTRACT_PATH", "EXTRACT_CRITICAL",
-           "LAYOUT_AUTO", "LAYOUT_REGISTER", "LAYOUT_STREAMED", "PAT_QC_ORBITS"]
+           "LAYOUT_AUTO", "LAYOUT_REGISTER", "LAYOUT_STREAMED", "LAYOUT_STREAMED_GATHER",
+           "LAYOUT_STREAMED_ACCUM", "PAT_QC_ORBITS"]
 
 DEC_OMS, DEC_SPA, DEC_LNMS = A.TS_DEC_OMS_I8, A.TS_DEC_SPA_F32, A.TS_DEC_LNMS_Q4
 PAT_SINGLES, PAT_PAIRS, PAT_TRIPLES = A.TS_PAT_SINGLES, A.TS_PAT_PAIRS, A.TS_PAT_TRIPLES
 PAT_QC_ORBITS = A.TS_PAT_QC_ORBITS
 EXTRACT_PATH, EXTRACT_CRITICAL = A.TS_EXTRACT_PATH, A.TS_EXTRACT_CRITICAL
 LAYOUT_AUTO, LAYOUT_REGISTER, LAYOUT_STREAMED = A.TS_LAYOUT_AUTO, A.TS_LAYOUT_REGISTER, A.TS_LAYOUT_STREAMED
+LAYOUT_STREAMED_GATHER, LAYOUT_STREAMED_ACCUM = A.TS_LAYOUT_STREAMED_GATHER, A.TS_LAYOUT_STREAMED_ACCUM
 
 _lib = None
 
@@ -320,7 +322,8 @@ class Code:
                        layout: int = 0) -> dict:
         """Patterns: numpy (host) or a torch int32 CUDA tensor [P, width] (device);
         outputs come back in the same kind of memory.  layout: LAYOUT_AUTO,
-        LAYOUT_REGISTER or LAYOUT_STREAMED."""
+        LAYOUT_REGISTER, LAYOUT_STREAMED or one streamed variant
+        (LAYOUT_STREAMED_GATHER, LAYOUT_STREAMED_ACCUM)."""
         rate = (1.0 - self.m / self.n) if rate is None else rate
         o = A.SearchOpts(decoder, max_iter, oms_offset, ebn0_db, rate, llr_scale, k_max, k_den,
                          a_max, extract_mode, collect_from_iter, A.TS_MEM_HOST, layout)

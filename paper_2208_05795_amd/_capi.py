@@ -13,6 +13,7 @@ TS_DEC_OMS_I8, TS_DEC_SPA_F32, TS_DEC_LNMS_Q4 = 0, 1, 2
 TS_EXTRACT_PATH, TS_EXTRACT_CRITICAL = 0, 1
 TS_MEM_HOST, TS_MEM_DEVICE = 0, 1
 TS_LAYOUT_AUTO, TS_LAYOUT_REGISTER, TS_LAYOUT_STREAMED = 0, 1, 2
+TS_LAYOUT_STREAMED_GATHER, TS_LAYOUT_STREAMED_ACCUM = 3, 4
 TS_PAT_QC_ORBITS = 0x100
 TS_JOB_SEARCH, TS_JOB_IS = 1, 2
 TS_JOB_QUEUED, TS_JOB_RUNNING, TS_JOB_DONE, TS_JOB_CANCELLED = 0, 1, 2, 3

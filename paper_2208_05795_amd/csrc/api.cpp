@@ -164,7 +164,7 @@ int check_search_opts(const ts_code *code, const ts_search_opts *o, int32_t widt
     if (!(o->rate > 0.0 && o->rate <= 1.0) || !(o->llr_scale > 0.0)) { set_error("rate / llr_scale out of range"); return TS_E_INVAL; }
     if (o->extract_mode != TS_EXTRACT_PATH && o->extract_mode != TS_EXTRACT_CRITICAL) { set_error("bad extract_mode"); return TS_E_INVAL; }
     if (o->mem != TS_MEM_HOST && o->mem != TS_MEM_DEVICE) { set_error("bad mem kind"); return TS_E_INVAL; }
-    if (o->layout < TS_LAYOUT_AUTO || o->layout > TS_LAYOUT_STREAMED) { set_error("bad layout"); return TS_E_INVAL; }
+    if (o->layout < TS_LAYOUT_AUTO || o->layout > TS_LAYOUT_STREAMED_ACCUM) { set_error("bad layout"); return TS_E_INVAL; }
     if (width < 1 || width > kMaxWidth) { set_error("width must be 1..%d", kMaxWidth); return TS_E_INVAL; }
     if (code->dv_max > kDvMax) { set_error("variable degree %d above the sieve's limit %d", code->dv_max, kDvMax); return TS_E_INVAL; }
     return TS_OK;
@@ -229,9 +229,8 @@ static int select_shape(ts_ctx *ctx, ts_code *code, const ts_search_opts *o, int
     int rc = plan_candidates(ctx, code, o->decoder, o->max_iter, shapes);
     if (rc) return rc;
     if (o->layout != TS_LAYOUT_AUTO) {
-        const int want = o->layout == TS_LAYOUT_REGISTER ? kPlanRegister : kPlanStreamed;
         shapes->erase(std::remove_if(shapes->begin(), shapes->end(),
-                                     [&](const SearchPlan &p) { return p.kind != want; }),
+                                     [&](const SearchPlan &p) { return !layout_accepts(o->layout, p); }),
                       shapes->end());
         if (shapes->empty()) {
             set_error("the requested decoder layout does not fit this code");
@@ -519,7 +518,7 @@ int check_is_opts(const ts_code *code, const int32_t *ts_bits, int32_t a, const 
     if (o->max_iter < 1 || o->max_iter > kMaxIter) { set_error("max_iter must be 1..%d", kMaxIter); return TS_E_INVAL; }
     if (!(o->rate > 0.0 && o->rate <= 1.0)) { set_error("rate out of range"); return TS_E_INVAL; }
     if (!std::isfinite(o->ebn0_db) || !std::isfinite(o->shift)) { set_error("Eb/N0 and shift must be finite"); return TS_E_INVAL; }
-    if (o->layout < TS_LAYOUT_AUTO || o->layout > TS_LAYOUT_STREAMED) { set_error("bad layout"); return TS_E_INVAL; }
+    if (o->layout < TS_LAYOUT_AUTO || o->layout > TS_LAYOUT_STREAMED_ACCUM) { set_error("bad layout"); return TS_E_INVAL; }
     std::vector<int32_t> t(ts_bits, ts_bits + a);
     std::sort(t.begin(), t.end());
     for (int i = 0; i < a; ++i)

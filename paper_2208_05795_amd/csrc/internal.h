@@ -92,17 +92,20 @@ struct DevCode {
 // LDS layout of a streamed frame (host and device).
 struct LdsG {
     int np, W;
-    size_t app, imask, wsyn, pcnt, cls, qtab, extra, total;
+    size_t app, acc, imask, wsyn, pcnt, cls, qtab, extra, total;
 };
 
-// qbytes: size of the QC index tables copied to LDS (0 = read g_cn / g_vslot)
-__host__ __device__ inline LdsG lds_layout_g(int n, int T, int qbytes) {
+// qbytes: size of the QC index tables copied to LDS (0 = read g_cn / g_vslot);
+// acc: the accumulating variant's second array of np sums
+__host__ __device__ inline LdsG lds_layout_g(int n, int T, int qbytes, bool acc = false) {
     LdsG L;
     L.np = (n + 1 + 63) & ~63;
     L.W = L.np >> 6;
     size_t o = 0;
     L.app = o;
     o += (size_t)L.np * 4;
+    L.acc = o;
+    if (acc) o += (size_t)L.np * 4;
     o = (o + 15) & ~(size_t)15;
     L.imask = o;
     o += (size_t)L.W * 8;
@@ -258,13 +261,26 @@ struct SearchPlan {
     int kind;       // kPlanRegister: messages in registers; kPlanStreamed: in global memory
     int decoder;    // TS_DEC_* of the kernel (search plans)
     int block;      // threads per workgroup
-    int cpt;        // checks per thread (register kind)
+    int cpt;        // checks per thread (register kind); streamed: 0 gathering, 1 accumulating
     int dc;         // padded check degree of the kernel (streamed: largest class)
     size_t lds;     // dynamic LDS bytes
     int grid;       // persistent workgroups
     size_t slot_bytes;   // streamed: global scratch per workgroup
     size_t hist_off;     // streamed: offset of the iteration history in a slot
 };
+
+// Whether a plan is allowed under a TS_LAYOUT_* request (streamed plans carry
+// their variant in cpt: 0 gathering, 1 accumulating).
+inline bool layout_accepts(int layout, const SearchPlan &p) {
+    switch (layout) {
+        case TS_LAYOUT_REGISTER: return p.kind == kPlanRegister;
+        case TS_LAYOUT_STREAMED: return p.kind == kPlanStreamed;
+        case TS_LAYOUT_STREAMED_GATHER: return p.kind == kPlanStreamed && p.cpt == 0;
+        case TS_LAYOUT_STREAMED_ACCUM: return p.kind == kPlanStreamed && p.cpt == 1;
+        default: return true;
+    }
+}
+
 
 struct SearchLaunch {
     const DevCode *code;

@@ -1125,6 +1125,7 @@ struct GFrame {
     const int *cdc, *cc0, *cstr, *coff;   // LDS copy of the class table
     const int *g_cn, *g_vslot;         // the code's slot tables
     int ncls, n, np, W, T, m, dv_pad, n_tab;
+    int *acc;                          // LDS [np] APP - lambda sums (accumulating variant) or nullptr
     // QC codes: indices computed from the LDS copy of the per-circulant tables
     const int *qtab, *rowpos;
     int qc, qdc, qdv, qvar, z;
@@ -1138,7 +1139,7 @@ __device__ __forceinline__ int g_lambda(const GFrame &F, int v) {
 
 // Check pass of one check (sorted position p, class q); returns the parity of
 // the hard decisions of APP_{t-1} on its variables.
-template <class Rule, int DC, class M>
+template <class Rule, int DC, class M, bool kAcc>
 __device__ __forceinline__ int check_g(const GFrame &F, int q, int p, int t, int offset) {
     const int stride = F.cstr[q];
     const size_t base = (size_t)F.coff[q] + (size_t)(p - F.cc0[q]);
@@ -1164,13 +1165,19 @@ __device__ __forceinline__ int check_g(const GFrame &F, int q, int p, int t, int
         Rule::template update<DC>(val, c2v, nb, F.n, offset);
 #pragma unroll
         for (int j = 0; j < DC; ++j) msg[base + (size_t)j * stride] = (M)c2v[j];
+        if constexpr (kAcc) {
+            // APP_t - lambda accumulated in LDS (exact integer sums, any order)
+#pragma unroll
+            for (int j = 0; j < DC; ++j)
+                if (nb[j] != F.n) atomicAdd(&F.acc[nb[j]], c2v[j]);
+        }
     }
     return par;
 }
 
 // One decode of a streamed frame.  On entry APP (LDS) holds the channel values
 // (slot n: the padding value), wsyn/pcnt are zero, all threads passed a barrier.
-template <class Rule, int DCMAX, class M>
+template <class Rule, int DCMAX, class M, bool kAcc>
 __device__ DecRes run_decode_g(const GFrame &F, int offset) {
     const int n = F.n, W = F.W, T = F.T, mm = F.m;
     const int B = blockDim.x, NW = B >> 6;
@@ -1186,7 +1193,7 @@ __device__ DecRes run_decode_g(const GFrame &F, int offset) {
 #define TSG_GCASE(D)                                                             \
     case D:                                                                      \
         if constexpr (D <= DCMAX && !(DCMAX == 32 && D == 24))                   \
-            par = check_g<Rule, D, M>(F, q, p, t, offset);                       \
+            par = check_g<Rule, D, M, kAcc>(F, q, p, t, offset);                 \
         break;
                 TSG_GCASE(3) TSG_GCASE(4) TSG_GCASE(6) TSG_GCASE(8)
                 TSG_GCASE(12) TSG_GCASE(16) TSG_GCASE(24) TSG_GCASE(32)
@@ -1216,7 +1223,12 @@ __device__ DecRes run_decode_g(const GFrame &F, int offset) {
         for (int i = wid; i < W; i += NW) {
             const int v = i * 64 + lane;
             int x = 0;
-            if (v < n) {
+            if (v < n && kAcc) {
+                const int sum = g_lambda(F, v) + F.acc[v];
+                F.acc[v] = 0;
+                F.app[v] = sum;
+                x = sum < 0;
+            } else if (v < n) {
                 int sum = g_lambda(F, v);
                 if (F.qc) {
                     // block column by a float estimate of v / z, corrected to exact
@@ -1255,11 +1267,12 @@ __device__ DecRes run_decode_g(const GFrame &F, int offset) {
 // Binds a streamed frame to a job: LDS regions, the workgroup's scratch slot,
 // the code's tables and an LDS copy of its class table.
 __device__ __forceinline__ void g_bind(const DevCode &cd, int T, unsigned char *frame,
-                                       unsigned char *slot, GFrame &F, LdsG &L) {
+                                       unsigned char *slot, GFrame &F, LdsG &L, bool acc) {
     const int n = uni(cd.n);
     T = uni(T);
     const int qc = uni(cd.q_ok);
-    L = lds_layout_g(n, T, qc ? uni(cd.q_bytes) : 0);
+    L = lds_layout_g(n, T, qc ? uni(cd.q_bytes) : 0, acc);
+    F.acc = acc ? (int *)(frame + L.acc) : nullptr;
     int *cls = (int *)(frame + L.cls);
     const int tid = threadIdx.x;
     if (tid < kGMaxCls) {
@@ -1306,7 +1319,7 @@ __device__ __forceinline__ void g_bind(const DevCode &cd, int T, unsigned char *
     }
 }
 
-template <class Rule, int DCMAX, class M>
+template <class Rule, int DCMAX, class M, bool kAcc>
 struct GSearchDec {
     const SearchLaunch *a;
     GFrame F;
@@ -1317,7 +1330,7 @@ struct GSearchDec {
         a = &J.a;
         unsigned char *slot = J.a.gscr + (size_t)blockIdx.x * J.a.slot_bytes;
         LdsG L;
-        g_bind(J.cd, J.a.max_iter, frame, slot, F, L);
+        g_bind(J.cd, J.a.max_iter, frame, slot, F, L, kAcc);
         imask = (unsigned long long *)(frame + L.imask);
         W = L.W;
         F.imask = imask;
@@ -1332,30 +1345,38 @@ struct GSearchDec {
         F.lam_imp = impulse_lambda<Rule>(*a, K);
         __syncthreads();
         for (int v = tid; v < F.np; v += B) F.app[v] = v < n ? g_lambda(F, v) : Rule::kDummy;
+        if constexpr (kAcc)
+            for (int v = tid; v < F.np; v += B) F.acc[v] = 0;
         for (int i = tid; i < F.T + 2; i += B) {
             F.wsyn[i] = 0;
             F.pcnt[i] = 0;
         }
         __syncthreads();
-        return run_decode_g<Rule, DCMAX, M>(F, a->offset);
+        return run_decode_g<Rule, DCMAX, M, kAcc>(F, a->offset);
     }
     __device__ __forceinline__ const unsigned long long *hist() const { return F.hist; }
 };
 
 // Workgroup bounds of the streamed kernels (the register budget follows).
-template <int DCMAX> struct MaxBlockG { static constexpr int value = DCMAX <= 16 ? 1024 : 512; };
-template <int DCMAX> struct MaxBlockGIs { static constexpr int value = MaxBlockG<DCMAX>::value; };
+// (the accumulating variant keeps the neighbour indices live across the
+// update, so it takes at most 512 threads and twice the registers)
+template <int DCMAX, bool kAcc = false> struct MaxBlockG {
+    static constexpr int value = (DCMAX <= 16 && !kAcc) ? 1024 : 512;
+};
+template <int DCMAX, bool kAcc = false> struct MaxBlockGIs { static constexpr int value = MaxBlockG<DCMAX, kAcc>::value; };
 
-template <class Rule, int DCMAX>
-__global__ __launch_bounds__((MaxBlockG<DCMAX>::value)) void k_search_g(const SearchJob *jobs, int n_jobs,
+// kAcc: the accumulating variant (APP sums by LDS atomics in the check pass;
+// the variable pass reads no messages), for frames whose two LDS arrays fit.
+template <class Rule, int DCMAX, bool kAcc>
+__global__ __launch_bounds__((MaxBlockG<DCMAX, kAcc>::value)) void k_search_g(const SearchJob *jobs, int n_jobs,
                                                                        int *queue, long long n_items) {
     typedef typename std::conditional<Rule::kDummy == OmsRule::kDummy, signed char, int>::type M;
     extern __shared__ __align__(16) unsigned char smem[];
-    GSearchDec<Rule, DCMAX, M> dec;
+    GSearchDec<Rule, DCMAX, M, kAcc> dec;
     search_jobs(jobs, n_jobs, queue, n_items, dec, smem);
 }
 
-template <int DCMAX>
+template <int DCMAX, bool kAcc>
 struct GIsDec {
     IsChan a;
     GFrame F;
@@ -1367,7 +1388,7 @@ struct GIsDec {
         a = is_chan(J.a);
         unsigned char *slot = J.a.gscr + (size_t)blockIdx.x * J.a.slot_bytes;
         LdsG L;
-        g_bind(J.cd, J.a.max_iter, frame, slot, F, L);
+        g_bind(J.cd, J.a.max_iter, frame, slot, F, L, kAcc);
         lam = uni((int *)(slot + J.a.lam_off));
         F.imask = nullptr;
         F.lam_g = lam;
@@ -1388,20 +1409,22 @@ struct GIsDec {
             app[v] = l;
         });
         for (int v = n + tid; v < F.np; v += B) F.app[v] = SpaRule::kDummy;
+        if constexpr (kAcc)
+            for (int v = tid; v < F.np; v += B) F.acc[v] = 0;
         for (int i = tid; i < F.T + 2; i += B) {
             F.wsyn[i] = 0;
             F.pcnt[i] = 0;
         }
         __syncthreads();
-        return run_decode_g<SpaIsRule, DCMAX, int>(F, 0);
+        return run_decode_g<SpaIsRule, DCMAX, int, kAcc>(F, 0);
     }
 };
 
-template <int DCMAX>
-__global__ __launch_bounds__((MaxBlockGIs<DCMAX>::value)) void k_is_g(const IsJob *jobs, int n_jobs,
+template <int DCMAX, bool kAcc>
+__global__ __launch_bounds__((MaxBlockGIs<DCMAX, kAcc>::value)) void k_is_g(const IsJob *jobs, int n_jobs,
                                                                      int *queue, long long n_items) {
     extern __shared__ __align__(16) unsigned char smem[];
-    GIsDec<DCMAX> dec;
+    GIsDec<DCMAX, kAcc> dec;
     is_jobs(jobs, n_jobs, queue, n_items, dec, smem);
 }
 
@@ -1429,12 +1452,15 @@ const KEntry kTable[] = {
 
 // streamed-frame kernels, by largest check-degree class
 struct GEntry {
-    int dcmax, max_block, is_max_block;
-    SearchKernel oms, spa;
-    IsKernel is;
+    int dcmax, max_block[2], is_max_block[2];   // [0] gathering, [1] accumulating variant
+    SearchKernel oms[2], spa[2];
+    IsKernel is[2];
 };
-#define TSG_G(D) \
-    {D, MaxBlockG<D>::value, MaxBlockGIs<D>::value, k_search_g<OmsRule, D>, k_search_g<SpaRule, D>, k_is_g<D>}
+#define TSG_G(D)                                                                                 \
+    {D, {MaxBlockG<D, false>::value, MaxBlockG<D, true>::value},                                 \
+     {MaxBlockGIs<D, false>::value, MaxBlockGIs<D, true>::value},                                \
+     {k_search_g<OmsRule, D, false>, k_search_g<OmsRule, D, true>},                              \
+     {k_search_g<SpaRule, D, false>, k_search_g<SpaRule, D, true>}, {k_is_g<D, false>, k_is_g<D, true>}}
 const GEntry kGTable[] = {TSG_G(16), TSG_G(24), TSG_G(32)};
 #undef TSG_G
 
@@ -1460,18 +1486,19 @@ int padded_degree(const ts_code *c) {
 
 int streamed_dcmax(const ts_code *c) { return c->dc_max <= 16 ? 16 : (c->dc_max <= 24 ? 24 : 32); }
 
-// Streamed plans: every workgroup size up to the kernel's bound that fits.
-int add_streamed_plans(ts_ctx *ctx, const ts_code *c, bool search, int decoder, int max_iter,
-                       std::vector<SearchPlan> *out) {
+// Streamed plans: both variants (cpt 0 gathering, 1 accumulating) and every
+// workgroup size up to the kernel's bound that fits.
+int add_streamed_variant(ts_ctx *ctx, const ts_code *c, bool search, int decoder, int max_iter,
+                         int var, std::vector<SearchPlan> *out) {
     const GEntry *g = find_g(streamed_dcmax(c));
-    const size_t lds = kHdrLds + lds_layout_g(c->n, max_iter, c->dev.q_ok ? c->dev.q_bytes : 0).total;
+    const size_t lds = kHdrLds + lds_layout_g(c->n, max_iter, c->dev.q_ok ? c->dev.q_bytes : 0, var == 1).total;
     if (!g || lds > ctx->lds_per_block) return TS_OK;
     size_t aux = 0;
     const size_t slot = streamed_slot_bytes(c, decoder, max_iter, search, &aux);
-    const void *kern = search ? (const void *)(decoder == TS_DEC_OMS_I8 ? g->oms : g->spa)
-                              : (const void *)g->is;
+    const void *kern = search ? (const void *)(decoder == TS_DEC_OMS_I8 ? g->oms[var] : g->spa[var])
+                              : (const void *)g->is[var];
     for (int block : {256, 512, 1024}) {
-        if (block > (search ? g->max_block : g->is_max_block)) continue;
+        if (block > (search ? g->max_block[var] : g->is_max_block[var])) continue;
         int per_cu = 0;
         TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds));
         if (per_cu < 1) continue;
@@ -1479,13 +1506,22 @@ int add_streamed_plans(ts_ctx *ctx, const ts_code *c, bool search, int decoder, 
         p.kind = kPlanStreamed;
         p.decoder = decoder;
         p.block = block;
-        p.cpt = 0;
+        p.cpt = var;
         p.dc = g->dcmax;
         p.lds = lds;
         p.grid = per_cu * ctx->num_cu;
         p.slot_bytes = slot;
         p.hist_off = aux;
         out->push_back(p);
+    }
+    return TS_OK;
+}
+
+int add_streamed_plans(ts_ctx *ctx, const ts_code *c, bool search, int decoder, int max_iter,
+                       std::vector<SearchPlan> *out) {
+    for (int var = 0; var < 2; ++var) {
+        const int rc = add_streamed_variant(ctx, c, search, decoder, max_iter, var, out);
+        if (rc) return rc;
     }
     return TS_OK;
 }
@@ -1559,9 +1595,9 @@ static SearchKernel search_kernel(const SearchPlan &plan, int decoder) {
         if (!ke) return nullptr;
         return decoder == TS_DEC_OMS_I8 ? ke->oms : (decoder == TS_DEC_SPA_F32 ? ke->spa : ke->lnms);
     }
-    if (decoder == TS_DEC_LNMS_Q4) return nullptr;
+    if (decoder == TS_DEC_LNMS_Q4 || plan.cpt < 0 || plan.cpt > 1) return nullptr;
     const GEntry *g = find_g(plan.dc);
-    return g ? (decoder == TS_DEC_OMS_I8 ? g->oms : g->spa) : nullptr;
+    return g ? (decoder == TS_DEC_OMS_I8 ? g->oms[plan.cpt] : g->spa[plan.cpt]) : nullptr;
 }
 
 static IsKernel is_kernel(const SearchPlan &plan) {
@@ -1569,8 +1605,9 @@ static IsKernel is_kernel(const SearchPlan &plan) {
         const KEntry *k = find_kernel(plan.dc, plan.cpt);
         return k ? k->is : nullptr;
     }
+    if (plan.cpt < 0 || plan.cpt > 1) return nullptr;
     const GEntry *g = find_g(plan.dc);
-    return g ? g->is : nullptr;
+    return g ? g->is[plan.cpt] : nullptr;
 }
 
 int occupancy_grid(ts_ctx *ctx, const SearchPlan &plan, int decoder, bool search, int *grid) {
@@ -1672,7 +1709,7 @@ int plan_is_candidates(ts_ctx *ctx, const ts_code *c, int max_iter, int layout,
     const int dc = padded_degree(c);
     if (!dc) return TS_E_INVAL;
     const size_t lds = kHdrLds + lds_layout(c->n, max_iter, false).total;
-    if (lds <= ctx->lds_per_block && layout != TS_LAYOUT_STREAMED) {
+    if (lds <= ctx->lds_per_block && (layout == TS_LAYOUT_AUTO || layout == TS_LAYOUT_REGISTER)) {
         for (int cp : {1, 2, 4, 8}) {
             const KEntry *k = find_kernel(dc, cp);
             if (!k) continue;
@@ -1696,6 +1733,9 @@ int plan_is_candidates(ts_ctx *ctx, const ts_code *c, int max_iter, int layout,
     if (layout != TS_LAYOUT_REGISTER) {
         const int rc = add_streamed_plans(ctx, c, false, TS_DEC_SPA_F32, max_iter, out);
         if (rc) return rc;
+        out->erase(std::remove_if(out->begin(), out->end(),
+                                  [&](const SearchPlan &p) { return !layout_accepts(layout, p); }),
+                   out->end());
     }
     if (out->empty()) {
         set_error(layout == TS_LAYOUT_AUTO ? "code (n = %d) needs more LDS per workgroup than the device has"

@@ -42,13 +42,19 @@ def _sample(allp, k, seed):
     return np.ascontiguousarray(allp[sel])
 
 
-def _both_layouts(g, pats, **kw):
+def _all_layouts(g, pats, **kw):
+    """Register layout, then the streamed layout's gathering and accumulating
+    variants (forced)."""
     import paper_2208_05795_amd as tsg
     out = []
-    for lay in (tsg.LAYOUT_REGISTER, tsg.LAYOUT_STREAMED):
+    for lay, want, var in ((tsg.LAYOUT_REGISTER, tsg.LAYOUT_REGISTER, None),
+                           (tsg.LAYOUT_STREAMED_GATHER, tsg.LAYOUT_STREAMED, 0),
+                           (tsg.LAYOUT_STREAMED_ACCUM, tsg.LAYOUT_STREAMED, 1)):
         g.reset_ts()
         r = g.impulse_search(pats, layout=lay, **kw)
-        assert r["stats"]["layout"] == lay
+        assert r["stats"]["layout"] == want
+        if var is not None:
+            assert r["stats"]["checks_per_thread"] == var
         out.append(({k: np.asarray(r[k]) for k in KEYS}, _ts(g.collect()), r["stats"]))
     return out
 
@@ -69,12 +75,13 @@ def test_layouts_identical_oms(ctx, oracle_mod, name):
     pats = allp if name == "tiny" else _sample(allp, 3000, 21)
     _say(f"{name} OMS register vs streamed, {len(pats)} patterns")
     g = ctx.load_code(code)
-    (ra, ta, sa), (rb, tb, sb) = _both_layouts(g, pats, a_max=12)
-    _same(ra, rb, name)
-    assert ta == tb
-    assert sa["edge_updates"] == sb["edge_updates"] and sa["decodes"] == sb["decodes"]
-    _say(f"  identical: {len(ta)} TS, {sa['edge_updates']:.3e} edge-updates; "
-         f"decode ms register {sa['decode_ms']:.2f} streamed {sb['decode_ms']:.2f}")
+    (ra, ta, sa), (rb, tb, sb), (rc, tc, sc) = _all_layouts(g, pats, a_max=12)
+    for r, t, st, lab in ((rb, tb, sb, "gather"), (rc, tc, sc, "accum")):
+        _same(ra, r, f"{name} {lab}")
+        assert ta == t
+        assert sa["edge_updates"] == st["edge_updates"] and sa["decodes"] == st["decodes"]
+    _say(f"  identical: {len(ta)} TS, {sa['edge_updates']:.3e} edge-updates; decode ms register "
+         f"{sa['decode_ms']:.2f} streamed gather {sb['decode_ms']:.2f} accum {sc['decode_ms']:.2f}")
     g.free()
 
 
@@ -86,11 +93,12 @@ def test_layouts_identical_spa(ctx, oracle_mod, name):
     pats = _sample(oracle_mod.pattern_list(oc, [1, 2, 3]), 400, 22)
     _say(f"{name} SPA register vs streamed, {len(pats)} patterns")
     g = ctx.load_code(code)
-    (ra, ta, sa), (rb, tb, sb) = _both_layouts(g, pats, decoder=tsg.DEC_SPA, a_max=12, **SPA)
-    _same(ra, rb, name)
-    assert ta == tb
+    (ra, ta, sa), (rb, tb, sb), (rc, tc, sc) = _all_layouts(g, pats, decoder=tsg.DEC_SPA, a_max=12, **SPA)
+    for r, t, lab in ((rb, tb, "gather"), (rc, tc, "accum")):
+        _same(ra, r, f"{name} {lab}")
+        assert ta == t
     _say(f"  identical: {len(ta)} TS; decode ms register {sa['decode_ms']:.2f} "
-         f"streamed {sb['decode_ms']:.2f}")
+         f"streamed gather {sb['decode_ms']:.2f} accum {sc['decode_ms']:.2f}")
     g.free()
 
 
@@ -101,12 +109,13 @@ def test_layouts_identical_is(ctx, oracle_mod, name):
     g = ctx.load_code(code)
     bits = [int(x) for x in g.csr()[1][:4]]   # the variables of check 0 (a 4-subset)
     res = [g.is_estimate(bits, 1.0, 2.0, 3000, seed=5, stream=2, want_fail=True, layout=lay)
-           for lay in (tsg.LAYOUT_REGISTER, tsg.LAYOUT_STREAMED)]
+           for lay in (tsg.LAYOUT_REGISTER, tsg.LAYOUT_STREAMED_GATHER, tsg.LAYOUT_STREAMED_ACCUM)]
     assert res[0]["stats"]["layout"] == tsg.LAYOUT_REGISTER
-    assert res[1]["stats"]["layout"] == tsg.LAYOUT_STREAMED
-    assert np.array_equal(res[0]["fail"], res[1]["fail"])
-    for f in ("p_hat", "var", "sum_w", "sum_w2", "n_fail"):
-        assert res[0][f] == res[1][f], f
+    for var, r in ((0, res[1]), (1, res[2])):
+        assert r["stats"]["layout"] == tsg.LAYOUT_STREAMED and r["stats"]["checks_per_thread"] == var
+        assert np.array_equal(res[0]["fail"], r["fail"])
+        for f in ("p_hat", "var", "sum_w", "sum_w2", "n_fail"):
+            assert res[0][f] == r[f], f
     _say(f"{name} IS register vs streamed identical: p {res[0]['p_hat']:.4e}, "
          f"{int(res[0]['n_fail'])} failures")
     assert res[0]["n_fail"] > 0
@@ -151,18 +160,24 @@ def test_serving_code_oms_vs_oracle(ctx, oracle_mod, pool, which):
     g = ctx.load_code(code)
     # 20 iterations (impulses on these codes are corrected), then 2 iterations
     # from which most impulses fail, so bisection and extraction run as well
+    # the smallest code also through both streamed variants (the largest only
+    # fits the gathering one)
+    layouts = [tsg.LAYOUT_AUTO] + ([tsg.LAYOUT_STREAMED_GATHER, tsg.LAYOUT_STREAMED_ACCUM]
+                                   if which == "smallest" else [])
     for kw in (dict(max_iter=20), dict(max_iter=2, collect_from_iter=1)):
         _say(f"{code.name} (n={code.n}, m={code.m}) OMS vs oracle, {len(pats)} patterns, {kw}")
         ref = oracle_mod.search(oc, pats, a_max=12, **kw)
-        g.reset_ts()
-        got = g.impulse_search(pats, a_max=12, **kw)
-        if code.n > 20000:
-            assert got["stats"]["layout"] == tsg.LAYOUT_STREAMED
-        for k in KEYS:
-            assert np.array_equal(np.asarray(got[k]), ref[k]), k
-        assert _ts(g.collect()) == _ts(ref["ts"])
-        assert got["stats"]["edge_updates"] == ref["edge_updates"]
-        _say(f"  bit-exact; {len(ref['ts'])} TS, failing patterns {(ref['k_crit'] >= 0).sum()}")
+        for lay in layouts:
+            g.reset_ts()
+            got = g.impulse_search(pats, a_max=12, layout=lay, **kw)
+            if code.n > 20000:
+                assert got["stats"]["layout"] == tsg.LAYOUT_STREAMED
+            for k in KEYS:
+                assert np.array_equal(np.asarray(got[k]), ref[k]), (lay, k)
+            assert _ts(g.collect()) == _ts(ref["ts"])
+            assert got["stats"]["edge_updates"] == ref["edge_updates"]
+        _say(f"  bit-exact ({len(layouts)} layouts); {len(ref['ts'])} TS, "
+             f"failing patterns {(ref['k_crit'] >= 0).sum()}")
     g.free()
 
 
@@ -230,6 +245,8 @@ def test_forced_layout_that_does_not_fit(ctx, pool):
     g = ctx.load_code(_largest(pool))
     with pytest.raises(tsg.TsgError):
         g.impulse_search(np.array([[0]], dtype=np.int32), layout=tsg.LAYOUT_REGISTER)
+    with pytest.raises(tsg.TsgError):   # two LDS arrays of 25.7k sums do not fit
+        g.impulse_search(np.array([[0]], dtype=np.int32), layout=tsg.LAYOUT_STREAMED_ACCUM)
     with pytest.raises(tsg.TsgError):
         g.impulse_search(np.array([[0]], dtype=np.int32), layout=7)
     g.free()
