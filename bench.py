@@ -116,13 +116,17 @@ def main():
         r = c.impulse_search(pats, **spa_kw)
         ts_spa = c.collect()
         rec["spa"] = r["stats"]
-        is_eu, is_ms, is_res = 0, 0.0, []
-        for t in ts_spa[:n_is]:
-            out = c.is_estimate(list(t.bits), 3.0, -1.0, args.is_frames, seed=7, max_iter=50)
-            is_eu += out["stats"]["edge_updates"]
-            is_ms += out["stats"]["decode_ms"]
-            is_res.append(out)
-        rec["is"] = {"edge_updates": is_eu, "decode_ms": is_ms}
+        # IS of the most harmful sets as one batch (their eps* shifts from one
+        # search launch, their frames in one persistent launch)
+        jobs = [("is", c, list(t.bits), dict(ebn0_db=3.0, shift=-1.0, n_frames=args.is_frames, seed=7,
+                                             max_iter=50)) for t in ts_spa[:n_is]]
+        ids = ctx.run_batch(jobs)
+        st = ctx.stats()
+        infos = [ctx.poll(j) for j in ids]
+        for j in ids:
+            ctx.release(j)
+        is_res = [i["is"] for i in infos]
+        rec["is"] = {"edge_updates": sum(i["edge_updates"] for i in infos), "decode_ms": st["decode_ms"]}
         rec["ts_oms"], rec["ts_spa"], rec["is_res"] = len(ts_oms), len(ts_spa), is_res
         return rec
 

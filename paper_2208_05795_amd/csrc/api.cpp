@@ -462,9 +462,7 @@ int run_search(ts_exec &ex, ts_code *code, DevTable &table, const ts_search_opts
 
 // eps* of the noiseless SPA impulse on the whole set (device bits d_t), grid
 // 2^-10 up to 32: the default mean shift of the IS frames.
-int is_eps_shift(ts_exec &ex, ts_code *code, const int32_t *d_t, int32_t a, const ts_is_opts *o,
-                 double *shift) {
-    hipStream_t s = ex.stream;
+static ts_search_opts eps_search_opts(const ts_is_opts *o) {
     ts_search_opts so{};
     so.decoder = TS_DEC_SPA_F32;
     so.max_iter = o->max_iter;
@@ -478,6 +476,50 @@ int is_eps_shift(ts_exec &ex, ts_code *code, const int32_t *d_t, int32_t a, cons
     so.collect_from_iter = -1;
     so.mem = TS_MEM_DEVICE;
     so.layout = o->layout;
+    return so;
+}
+
+// eps* of several sets of one code under the same IS options: one search
+// launch with one pattern per set (a pattern's decodes do not depend on the
+// other patterns of the launch), so every value is the one is_eps_shift gives.
+int is_eps_shifts(ts_exec &ex, ts_code *code, const ts_is_opts *o,
+                  const std::vector<std::vector<int32_t>> &sets, double *shift) {
+    hipStream_t s = ex.stream;
+    const int J = (int)sets.size();
+    if (J == 0) return TS_OK;
+    int W = 1;
+    for (const auto &t : sets) W = std::max(W, (int)t.size());
+    std::vector<int32_t> pat((size_t)J * W, -1), kc(J);
+    for (int j = 0; j < J; ++j) {
+        std::vector<int32_t> t = sets[j];
+        std::sort(t.begin(), t.end());
+        std::copy(t.begin(), t.end(), pat.begin() + (size_t)j * W);
+    }
+    const ts_search_opts so = eps_search_opts(o);
+    DBuf d_pat(ex, pat.size() * 4), outs(ex, (size_t)5 * J * 4);
+    if (!d_pat.p || !outs.p) { set_error("device allocation failed"); return TS_E_NOMEM; }
+    TSG_HIP(hipMemcpyAsync(d_pat.p, pat.data(), pat.size() * 4, hipMemcpyHostToDevice, s));
+    int32_t *d_out[5];
+    for (int i = 0; i < 5; ++i) d_out[i] = outs.as<int32_t>() + (size_t)i * J;
+    DevTable none{};
+    int rc = run_search(ex, code, none, &so, d_pat.as<int32_t>(), J, W, d_out, false);
+    if (rc) return rc;
+    TSG_HIP(hipMemcpyAsync(kc.data(), d_out[0], (size_t)J * 4, hipMemcpyDeviceToHost, s));
+    TSG_HIP(hipStreamSynchronize(s));
+    for (int j = 0; j < J; ++j) {
+        if (kc[j] < 0) {
+            set_error("the impulse on the whole set never fails; give a shift");
+            return TS_E_INVAL;
+        }
+        shift[j] = kc[j] / 1024.0;
+    }
+    return TS_OK;
+}
+
+int is_eps_shift(ts_exec &ex, ts_code *code, const int32_t *d_t, int32_t a, const ts_is_opts *o,
+                 double *shift) {
+    hipStream_t s = ex.stream;
+    const ts_search_opts so = eps_search_opts(o);
     DBuf outs(ex, 5 * 4);
     if (!outs.p) return TS_E_NOMEM;
     int32_t *d_out[5];

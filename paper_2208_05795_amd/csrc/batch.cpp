@@ -111,17 +111,22 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
             I.push_back(it);
         }
     }
-    // eps* shifts (a one-pattern search each) before the batch
-    for (IItem &it : I) {
-        if (it.shift >= 0.0) continue;
-        std::vector<int32_t> t(it.b->ts_bits, it.b->ts_bits + it.b->a);
-        std::sort(t.begin(), t.end());
-        int32_t *d_t = (int32_t *)ex.dalloc(kMaxWidth * 4);
-        if (!d_t) { set_error("device allocation failed"); return TS_E_NOMEM; }
-        TSG_HIP(hipMemcpyAsync(d_t, t.data(), t.size() * 4, hipMemcpyHostToDevice, s));
-        rc = is_eps_shift(ex, it.b->code, d_t, it.b->a, &it.b->io, &it.shift);
-        ex.dfree(d_t);
-        if (rc) return rc;
+    // eps* shifts before the batch: one search launch per (code, options),
+    // one pattern per set
+    {
+        std::map<std::tuple<ts_code *, int, double, double, int>, std::vector<IItem *>> need;
+        for (IItem &it : I)
+            if (it.shift < 0.0)
+                need[std::make_tuple(it.b->code, it.b->io.max_iter, it.b->io.ebn0_db, it.b->io.rate,
+                                     it.b->io.layout)].push_back(&it);
+        for (auto &kv : need) {
+            std::vector<std::vector<int32_t>> sets;
+            for (IItem *it : kv.second) sets.emplace_back(it->b->ts_bits, it->b->ts_bits + it->b->a);
+            std::vector<double> sh(sets.size());
+            rc = is_eps_shifts(ex, std::get<0>(kv.first), &kv.second.front()->b->io, sets, sh.data());
+            if (rc) return rc;
+            for (size_t j = 0; j < sets.size(); ++j) kv.second[j]->shift = sh[j];
+        }
     }
     // ---- groups -----------------------------------------------------------
     std::vector<Group> G;

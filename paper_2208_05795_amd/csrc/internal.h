@@ -386,6 +386,8 @@ int first_iter(const ts_code *code, const ts_search_opts *o);
 int64_t rec_capacity(const ts_search_opts *o, int t0, int64_t P, bool sieve, int64_t *worst);
 void fill_search_launch(const ts_code *code, const ts_search_opts *o, int t0, int32_t width,
                         SearchLaunch *a);
+int is_eps_shifts(ts_exec &ex, ts_code *code, const ts_is_opts *o,
+                  const std::vector<std::vector<int32_t>> &sets, double *shift);
 int is_eps_shift(ts_exec &ex, ts_code *code, const int32_t *d_t, int32_t a, const ts_is_opts *o,
                  double *shift);
 void is_fill_result(const double red[4], int64_t K, double shift, ts_is_result *res);

@@ -141,3 +141,27 @@ def test_batch_rejects_bad_job(mixed):
             ctx.run_batch([("search", c, np.array([[0]], dtype=np.int32), {}),
                            ("search", c, np.array([[96]], dtype=np.int32), {})])
         assert ctx.run_batch([]) == []
+
+
+def test_batch_eps_shifts_equal_alone():
+    """IS jobs whose shift is eps* (the impulse on the whole set): in a batch
+    the shifts of all sets of a code come from one search launch; every job
+    must equal the same call alone."""
+    import paper_2208_05795_amd as tsg
+    code = workloads.peg1008_code()
+    with tsg.Context(0) as ctx:
+        g = ctx.load_code(code)
+        rp, col = g.csr()
+        sets = [sorted(int(x) for x in col[rp[r]:rp[r + 1]])[:4] for r in (0, 1, 2)]
+        kw = dict(ebn0_db=3.0, shift=-1.0, n_frames=2048, seed=11, max_iter=50)
+        alone = [g.is_estimate(b, kw["ebn0_db"], kw["shift"], kw["n_frames"], kw["seed"],
+                               max_iter=50, stream=i) for i, b in enumerate(sets)]
+        ids = ctx.run_batch([("is", g, b, dict(kw, stream=i)) for i, b in enumerate(sets)])
+        for a, jid in zip(alone, ids):
+            info = ctx.poll(jid)
+            assert info["state"] == 2 and info["status"] == 0, info
+            got = info["is"]
+            for f in ("shift_used", "p_hat", "var", "sum_w", "sum_w2", "n_fail"):
+                assert a[f] == got[f], f
+            ctx.release(jid)
+        _say(f"eps* shifts {[a['shift_used'] for a in alone]}: batch equals alone")
