@@ -170,13 +170,13 @@ int check_search_opts(const ts_code *code, const ts_search_opts *o, int32_t widt
     return TS_OK;
 }
 
-// Autotuner: times every candidate launch shape once on a probe of the job's own
-// patterns (candidate writing off) and keeps the fastest per (code, decoder,
-// iteration count, layout request).  Shapes only change the schedule, never the
-// results.
-// Autotuner score of a probe time: a streamed shape must beat a register one
-// by 10%, since in batches its message traffic meets other launches in L2 and
-// the MALL (probes run alone) while register frames stay on chip.
+// Autotuner: times every candidate launch shape twice on a probe of the job's
+// own patterns (candidate writing off) and keeps the best score per (code,
+// decoder, iteration count, layout request).  Shapes only change the schedule,
+// never the results.  Score of a probe time: a streamed shape must beat a
+// register one by 10%, since in batches its message traffic meets other
+// launches in L2 and the MALL (probes run alone) while register frames stay
+// on chip.
 static float tune_score(const SearchPlan &p, float ms) { return p.kind == kPlanStreamed ? 1.1f * ms : ms; }
 
 static int tune_shape(ts_exec &ex, const std::vector<SearchPlan> &cands,

@@ -1,9 +1,9 @@
 // Batched execution of several search and IS jobs, possibly on different codes.
 //
 // Every job is planned as if run alone (the code's autotuned shape, else the
-// first that fits).  Jobs whose plans name the same kernel, a workgroup size in
-// the same power-of-two bucket and frames that fit the same number of times
-// into a CU's LDS form a group; a group runs as ONE persistent
+// first that fits).  Jobs whose plans name the same kernel and workgroup size
+// and whose frames fit the same number of times into a CU's LDS form a group
+// (so every job runs at its own tuned shape); a group runs as ONE persistent
 // launch whose workgroups pull items (patterns or IS frames) of all its jobs
 // from a single queue, so small jobs fill the device together and no launch
 // tail or host round trip separates them.  Groups go to the executor's side
@@ -26,12 +26,6 @@ int plan_search_shape(ts_exec &ex, ts_code *code, const ts_search_opts *o, int64
 namespace {
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
-
-int bucket(int block) {
-    int b = 64;
-    while (b < block) b <<= 1;
-    return b;
-}
 
 struct SItem {
     BatchJob *b;
@@ -136,7 +130,7 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
         // fit the same number of times into a CU's LDS share one, so that no job
         // loses occupancy to a larger code's frame
         const int lds_fit = (int)(ctx->lds_per_block / std::max<size_t>(p.lds, 1));
-        const auto key = std::make_tuple(search ? 1 : 0, p.kind, p.dc, p.cpt, p.decoder, bucket(p.block), lds_fit);
+        const auto key = std::make_tuple(search ? 1 : 0, p.kind, p.dc, p.cpt, p.decoder, p.block, lds_fit);
         auto f = gid.find(key);
         if (f != gid.end()) {
             Group &g = G[f->second];
