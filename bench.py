@@ -337,7 +337,7 @@ def bench_batch(tsg):
         jobs.append(("is", g, bits, dict(ebn0_db=3.0, shift=1.0, n_frames=16384, seed=40 + i,
                                          max_iter=50)))
 
-    def plain():
+    def plain(jobs):
         res = []
         for kind, g, data, kw in jobs:
             if kind == "search":
@@ -351,19 +351,19 @@ def bench_batch(tsg):
                 res.append(("is", r["p_hat"], r["n_fail"], r["stats"]["edge_updates"]))
         return res
 
-    def batched():
+    def batched(jobs):
         ids = ctx.run_batch(jobs)
         st = ctx.stats()
         return _job_results(ctx, ids, jobs), st
 
     _say("batched: warm-up (autotunes every code)")
-    plain()
-    batched()
+    plain(jobs)
+    batched(jobs)
     t0 = time.perf_counter()
-    ref = plain()
+    ref = plain(jobs)
     t_plain = time.perf_counter() - t0
     t0 = time.perf_counter()
-    got, st = batched()
+    got, st = batched(jobs)
     t_batch = time.perf_counter() - t0
     def same_job(a, b):
         if a[0] != b[0] or a[3] != b[3]:
@@ -375,6 +375,24 @@ def bench_batch(tsg):
     same = all(same_job(a, b) for a, b in zip(ref, got))
     eu = sum(r[3] for r in ref)
     ts = sum(len(r[2][0]) for r in ref if r[0] == "search")
+    # the same codes with small jobs (256 patterns, 1024 IS frames): a plain
+    # call no longer fills the device, a batch still does
+    small = []
+    for kind, g, data, kw in jobs:
+        if kind == "search":
+            small.append((kind, g, np.ascontiguousarray(data[:256]), kw))
+        else:
+            small.append((kind, g, data, dict(kw, n_frames=1024)))
+    plain(small)
+    batched(small)
+    t0 = time.perf_counter()
+    ref_s = plain(small)
+    t_plain_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    got_s, _ = batched(small)
+    t_batch_s = time.perf_counter() - t0
+    eu_s = sum(r[3] for r in ref_s)
+    same_s = all(same_job(a, b) for a, b in zip(ref_s, got_s))
     ctx.close()
     return {"workload": "64 QC codes, bases 3x6/4x8/3x12/4x24, Z 16..384 (seed 4); per code 4096 "
                         "impulse patterns OMS-i8 20it + 16384 IS frames SPA-f32 50it at 3 dB",
@@ -383,7 +401,12 @@ def bench_batch(tsg):
                       "ts_found_per_s": ts / t_plain},
             "batched": {"seconds": t_batch, "edge_updates_per_s": eu / t_batch,
                         "ts_found_per_s": ts / t_batch, "decode_launches": st["decode_launches"]},
-            "speedup": t_plain / t_batch, "results_identical": bool(same)}
+            "speedup": t_plain / t_batch, "results_identical": bool(same),
+            "small_jobs": {"workload": "the same 64 codes, 256 patterns + 1024 IS frames per code",
+                           "plain_s": t_plain_s, "batched_s": t_batch_s,
+                           "plain_edge_updates_per_s": eu_s / t_plain_s,
+                           "batched_edge_updates_per_s": eu_s / t_batch_s,
+                           "speedup": t_plain_s / t_batch_s, "results_identical": bool(same_s)}}
 
 
 def _serve_stream(pool, graphs, rng, seconds, rate):
