@@ -588,7 +588,11 @@ def bench_qc2640(tsg):
                                      "speedup": t_search / t_reduced, "same_ts": same},
             "union_bound": {"seconds": t_ub, "edge_updates": eu_ub, "edge_updates_per_s": eu_ub / t_ub,
                             "fer": {f"{p['ebn0_db']:g}dB": {"fer": p["fer"], "ci": [p["ci_lo"], p["ci_hi"]]}
-                                    for p in ub["points"]}}}
+                                    for p in ub["points"]},
+                            # per SNR, per set of the table: (shift eps*, failing frames, P_hat)
+                            "per_ts": {f"{p['ebn0_db']:g}dB": [[r["shift_used"], r["n_fail"], r["p_hat"]]
+                                                               for r in rows]
+                                       for p, rows in zip(ub["points"], ub["per_ts"])}}}
 
 
 def bench_layered(tsg):
