@@ -63,7 +63,9 @@ typedef struct {
 /* Creates a context on opts->device.  opts may be NULL (device 0, own stream).
  * Errors: TS_E_DEVICE (no device / HIP failure), TS_E_INVAL. */
 int ts_create(const ts_ctx_opts *opts, ts_ctx **out);
-/* Frees the context and every code still loaded on it. */
+/* Frees the context and every code still loaded on it.  Queued served jobs are
+ * cancelled and running ones finish first.  No other call on the context may
+ * be in progress or follow (including ts_poll waits of other threads). */
 int ts_destroy(ts_ctx *ctx);
 /* Message of the last failed call on this thread ("" if none).  Valid until the
  * thread's next call. */

@@ -123,7 +123,7 @@ void fill_search_launch(const ts_code *code, const ts_search_opts *o, int t0, in
     a->decoder = o->decoder;
     a->max_iter = o->max_iter;
     a->offset = o->oms_offset;
-    const long q = std::lround(o->llr_scale * h);
+    const long q = std::lround(std::min(o->llr_scale * h, 1e6));   // saturated below anyway
     a->q_base = o->decoder == TS_DEC_LNMS_Q4 ? (int)(q > 7 ? 7 : (q < -7 ? -7 : q)) : sat127(q);
     a->k_max = o->k_max;
     a->k_den = o->k_den;
@@ -162,6 +162,7 @@ int check_search_opts(const ts_code *code, const ts_search_opts *o, int32_t widt
     if (o->k_den < 1) { set_error("k_den must be positive"); return TS_E_INVAL; }
     if (o->oms_offset < 0 || o->oms_offset > 127) { set_error("oms_offset must be 0..127"); return TS_E_INVAL; }
     if (!(o->rate > 0.0 && o->rate <= 1.0) || !(o->llr_scale > 0.0)) { set_error("rate / llr_scale out of range"); return TS_E_INVAL; }
+    if (!std::isfinite(o->ebn0_db) || !std::isfinite(o->llr_scale)) { set_error("Eb/N0 and llr_scale must be finite"); return TS_E_INVAL; }
     if (o->extract_mode != TS_EXTRACT_PATH && o->extract_mode != TS_EXTRACT_CRITICAL) { set_error("bad extract_mode"); return TS_E_INVAL; }
     if (o->mem != TS_MEM_HOST && o->mem != TS_MEM_DEVICE) { set_error("bad mem kind"); return TS_E_INVAL; }
     if (o->layout < TS_LAYOUT_AUTO || o->layout > TS_LAYOUT_STREAMED_ACCUM) { set_error("bad layout"); return TS_E_INVAL; }

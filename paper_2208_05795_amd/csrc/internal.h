@@ -214,7 +214,7 @@ struct ts_ctx {
     std::vector<ts_code *> codes;
     int num_cu = 0;
     size_t lds_per_block = 0;
-    tsg::Server *server = nullptr;
+    std::atomic<tsg::Server *> server{nullptr};   // set once under mu, read without it
     double t0 = 0.0;   // creation time (ms, steady clock)
 };
 

@@ -70,6 +70,7 @@ int build_code(const ts_code_desc *d, ts_code *c) {
         }
         const int64_t n = (int64_t)d->nb * d->z, m = (int64_t)d->mb * d->z;
         if (n > (1 << 24) || m > (1 << 24)) { set_error("code too large"); return TS_E_INVAL; }
+        if ((int64_t)d->mb * d->nb > (1 << 24)) { set_error("base matrix too large"); return TS_E_INVAL; }
         for (int i = 0; i < d->mb * d->nb; ++i)
             if (d->shifts[i] < -1 || d->shifts[i] >= d->z) {
                 set_error("shift %d at %d outside [-1, z)", d->shifts[i], i);

@@ -163,8 +163,8 @@ void worker_main(Server *s, ts_exec *ex) {
 
 int server_get(ts_ctx *ctx, int slots, Server **out) {
     std::lock_guard<std::recursive_mutex> g(ctx->mu);
-    if (ctx->server) {
-        *out = ctx->server;
+    if (Server *cur = ctx->server.load()) {
+        *out = cur;
         return TS_OK;
     }
     Server *s = new Server();
@@ -287,7 +287,7 @@ void run_jobs(ts_exec &ex, std::vector<Job *> &js) {
 }  // namespace
 
 void server_stop(ts_ctx *ctx) {
-    Server *s = ctx->server;
+    Server *s = ctx->server.load();
     if (!s) return;
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -320,7 +320,7 @@ int ts_serve_start(ts_ctx *ctx, int32_t slots) {
     clear_error();
     if (!ctx) { set_error("null argument"); return TS_E_INVAL; }
     if (slots < 1 || slots > 16) { set_error("slots must be 1..16"); return TS_E_INVAL; }
-    if (ctx->server) { set_error("serving already started"); return TS_E_STATE; }
+    if (ctx->server.load()) { set_error("serving already started"); return TS_E_STATE; }
     Server *s = nullptr;
     return server_get(ctx, slots, &s);
 }
@@ -400,7 +400,7 @@ int ts_run_batch(ts_ctx *ctx, const ts_job_desc *jobs, int32_t n_jobs, uint64_t 
 int ts_poll(ts_ctx *ctx, uint64_t job_id, int32_t wait, ts_job_info *info) {
     clear_error();
     if (!ctx || !info) { set_error("null argument"); return TS_E_INVAL; }
-    Server *s = ctx->server;
+    Server *s = ctx->server.load();
     if (!s) { set_error("no job was submitted"); return TS_E_STATE; }
     std::unique_lock<std::mutex> lk(s->mu);
     Job *j = find_job(s, job_id);
@@ -427,7 +427,7 @@ int ts_job_outputs(ts_ctx *ctx, uint64_t job_id, ts_search_out *out, ts_record *
                    int32_t *bits, int64_t bits_cap) {
     clear_error();
     if (!ctx) { set_error("null argument"); return TS_E_INVAL; }
-    Server *s = ctx->server;
+    Server *s = ctx->server.load();
     if (!s) { set_error("no job was submitted"); return TS_E_STATE; }
     std::lock_guard<std::mutex> lk(s->mu);
     Job *j = find_job(s, job_id);
@@ -442,6 +442,7 @@ int ts_job_outputs(ts_ctx *ctx, uint64_t job_id, ts_search_out *out, ts_record *
     const int64_t n = (int64_t)j->recs.size() / 5;
     if (cap > 0 || bits_cap > 0) {
         if (cap < n || bits_cap < (int64_t)j->bits.size()) { set_error("output buffers too small"); return TS_E_TRUNC; }
+        if ((n > 0 && !recs) || (!j->bits.empty() && !bits)) { set_error("null output buffer"); return TS_E_INVAL; }
         int64_t off = 0;
         for (int64_t i = 0; i < n; ++i) {
             const int32_t *r = j->recs.data() + i * 5;
@@ -462,7 +463,7 @@ int ts_job_outputs(ts_ctx *ctx, uint64_t job_id, ts_search_out *out, ts_record *
 int ts_cancel(ts_ctx *ctx, uint64_t job_id) {
     clear_error();
     if (!ctx) { set_error("null argument"); return TS_E_INVAL; }
-    Server *s = ctx->server;
+    Server *s = ctx->server.load();
     if (!s) { set_error("no job was submitted"); return TS_E_STATE; }
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -484,7 +485,7 @@ int ts_cancel(ts_ctx *ctx, uint64_t job_id) {
 int ts_release(ts_ctx *ctx, uint64_t job_id) {
     clear_error();
     if (!ctx) { set_error("null argument"); return TS_E_INVAL; }
-    Server *s = ctx->server;
+    Server *s = ctx->server.load();
     if (!s) { set_error("no job was submitted"); return TS_E_STATE; }
     std::lock_guard<std::mutex> lk(s->mu);
     Job *j = find_job(s, job_id);

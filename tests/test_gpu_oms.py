@@ -162,6 +162,9 @@ def test_empty_and_invalid_inputs(ctx, tiny):
         g.impulse_search(np.zeros((1, 1), dtype=np.int32), k_den=8)
     with pytest.raises(tsg.TsgError):
         g.impulse_search(np.zeros((1, 1), dtype=np.int32), a_max=17)
+    for bad in (dict(ebn0_db=float("nan")), dict(llr_scale=float("inf"))):
+        with pytest.raises(tsg.TsgError):
+            g.impulse_search(np.zeros((1, 1), dtype=np.int32), **bad)
     assert g.collect() == []
     g.free()
 
