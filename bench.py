@@ -19,7 +19,7 @@ Beside it, with their own figures in the same JSON line:
              through ts_submit: p50/p99 latency and edge-updates/s;
   qc2640   - the (2640,1320) girth-8 QC stand-in: every tree-path triple
              searched with SPA, and one triple per orbit of the circulant shift
-             (same TS); then the union bound over the 16 most harmful TS at
+             (same TS); then the union bound over the (up to) 16 most harmful TS at
              2/3/4/5 dB, 10^5 IS frames each.
 
 Prints one JSON line.  The metric is edge-updates per second (one edge x one
@@ -543,7 +543,7 @@ def bench_serve(tsg, seconds, rate, stress_seconds=5.0):
 
 def bench_qc2640(tsg):
     """QC-2640: SPA search over every tree-path triple and over one triple per
-    orbit of the circulant shift (same TS), then the union bound over the 16
+    orbit of the circulant shift (same TS), then the union bound over the (up to) 16
     most harmful TS at 2, 3, 4, 5 dB with 10^5 IS frames each (shift eps*)."""
     import numpy as np
     import workloads
