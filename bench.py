@@ -51,7 +51,7 @@ VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 VALU_SLOTS_PER_EU = {"oms": 15.0, "spa": 2 * (3 * 4 + 5) + 6.0}
 # HBM traffic per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled x2 and x1 by a 1 GiB copy); None once the kernel changes.
-MEASURED_TRAFFIC_BYTES = {"spa": (22.10e6 + 188.67e6)}
+MEASURED_TRAFFIC_BYTES = {}
 
 
 def parse():
@@ -116,6 +116,7 @@ def main():
         r = c.impulse_search(pats, **spa_kw)
         ts_spa = c.collect()
         rec["spa"] = r["stats"]
+        rec["spa_out"] = {k: r[k] for k in ("k_crit", "iters_crit", "iters_lo", "tmin_crit", "n_cand")}
         # IS of the most harmful sets as one batch (their eps* shifts from one
         # search launch, their frames in one persistent launch)
         jobs = [("is", c, list(t.bits), dict(ebn0_db=3.0, shift=-1.0, n_frames=args.is_frames, seed=7,
@@ -146,6 +147,14 @@ def main():
 
     eu = sum(r["oms"]["edge_updates"] + r["spa"]["edge_updates"] + r["is"]["edge_updates"]
              for r in recs)
+    # outside the timed steps: the same SPA search with every iteration of every
+    # decode computed (no fixed-point exit), for the kernel's rate on full decodes
+    c.reset_ts()
+    rf = c.impulse_search(pats, full_iterations=True, **spa_kw)
+    ts_full = c.collect()
+    full = rf["stats"]
+    full_same = (len(ts_full) == recs[-1]["ts_spa"] and
+                 all(torch.equal(rf[k], v) for k, v in recs[-1]["spa_out"].items()))
     ts_found = sum(r["ts_oms"] + r["ts_spa"] for r in recs)
     cands = sum(r["oms"]["candidates"] + r["spa"]["candidates"] for r in recs)
     lds_peak = ctx.probe_lds()
@@ -158,7 +167,13 @@ def main():
         "spa_search": {"edge_updates": last["spa"]["edge_updates"],
                        "decode_ms": last["spa"]["decode_ms"], "sieve_ms": last["spa"]["extract_ms"],
                        "call_ms": last["spa"]["total_ms"], "ts_found": last["ts_spa"],
-                       "edge_updates_per_s": last["spa"]["edge_updates"] / (last["spa"]["decode_ms"] * 1e-3)},
+                       "edge_updates_per_s": last["spa"]["edge_updates"] / (last["spa"]["decode_ms"] * 1e-3),
+                       "shape": {k: last["spa"][k] for k in ("layout", "block_threads", "checks_per_thread",
+                                                              "grid_blocks")}},
+        "spa_search_full_iterations": {
+            "edge_updates": full["edge_updates"], "decode_ms": full["decode_ms"],
+            "edge_updates_per_s": full["edge_updates"] / (full["decode_ms"] * 1e-3),
+            "same_results": bool(full_same)},
         "is": {"edge_updates": last["is"]["edge_updates"], "decode_ms": last["is"]["decode_ms"],
                "frames": n_is * args.is_frames,
                "p_hat": [r["p_hat"] for r in last["is_res"]],
@@ -191,6 +206,9 @@ def main():
                 "achieved_GBs": round(lds_bpe * eu_per_launch / launch_s / 1e9, 1),
                 "peak_GBs_measured": round(lds_peak / 1e9, 1),
                 "frac_of_measured_peak": round(lds_bpe * eu_per_launch / launch_s / lds_peak, 4)},
+        # the same kernel on the same patterns with every iteration computed
+        "full_iterations_frac": round(VALU_SLOTS_PER_EU["spa"] * full["edge_updates"]
+                                      / (full["decode_ms"] * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4),
     }
     line = {
         "metric": "BP edge-updates/s (TS search + IS, one job)",

@@ -179,6 +179,11 @@ typedef struct {
     int32_t collect_from_iter; /* first iteration whose error set is sieved; -1 = girth/2 */
     int32_t mem;               /* TS_MEM_HOST / TS_MEM_DEVICE for patterns and outputs */
     int32_t layout;            /* TS_LAYOUT_*; TS_E_INVAL if the forced layout does not fit */
+    int32_t full_iterations;   /* 0: a decode that reaches a fixed point (no check message
+                                * changes in an iteration, so every later iteration repeats
+                                * the last one) stops computing and fills in its remaining
+                                * iterations; nonzero: compute every iteration.  Results are
+                                * identical; statistics count computed iterations only. */
 } ts_search_opts;
 
 typedef struct {            /* caller-owned arrays of n_patterns entries */
@@ -235,6 +240,7 @@ typedef struct {
     uint64_t frame_base;     /* first frame counter (resumable streams) */
     uint32_t stream;         /* Philox stream tag */
     int32_t layout;          /* TS_LAYOUT_* (AUTO: register layout when it fits) */
+    int32_t full_iterations; /* as in ts_search_opts (also for the eps* searches) */
 } ts_is_opts;
 
 typedef struct {

@@ -136,7 +136,7 @@ class Context:
                      oms_offset: int = 1, ebn0_db: float = 3.0, rate: Optional[float] = None,
                      llr_scale: float = 4.0, k_max: int = 512, k_den: int = 16, a_max: int = 6,
                      extract_mode: int = EXTRACT_PATH, collect_from_iter: int = -1,
-                     layout: int = 0):
+                     layout: int = 0, full_iterations: bool = False):
         pats = _i32(patterns)
         if pats.ndim == 1:
             pats = pats.reshape(-1, 1)
@@ -145,20 +145,20 @@ class Context:
         d.kind, d.code = A.TS_JOB_SEARCH, code._h
         d.search = A.SearchOpts(decoder, max_iter, oms_offset, ebn0_db, rate, llr_scale, k_max,
                                 k_den, a_max, extract_mode, collect_from_iter, A.TS_MEM_HOST,
-                                layout)
+                                layout, int(full_iterations))
         d.patterns, d.n_patterns, d.width = pats.ctypes.data, pats.shape[0], pats.shape[1]
         return d, pats
 
     @staticmethod
     def _is_desc(code: "Code", ts_bits, ebn0_db: float, shift: float, n_frames: int,
                  seed: int, frame_base: int = 0, stream: int = 0, max_iter: int = 50,
-                 rate: Optional[float] = None, layout: int = 0):
+                 rate: Optional[float] = None, layout: int = 0, full_iterations: bool = False):
         t = _i32(ts_bits)
         rate = (1.0 - code.m / code.n) if rate is None else rate
         d = A.JobDesc()
         d.kind, d.code = A.TS_JOB_IS, code._h
         d.is_ = A.IsOpts(max_iter, ebn0_db, rate, shift, n_frames, seed, frame_base, stream,
-                         layout)
+                         layout, int(full_iterations))
         d.ts_bits, d.a = t.ctypes.data, t.size
         return d, t
 
@@ -319,14 +319,16 @@ class Code:
                        oms_offset: int = 1, ebn0_db: float = 3.0, rate: Optional[float] = None,
                        llr_scale: float = 4.0, k_max: int = 512, k_den: int = 16, a_max: int = 6,
                        extract_mode: int = EXTRACT_PATH, collect_from_iter: int = -1,
-                       layout: int = 0) -> dict:
+                       layout: int = 0, full_iterations: bool = False) -> dict:
         """Patterns: numpy (host) or a torch int32 CUDA tensor [P, width] (device);
         outputs come back in the same kind of memory.  layout: LAYOUT_AUTO,
         LAYOUT_REGISTER, LAYOUT_STREAMED or one streamed variant
-        (LAYOUT_STREAMED_GATHER, LAYOUT_STREAMED_ACCUM)."""
+        (LAYOUT_STREAMED_GATHER, LAYOUT_STREAMED_ACCUM).  full_iterations: compute
+        every iteration of every decode (no fixed-point exit; same results)."""
         rate = (1.0 - self.m / self.n) if rate is None else rate
         o = A.SearchOpts(decoder, max_iter, oms_offset, ebn0_db, rate, llr_scale, k_max, k_den,
-                         a_max, extract_mode, collect_from_iter, A.TS_MEM_HOST, layout)
+                         a_max, extract_mode, collect_from_iter, A.TS_MEM_HOST, layout,
+                         int(full_iterations))
         out = A.SearchOut()
         if _is_torch_cuda(patterns):
             import torch
@@ -413,10 +415,11 @@ class Code:
     def is_estimate(self, ts_bits, ebn0_db: float, shift: float, n_frames: int, seed: int,
                     frame_base: int = 0, stream: int = 0, max_iter: int = 50,
                     rate: Optional[float] = None, want_fail: bool = False,
-                    layout: int = 0) -> dict:
+                    layout: int = 0, full_iterations: bool = False) -> dict:
         rate = (1.0 - self.m / self.n) if rate is None else rate
         t = _i32(ts_bits)
-        o = A.IsOpts(max_iter, ebn0_db, rate, shift, n_frames, seed, frame_base, stream, layout)
+        o = A.IsOpts(max_iter, ebn0_db, rate, shift, n_frames, seed, frame_base, stream, layout,
+                     int(full_iterations))
         r = A.IsResult()
         fo = np.zeros(n_frames, dtype=np.uint8) if want_fail else None
         _check(lib().ts_is_estimate(self.ctx.handle, self._h, t.ctypes.data, t.size, C.byref(o),

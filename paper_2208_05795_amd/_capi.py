@@ -44,7 +44,7 @@ class SearchOpts(C.Structure):
                 ("ebn0_db", C.c_double), ("rate", C.c_double), ("llr_scale", C.c_double),
                 ("k_max", C.c_int32), ("k_den", C.c_int32), ("a_max", C.c_int32),
                 ("extract_mode", C.c_int32), ("collect_from_iter", C.c_int32), ("mem", C.c_int32),
-                ("layout", C.c_int32)]
+                ("layout", C.c_int32), ("full_iterations", C.c_int32)]
 
 
 class SearchOut(C.Structure):
@@ -61,7 +61,8 @@ class Record(C.Structure):
 class IsOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("ebn0_db", C.c_double), ("rate", C.c_double),
                 ("shift", C.c_double), ("n_frames", C.c_int64), ("seed", C.c_uint64),
-                ("frame_base", C.c_uint64), ("stream", C.c_uint32), ("layout", C.c_int32)]
+                ("frame_base", C.c_uint64), ("stream", C.c_uint32), ("layout", C.c_int32),
+                ("full_iterations", C.c_int32)]
 
 
 class IsResult(C.Structure):

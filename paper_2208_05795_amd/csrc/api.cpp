@@ -133,6 +133,7 @@ void fill_search_launch(const ts_code *code, const ts_search_opts *o, int t0, in
     a->a_max = o->a_max;
     a->extract_mode = o->extract_mode;
     a->width = width;
+    a->fp_exit = o->full_iterations ? 0 : 1;
 }
 
 size_t search_bytes_estimate(const ts_code *code, const ts_search_opts *o, int64_t P, int32_t width) {
@@ -141,8 +142,7 @@ size_t search_bytes_estimate(const ts_code *code, const ts_search_opts *o, int64
     std::vector<SearchPlan> shapes;
     if (plan_candidates(code->ctx, code, o->decoder, o->max_iter, &shapes) == TS_OK)
         for (const SearchPlan &p : shapes)
-            if (p.kind == kPlanStreamed)
-                scr = std::max(scr, (size_t)std::min<int64_t>(p.grid, std::max<int64_t>(P, 1)) * p.slot_bytes);
+            scr = std::max(scr, (size_t)std::min<int64_t>(p.grid, std::max<int64_t>(P, 1)) * p.slot_bytes);
     return (size_t)P * (width + 5) * 4 + (size_t)cap * kRecStride * 4 + table_bytes(1 << 16) + scr + 4096;
 }
 
@@ -182,15 +182,32 @@ static float tune_score(const SearchPlan &p, float ms) { return p.kind == kPlanS
 
 static int tune_shape(ts_exec &ex, const std::vector<SearchPlan> &cands,
                       const SearchLaunch &base, int64_t P, SearchPlan *best) {
+    // the probe: four patterns per workgroup of the widest shape, taken at an
+    // even stride over the whole list (pattern lists are ordered by kind, and
+    // decode lengths differ between kinds)
     int64_t probe = 0;
-    for (const SearchPlan &p : cands) probe = std::max<int64_t>(probe, 2 * (int64_t)p.grid);
+    for (const SearchPlan &p : cands) probe = std::max<int64_t>(probe, 4 * (int64_t)p.grid);
     probe = std::min(probe, P);
+    const bool strided = probe < P;
+    DBuf sample(ex, strided ? (size_t)probe * base.width * 4 : 0);
+    const int *pat = base.patterns;
+    if (strided) {
+        if (!sample.p) {
+            set_error("device allocation of the tuning probe failed");
+            return TS_E_NOMEM;
+        }
+        const size_t row = (size_t)base.width * 4;
+        TSG_HIP(hipMemcpy2DAsync(sample.p, row, base.patterns, (size_t)(P / probe) * row, row, (size_t)probe,
+                                 hipMemcpyDeviceToDevice, ex.stream));
+        pat = sample.as<int>();
+    }
     float best_ms = 0.0f;
     for (const SearchPlan &p : cands) {
         float ms_min = 0.0f;
         for (int rep = 0; rep < 2; ++rep) {   // the faster of two timings
             SearchLaunch a = base;
             a.t0 = a.max_iter + 1;   // no candidate is written while timing
+            a.patterns = pat;
             a.n_patterns = (int)probe;
             a.pat_base = 0;
             int rc = launch_fill(ex.stream, a.queue, 0, 2);
@@ -218,7 +235,6 @@ static bool same_shape(const SearchPlan &p, const SearchShape &s) {
 }
 
 static size_t scratch_bytes(const SearchPlan &p, int64_t P) {
-    if (p.kind != kPlanStreamed) return 0;
     return (size_t)std::min<int64_t>(p.grid, std::max<int64_t>(P, 1)) * p.slot_bytes;
 }
 
@@ -477,6 +493,7 @@ static ts_search_opts eps_search_opts(const ts_is_opts *o) {
     so.collect_from_iter = -1;
     so.mem = TS_MEM_DEVICE;
     so.layout = o->layout;
+    so.full_iterations = o->full_iterations;
     return so;
 }
 
@@ -602,6 +619,7 @@ int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const 
     L.seed = o->seed;
     L.frame_base = o->frame_base;
     L.stream = o->stream;
+    L.fp_exit = o->full_iterations ? 0 : 1;
     L.ts = d_t.as<int32_t>();
     L.a = a;
     L.fail = d_fail.as<unsigned char>();
@@ -614,7 +632,7 @@ int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const 
     if (rc) return rc;
     size_t scr = 0;
     for (const SearchPlan &p : need_tune ? shapes : std::vector<SearchPlan>{plan})
-        if (p.kind == kPlanStreamed) scr = std::max(scr, (size_t)std::min<int64_t>(p.grid, K) * p.slot_bytes);
+        scr = std::max(scr, (size_t)std::min<int64_t>(p.grid, K) * p.slot_bytes);
     DBuf scratch(ex, scr);
     if (scr && !scratch.p) { set_error("device allocation of the decoder scratch failed"); return TS_E_NOMEM; }
     L.gscr = scr ? scratch.as<unsigned char>() : nullptr;

@@ -165,7 +165,7 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
         rc = occupancy_grid(ctx, g.plan, g.plan.decoder, g.search, &g.plan.grid);
         if (rc) return rc;
         const long long grid = std::min<long long>(g.plan.grid, g.n_items);
-        g.scratch_bytes = g.plan.kind == kPlanStreamed ? (size_t)grid * g.plan.slot_bytes : 0;
+        g.scratch_bytes = (size_t)grid * g.plan.slot_bytes;
     }
     // ---- one arena: zeroed counters first, then the buffers ---------------
     // per job 8 ints: [0] candidate count, [1] error flags, [4..7] two 64-bit
@@ -250,6 +250,7 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
         L.seed = it.b->io.seed;
         L.frame_base = it.b->io.frame_base;
         L.stream = it.b->io.stream;
+        L.fp_exit = it.b->io.full_iterations ? 0 : 1;
         L.ts = (const int *)(arena + it.ts);
         L.a = it.b->a;
         L.fail = arena + it.fail;

@@ -265,7 +265,7 @@ struct SearchPlan {
     int dc;         // padded check degree of the kernel (streamed: largest class)
     size_t lds;     // dynamic LDS bytes
     int grid;       // persistent workgroups
-    size_t slot_bytes;   // streamed: global scratch per workgroup
+    size_t slot_bytes;   // global scratch per workgroup (register kind: message save area)
     size_t hist_off;     // streamed: offset of the iteration history in a slot
 };
 
@@ -297,8 +297,9 @@ struct SearchLaunch {
     int *rec_count;
     unsigned long long *counters;   // [0] decodes, [1] iterations
     int *err;
-    unsigned char *gscr;            // streamed kind: grid x slot_bytes scratch
+    unsigned char *gscr;            // grid x slot_bytes scratch (nullptr: none)
     long long slot_bytes, hist_off;
+    int fp_exit;                    // register kind: end decodes at a fixed point
 };
 
 int plan_search(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter, SearchPlan *plan);
@@ -331,8 +332,9 @@ struct IsDev {
     unsigned char *fail;
     double *wf;
     unsigned long long *counters;
-    unsigned char *gscr;   // streamed kind: per-workgroup scratch
+    unsigned char *gscr;   // per-workgroup scratch (nullptr: none)
     long long slot_bytes, lam_off;
+    int fp_exit;           // register kind: end decodes at a fixed point
 };
 
 struct IsJob {
@@ -357,9 +359,10 @@ struct IsLaunch {
     unsigned char *fail;    // [n_frames]
     double *wf;             // [n_frames]
     unsigned long long *counters;
-    unsigned char *gscr;    // streamed kind: grid x slot_bytes scratch
+    unsigned char *gscr;    // grid x slot_bytes scratch
+    int fp_exit;            // end decodes at a fixed point
 };
-// IS launch shape (streamed kind: plan.slot_bytes of scratch per workgroup)
+// IS launch shape (plan.slot_bytes of scratch per workgroup)
 int plan_is(ts_ctx *ctx, const ts_code *c, int max_iter, int layout, SearchPlan *plan);
 int plan_is_candidates(ts_ctx *ctx, const ts_code *c, int max_iter, int layout,
                        std::vector<SearchPlan> *out);

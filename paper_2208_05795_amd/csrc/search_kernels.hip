@@ -265,7 +265,7 @@ __device__ __forceinline__ int q4_impulse(int qb, int k) {
 // Shared-memory layout of a frame (byte offsets).
 struct Lds {
     int np, W, T;
-    size_t lam, app, hist, imask, wsyn, pcnt, extra, total;
+    size_t lam, app, hist, imask, wsyn, pcnt, moved, extra, total;
 };
 
 __host__ __device__ inline Lds lds_layout(int n, int T, bool with_hist) {
@@ -287,6 +287,8 @@ __host__ __device__ inline Lds lds_layout(int n, int T, bool with_hist) {
     o += (size_t)(T + 2) * 4;
     L.pcnt = o;
     o += (size_t)(T + 2) * 4;
+    L.moved = o;
+    o += (size_t)(T + 2) * 4;
     o = (o + 15) & ~(size_t)15;
     L.extra = o;   // IS: Philox normals of the TS bits (doubles) and the TS bits
     o += (size_t)kMaxWidth * 8 + (size_t)kMaxWidth * 4;
@@ -298,11 +300,14 @@ struct Frame {
     int *lam, *app;
     unsigned long long *hist;   // nullable
     int *wsyn, *pcnt;
+    int *moved;   // per iteration: bit 0 APP changed, bit 1 a check message changed
+    int *vsave;   // global save area of the messages (B x CPT x DC), or nullptr
     int n, np, W, T;
 };
 
 struct DecRes {
     int fail, iters, tmin;
+    int run;   // iterations computed (below iters when a fixed point ends the decode)
 };
 
 template <int DC, int CPT>
@@ -335,11 +340,19 @@ __device__ __forceinline__ DecRes run_decode(const Frame &F, const int (&nb)[CPT
 #pragma unroll
         for (int j = 0; j < DC; ++j) c2v[c][j] = 0;
     int cur = 0, nxt = 1, spare = 2;
-    int iters = T, wmin = INT_MAX, tmin = 0;
+    int iters = T, wmin = INT_MAX, tmin = 0, fixed = 0;
+    bool verify = false;   // iteration t compares its messages with those of t - 1
     for (int t = 1; t <= T + 1; ++t) {
         const int *A = F.app + cur * np;
         int *N = F.app + nxt * np;
         int unsat = 0;
+        if (verify) {   // the thread's messages, contiguous
+            int *vs = F.vsave + (unsigned)tid * (CPT * DC);
+#pragma unroll
+            for (int c = 0; c < CPT; ++c)
+#pragma unroll
+                for (int j = 0; j < DC; ++j) vs[c * DC + j] = c2v[c][j];
+        }
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
             int val[DC];
@@ -368,9 +381,26 @@ __device__ __forceinline__ DecRes run_decode(const Frame &F, const int (&nb)[CPT
             }
             if (lane == 0 && pc) atomicAdd(&F.pcnt[t - 1], pc);
         }
+        if (verify) {
+            const int *vs = F.vsave + (unsigned)tid * (CPT * DC);
+            unsigned chg = 0;   // padded edges carry nothing, so they are skipped
+#pragma unroll
+            for (int c = 0; c < CPT; ++c)
+#pragma unroll
+                for (int j = 0; j < DC; ++j)
+                    if (nb[c][j] != n) chg |= (unsigned)(c2v[c][j] ^ vs[c * DC + j]);
+            if (__any(chg != 0u) && lane == 0) atomicOr(&F.moved[t], 2);
+        }
         if (t < T) {
+            // the spare buffer holds APP_{t-2} (t >= 2) until it is reset to
+            // lambda here: APP_{t-1} = APP_{t-2} points to a fixed point
             int *S = F.app + spare * np;
-            for (int v = tid; v < np; v += B) S[v] = F.lam[v];
+            bool same = true;
+            for (int v = tid; v < np; v += B) {
+                same &= S[v] == A[v];
+                S[v] = F.lam[v];
+            }
+            if (t >= 2 && !__all(same) && lane == 0) atomicOr(&F.moved[t], 1);
         }
         __syncthreads();
         if (t >= 2) {
@@ -383,16 +413,39 @@ __device__ __forceinline__ DecRes run_decode(const Frame &F, const int (&nb)[CPT
                 iters = t - 1;
                 break;
             }
+            if (verify && (F.moved[t] & 2) == 0) {
+                fixed = t;
+                break;
+            }
+            verify = F.vsave && t < T && (F.moved[t] & 1) == 0;
         }
         const int tmp = cur;
         cur = nxt;
         nxt = spare;
         spare = tmp;
     }
+    if (fixed) {
+        // No check message changed in iteration t = fixed (padded edges carry
+        // none), so APP_t = APP_{t-1} and every later iteration repeats
+        // iteration t - 1: its records stand for iterations t..T, and the
+        // decode ends at T as if run to the end.
+        const int t = fixed, w = F.wsyn[t - 1], pc = F.pcnt[t - 1];
+        for (int i = tid; i <= T - t; i += B) {
+            F.wsyn[t + i] = w;
+            F.pcnt[t + i] = pc;
+        }
+        if (F.hist) {
+            const unsigned long long *src = F.hist + (size_t)(t - 2) * W;
+            unsigned long long *dst = F.hist + (size_t)(t - 1) * W;
+            for (int i = tid; i < (T - t + 1) * W; i += B) dst[i] = src[i % W];
+        }
+        __syncthreads();
+    }
     DecRes r;
     r.iters = iters;
     r.tmin = tmin;
     r.fail = F.pcnt[iters] > 0;
+    r.run = fixed ? fixed - 1 : iters;
     return r;
 }
 
@@ -546,7 +599,7 @@ __device__ __forceinline__ void search_jobs(const SearchJob *jobs, int n_jobs, i
         }
         const int pg = a.pat_base + pl;
         DecRes r = dec.decode(a.k_max);
-        my_iters += r.iters;
+        my_iters += r.run;
         my_dec += 1;
         int kc = -1, it_hi = 0, tm_hi = 0, it_lo = r.iters;
         if (r.fail) {
@@ -558,7 +611,7 @@ __device__ __forceinline__ void search_jobs(const SearchJob *jobs, int n_jobs, i
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
                 r = dec.decode(mid);
-                my_iters += r.iters;
+                my_iters += r.run;
                 my_dec += 1;
                 if (r.fail) {
                     hi = mid;
@@ -620,6 +673,9 @@ struct RegSearchDec {
         F.hist = (unsigned long long *)(frame + L.hist);
         F.wsyn = (int *)(frame + L.wsyn);
         F.pcnt = (int *)(frame + L.pcnt);
+        F.moved = (int *)(frame + L.moved);
+        F.vsave = J.a.gscr && J.a.fp_exit ? (int *)uni(J.a.gscr + (size_t)blockIdx.x * J.a.slot_bytes)
+                                          : nullptr;
         F.n = n;
         F.np = L.np;
         F.W = L.W;
@@ -644,6 +700,7 @@ struct RegSearchDec {
         for (int i = tid; i < F.T + 2; i += B) {
             F.wsyn[i] = 0;
             F.pcnt[i] = 0;
+            F.moved[i] = 0;
         }
         __syncthreads();
         return run_decode<Rule, DC, CPT>(F, nb, c2v, offset);
@@ -764,6 +821,7 @@ __device__ __forceinline__ DecRes run_decode_l(const Frame &F, const int (&nb)[C
     r.iters = iters;
     r.tmin = tmin;
     r.fail = F.pcnt[iters] > 0;
+    r.run = iters;
     return r;
 }
 
@@ -786,6 +844,8 @@ struct LayDec {
         F.hist = (unsigned long long *)(frame + L.hist);
         F.wsyn = (int *)(frame + L.wsyn);
         F.pcnt = (int *)(frame + L.pcnt);
+        F.moved = (int *)(frame + L.moved);
+        F.vsave = nullptr;
         F.n = n;
         F.np = L.np;
         F.W = L.W;
@@ -948,7 +1008,7 @@ __device__ __forceinline__ void is_jobs(const IsJob *jobs, int n_jobs, int *queu
         }
         const int f = it - (int)J.item0;
         const DecRes r = dec.decode_frame(f);
-        my_iters += r.iters;
+        my_iters += r.run;
         if (tid == 0) is_finish(J.a, f, r, dec.tn);
     }
     if (cur >= 0 && tid == 0) atomicAdd(&J.a.counters[1], my_iters);
@@ -972,6 +1032,9 @@ struct RegIsDec {
         F.hist = nullptr;
         F.wsyn = (int *)(frame + L.wsyn);
         F.pcnt = (int *)(frame + L.pcnt);
+        F.moved = (int *)(frame + L.moved);
+        F.vsave = J.a.gscr && J.a.fp_exit ? (int *)uni(J.a.gscr + (size_t)blockIdx.x * J.a.slot_bytes)
+                                          : nullptr;
         F.n = n;
         F.np = L.np;
         F.W = L.W;
@@ -998,6 +1061,7 @@ struct RegIsDec {
         for (int i = tid; i < F.T + 2; i += B) {
             F.wsyn[i] = 0;
             F.pcnt[i] = 0;
+            F.moved[i] = 0;
         }
         __syncthreads();
         return run_decode<SpaIsRule, DC, CPT>(F, nb, c2v, 0);
@@ -1261,6 +1325,7 @@ __device__ DecRes run_decode_g(const GFrame &F, int offset) {
     r.iters = iters;
     r.tmin = tmin;
     r.fail = F.pcnt[iters] > 0;
+    r.run = iters;
     return r;
 }
 
@@ -1563,7 +1628,9 @@ int plan_candidates(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter,
             p.dc = dc;
             p.lds = lds;
             p.grid = per_cu * ctx->num_cu;
-            p.slot_bytes = 0;
+            // save area of the messages for the fixed-point test (not used by
+            // the layered decoder)
+            p.slot_bytes = decoder == TS_DEC_LNMS_Q4 ? 0 : (size_t)block * cp * dc * 4;
             p.hist_off = 0;
             out->push_back(p);
         }
@@ -1672,14 +1739,13 @@ int launch_search(ts_exec &ex, const SearchPlan &plan0, const SearchLaunch &a) {
     j.a = a;
     j.cd = *a.code;
     j.item0 = 0;
-    if (plan.kind == kPlanStreamed) {
-        if (!a.gscr) {
-            set_error("streamed launch without scratch");
-            return TS_E_INVAL;
-        }
-        j.a.slot_bytes = (long long)plan.slot_bytes;
-        j.a.hist_off = (long long)plan.hist_off;
+    if (plan.kind == kPlanStreamed && !a.gscr) {
+        set_error("streamed launch without scratch");
+        return TS_E_INVAL;
     }
+    // register kind without scratch: no message save area (no fixed-point test)
+    j.a.slot_bytes = (long long)plan.slot_bytes;
+    j.a.hist_off = (long long)plan.hist_off;
     if (a.n_patterns <= 0) return TS_OK;
     void *dj = nullptr;
     int slot = -1;
@@ -1726,7 +1792,8 @@ int plan_is_candidates(ts_ctx *ctx, const ts_code *c, int max_iter, int layout,
             p.dc = dc;
             p.lds = lds;
             p.grid = per_cu * ctx->num_cu;
-            p.slot_bytes = p.hist_off = 0;
+            p.slot_bytes = (size_t)b * cp * dc * 4;   // save area of the messages
+            p.hist_off = 0;
             out->push_back(p);
         }
     }
@@ -1771,6 +1838,7 @@ IsDev make_is_dev(const IsLaunch &a, const SearchPlan &plan) {
     d.wf = a.wf;
     d.counters = a.counters;
     d.gscr = a.gscr;
+    d.fp_exit = a.fp_exit;
     d.slot_bytes = (long long)plan.slot_bytes;
     d.lam_off = (long long)plan.hist_off;
     return d;

@@ -228,12 +228,11 @@ int make_job(ts_ctx *ctx, const ts_job_desc *d, Job **out) {
         j->io = d->is;
         j->ts_bits.assign(d->ts_bits, d->ts_bits + d->a);
         j->est = (size_t)d->is.n_frames * 9 + (1 << 20);
-        std::vector<SearchPlan> ips;   // scratch of the largest streamed shape the autotuner may try
+        std::vector<SearchPlan> ips;   // scratch of the largest shape the autotuner may try
         size_t scr = 0;
         if (plan_is_candidates(ctx, d->code, d->is.max_iter, d->is.layout, &ips) == TS_OK)
             for (const SearchPlan &ip : ips)
-                if (ip.kind == kPlanStreamed)
-                    scr = std::max(scr, (size_t)std::min<int64_t>(ip.grid, d->is.n_frames) * ip.slot_bytes);
+                scr = std::max(scr, (size_t)std::min<int64_t>(ip.grid, d->is.n_frames) * ip.slot_bytes);
         j->est += scr;
     } else {
         delete j;

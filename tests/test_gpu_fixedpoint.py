@@ -1,0 +1,110 @@
+"""The fixed-point exit of the register-layout decoders: a decode whose check
+messages do not change in an iteration stops computing and fills in its
+remaining iterations (each repeats the last).  Every output must equal that of
+the same call with every iteration computed (full_iterations), bit for bit:
+per-pattern arrays, the TS table, IS estimates and failure flags; the exit
+must also actually fire (fewer computed edge-updates) where decodes fail.
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("k_crit", "iters_crit", "iters_lo", "tmin_crit", "n_cand")
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2208_05795_amd as tsg
+    c = tsg.Context(0)
+    yield c
+    c.close()
+
+
+def _search_both(ctx, code, pats, **kw):
+    out = []
+    for full in (True, False):
+        g = ctx.load_code(code)
+        r = g.impulse_search(pats, full_iterations=full, **kw)
+        recs, bits = g.collect_arrays()
+        out.append((r, recs, bits))
+        g.free()
+    return out
+
+
+def _assert_same(full, fast, label):
+    (r0, recs0, bits0), (r1, recs1, bits1) = full, fast
+    for k in KEYS:
+        assert np.array_equal(np.asarray(r0[k]), np.asarray(r1[k])), (label, k)
+    assert np.array_equal(recs0, recs1), label
+    assert np.array_equal(bits0, bits1), label
+    e0, e1 = r0["stats"]["edge_updates"], r1["stats"]["edge_updates"]
+    _say(f"{label}: identical; computed edge-updates {e0} full, {e1} with the exit "
+         f"({e1 / max(e0, 1):.3f})")
+    return e0, e1
+
+
+def test_spa_peg_exit_identical(ctx):
+    import paper_2208_05795_amd as tsg
+    code = workloads.peg1008_code()
+    g = ctx.load_code(code)
+    allp = g.pattern_list([tsg.PAT_SINGLES, tsg.PAT_PAIRS, tsg.PAT_TRIPLES])
+    g.free()
+    rng = np.random.default_rng(21)
+    pats = np.ascontiguousarray(allp[np.sort(rng.choice(len(allp), 4096, replace=False))])
+    kw = dict(decoder=tsg.DEC_SPA, max_iter=50, k_max=32 * 1024, k_den=1024, a_max=12,
+              layout=tsg.LAYOUT_REGISTER)
+    e0, e1 = _assert_same(*_search_both(ctx, code, pats, **kw), "peg SPA")
+    assert e1 < e0   # failing SPA decodes reach fixed points
+
+
+def test_spa_qc2640_exit_identical(ctx):
+    import paper_2208_05795_amd as tsg
+    code = workloads.qc2640_code()
+    g = ctx.load_code(code)
+    pats = g.make_patterns(tsg.PAT_TRIPLES | tsg.PAT_QC_ORBITS)
+    g.free()
+    kw = dict(decoder=tsg.DEC_SPA, max_iter=50, k_max=32 * 1024, k_den=1024, a_max=12,
+              layout=tsg.LAYOUT_REGISTER)
+    _assert_same(*_search_both(ctx, code, pats, **kw), "qc2640 SPA orbit representatives")
+
+
+@pytest.mark.parametrize("scale", [4.0, 1.2])
+def test_oms_exit_identical(ctx, scale):
+    import paper_2208_05795_amd as tsg
+    code = workloads.peg1008_code()
+    g = ctx.load_code(code)
+    pats = g.pattern_list([tsg.PAT_SINGLES, tsg.PAT_PAIRS])
+    g.free()
+    kw = dict(decoder=tsg.DEC_OMS, max_iter=20, llr_scale=scale, a_max=12,
+              layout=tsg.LAYOUT_REGISTER)
+    _assert_same(*_search_both(ctx, code, pats, **kw), f"peg OMS scale {scale}")
+
+
+def test_is_exit_identical(ctx):
+    import paper_2208_05795_amd as tsg
+    code = workloads.peg1008_code()
+    g = ctx.load_code(code)
+    g.impulse_search(g.pattern_list([tsg.PAT_SINGLES, tsg.PAT_PAIRS])[:2048], decoder=tsg.DEC_SPA,
+                     max_iter=50, k_max=32 * 1024, k_den=1024, a_max=12)
+    ts = g.collect()
+    assert ts
+    bits = list(ts[0].bits)
+    res = []
+    for full in (True, False):
+        r = g.is_estimate(bits, 3.0, -1.0, 8192, seed=5, want_fail=True,
+                          layout=tsg.LAYOUT_REGISTER, full_iterations=full)
+        res.append(r)
+    g.free()
+    a, b = res
+    assert np.array_equal(a["fail"], b["fail"])
+    for k in ("p_hat", "var", "sum_w", "sum_w2", "n_fail", "shift_used"):
+        assert a[k] == b[k], k
+    _say(f"IS: identical; computed edge-updates {a['stats']['edge_updates']} full, "
+         f"{b['stats']['edge_updates']} with the exit")
