@@ -452,13 +452,19 @@ __device__ __forceinline__ DecRes run_decode(const Frame &F, const int (&nb)[CPT
 // Writes the candidate error sets U_t = S(x_t) u I, t = t0..iters, of one
 // failing decode to the record buffer (wavefront 0; consecutive equal sets are
 // merged into one record with a multiplicity).
+// Iterations after `run` repeat iteration `run` (fixed-point exit): once the
+// previous iteration was one of them, the rest only add to the multiplicity.
 __device__ void write_candidates(const SearchLaunch &a, const unsigned long long *hist,
-                                 const unsigned long long *imask, int W, int iters,
+                                 const unsigned long long *imask, int W, int iters, int run,
                                  int pg, int k) {
     if (threadIdx.x < 64) {
         const int lane = lane_id();
         int last = -1, mult = 0;
         for (int t = a.t0; t <= iters; ++t) {
+            if (t > run && t > a.t0) {   // set(t) = set(t - 1) from here to iters
+                if (last >= 0) mult += iters - t + 1;
+                break;
+            }
             const unsigned long long *h = hist + (size_t)(t - 1) * W;
             int cnt = 0;
             for (int i = lane; i < W; i += 64) cnt += __popcll(h[i] | imask[i]);
@@ -603,7 +609,7 @@ __device__ __forceinline__ void search_jobs(const SearchJob *jobs, int n_jobs, i
         my_dec += 1;
         int kc = -1, it_hi = 0, tm_hi = 0, it_lo = r.iters;
         if (r.fail) {
-            write_candidates(a, dec.hist(), imask, W, r.iters, pg, a.k_max);
+            write_candidates(a, dec.hist(), imask, W, r.iters, r.run, pg, a.k_max);
             int lo = 0, hi = a.k_max;
             it_hi = r.iters;
             tm_hi = r.tmin;
@@ -617,7 +623,7 @@ __device__ __forceinline__ void search_jobs(const SearchJob *jobs, int n_jobs, i
                     hi = mid;
                     it_hi = r.iters;
                     tm_hi = r.tmin;
-                    write_candidates(a, dec.hist(), imask, W, r.iters, pg, mid);
+                    write_candidates(a, dec.hist(), imask, W, r.iters, r.run, pg, mid);
                 } else {
                     lo = mid;
                     it_lo = r.iters;
