@@ -182,11 +182,12 @@ static float tune_score(const SearchPlan &p, float ms) { return p.kind == kPlanS
 
 static int tune_shape(ts_exec &ex, const std::vector<SearchPlan> &cands,
                       const SearchLaunch &base, int64_t P, SearchPlan *best) {
-    // the probe: four patterns per workgroup of the widest shape, taken at an
-    // even stride over the whole list (pattern lists are ordered by kind, and
-    // decode lengths differ between kinds)
+    // the probe: sixteen patterns per workgroup of the widest shape (fewer let
+    // the tail of a few long bisections decide), taken at an even stride over
+    // the whole list (pattern lists are ordered by kind, and decode lengths
+    // differ between kinds)
     int64_t probe = 0;
-    for (const SearchPlan &p : cands) probe = std::max<int64_t>(probe, 4 * (int64_t)p.grid);
+    for (const SearchPlan &p : cands) probe = std::max<int64_t>(probe, 16 * (int64_t)p.grid);
     probe = std::min(probe, P);
     const bool strided = probe < P;
     DBuf sample(ex, strided ? (size_t)probe * base.width * 4 : 0);
