@@ -206,6 +206,8 @@ static int tune_shape(ts_exec &ex, const std::vector<SearchPlan> &cands,
     for (const SearchPlan &p : cands) {
         float ms_min = 0.0f;
         for (int rep = 0; rep < 2; ++rep) {   // the faster of two timings
+            // a shape already 1.5x slower than the best needs no second timing
+            if (rep == 1 && best_ms > 0.0f && tune_score(p, ms_min) > 1.5f * best_ms) break;
             SearchLaunch a = base;
             a.t0 = a.max_iter + 1;   // no candidate is written while timing
             a.patterns = pat;
