@@ -427,18 +427,10 @@ __device__ __forceinline__ DecRes run_decode(const Frame &F, const int (&nb)[CPT
     if (fixed) {
         // No check message changed in iteration t = fixed (padded edges carry
         // none), so APP_t = APP_{t-1} and every later iteration repeats
-        // iteration t - 1: its records stand for iterations t..T, and the
-        // decode ends at T as if run to the end.
-        const int t = fixed, w = F.wsyn[t - 1], pc = F.pcnt[t - 1];
-        for (int i = tid; i <= T - t; i += B) {
-            F.wsyn[t + i] = w;
-            F.pcnt[t + i] = pc;
-        }
-        if (F.hist) {
-            const unsigned long long *src = F.hist + (size_t)(t - 2) * W;
-            unsigned long long *dst = F.hist + (size_t)(t - 1) * W;
-            for (int i = tid; i < (T - t + 1) * W; i += B) dst[i] = src[i % W];
-        }
+        // iteration t - 1 = run: the decode ends at T as if run to the end.
+        // Of the records after run only the number of 1s at T is read here;
+        // the candidate writer reads history row run for the later ones.
+        if (tid == 0) F.pcnt[T] = F.pcnt[fixed - 1];
         __syncthreads();
     }
     DecRes r;
@@ -452,8 +444,9 @@ __device__ __forceinline__ DecRes run_decode(const Frame &F, const int (&nb)[CPT
 // Writes the candidate error sets U_t = S(x_t) u I, t = t0..iters, of one
 // failing decode to the record buffer (wavefront 0; consecutive equal sets are
 // merged into one record with a multiplicity).
-// Iterations after `run` repeat iteration `run` (fixed-point exit): once the
-// previous iteration was one of them, the rest only add to the multiplicity.
+// Iterations after `run` repeat iteration `run` (fixed-point exit; their
+// history rows are not written, row `run` stands for them): once the previous
+// iteration was one of them, the rest only add to the multiplicity.
 __device__ void write_candidates(const SearchLaunch &a, const unsigned long long *hist,
                                  const unsigned long long *imask, int W, int iters, int run,
                                  int pg, int k) {
@@ -465,7 +458,7 @@ __device__ void write_candidates(const SearchLaunch &a, const unsigned long long
                 if (last >= 0) mult += iters - t + 1;
                 break;
             }
-            const unsigned long long *h = hist + (size_t)(t - 1) * W;
+            const unsigned long long *h = hist + (size_t)((t < run ? t : run) - 1) * W;
             int cnt = 0;
             for (int i = lane; i < W; i += 64) cnt += __popcll(h[i] | imask[i]);
             cnt = wave_sum(cnt);
