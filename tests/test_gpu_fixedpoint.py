@@ -108,3 +108,45 @@ def test_is_exit_identical(ctx):
         assert a[k] == b[k], k
     _say(f"IS: identical; computed edge-updates {a['stats']['edge_updates']} full, "
          f"{b['stats']['edge_updates']} with the exit")
+
+
+def test_batch_exit_identical(ctx):
+    """Batched search and IS jobs (shared persistent launches, one scratch arena
+    per shape group) give the same outputs with and without the exit."""
+    import paper_2208_05795_amd as tsg
+    peg = ctx.load_code(workloads.peg1008_code())
+    qc = ctx.load_code(workloads.qc2640_code())
+    rng = np.random.default_rng(4)
+    allp = peg.pattern_list([tsg.PAT_PAIRS, tsg.PAT_TRIPLES])
+    pp = np.ascontiguousarray(allp[np.sort(rng.choice(len(allp), 2048, replace=False))])
+    qp = qc.make_patterns(tsg.PAT_TRIPLES | tsg.PAT_QC_ORBITS)
+    spa = dict(decoder=tsg.DEC_SPA, max_iter=50, k_max=32 * 1024, k_den=1024, a_max=12)
+    peg.impulse_search(pp[:512], **spa)
+    bits = list(peg.collect()[0].bits)
+    outs = []
+    for full in (True, False):
+        jobs = [("search", peg, pp, dict(spa, full_iterations=full)),
+                ("search", qc, qp, dict(spa, full_iterations=full)),
+                ("is", peg, bits, dict(ebn0_db=3.0, shift=-1.0, n_frames=4096, seed=9,
+                                       full_iterations=full))]
+        ids = ctx.run_batch(jobs)
+        res = []
+        for j in ids:
+            info = ctx.poll(j)
+            if info["n_patterns"]:
+                o = ctx.job_outputs(j, arrays=True)
+                res.append(({k: np.asarray(o[k]) for k in KEYS}, o["ts_recs"], o["ts_bits"]))
+            else:
+                res.append(info["is"])
+            ctx.release(j)
+        outs.append(res)
+    for a, b in zip(*outs):
+        if isinstance(a, dict):
+            assert a == b
+        else:
+            for k in KEYS:
+                assert np.array_equal(a[0][k], b[0][k]), k
+            assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    _say("batch: identical with and without the exit")
+    peg.free()
+    qc.free()
