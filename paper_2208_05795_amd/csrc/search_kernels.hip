@@ -748,12 +748,23 @@ __device__ __forceinline__ DecRes run_decode_l(const Frame &F, const int (&nb)[C
     const int B = blockDim.x, NW = B >> 6;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     int *A = F.app;
+    int *S = F.app + F.np;   // APP at the start of a verifying sweep (LDS slot 1)
 #pragma unroll
     for (int c = 0; c < CPT; ++c)
 #pragma unroll
         for (int j = 0; j < DC; ++j) c2v[c][j] = 0;
-    int iters = T, wmin = INT_MAX, tmin = 0;
+    int iters = T, wmin = INT_MAX, tmin = 0, fixed = 0;
+    bool verify = false;   // sweep t compares its end state with its start state
     for (int t = 1; t <= T; ++t) {
+        if (verify) {
+            int *vs = F.vsave + (unsigned)tid * (CPT * DC);
+#pragma unroll
+            for (int c = 0; c < CPT; ++c)
+#pragma unroll
+                for (int j = 0; j < DC; ++j) vs[c * DC + j] = c2v[c][j];
+            for (int v = tid; v < F.np; v += B) S[v] = A[v];
+            __syncthreads();   // the snapshot is complete before layer 0 writes A
+        }
         for (int L = 0; L < n_layers; ++L) {
 #pragma unroll
             for (int c = 0; c < CPT; ++c) {
@@ -805,6 +816,17 @@ __device__ __forceinline__ DecRes run_decode_l(const Frame &F, const int (&nb)[C
             pc += __popcll(mask);
         }
         if (lane == 0 && pc) atomicAdd(&F.pcnt[t], pc);
+        if (verify) {
+            const int *vs = F.vsave + (unsigned)tid * (CPT * DC);
+            unsigned chg = 0;   // padded edges carry nothing, so they are skipped
+#pragma unroll
+            for (int c = 0; c < CPT; ++c)
+#pragma unroll
+                for (int j = 0; j < DC; ++j)
+                    if (nb[c][j] != n) chg |= (unsigned)(c2v[c][j] ^ vs[c * DC + j]);
+            for (int v = tid; v < n; v += B) chg |= (unsigned)(A[v] ^ S[v]);
+            if (__any(chg != 0u) && lane == 0) atomicOr(&F.moved[t], 1);
+        }
         __syncthreads();
         const int w = F.wsyn[t];
         if (w < wmin) {
@@ -815,12 +837,24 @@ __device__ __forceinline__ DecRes run_decode_l(const Frame &F, const int (&nb)[C
             iters = t;
             break;
         }
+        if (verify && F.moved[t] == 0) {
+            // the sweep left every check message and APP value as it found
+            // them: every later sweep repeats it (the decode ends at T)
+            fixed = t;
+            break;
+        }
+        // syndrome weight and number of 1s unchanged: check the next sweep
+        verify = F.vsave && t >= 2 && t < T && w == F.wsyn[t - 1] && F.pcnt[t] == F.pcnt[t - 1];
+    }
+    if (fixed) {
+        if (tid == 0) F.pcnt[T] = F.pcnt[fixed];
+        __syncthreads();
     }
     DecRes r;
     r.iters = iters;
     r.tmin = tmin;
     r.fail = F.pcnt[iters] > 0;
-    r.run = iters;
+    r.run = fixed ? fixed : iters;
     return r;
 }
 
@@ -844,7 +878,8 @@ struct LayDec {
         F.wsyn = (int *)(frame + L.wsyn);
         F.pcnt = (int *)(frame + L.pcnt);
         F.moved = (int *)(frame + L.moved);
-        F.vsave = nullptr;
+        F.vsave = J.a.gscr && J.a.fp_exit ? (int *)uni(J.a.gscr + (size_t)blockIdx.x * J.a.slot_bytes)
+                                          : nullptr;
         F.n = n;
         F.np = L.np;
         F.W = L.W;
@@ -873,6 +908,7 @@ struct LayDec {
         for (int i = tid; i < F.T + 2; i += B) {
             F.wsyn[i] = 0;
             F.pcnt[i] = 0;
+            F.moved[i] = 0;
         }
         __syncthreads();
         return run_decode_l<DC, CPT>(F, nb, lay, n_layers, c2v);
@@ -880,9 +916,16 @@ struct LayDec {
     __device__ __forceinline__ const unsigned long long *hist() const { return F.hist; }
 };
 
+// Occupancy the layered kernels keep with the fixed-point test's registers.
 template <int DC, int CPT>
-__global__ __launch_bounds__((MaxBlock<DC, CPT>::value)) void k_search_l(const SearchJob *jobs, int n_jobs,
-                                                                        int *queue, long long n_items) {
+struct LayWaves {
+    static constexpr int value = (DC == 6 && CPT == 1) ? 6 : (DC == 6 && CPT == 2) ? 5 : 1;
+};
+
+template <int DC, int CPT>
+__global__ __launch_bounds__((MaxBlock<DC, CPT>::value))
+__attribute__((amdgpu_waves_per_eu(LayWaves<DC, CPT>::value))) void k_search_l(const SearchJob *jobs, int n_jobs,
+                                                                       int *queue, long long n_items) {
     extern __shared__ __align__(16) unsigned char smem[];
     LayDec<DC, CPT> dec;
     search_jobs(jobs, n_jobs, queue, n_items, dec, smem);
@@ -1627,9 +1670,7 @@ int plan_candidates(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter,
             p.dc = dc;
             p.lds = lds;
             p.grid = per_cu * ctx->num_cu;
-            // save area of the messages for the fixed-point test (not used by
-            // the layered decoder)
-            p.slot_bytes = decoder == TS_DEC_LNMS_Q4 ? 0 : (size_t)block * cp * dc * 4;
+            p.slot_bytes = (size_t)block * cp * dc * 4;   // message save area (fixed-point test)
             p.hist_off = 0;
             out->push_back(p);
         }

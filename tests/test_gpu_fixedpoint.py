@@ -87,6 +87,23 @@ def test_oms_exit_identical(ctx, scale):
     _assert_same(*_search_both(ctx, code, pats, **kw), f"peg OMS scale {scale}")
 
 
+@pytest.mark.parametrize("which", ["peg", "qc2640"])
+def test_lnms_exit_identical(ctx, which):
+    """The layered decoder's exit (a sweep that leaves every message and APP
+    value unchanged), at a weak channel scale where every impulse fails."""
+    import paper_2208_05795_amd as tsg
+    code = workloads.peg1008_code() if which == "peg" else workloads.qc2640_code()
+    g = ctx.load_code(code)
+    if which == "peg":
+        pats = g.pattern_list([tsg.PAT_SINGLES, tsg.PAT_PAIRS])
+    else:
+        pats = g.make_patterns(tsg.PAT_TRIPLES)[::8]
+    g.free()
+    kw = dict(decoder=tsg.DEC_LNMS, max_iter=20, llr_scale=0.3, k_max=512, k_den=16, a_max=12)
+    e0, e1 = _assert_same(*_search_both(ctx, code, pats, **kw), f"{which} layered min-sum x0.3")
+    assert e1 <= e0
+
+
 def test_is_exit_identical(ctx):
     import paper_2208_05795_amd as tsg
     code = workloads.peg1008_code()

@@ -57,7 +57,10 @@ def test_lnms_search_bit_exact(ctx, oracle_mod, name, kinds, sample, iters, snr,
             bad = np.nonzero(np.asarray(got[k]) != ref[k])[0]
             raise AssertionError(f"{k} differs at {bad[:8]}: {np.asarray(got[k])[bad[:8]]} vs {ref[k][bad[:8]]}")
     assert _ts(g.collect()) == _ts(ref["ts"])
-    assert got["stats"]["edge_updates"] == ref["edge_updates"]
+    # the oracle computes every iteration; the fixed-point exit computes fewer
+    assert got["stats"]["edge_updates"] <= ref["edge_updates"]
+    full = g.impulse_search(pats, decoder=tsg.DEC_LNMS, full_iterations=True, **kw)
+    assert full["stats"]["edge_updates"] == ref["edge_updates"]
     _say(f"{name} layered min-sum, {len(pats)} patterns, {iters} it, {snr} dB x {scale}: bit-exact; "
          f"{(ref['k_crit'] >= 0).sum()} failing, {int(ref['n_cand'].sum())} candidates, "
          f"{len(ref['ts'])} TS")

@@ -71,8 +71,11 @@ def test_tiny_full_search_bit_exact(ctx, oracle_mod, tiny, tiny_search):
     got = g.impulse_search(pats, a_max=6)
     _same(got, ref)
     assert _ts(g.collect()) == _ts(ref["ts"])
-    assert got["stats"]["edge_updates"] == ref["edge_updates"]
+    # the oracle computes every iteration; the fixed-point exit may compute fewer
+    assert got["stats"]["edge_updates"] <= ref["edge_updates"]
     assert got["stats"]["decodes"] == ref["decodes"]
+    full = g.impulse_search(pats, a_max=6, full_iterations=True)
+    assert full["stats"]["edge_updates"] == ref["edge_updates"]
     g.free()
 
 

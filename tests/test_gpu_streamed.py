@@ -79,7 +79,8 @@ def test_layouts_identical_oms(ctx, oracle_mod, name):
     for r, t, st, lab in ((rb, tb, sb, "gather"), (rc, tc, sc, "accum")):
         _same(ra, r, f"{name} {lab}")
         assert ta == t
-        assert sa["edge_updates"] == st["edge_updates"] and sa["decodes"] == st["decodes"]
+        # the register layout's fixed-point exit may compute fewer iterations
+        assert sa["edge_updates"] <= st["edge_updates"] and sa["decodes"] == st["decodes"]
     _say(f"  identical: {len(ta)} TS, {sa['edge_updates']:.3e} edge-updates; decode ms register "
          f"{sa['decode_ms']:.2f} streamed gather {sb['decode_ms']:.2f} accum {sc['decode_ms']:.2f}")
     g.free()
@@ -175,7 +176,7 @@ def test_serving_code_oms_vs_oracle(ctx, oracle_mod, pool, which):
             for k in KEYS:
                 assert np.array_equal(np.asarray(got[k]), ref[k]), (lay, k)
             assert _ts(g.collect()) == _ts(ref["ts"])
-            assert got["stats"]["edge_updates"] == ref["edge_updates"]
+            assert got["stats"]["edge_updates"] <= ref["edge_updates"]   # fixed-point exit
         _say(f"  bit-exact ({len(layouts)} layouts); {len(ref['ts'])} TS, "
              f"failing patterns {(ref['k_crit'] >= 0).sum()}")
     g.free()
