@@ -182,32 +182,36 @@ static float tune_score(const SearchPlan &p, float ms) { return p.kind == kPlanS
 
 static int tune_shape(ts_exec &ex, const std::vector<SearchPlan> &cands,
                       const SearchLaunch &base, int64_t P, SearchPlan *best) {
-    // the probe: sixteen patterns per workgroup of the widest shape (fewer let
-    // the tail of a few long bisections decide), taken at an even stride over
-    // the whole list (pattern lists are ordered by kind, and decode lengths
-    // differ between kinds)
-    int64_t probe = 0;
-    for (const SearchPlan &p : cands) probe = std::max<int64_t>(probe, 16 * (int64_t)p.grid);
-    probe = std::min(probe, P);
-    const bool strided = probe < P;
-    DBuf sample(ex, strided ? (size_t)probe * base.width * 4 : 0);
-    const int *pat = base.patterns;
-    if (strided) {
-        if (!sample.p) {
-            set_error("device allocation of the tuning probe failed");
-            return TS_E_NOMEM;
-        }
-        const size_t row = (size_t)base.width * 4;
-        TSG_HIP(hipMemcpy2DAsync(sample.p, row, base.patterns, (size_t)(P / probe) * row, row, (size_t)probe,
-                                 hipMemcpyDeviceToDevice, ex.stream));
-        pat = sample.as<int>();
+    // each shape's probe: sixteen patterns per workgroup of that shape (fewer
+    // let the tail of a few long bisections decide), taken at an even stride
+    // over the whole list (pattern lists are ordered by kind, and decode
+    // lengths differ between kinds); shapes are compared by time per pattern
+    int64_t probe_max = 0;
+    for (const SearchPlan &p : cands) probe_max = std::max<int64_t>(probe_max, 16 * (int64_t)p.grid);
+    probe_max = std::min(probe_max, P);
+    DBuf sample(ex, probe_max < P ? (size_t)probe_max * base.width * 4 : 0);
+    if (probe_max < P && !sample.p) {
+        set_error("device allocation of the tuning probe failed");
+        return TS_E_NOMEM;
     }
-    float best_ms = 0.0f;
+    const size_t row = (size_t)base.width * 4;
+    int64_t sampled = 0;   // probe size the sample buffer holds
+    float best_ms = 0.0f;  // best score per pattern
     for (const SearchPlan &p : cands) {
+        const int64_t probe = std::min<int64_t>(16 * (int64_t)p.grid, P);
+        const int *pat = base.patterns;
+        if (probe < P) {
+            if (sampled != probe) {
+                TSG_HIP(hipMemcpy2DAsync(sample.p, row, base.patterns, (size_t)(P / probe) * row, row,
+                                         (size_t)probe, hipMemcpyDeviceToDevice, ex.stream));
+                sampled = probe;
+            }
+            pat = sample.as<int>();
+        }
         float ms_min = 0.0f;
         for (int rep = 0; rep < 2; ++rep) {   // the faster of two timings
             // a shape already 1.5x slower than the best needs no second timing
-            if (rep == 1 && best_ms > 0.0f && tune_score(p, ms_min) > 1.5f * best_ms) break;
+            if (rep == 1 && best_ms > 0.0f && tune_score(p, ms_min) / (float)probe > 1.5f * best_ms) break;
             SearchLaunch a = base;
             a.t0 = a.max_iter + 1;   // no candidate is written while timing
             a.patterns = pat;
@@ -224,7 +228,7 @@ static int tune_shape(ts_exec &ex, const std::vector<SearchPlan> &cands,
             TSG_HIP(hipEventElapsedTime(&ms, ex.ev[0], ex.ev[1]));
             if (rep == 0 || ms < ms_min) ms_min = ms;
         }
-        const float score = tune_score(p, ms_min);
+        const float score = tune_score(p, ms_min) / (float)probe;
         if (best_ms == 0.0f || score < best_ms) {
             best_ms = score;
             *best = p;
