@@ -389,7 +389,8 @@ typedef struct {
     double extract_ms;       /* same for the sieve/canonicalise/insert kernels */
     double total_ms;         /* the whole call on the stream */
     int64_t decodes;         /* decodes executed */
-    int64_t edge_updates;    /* sum over decodes of iterations x edges */
+    int64_t edge_updates;    /* sum over decodes of computed iterations x edges (iterations
+                              * filled in after a fixed point are not counted) */
     int64_t candidates;      /* raw candidate error sets written */
     int32_t decode_launches;
     int32_t extract_launches;
