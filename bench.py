@@ -110,17 +110,18 @@ def main():
         rec = {}
         c.reset_ts()
         r = c.impulse_search(pats, **oms_kw)
-        ts_oms = c.collect()
+        ts_oms, _ = c.collect_arrays()   # the TS table as arrays (no per-set objects)
         rec["oms"] = r["stats"]
         c.reset_ts()
         r = c.impulse_search(pats, **spa_kw)
-        ts_spa = c.collect()
+        ts_spa, spa_bits = c.collect_arrays()
         rec["spa"] = r["stats"]
         rec["spa_out"] = {k: r[k] for k in ("k_crit", "iters_crit", "iters_lo", "tmin_crit", "n_cand")}
         # IS of the most harmful sets as one batch (their eps* shifts from one
         # search launch, their frames in one persistent launch)
-        jobs = [("is", c, list(t.bits), dict(ebn0_db=3.0, shift=-1.0, n_frames=args.is_frames, seed=7,
-                                             max_iter=50)) for t in ts_spa[:n_is]]
+        jobs = [("is", c, spa_bits[t["bits_off"]:t["bits_off"] + t["a"]],
+                 dict(ebn0_db=3.0, shift=-1.0, n_frames=args.is_frames, seed=7, max_iter=50))
+                for t in ts_spa[:n_is]]
         ids = ctx.run_batch(jobs)
         st = ctx.stats()
         infos = [ctx.poll(j) for j in ids]

@@ -74,9 +74,12 @@ _REC_DTYPE = np.dtype([("a", np.int32), ("b", np.int32), ("orbit", np.int32),
 
 
 def _ts_records(recs: np.ndarray, bits: np.ndarray) -> List[TsRecord]:
-    return [TsRecord(int(r["a"]), int(r["b"]), int(r["orbit"]), int(r["first_pattern"]),
-                     int(r["k_crit"]), tuple(int(x) for x in bits[r["bits_off"]:r["bits_off"] + r["a"]]))
-            for r in recs]
+    # whole columns to Python lists first (per-row field access is slow)
+    a, b, orb = recs["a"].tolist(), recs["b"].tolist(), recs["orbit"].tolist()
+    fp, kc, off = recs["first_pattern"].tolist(), recs["k_crit"].tolist(), recs["bits_off"].tolist()
+    bl = np.asarray(bits).tolist()
+    return [TsRecord(a[i], b[i], orb[i], fp[i], kc[i], tuple(bl[off[i]:off[i] + a[i]]))
+            for i in range(len(a))]
 
 
 class Context:

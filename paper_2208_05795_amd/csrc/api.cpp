@@ -783,6 +783,19 @@ void exec_fini(ts_exec &ex) {
 namespace tsg {
 int exec_create(ts_exec &ex, ts_ctx *ctx) { return exec_init(ex, ctx, nullptr, true); }
 void exec_destroy(ts_exec &ex) { exec_fini(ex); }
+int table_readout(ts_ctx *ctx, const ts_code *code, const std::vector<int32_t> **recs,
+                  const std::vector<int32_t> **bits) {
+    if (code->readout_version != code->table_version) {
+        code->readout_version = ~0ull;
+        const int rc = collect_table(ctx->main, code->table, code->readout_recs, code->readout_bits);
+        if (rc) return rc;
+        code->readout_version = code->table_version;
+    }
+    *recs = &code->readout_recs;
+    *bits = &code->readout_bits;
+    return TS_OK;
+}
+
 }  // namespace tsg
 
 extern "C" {
@@ -938,6 +951,7 @@ int ts_reset_ts(ts_ctx *ctx, ts_code *code) {
     if (code->ctx != ctx) { set_error("code belongs to another context"); return TS_E_STATE; }
     (void)hipStreamSynchronize(ctx->main.stream);
     table_free(ctx->main, code->table);
+    ++code->table_version;
     return TS_OK;
 }
 
@@ -951,6 +965,7 @@ int ts_impulse_search(ts_ctx *ctx, ts_code *code, const ts_search_opts *o, const
     ex.stats = ts_stats{};
     int rc = check_search_opts(code, o, width);
     if (rc) return rc;
+    ++code->table_version;   // the search may add sets to the table
     if (n_patterns < 0) { set_error("negative pattern count"); return TS_E_INVAL; }
     if (n_patterns == 0) return TS_OK;
     if (!patterns || !out->k_crit || !out->iters_crit || !out->iters_lo || !out->tmin_crit || !out->n_cand) {
@@ -995,9 +1010,10 @@ int ts_collect(ts_ctx *ctx, const ts_code *code, ts_record *recs, int64_t cap, i
     if (!ctx || !code || !n_out || !bits_out) { set_error("null argument"); return TS_E_INVAL; }
     std::lock_guard<std::recursive_mutex> g(ctx->mu);
     if (code->ctx != ctx) { set_error("code belongs to another context"); return TS_E_STATE; }
-    std::vector<int32_t> rh, bh;
-    int rc = collect_table(ctx->main, code->table, rh, bh);
+    const std::vector<int32_t> *rp = nullptr, *bp = nullptr;
+    int rc = table_readout(ctx, code, &rp, &bp);
     if (rc) return rc;
+    const std::vector<int32_t> &rh = *rp, &bh = *bp;
     const int64_t n = (int64_t)rh.size() / 5;
     *n_out = n;
     *bits_out = (int64_t)bh.size();

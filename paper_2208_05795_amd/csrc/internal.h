@@ -232,6 +232,10 @@ struct ts_code {
     tsg::DevCode dev{};
     std::vector<void *> dev_allocs;
     tsg::DevTable table{};          // the code's TS table (synchronous calls)
+    // ordered read-out of the table, kept until a call may change the table
+    uint64_t table_version = 0;
+    mutable uint64_t readout_version = ~0ull;
+    mutable std::vector<int32_t> readout_recs, readout_bits;
     std::atomic<int> jobs_in_flight{0};
     // launch shapes chosen by the autotuner, keyed by (decoder, max_iter)
     std::mutex tune_mu;
@@ -253,6 +257,10 @@ void table_free(ts_exec &ex, DevTable &t);
 int table_grow_if_needed(ts_exec &ex, DevTable &t, int64_t incoming);
 int collect_table(ts_exec &ex, const DevTable &t, std::vector<int32_t> &rec_host,
                   std::vector<int32_t> &bits_host);
+// The code's table in order (collect_table), read again only after a call that
+// may have changed it.  Caller holds ctx->mu.
+int table_readout(ts_ctx *ctx, const ts_code *code, const std::vector<int32_t> **recs,
+                  const std::vector<int32_t> **bits);
 size_t table_bytes(int cap);
 
 // search (search_kernels.hip)

@@ -19,9 +19,10 @@ int ts_spectrum(ts_ctx *ctx, const ts_code *code, int32_t a_max, int32_t b_max, 
     if (a_max < 1 || a_max > kMaxAmax || b_max < 0 || b_max > 1024) { set_error("a_max must be 1..%d, b_max 0..1024", kMaxAmax); return TS_E_INVAL; }
     std::lock_guard<std::recursive_mutex> g(ctx->mu);
     if (code->ctx != ctx) { set_error("code belongs to another context"); return TS_E_STATE; }
-    std::vector<int32_t> rh, bh;
-    const int rc = collect_table(ctx->main, code->table, rh, bh);
+    const std::vector<int32_t> *rp = nullptr, *bp = nullptr;
+    const int rc = table_readout(ctx, code, &rp, &bp);
     if (rc) return rc;
+    const std::vector<int32_t> &rh = *rp;
     std::memset(counts, 0, sizeof(int64_t) * (size_t)(a_max + 1) * (b_max + 1));
     for (size_t i = 0; i + 4 < rh.size(); i += 5) {
         const int a = rh[i], b = rh[i + 1], orbit = rh[i + 2];
@@ -41,9 +42,10 @@ int ts_union_bound(ts_ctx *ctx, ts_code *code, const ts_ub_opts *o, ts_ub_point 
     }
     std::lock_guard<std::recursive_mutex> g(ctx->mu);
     if (code->ctx != ctx) { set_error("code belongs to another context"); return TS_E_STATE; }
-    std::vector<int32_t> rh, bh;
-    int rc = collect_table(ctx->main, code->table, rh, bh);
+    const std::vector<int32_t> *rp = nullptr, *bp = nullptr;
+    int rc = table_readout(ctx, code, &rp, &bp);
     if (rc) return rc;
+    const std::vector<int32_t> rh = *rp, bh = *bp;   // copies: the jobs point into them
     const int n_avail = (int)(rh.size() / 5);
     if (n_avail < o->n_ts) {
         set_error("the code's TS table holds %d sets, %d requested", n_avail, o->n_ts);
