@@ -352,7 +352,12 @@ struct IsJob {
 };
 
 constexpr size_t kJobLds = ((sizeof(SearchJob) > sizeof(IsJob) ? sizeof(SearchJob) : sizeof(IsJob)) + 15) & ~(size_t)15;
-constexpr size_t kShLds = 32 * 4;
+// Scratch words of the job header: 32 words, then (search kernels) a staging
+// list and the per-pattern cache of candidate sets already recorded
+// (kDedupSets entries: record index, size, amplitude index, spare, variables).
+constexpr int kDedupSets = 2;
+constexpr int kDedupStride = 4 + kCapMax;
+constexpr size_t kShLds = (32 + kCapMax + kDedupSets * kDedupStride) * 4;
 constexpr size_t kHdrLds = kJobLds + kShLds;
 
 // importance sampling

@@ -442,20 +442,35 @@ __device__ __forceinline__ DecRes run_decode(const Frame &F, const int (&nb)[CPT
 }
 
 // Writes the candidate error sets U_t = S(x_t) u I, t = t0..iters, of one
-// failing decode to the record buffer (wavefront 0; consecutive equal sets are
-// merged into one record with a multiplicity).
+// failing decode to the record buffer (wavefront 0).  A record carries a
+// multiplicity: consecutive equal sets share one record, and so does a set
+// equal to one of the last kDedupSets sets recorded for the same pattern (in
+// any of its decodes; in the critical extraction mode only at the same
+// amplitude index), whose record then gains the multiplicity.  The sieve
+// weighs each record by its multiplicity, so the outcome is that of one record
+// per iteration.  dd: staging list and the pattern's cache (header scratch).
 // Iterations after `run` repeat iteration `run` (fixed-point exit; their
 // history rows are not written, row `run` stands for them): once the previous
 // iteration was one of them, the rest only add to the multiplicity.
 __device__ void write_candidates(const SearchLaunch &a, const unsigned long long *hist,
                                  const unsigned long long *imask, int W, int iters, int run,
-                                 int pg, int k) {
+                                 int pg, int k, int *dd) {
     if (threadIdx.x < 64) {
         const int lane = lane_id();
-        int last = -1, mult = 0;
+        int *stage = dd;
+        int *cache = dd + kCapMax;
+        // last >= 0: the current run's own record; -2: merged into record
+        // `into`; -1: no record
+        int last = -1, into = -1, mult = 0;
+        auto finish = [&]() {
+            if (lane == 0) {
+                if (last >= 0) a.recs[(size_t)last * kRecStride + 3] = mult;
+                else if (last == -2) atomicAdd(&a.recs[(size_t)into * kRecStride + 3], mult);
+            }
+        };
         for (int t = a.t0; t <= iters; ++t) {
             if (t > run && t > a.t0) {   // set(t) = set(t - 1) from here to iters
-                if (last >= 0) mult += iters - t + 1;
+                if (last != -1) mult += iters - t + 1;
                 break;
             }
             const unsigned long long *h = hist + (size_t)((t < run ? t : run) - 1) * W;
@@ -463,11 +478,11 @@ __device__ void write_candidates(const SearchLaunch &a, const unsigned long long
             for (int i = lane; i < W; i += 64) cnt += __popcll(h[i] | imask[i]);
             cnt = wave_sum(cnt);
             if (cnt > a.cap) {
-                if (last >= 0 && lane == 0) a.recs[(size_t)last * kRecStride + 3] = mult;
+                finish();
                 last = -1;
                 continue;
             }
-            if (last >= 0) {
+            if (last != -1) {
                 const unsigned long long *hp = h - W;
                 int diff = 0;
                 for (int i = lane; i < W; i += 64) diff |= ((h[i] | imask[i]) != (hp[i] | imask[i]));
@@ -475,7 +490,36 @@ __device__ void write_candidates(const SearchLaunch &a, const unsigned long long
                     ++mult;
                     continue;
                 }
-                if (lane == 0) a.recs[(size_t)last * kRecStride + 3] = mult;
+                finish();
+            }
+            // the set's variables in ascending order
+            int off = 0;
+            for (int i0 = 0; i0 < W; i0 += 64) {
+                const int i = i0 + lane;
+                unsigned long long wv = i < W ? (h[i] | imask[i]) : 0ull;
+                const int pc = __popcll(wv);
+                int pos = off + wave_excl_scan(pc);
+                while (wv) {
+                    const int b = __ffsll((unsigned long long)wv) - 1;
+                    stage[pos++] = i * 64 + b;
+                    wv &= wv - 1;
+                }
+                off += wave_sum(pc);
+            }
+            wave_sync();
+            int match = -1;
+            for (int e = 0; e < kDedupSets && match < 0; ++e) {
+                const int *ce = cache + e * kDedupStride;
+                if (ce[0] >= 0 && ce[1] == cnt && (a.extract_mode != TS_EXTRACT_CRITICAL || ce[2] == k)) {
+                    const bool eq = lane >= cnt || stage[lane] == ce[4 + lane];
+                    if (__all(eq)) match = ce[0];
+                }
+            }
+            if (match >= 0) {
+                last = -2;
+                into = match;
+                mult = 1;
+                continue;
             }
             int r = 0;
             if (lane == 0) r = atomicAdd(a.rec_count, 1);
@@ -492,23 +536,24 @@ __device__ void write_candidates(const SearchLaunch &a, const unsigned long long
                 rec[3] = 1;
                 rec[4] = cnt;
             }
-            int off = 0;
-            for (int i0 = 0; i0 < W; i0 += 64) {
-                const int i = i0 + lane;
-                unsigned long long wv = i < W ? (h[i] | imask[i]) : 0ull;
-                const int pc = __popcll(wv);
-                int pos = off + wave_excl_scan(pc);
-                while (wv) {
-                    const int b = __ffsll((unsigned long long)wv) - 1;
-                    rec[kRecHdr + pos++] = i * 64 + b;
-                    wv &= wv - 1;
-                }
-                off += wave_sum(pc);
+            if (lane < cnt) rec[kRecHdr + lane] = stage[lane];
+            // remember the set (entries replaced in turn; the turn is kept in
+            // entry 0's spare word)
+            const int v = cache[3];
+            int *ce = cache + v * kDedupStride;
+            wave_sync();
+            if (lane < cnt) ce[4 + lane] = stage[lane];
+            if (lane == 0) {
+                ce[0] = r;
+                ce[1] = cnt;
+                ce[2] = k;
+                cache[3] = (v + 1) % kDedupSets;
             }
+            wave_sync();
             last = r;
             mult = 1;
         }
-        if (last >= 0 && lane == 0) a.recs[(size_t)last * kRecStride + 3] = mult;
+        finish();
     }
     __syncthreads();
 }
@@ -597,12 +642,16 @@ __device__ __forceinline__ void search_jobs(const SearchJob *jobs, int n_jobs, i
             else if (v >= 0) atomicOr(&imask[v >> 6], 1ull << (v & 63));
         }
         const int pg = a.pat_base + pl;
+        if (tid == 0) {   // the pattern's cache of recorded sets starts empty
+            for (int e = 0; e < kDedupSets; ++e) sh[32 + kCapMax + e * kDedupStride] = -1;
+            sh[32 + kCapMax + 3] = 0;
+        }
         DecRes r = dec.decode(a.k_max);
         my_iters += r.run;
         my_dec += 1;
         int kc = -1, it_hi = 0, tm_hi = 0, it_lo = r.iters;
         if (r.fail) {
-            write_candidates(a, dec.hist(), imask, W, r.iters, r.run, pg, a.k_max);
+            write_candidates(a, dec.hist(), imask, W, r.iters, r.run, pg, a.k_max, sh + 32);
             int lo = 0, hi = a.k_max;
             it_hi = r.iters;
             tm_hi = r.tmin;
@@ -616,7 +665,7 @@ __device__ __forceinline__ void search_jobs(const SearchJob *jobs, int n_jobs, i
                     hi = mid;
                     it_hi = r.iters;
                     tm_hi = r.tmin;
-                    write_candidates(a, dec.hist(), imask, W, r.iters, r.run, pg, mid);
+                    write_candidates(a, dec.hist(), imask, W, r.iters, r.run, pg, mid, sh + 32);
                 } else {
                     lo = mid;
                     it_lo = r.iters;
