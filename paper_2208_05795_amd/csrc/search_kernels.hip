@@ -392,15 +392,22 @@ __device__ __forceinline__ DecRes run_decode(const Frame &F, const int (&nb)[CPT
             if (__any(chg != 0u) && lane == 0) atomicOr(&F.moved[t], 2);
         }
         if (t < T) {
-            // the spare buffer holds APP_{t-2} (t >= 2) until it is reset to
-            // lambda here: APP_{t-1} = APP_{t-2} points to a fixed point
+            // a hash of the thread's new messages, unchanged on every thread,
+            // points to a fixed point (the next iteration verifies it); the
+            // last iteration's hash is kept in the save area
+            unsigned hh = 0;
+#pragma unroll
+            for (int c = 0; c < CPT; ++c)
+#pragma unroll
+                for (int j = 0; j < DC; ++j) hh = hh * 0x9E3779B1u + (unsigned)c2v[c][j];
+            unsigned hp = 0;
+            if (F.vsave) hp = (unsigned)F.vsave[B * CPT * DC + tid];
             int *S = F.app + spare * np;
-            bool same = true;
-            for (int v = tid; v < np; v += B) {
-                same &= S[v] == A[v];
-                S[v] = F.lam[v];
+            for (int v = tid; v < np; v += B) S[v] = F.lam[v];
+            if (F.vsave) {
+                F.vsave[B * CPT * DC + tid] = (int)hh;
+                if (t >= 2 && !__all(hh == hp) && lane == 0) atomicOr(&F.moved[t], 1);
             }
-            if (t >= 2 && !__all(same) && lane == 0) atomicOr(&F.moved[t], 1);
         }
         __syncthreads();
         if (t >= 2) {
@@ -417,6 +424,7 @@ __device__ __forceinline__ DecRes run_decode(const Frame &F, const int (&nb)[CPT
                 fixed = t;
                 break;
             }
+            // the messages' hash did not change: iteration t + 1 checks them
             verify = F.vsave && t < T && (F.moved[t] & 1) == 0;
         }
         const int tmp = cur;
@@ -1719,7 +1727,7 @@ int plan_candidates(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter,
             p.dc = dc;
             p.lds = lds;
             p.grid = per_cu * ctx->num_cu;
-            p.slot_bytes = (size_t)block * cp * dc * 4;   // message save area (fixed-point test)
+            p.slot_bytes = (size_t)block * (cp * dc + 1) * 4;   // message save area and hash (fixed-point test)
             p.hist_off = 0;
             out->push_back(p);
         }
@@ -1881,7 +1889,7 @@ int plan_is_candidates(ts_ctx *ctx, const ts_code *c, int max_iter, int layout,
             p.dc = dc;
             p.lds = lds;
             p.grid = per_cu * ctx->num_cu;
-            p.slot_bytes = (size_t)b * cp * dc * 4;   // save area of the messages
+            p.slot_bytes = (size_t)b * (cp * dc + 1) * 4;   // save area of the messages and their hash
             p.hist_off = 0;
             out->push_back(p);
         }
