@@ -302,6 +302,7 @@ struct Frame {
     int *wsyn, *pcnt;
     int *moved;   // per iteration: bit 0 APP changed, bit 1 a check message changed
     int *vsave;   // global save area of the messages (B x CPT x DC), or nullptr
+    unsigned *hsh;   // LDS after the frame: each thread's hash of its last messages
     int n, np, W, T;
 };
 
@@ -393,21 +394,17 @@ __device__ __forceinline__ DecRes run_decode(const Frame &F, const int (&nb)[CPT
         }
         if (t < T) {
             // a hash of the thread's new messages, unchanged on every thread,
-            // points to a fixed point (the next iteration verifies it); the
-            // last iteration's hash is kept in the save area
+            // points to a fixed point (the next iteration verifies it)
             unsigned hh = 0;
 #pragma unroll
             for (int c = 0; c < CPT; ++c)
 #pragma unroll
                 for (int j = 0; j < DC; ++j) hh = hh * 0x9E3779B1u + (unsigned)c2v[c][j];
-            unsigned hp = 0;
-            if (F.vsave) hp = (unsigned)F.vsave[B * CPT * DC + tid];
+            const unsigned hp = F.hsh[tid];
+            F.hsh[tid] = hh;
             int *S = F.app + spare * np;
             for (int v = tid; v < np; v += B) S[v] = F.lam[v];
-            if (F.vsave) {
-                F.vsave[B * CPT * DC + tid] = (int)hh;
-                if (t >= 2 && !__all(hh == hp) && lane == 0) atomicOr(&F.moved[t], 1);
-            }
+            if (t >= 2 && !__all(hh == hp) && lane == 0) atomicOr(&F.moved[t], 1);
         }
         __syncthreads();
         if (t >= 2) {
@@ -730,6 +727,7 @@ struct RegSearchDec {
         F.wsyn = (int *)(frame + L.wsyn);
         F.pcnt = (int *)(frame + L.pcnt);
         F.moved = (int *)(frame + L.moved);
+        F.hsh = (unsigned *)(frame + L.total);
         F.vsave = J.a.gscr && J.a.fp_exit ? (int *)uni(J.a.gscr + (size_t)blockIdx.x * J.a.slot_bytes)
                                           : nullptr;
         F.n = n;
@@ -935,6 +933,7 @@ struct LayDec {
         F.wsyn = (int *)(frame + L.wsyn);
         F.pcnt = (int *)(frame + L.pcnt);
         F.moved = (int *)(frame + L.moved);
+        F.hsh = (unsigned *)(frame + L.total);
         F.vsave = J.a.gscr && J.a.fp_exit ? (int *)uni(J.a.gscr + (size_t)blockIdx.x * J.a.slot_bytes)
                                           : nullptr;
         F.n = n;
@@ -1132,6 +1131,7 @@ struct RegIsDec {
         F.wsyn = (int *)(frame + L.wsyn);
         F.pcnt = (int *)(frame + L.pcnt);
         F.moved = (int *)(frame + L.moved);
+        F.hsh = (unsigned *)(frame + L.total);
         F.vsave = J.a.gscr && J.a.fp_exit ? (int *)uni(J.a.gscr + (size_t)blockIdx.x * J.a.slot_bytes)
                                           : nullptr;
         F.n = n;
@@ -1716,8 +1716,10 @@ int plan_candidates(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter,
             const int block = ((c->m + cp - 1) / cp + 63) / 64 * 64;
             if (block > ke->max_block) continue;
             SearchKernel kern = decoder == TS_DEC_OMS_I8 ? ke->oms : (decoder == TS_DEC_SPA_F32 ? ke->spa : ke->lnms);
+            const size_t lds_b = lds + (size_t)block * 4;   // + the threads' message hashes
+            if (lds_b > ctx->lds_per_block) continue;
             int per_cu = 0;
-            TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, block, lds));
+            TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, block, lds_b));
             if (per_cu < 1) continue;
             SearchPlan p;
             p.kind = kPlanRegister;
@@ -1725,9 +1727,9 @@ int plan_candidates(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter,
             p.block = block;
             p.cpt = cp;
             p.dc = dc;
-            p.lds = lds;
+            p.lds = lds_b;
             p.grid = per_cu * ctx->num_cu;
-            p.slot_bytes = (size_t)block * (cp * dc + 1) * 4;   // message save area and hash (fixed-point test)
+            p.slot_bytes = (size_t)block * cp * dc * 4;   // message save area (fixed-point test)
             p.hist_off = 0;
             out->push_back(p);
         }
@@ -1878,8 +1880,10 @@ int plan_is_candidates(ts_ctx *ctx, const ts_code *c, int max_iter, int layout,
             if (!k) continue;
             const int b = ((c->m + cp - 1) / cp + 63) / 64 * 64;
             if (b > k->is_max_block) continue;
+            const size_t lds_b = lds + (size_t)b * 4;   // + the threads' message hashes
+            if (lds_b > ctx->lds_per_block) continue;
             int per_cu = 0;
-            TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k->is, b, lds));
+            TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k->is, b, lds_b));
             if (per_cu < 1) continue;
             SearchPlan p;
             p.kind = kPlanRegister;
@@ -1887,9 +1891,9 @@ int plan_is_candidates(ts_ctx *ctx, const ts_code *c, int max_iter, int layout,
             p.block = b;
             p.cpt = cp;
             p.dc = dc;
-            p.lds = lds;
+            p.lds = lds_b;
             p.grid = per_cu * ctx->num_cu;
-            p.slot_bytes = (size_t)b * (cp * dc + 1) * 4;   // save area of the messages and their hash
+            p.slot_bytes = (size_t)b * cp * dc * 4;   // save area of the messages
             p.hist_off = 0;
             out->push_back(p);
         }
