@@ -51,7 +51,7 @@ VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 VALU_SLOTS_PER_EU = {"oms": 15.0, "spa": 2 * (3 * 4 + 5) + 6.0}
 # HBM traffic per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled x2 and x1 by a 1 GiB copy); None once the kernel changes.
-MEASURED_TRAFFIC_BYTES = {"spa": (2272.55e6 + 13400.23e6)}
+MEASURED_TRAFFIC_BYTES = {"spa": (582.81e6 + 10101.54e6)}
 
 
 def parse():
