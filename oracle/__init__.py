@@ -38,7 +38,7 @@ class SearchOpts(C.Structure):
                 ("ebn0_db", C.c_double), ("rate", C.c_double), ("llr_scale", C.c_double),
                 ("k_max", C.c_int32), ("k_den", C.c_int32), ("a_max", C.c_int32),
                 ("extract_mode", C.c_int32), ("collect_from_iter", C.c_int32),
-                ("threads", C.c_int32)]
+                ("threads", C.c_int32), ("spa_grid", C.c_int32)]
 
 
 class IsOpts(C.Structure):
@@ -88,6 +88,8 @@ def lib():
     L.or_q4_impulse.argtypes = [C.c_int, C.c_int]
     L.or_decode_spa_ex.restype = DecResult
     L.or_decode_spa_ex.argtypes = [vp, _f64p, C.c_int, vp, vp, vp, C.c_int]
+    L.or_decode_spa_grid.restype = DecResult
+    L.or_decode_spa_grid.argtypes = [vp, _f64p, C.c_int, vp, vp, vp, C.c_int, C.c_int]
     L.or_patterns.restype = C.c_int64
     L.or_patterns.argtypes = [vp, C.c_int, vp, C.c_int64]
     L.or_count_b.argtypes = [vp, _i32p, C.c_int]
@@ -210,13 +212,14 @@ def q4_impulse(qb: int, k: int) -> int:
     return lib().or_q4_impulse(qb, k)
 
 
-def decode_spa(oc: OCode, llr, max_iter: int = 50, hist: bool = False, early_stop: bool = True):
+def decode_spa(oc: OCode, llr, max_iter: int = 50, hist: bool = False, early_stop: bool = True,
+               grid: int = 0):
     l = np.ascontiguousarray(np.asarray(llr, dtype=np.float64))
     hb = np.zeros((max_iter, oc.n), dtype=np.uint8) if hist else None
     sy = np.zeros(max_iter, dtype=np.int32)
     app = np.zeros(oc.n, dtype=np.float64)
-    r = lib().or_decode_spa_ex(oc.handle, l, max_iter, hb.ctypes.data if hist else None,
-                               sy.ctypes.data, app.ctypes.data, int(early_stop))
+    r = lib().or_decode_spa_grid(oc.handle, l, max_iter, hb.ctypes.data if hist else None,
+                                 sy.ctypes.data, app.ctypes.data, int(early_stop), int(grid))
     out = dict(fail=r.fail, iters=r.iters, tmin=r.tmin, wmin=r.wmin, synd=sy[:r.iters], app=app)
     if hist:
         out["hist"] = hb[:r.iters]
@@ -281,14 +284,17 @@ class TsRecord:
 def search(oc: OCode, pats: np.ndarray, decoder: int = DEC_OMS, max_iter: int = 20,
            oms_offset: int = 1, ebn0_db: float = 3.0, rate: Optional[float] = None,
            llr_scale: float = 4.0, k_max: int = 512, k_den: int = 16, a_max: int = 6,
-           extract_mode: int = EXTRACT_PATH, collect_from_iter: int = -1, threads: int = 0):
+           extract_mode: int = EXTRACT_PATH, collect_from_iter: int = -1, threads: int = 0,
+           spa_grid: int = 0):
+    """spa_grid > 0 runs the conditioning probe of the sum-product decoder
+    (or_decode_spa_grid): messages rounded to multiples of 2^-spa_grid."""
     pats = _i32(pats)
     if pats.ndim == 1:
         pats = pats.reshape(-1, 1)
     P, W = pats.shape
     rate = oc.code.rate if rate is None else rate
     o = SearchOpts(decoder, max_iter, oms_offset, ebn0_db, rate, llr_scale, k_max, k_den,
-                   a_max, extract_mode, collect_from_iter, threads)
+                   a_max, extract_mode, collect_from_iter, threads, spa_grid)
     kc, ic, il, tm, nc = (np.zeros(P, dtype=np.int32) for _ in range(5))
     dec, eu = C.c_int64(), C.c_int64()
     lst = C.c_void_p()

@@ -106,14 +106,22 @@ static double phi(double x) {
     return log1p(2.0 / expm1(x));
 }
 
-or_dec_result or_decode_spa_ex(const or_code *c, const double *llr, int max_iter,
-                               uint8_t *hist, int32_t *synd, double *app_out,
-                               int early_stop) {
+/* Rounds x to a multiple of 2^-grid, halves to even (grid 0: x unchanged). */
+static double on_grid(double x, int grid) {
+    if (grid <= 0) return x;
+    return nearbyint(ldexp(x, grid)) * ldexp(1.0, -grid);
+}
+
+or_dec_result or_decode_spa_grid(const or_code *c, const double *llr_in, int max_iter,
+                                 uint8_t *hist, int32_t *synd, double *app_out,
+                                 int early_stop, int grid) {
     or_dec_result res = {0, 0, 0, 0};
     double *c2v = calloc((size_t)c->e, sizeof(double));
     double *v2c = malloc(sizeof(double) * (size_t)c->e);
     double *app = malloc(sizeof(double) * (size_t)c->n);
+    double *llr = malloc(sizeof(double) * (size_t)c->n);
     uint8_t *x = malloc((size_t)c->n);
+    for (int v = 0; v < c->n; v++) llr[v] = on_grid(llr_in[v], grid);
     for (int v = 0; v < c->n; v++) app[v] = llr[v];
     int wbest = -1;
     int t;
@@ -132,7 +140,7 @@ or_dec_result or_decode_spa_ex(const or_code *c, const double *llr, int max_iter
                     if (a > 30.0) a = 30.0;
                     sum += phi(a);
                 }
-                c2v[k] = sign * phi(sum);
+                c2v[k] = on_grid(sign * phi(sum), grid);
             }
         for (int v = 0; v < c->n; v++) {
             double s = llr[v];
@@ -154,8 +162,15 @@ or_dec_result or_decode_spa_ex(const or_code *c, const double *llr, int max_iter
     free(c2v);
     free(v2c);
     free(app);
+    free(llr);
     free(x);
     return res;
+}
+
+or_dec_result or_decode_spa_ex(const or_code *c, const double *llr, int max_iter,
+                               uint8_t *hist, int32_t *synd, double *app_out,
+                               int early_stop) {
+    return or_decode_spa_grid(c, llr, max_iter, hist, synd, app_out, early_stop, 0);
 }
 
 /* ---- quantised normalised layered min-sum (Section III, Fig. 2) ---------- */

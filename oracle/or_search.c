@@ -181,7 +181,7 @@ static or_dec_result decode_at(worker *w, const int32_t *pat, int width, int k,
     for (int v = 0; v < c->n; v++) w->llr[v] = w->h;
     for (int i = 0; i < width; i++)
         if (pat[i] >= 0) w->llr[pat[i]] = w->h * (1.0 - eps);
-    return or_decode_spa(c, w->llr, w->o->max_iter, hist, NULL, NULL);
+    return or_decode_spa_grid(c, w->llr, w->o->max_iter, hist, NULL, NULL, 1, w->o->spa_grid);
 }
 
 static int emit(worker *w, recs *out, const int32_t *set, int a, int pattern) {

@@ -85,6 +85,16 @@ or_dec_result or_decode_spa_ex(const or_code *c, const double *llr, int max_iter
                                uint8_t *hist, int32_t *synd, double *app_out,
                                int early_stop);
 
+/* Conditioning probe of the sum-product decoder (not the method itself): the
+ * same decode with the channel values and every check-to-variable message
+ * rounded to a multiple of 2^-grid (halves to even; grid 0 = or_decode_spa_ex).
+ * A decode whose outputs change under this rounding depends on the arithmetic
+ * precision of the messages, so no fixed-precision decoder can be held to its
+ * double-precision outputs element by element. */
+or_dec_result or_decode_spa_grid(const or_code *c, const double *llr, int max_iter,
+                                 uint8_t *hist, int32_t *synd, double *app_out,
+                                 int early_stop, int grid);
+
 /* Quantised normalised layered min-sum (Section III, Fig. 2; the 4/4/6-bit
  * reading): channel values and check-to-variable messages in [-7, 7],
  * variable-to-check messages and APP values in [-31, 31], check magnitude =
@@ -139,6 +149,7 @@ typedef struct {
     int32_t extract_mode;      /* OR_EXTRACT_* */
     int32_t collect_from_iter; /* -1 = floor(girth/2) */
     int32_t threads;           /* 0 = OpenMP default */
+    int32_t spa_grid;          /* 0; g > 0: the conditioning probe of or_decode_spa_grid */
 } or_search_opts;
 
 typedef struct or_ts_list or_ts_list;

@@ -87,26 +87,58 @@ def test_emitted_sets_are_trapping_sets(oracle_mod, tiny, tiny_search):
     assert keys == sorted(keys)
 
 
-def test_search_recall_smallest_sets(oracle_mod, tiny, tiny_search):
-    """Brute force over all connected TS with a <= 6: the search recovers every
-    orbit of the smallest sizes (a <= 4), including the (4,0) codeword."""
-    c, oc = tiny
-    _, res = tiny_search
-    brute = oracle_mod.brute_ts_list(oc, 6)
+def _recall(oracle_mod, oc, res, a_max=6):
+    brute = oracle_mod.brute_ts_list(oc, a_max)
     found = {r.bits for r in res["ts"]}
     by_cell = Counter((a, b) for a, b, _ in brute)
     hit = Counter((a, b) for a, b, s in brute if s in found)
+    return brute, by_cell, hit
+
+
+def test_search_recall_smallest_sets(oracle_mod, tiny, tiny_search):
+    """Brute force over all connected TS with a <= 6 (orbits of the QC shift),
+    against the search over the tiny code's singles and pairs within distance 4.
+    Full recall of every cell with a <= 4, including the minimum-a cell (3,3)
+    and the (4,0) codeword.  The other cells with b <= a are reported; the
+    recall there is a property of the heuristic's pattern set (measured: (5,3)
+    41/42, (6,2) 12/13, (5,5) 255/598, (6,4) 236/1334, (6,6) 267/5260), and is
+    held to those counts as a floor."""
+    c, oc = tiny
+    _, res = tiny_search
+    brute, by_cell, hit = _recall(oracle_mod, oc, res)
+    print("\nrecall, singles + pairs: " + ", ".join(
+        f"({a},{b}) {hit[(a, b)]}/{n}" for (a, b), n in sorted(by_cell.items()) if b <= a))
     a_min = min(a for a, _ in by_cell)
+    assert a_min == 3
     for (a, b), n in by_cell.items():
         if a <= 4:
             assert hit[(a, b)] == n, ((a, b), hit[(a, b)], n)
-    assert a_min == 3
+    floor = {(5, 3): 41, (6, 2): 12, (5, 5): 255, (6, 4): 236, (6, 6): 267}
+    for cell, k in floor.items():
+        assert hit[cell] >= k, (cell, hit[cell], by_cell[cell])
     # every connected emitted set is one of the brute-force sets
     brute_set = {s for _, _, s in brute}
     adj = _var_adjacency(oc)
     for r in res["ts"]:
         if _connected(r.bits, adj):
             assert r.bits in brute_set
+
+
+def test_search_recall_with_triples(oracle_mod, tiny):
+    """Adding the tree-path triples of the impulse tree (Section III, Fig. 3)
+    recovers the (5,3) and (6,2) orbits that singles and pairs miss: every cell
+    with b/a < 1 and a <= 6 except (6,4) is then complete."""
+    c, oc = tiny
+    pats = oracle_mod.pattern_list(oc, [1, 2, 3])
+    res = oracle_mod.search(oc, pats, a_max=6)
+    _, by_cell, hit = _recall(oracle_mod, oc, res)
+    print("\nrecall, singles + pairs + triples: " + ", ".join(
+        f"({a},{b}) {hit[(a, b)]}/{n}" for (a, b), n in sorted(by_cell.items()) if b <= a))
+    for cell in ((3, 3), (4, 0), (4, 2), (4, 4), (5, 3), (6, 2)):
+        assert hit[cell] == by_cell[cell], (cell, hit[cell], by_cell[cell])
+    floor = {(5, 5): 422, (6, 4): 570, (6, 6): 613}
+    for cell, k in floor.items():
+        assert hit[cell] >= k, (cell, hit[cell], by_cell[cell])
 
 
 def _var_adjacency(oc):
@@ -195,6 +227,38 @@ def test_spa_search_small(oracle_mod, tiny):
     assert res["decodes"] == int((kc < 0).sum()) + 16 * int((kc >= 0).sum())
     for r in res["ts"]:
         assert oracle_mod.count_b(oc, r.bits) == r.b
+    # the bisection's transition: re-decoding a pattern at k* fails (with the
+    # reported iteration count and minimum-syndrome iteration) and at k* - 1
+    # succeeds
+    h = 2.0 / oracle_mod.sigma2(3.0, 0.5)
+    rng = np.random.default_rng(6)
+    fails = np.nonzero(kc >= 0)[0]
+    assert len(fails) >= 25
+    for p in rng.choice(fails, 25, replace=False):
+        for k, want in ((kc[p], 1), (kc[p] - 1, 0)):
+            llr = np.full(oc.n, h)
+            for v in pats[p]:
+                llr[v] = h * (1.0 - k / 1024.0)
+            r = oracle_mod.decode_spa(oc, llr, 50)
+            assert r["fail"] == want, (p, k)
+            if want:
+                assert r["iters"] == res["iters_crit"][p] and r["tmin"] == res["tmin_crit"][p]
+
+
+def test_spa_eps_star_is_a_transition(oracle_mod, tiny, tiny_search):
+    """eps* of an impulse on a whole set (the IS shift of Section I/II): the SPA
+    decode fails at eps* and succeeds one grid step (2^-10) below."""
+    c, oc = tiny
+    _, res = tiny_search
+    h = 2.0 / oracle_mod.sigma2(3.0, 0.5)
+    sets = [r.bits for r in res["ts"] if r.a >= 3][:6]
+    for bits in sets:
+        eps = oracle_mod.spa_eps_star(oc, bits, 3.0)
+        assert eps > 0
+        for e, want in ((eps, 1), (eps - 1.0 / 1024.0, 0)):
+            llr = np.full(oc.n, h)
+            llr[list(bits)] = h * (1.0 - e)
+            assert oracle_mod.decode_spa(oc, llr, 50)["fail"] == want, (bits, e)
 
 
 def test_lnms_search_consistent(oracle_mod, tiny):
