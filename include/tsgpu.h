@@ -58,6 +58,10 @@ typedef struct {
     void (*free)(void *ptr, void *user);
     void *user;
     size_t hbm_budget_bytes;   /* 0 = no limit; the serving admission check uses it */
+    size_t rec_buffer_bytes;   /* device buffer for the candidate error sets of one search
+                                * launch; 0 = 256 MiB.  Never smaller than one pattern's
+                                * worst case; a launch whose candidates overflow it is
+                                * re-run in smaller chunks (same results and statistics) */
 } ts_ctx_opts;
 
 /* Creates a context on opts->device.  opts may be NULL (device 0, own stream).

@@ -87,12 +87,13 @@ class Context:
     allocator are torch's (current stream, caching allocator)."""
 
     def __init__(self, device: int = 0, torch_stream: bool = True, torch_alloc: bool = True,
-                 hbm_budget_bytes: int = 0):
+                 hbm_budget_bytes: int = 0, rec_buffer_bytes: int = 0):
         L = lib()
         self._keep = []
         opts = A.CtxOpts()
         opts.device = device
         opts.hbm_budget_bytes = hbm_budget_bytes
+        opts.rec_buffer_bytes = rec_buffer_bytes
         self.device = device
         if torch_stream or torch_alloc:
             import torch

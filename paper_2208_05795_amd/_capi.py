@@ -24,7 +24,8 @@ FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 class CtxOpts(C.Structure):
     _fields_ = [("device", C.c_int32), ("hip_stream", C.c_void_p), ("alloc", ALLOC_FN),
-                ("free", FREE_FN), ("user", C.c_void_p), ("hbm_budget_bytes", C.c_size_t)]
+                ("free", FREE_FN), ("user", C.c_void_p), ("hbm_budget_bytes", C.c_size_t),
+                ("rec_buffer_bytes", C.c_size_t)]
 
 
 class CodeDesc(C.Structure):

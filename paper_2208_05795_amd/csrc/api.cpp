@@ -101,10 +101,11 @@ double sigma2_of(double ebn0_db, double rate) { return 1.0 / (2.0 * rate * std::
 
 int sat127(long v) { return (int)(v > 127 ? 127 : (v < -127 ? -127 : v)); }
 
-int64_t rec_capacity(const ts_search_opts *o, int t0, int64_t P, bool sieve, int64_t *worst) {
+int64_t rec_capacity(const ts_search_opts *o, int t0, int64_t P, bool sieve, size_t max_bytes,
+                     int64_t *worst) {
     const int d_fail_max = 2 + (int)std::ceil(std::log2((double)o->k_max));
     const int64_t wp = sieve ? (int64_t)d_fail_max * std::max(1, o->max_iter - t0 + 1) : 0;
-    int64_t cap = std::min<int64_t>((256ll << 20) / (kRecStride * 4), wp * P);
+    int64_t cap = std::min<int64_t>((int64_t)(max_bytes / (kRecStride * 4)), wp * P);
     cap = std::max<int64_t>(std::max<int64_t>(cap, wp), 1);
     if (worst) *worst = wp;
     return cap;
@@ -137,7 +138,7 @@ void fill_search_launch(const ts_code *code, const ts_search_opts *o, int t0, in
 }
 
 size_t search_bytes_estimate(const ts_code *code, const ts_search_opts *o, int64_t P, int32_t width) {
-    const int64_t cap = rec_capacity(o, first_iter(code, o), P, true, nullptr);
+    const int64_t cap = rec_capacity(o, first_iter(code, o), P, true, code->ctx->rec_bytes, nullptr);
     size_t scr = 0;   // decoder scratch of the largest streamed shape the autotuner may try
     std::vector<SearchPlan> shapes;
     if (plan_candidates(code->ctx, code, o->decoder, o->max_iter, &shapes) == TS_OK)
@@ -381,7 +382,7 @@ int run_search(ts_exec &ex, ts_code *code, DevTable &table, const ts_search_opts
     // misc layout: [0] queue, [1] rec_count, [2] err, [4..7] counters (2 x u64)
     rc = launch_fill(s, d_misc, 0, 64);
     if (rc) return rc;
-    const int64_t rec_cap = rec_capacity(o, t0, P, sieve, nullptr);
+    const int64_t rec_cap = rec_capacity(o, t0, P, sieve, ctx->rec_bytes, nullptr);
     DBuf recs(ex, (size_t)rec_cap * kRecStride * 4);
     if (!recs.p) { set_error("device allocation of the candidate buffer failed"); return TS_E_NOMEM; }
 
@@ -420,9 +421,14 @@ int run_search(ts_exec &ex, ts_code *code, DevTable &table, const ts_search_opts
     TSG_HIP(hipEventRecord(ex.ev[4], s));
     int64_t chunk = P, pos = 0, cands = 0;
     double dec_ms = 0.0, sieve_ms = 0.0;
+    // decodes and computed iterations of the accepted chunks (a chunk whose
+    // candidates overflow the buffer is re-run, and its first run not counted)
+    unsigned long long cnt[2] = {0, 0};
     while (pos < P) {
         const int64_t len = std::min<int64_t>(chunk, P - pos);
         rc = launch_fill(s, d_misc, 0, 2);   // queue, rec_count
+        if (rc) return rc;
+        rc = launch_fill(s, d_misc + 4, 0, 4);   // the chunk's counters
         if (rc) return rc;
         a.patterns = d_pat + pos * width;
         a.n_patterns = (int)len;
@@ -431,7 +437,7 @@ int run_search(ts_exec &ex, ts_code *code, DevTable &table, const ts_search_opts
         rc = launch_search(ex, plan, a);
         if (rc) return rc;
         TSG_HIP(hipEventRecord(ex.ev[1], s));
-        TSG_HIP(hipMemcpyAsync(ex.pinned, d_misc, 16, hipMemcpyDeviceToHost, s));
+        TSG_HIP(hipMemcpyAsync(ex.pinned, d_misc, 32, hipMemcpyDeviceToHost, s));
         TSG_HIP(hipStreamSynchronize(s));
         float ms = 0.0f;
         TSG_HIP(hipEventElapsedTime(&ms, ex.ev[0], ex.ev[1]));
@@ -443,6 +449,12 @@ int run_search(ts_exec &ex, ts_code *code, DevTable &table, const ts_search_opts
             if (len == 1) { set_error("candidate buffer too small for one pattern"); return TS_E_NOMEM; }
             chunk = std::max<int64_t>(1, len / 2);   // re-run this chunk in smaller pieces
             continue;
+        }
+        {
+            unsigned long long c[2];
+            std::memcpy(c, ex.pinned + 4, 16);
+            cnt[0] += c[0];
+            cnt[1] += c[1];
         }
         if (sieve && nrec > 0) {
             cands += nrec;
@@ -465,8 +477,6 @@ int run_search(ts_exec &ex, ts_code *code, DevTable &table, const ts_search_opts
     float tot = 0.0f;
     TSG_HIP(hipEventElapsedTime(&tot, ex.ev[4], ex.ev[5]));
     const int err = ex.pinned[2];
-    unsigned long long cnt[2];
-    std::memcpy(cnt, ex.pinned + 4, 16);
     ex.stats.decode_ms += dec_ms;
     ex.stats.extract_ms += sieve_ms;
     ex.stats.total_ms += tot;
@@ -827,6 +837,7 @@ int ts_create(const ts_ctx_opts *opts, ts_ctx **out) {
         c->free_fn = opts->free;
         c->user = opts->user;
         c->budget = opts->hbm_budget_bytes;
+        if (opts->rec_buffer_bytes) c->rec_bytes = opts->rec_buffer_bytes;
     }
     int ncu = 0, lds = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||

@@ -93,7 +93,8 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
             rc = plan_search_shape(ex, b.code, &b.so, it.P, &it.plan);
             if (rc) return rc;
             it.t0 = first_iter(b.code, &b.so);
-            it.rec_cap = std::min<int64_t>(rec_capacity(&b.so, it.t0, it.P, true, nullptr), 2 * it.P + 4096);
+            it.rec_cap = std::min<int64_t>(rec_capacity(&b.so, it.t0, it.P, true, ex.ctx->rec_bytes, nullptr),
+                                           2 * it.P + 4096);
             S.push_back(it);
         } else {
             IItem it;
@@ -325,21 +326,21 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
     for (size_t i = 0; i < S.size(); ++i) {
         SItem &it = S[i];
         const int *misc = zh.data() + it.misc / 4;
-        unsigned long long cnt[2];
-        std::memcpy(cnt, misc + 4, 16);
-        it.b->edge_updates = (int64_t)cnt[1] * it.b->code->e;
-        ex.stats.decodes += (int64_t)cnt[0];
-        ex.stats.edge_updates += it.b->edge_updates;
         if (misc[1] & 1) {
             it.b->status = TS_E_INVAL;
             it.b->err = "pattern entry out of range";
             continue;
         }
         const int64_t nrec = misc[0];
-        if (nrec > it.rec_cap) {
+        if (nrec > it.rec_cap) {   // re-run alone below; this run's work is not counted
             rerun.push_back(&it);
             continue;
         }
+        unsigned long long cnt[2];
+        std::memcpy(cnt, misc + 4, 16);
+        it.b->edge_updates = (int64_t)cnt[1] * it.b->code->e;
+        ex.stats.decodes += (int64_t)cnt[0];
+        ex.stats.edge_updates += it.b->edge_updates;
         it.b->recs->clear();
         it.b->bits->clear();
         if (nrec > 0) {   // a table sized for the job's candidates (the read-out is sorted)

@@ -209,6 +209,7 @@ struct ts_ctx {
     void (*free_fn)(void *, void *) = nullptr;
     void *user = nullptr;
     size_t budget = 0;
+    size_t rec_bytes = 256ull << 20;   // candidate record buffer of one search launch
     std::recursive_mutex mu;
     ts_exec main;
     std::vector<ts_code *> codes;
@@ -399,7 +400,8 @@ int launch_is_reduce(hipStream_t s, const IsDev &d, const double *wf, const unsi
 // api.cpp: the work of one search / IS call on an executor
 double sigma2_of(double ebn0_db, double rate);
 int first_iter(const ts_code *code, const ts_search_opts *o);
-int64_t rec_capacity(const ts_search_opts *o, int t0, int64_t P, bool sieve, int64_t *worst);
+int64_t rec_capacity(const ts_search_opts *o, int t0, int64_t P, bool sieve, size_t max_bytes,
+                     int64_t *worst);
 void fill_search_launch(const ts_code *code, const ts_search_opts *o, int t0, int32_t width,
                         SearchLaunch *a);
 int is_eps_shifts(ts_exec &ex, ts_code *code, const ts_is_opts *o,
