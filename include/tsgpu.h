@@ -234,17 +234,25 @@ int ts_reset_ts(ts_ctx *ctx, ts_code *code);
 
 /* ---- importance sampling of one TS (Section I/II, Cole's TS weighting) ------ */
 
+#define TS_IS_COUNT_ALL 0   /* every failing frame counts */
+#define TS_IS_COUNT_TS 1    /* only failing frames whose final hard decision has every
+                             * bit of T in error (the frames of T's own error event) */
+#define TS_SHIFT_EPS 0      /* shift < 0: s = eps* of the SPA impulse on the whole set */
+#define TS_SHIFT_PILOT 1    /* shift < 0: s chosen by pilot runs (ts_is_estimate) */
+
 typedef struct {
     int32_t max_iter;        /* SPA iterations */
     double ebn0_db, rate;
-    double shift;            /* mean shift s of the TS bits; < 0: s = eps* of the
-                              * SPA impulse on the whole set (grid 2^-10 up to 32) */
+    double shift;            /* mean shift s of the TS bits; < 0: chosen by shift_rule */
     int64_t n_frames;        /* >= 2 */
     uint64_t seed;           /* Philox key */
     uint64_t frame_base;     /* first frame counter (resumable streams) */
     uint32_t stream;         /* Philox stream tag */
     int32_t layout;          /* TS_LAYOUT_* (AUTO: register layout when it fits) */
     int32_t full_iterations; /* as in ts_search_opts (also for the eps* searches) */
+    int32_t count_mode;      /* TS_IS_COUNT_ALL or TS_IS_COUNT_TS */
+    int32_t shift_rule;      /* TS_SHIFT_EPS or TS_SHIFT_PILOT (used when shift < 0) */
+    int64_t pilot_frames;    /* TS_SHIFT_PILOT: frames per grid point (0: 2000) */
 } ts_is_opts;
 
 typedef struct {
@@ -291,10 +299,13 @@ typedef struct {
     const double *ebn0_db;   /* [n_snr] host array */
     int32_t max_iter;        /* SPA iterations */
     double rate;             /* design rate for sigma */
-    double shift;            /* IS mean shift; < 0: eps* of each set (ts_is_estimate) */
+    double shift;            /* IS mean shift; < 0: chosen per (set, SNR) by shift_rule */
     int64_t n_frames;        /* frames per (set, SNR), >= 2 */
     uint64_t seed;           /* Philox key; stream tag of (set t, SNR i) = (i << 16) | t */
     int32_t layout;          /* TS_LAYOUT_* */
+    int32_t count_mode;      /* TS_IS_COUNT_ALL or TS_IS_COUNT_TS (as in ts_is_opts) */
+    int32_t shift_rule;      /* TS_SHIFT_EPS or TS_SHIFT_PILOT (as in ts_is_opts) */
+    int64_t pilot_frames;    /* as in ts_is_opts */
 } ts_ub_opts;
 
 typedef struct {

@@ -44,7 +44,8 @@ class SearchOpts(C.Structure):
 class IsOpts(C.Structure):
     _fields_ = [("decoder", C.c_int32), ("max_iter", C.c_int32), ("ebn0_db", C.c_double), ("rate", C.c_double),
                 ("shift", C.c_double), ("n_frames", C.c_int64), ("seed", C.c_uint64),
-                ("frame_base", C.c_uint64), ("stream", C.c_uint32), ("threads", C.c_int32)]
+                ("frame_base", C.c_uint64), ("stream", C.c_uint32), ("threads", C.c_int32),
+                ("count_mode", C.c_int32)]
 
 
 class IsResult(C.Structure):
@@ -106,6 +107,9 @@ def lib():
     L.or_normals.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_int, _f64p]
     L.or_is_estimate.argtypes = [vp, _i32p, C.c_int, C.POINTER(IsOpts), C.POINTER(IsResult),
                                  vp, C.POINTER(C.c_int64)]
+    L.or_is_pilot_shift.restype = C.c_double
+    L.or_is_pilot_shift.argtypes = [vp, _i32p, C.c_int, C.POINTER(IsOpts), C.c_double, C.c_int64,
+                                    _f64p]
     L.or_spa_eps_star.restype = C.c_double
     L.or_spa_eps_star.argtypes = [vp, _i32p, C.c_int, C.c_double, C.c_double, C.c_int,
                                   C.c_double]
@@ -331,16 +335,19 @@ def normals(seed: int, frame: int, stream: int, n: int) -> np.ndarray:
 
 
 IS_SPA, IS_LINEAR = 0, 1
+IS_COUNT_ALL, IS_COUNT_TS = 0, 1
 
 
 def is_estimate(oc: OCode, ts, ebn0_db: float, shift: float, n_frames: int, seed: int,
                 frame_base: int = 0, stream: int = 0, max_iter: int = 50,
                 rate: Optional[float] = None, threads: int = 0, want_fail: bool = False,
-                decoder: int = IS_SPA):
+                decoder: int = IS_SPA, count_mode: int = 0):
+    """want_fail: "fail" = per-frame flags (bit 0 failed, bit 1 failed with all
+    of T in error); count_mode IS_COUNT_TS counts only the latter."""
     t = _i32(ts)
     rate = oc.code.rate if rate is None else rate
     o = IsOpts(decoder, max_iter, ebn0_db, rate, shift, n_frames, seed, frame_base, stream,
-               threads)
+               threads, count_mode)
     r = IsResult()
     fo = np.zeros(n_frames, dtype=np.uint8) if want_fail else None
     eu = C.c_int64()
@@ -353,6 +360,20 @@ def is_estimate(oc: OCode, ts, ebn0_db: float, shift: float, n_frames: int, seed
     if want_fail:
         out["fail"] = fo
     return out
+
+
+def is_pilot_shift(oc: OCode, ts, ebn0_db: float, eps_star: float, pilot_frames: int, seed: int,
+                   frame_base: int = 0, stream: int = 0, max_iter: int = 50,
+                   rate: Optional[float] = None, threads: int = 0, count_mode: int = 0):
+    """(chosen shift, relative variance of each of the 9 grid points, -1 where
+    fewer than 10 counted failures)."""
+    t = _i32(ts)
+    rate = oc.code.rate if rate is None else rate
+    o = IsOpts(IS_SPA, max_iter, ebn0_db, rate, 0.0, 2, seed, frame_base, stream, threads,
+               count_mode)
+    rv = np.zeros(9, dtype=np.float64)
+    s = lib().or_is_pilot_shift(oc.handle, t, t.size, C.byref(o), eps_star, pilot_frames, rv)
+    return s, rv
 
 
 def spa_eps_star(oc: OCode, ts, ebn0_db: float, max_iter: int = 50, eps_max: float = 32.0,

@@ -10,7 +10,11 @@
  *   P   = (1/K) sum_f 1[fail_f] w_f,
  *   Var = (1/(K(K-1))) sum_f (1[fail_f] w_f - P)^2,   95% CI = P +- 1.96 sqrt(Var)
  * with the SPA decoder of or_decode.c.  w is the likelihood ratio of the
- * unshifted over the shifted Gaussian density of the a shifted bits.
+ * unshifted over the shifted Gaussian density of the a shifted bits.  Which
+ * failures count (count_mode): every failure, or only T's own error events,
+ * whose final hard decision has every bit of T in error and at most 2a bits in
+ * error in all (the failures of the union bound's term for T; wide decoding
+ * failures and other sets' events are not T's).
  *
  * Noise comes from Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random
  * numbers: as easy as 1, 2, 3", SC'11): counter (v>>2, frame_lo, frame_hi,
@@ -103,6 +107,7 @@ double or_spa_eps_star(const or_code *c, const int32_t *ts, int a, double ebn0_d
 int or_is_estimate(const or_code *c, const int32_t *ts, int a, const or_is_opts *o,
                    or_is_result *res, uint8_t *fail_out, int64_t *edge_updates) {
     if (o->n_frames < 2 || a < 1 || o->max_iter < 1) return -1;
+    if (o->count_mode != OR_IS_COUNT_ALL && o->count_mode != OR_IS_COUNT_TS) return -1;
     double sigma2 = or_sigma2(o->ebn0_db, o->rate), sigma = sqrt(sigma2);
     double s = o->shift;
     uint8_t *in_t = calloc((size_t)c->n, 1);
@@ -120,6 +125,7 @@ int or_is_estimate(const or_code *c, const int32_t *ts, int a, const or_is_opts 
     {
         double *nz = malloc(sizeof(double) * ((size_t)c->n + 4));
         double *llr = malloc(sizeof(double) * (size_t)c->n);
+        double *app = malloc(sizeof(double) * (size_t)c->n);
 #pragma omp for schedule(dynamic, 64)
         for (int64_t f = 0; f < o->n_frames; f++) {
             or_normals(o->seed, o->frame_base + (uint64_t)f, o->stream, c->n, nz);
@@ -136,16 +142,25 @@ int or_is_estimate(const or_code *c, const int32_t *ts, int a, const or_is_opts 
             if (o->decoder == OR_IS_LINEAR) {
                 r.fail = sum_y < 0.0;
                 r.iters = 0;
+                memcpy(app, llr, sizeof(double) * (size_t)c->n);
             } else {
-                r = or_decode_spa(c, llr, o->max_iter, NULL, NULL, NULL);
+                r = or_decode_spa(c, llr, o->max_iter, NULL, NULL, app);
             }
             eu += (int64_t)r.iters * c->e;
+            /* T's own error event: every bit of T decided 1 at the end of the
+             * decode, and at most 2a bits in error in all */
+            int t_err = r.fail, n_err = 0;
+            for (int i = 0; i < a && t_err; i++) t_err = app[ts[i]] < 0.0;
+            for (int v = 0; v < c->n; v++) n_err += app[v] < 0.0;
+            t_err = t_err && n_err <= 2 * a;
+            const int counted = o->count_mode == OR_IS_COUNT_TS ? t_err : r.fail;
             double w = exp(-a * s * s / (2.0 * sigma2) + (s / sigma) * sum_t);
-            wf[f] = r.fail ? w : 0.0;
-            failv[f] = (uint8_t)r.fail;
+            wf[f] = counted ? w : 0.0;
+            failv[f] = (uint8_t)(r.fail | (t_err << 1));
         }
         free(nz);
         free(llr);
+        free(app);
     }
     /* sums in frame order */
     double sw = 0.0, sw2 = 0.0;
@@ -153,7 +168,7 @@ int or_is_estimate(const or_code *c, const int32_t *ts, int a, const or_is_opts 
     for (int64_t f = 0; f < o->n_frames; f++) {
         sw += wf[f];
         sw2 += wf[f] * wf[f];
-        nf += failv[f];
+        nf += o->count_mode == OR_IS_COUNT_TS ? (failv[f] >> 1) & 1 : failv[f] & 1;
     }
     double K = (double)o->n_frames;
     double p = sw / K;
@@ -175,4 +190,33 @@ int or_is_estimate(const or_code *c, const int32_t *ts, int a, const or_is_opts 
     free(wf);
     free(failv);
     return 0;
+}
+
+/* Mean shift chosen by pilot runs (a reading of Cole's weighting, which leaves
+ * the shift open).  The grid is s_i = eps* (1/2 + i/16), i = 0..8; pilot i
+ * runs P frames with the estimate's options at s_i, on frame counters
+ * frame_base + 2^40 + i P (its own frames, none shared with the estimate).
+ * The chosen shift has the smallest relative variance Var / P_hat^2 among the
+ * grid points with at least 10 counted failures (the first such point on
+ * ties); without one it is eps*.  rv_out[9] (optional) receives each point's
+ * relative variance (-1 where it does not qualify). */
+double or_is_pilot_shift(const or_code *c, const int32_t *ts, int a, const or_is_opts *o,
+                         double eps_star, int64_t pilot_frames, double *rv_out) {
+    double best = -1.0, shift = eps_star;
+    for (int i = 0; i <= 8; i++) {
+        or_is_opts po = *o;
+        po.shift = eps_star * (0.5 + i / 16.0);
+        po.n_frames = pilot_frames;
+        po.frame_base = o->frame_base + (1ull << 40) + (uint64_t)i * (uint64_t)pilot_frames;
+        or_is_result r;
+        double rv = -1.0;
+        if (or_is_estimate(c, ts, a, &po, &r, NULL, NULL) == 0 && r.n_fail >= 10 && r.p_hat > 0.0)
+            rv = r.var / (r.p_hat * r.p_hat);
+        if (rv_out) rv_out[i] = rv;
+        if (rv >= 0.0 && (best < 0.0 || rv < best)) {
+            best = rv;
+            shift = po.shift;
+        }
+    }
+    return shift;
 }

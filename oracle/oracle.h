@@ -174,6 +174,9 @@ void or_normals(uint64_t seed, uint64_t frame, uint32_t stream, int n, double *o
 /* ---- importance sampling (Section I / II, Cole's TS weighting) ----------- */
 #define OR_IS_SPA 0
 #define OR_IS_LINEAR 1   /* test decoder: fails iff sum_{v in T} y_v < 0 */
+#define OR_IS_COUNT_ALL 0  /* every failure counts */
+#define OR_IS_COUNT_TS 1   /* only T's error events: at the end every bit of T and at most
+                            * 2a bits in all in error */
 typedef struct {
     int32_t decoder;        /* OR_IS_SPA, or OR_IS_LINEAR for the closed-form pin */
     int32_t max_iter;
@@ -184,15 +187,21 @@ typedef struct {
     uint64_t frame_base;
     uint32_t stream;        /* Philox stream tag */
     int32_t threads;
+    int32_t count_mode;     /* OR_IS_COUNT_ALL / OR_IS_COUNT_TS */
 } or_is_opts;
 typedef struct {
     double p_hat, var, ci_lo, ci_hi, sum_w, sum_w2;
     int64_t n, n_fail;
     double shift_used;
 } or_is_result;
-/* fail_out (optional, [n_frames]) receives each frame's failure flag. */
+/* fail_out (optional, [n_frames]) receives each frame's flags: bit 0 = the
+ * decode failed, bit 1 = it ended in T's error event (OR_IS_COUNT_TS). */
 int or_is_estimate(const or_code *c, const int32_t *ts, int a, const or_is_opts *o,
                    or_is_result *res, uint8_t *fail_out, int64_t *edge_updates);
+/* Pilot-chosen mean shift over the grid eps* (1/2 + i/16), i = 0..8, pilot_frames
+ * frames per point (see or_is.c); rv_out[9] optional. */
+double or_is_pilot_shift(const or_code *c, const int32_t *ts, int a, const or_is_opts *o,
+                         double eps_star, int64_t pilot_frames, double *rv_out);
 /* Critical impulse amplitude of the SPA decoder on the whole set (grid 2^-10). */
 double or_spa_eps_star(const or_code *c, const int32_t *ts, int a, double ebn0_db,
                        double rate, int max_iter, double eps_max);

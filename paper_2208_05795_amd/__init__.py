@@ -19,12 +19,15 @@ from . import _capi as A
 __all__ = ["DEC_LNMS", "Context", "Code", "TsRecord", "TsgError", "DEC_OMS", "DEC_SPA",
            "PAT_SINGLES", "PAT_PAIRS", "PAT_TRIPLES", "EXTRACT_PATH", "EXTRACT_CRITICAL",
            "LAYOUT_AUTO", "LAYOUT_REGISTER", "LAYOUT_STREAMED", "LAYOUT_STREAMED_GATHER",
-           "LAYOUT_STREAMED_ACCUM", "PAT_QC_ORBITS"]
+           "LAYOUT_STREAMED_ACCUM", "PAT_QC_ORBITS", "IS_COUNT_ALL", "IS_COUNT_TS", "SHIFT_EPS",
+           "SHIFT_PILOT"]
 
 DEC_OMS, DEC_SPA, DEC_LNMS = A.TS_DEC_OMS_I8, A.TS_DEC_SPA_F32, A.TS_DEC_LNMS_Q4
 PAT_SINGLES, PAT_PAIRS, PAT_TRIPLES = A.TS_PAT_SINGLES, A.TS_PAT_PAIRS, A.TS_PAT_TRIPLES
 PAT_QC_ORBITS = A.TS_PAT_QC_ORBITS
 EXTRACT_PATH, EXTRACT_CRITICAL = A.TS_EXTRACT_PATH, A.TS_EXTRACT_CRITICAL
+IS_COUNT_ALL, IS_COUNT_TS = A.TS_IS_COUNT_ALL, A.TS_IS_COUNT_TS
+SHIFT_EPS, SHIFT_PILOT = A.TS_SHIFT_EPS, A.TS_SHIFT_PILOT
 LAYOUT_AUTO, LAYOUT_REGISTER, LAYOUT_STREAMED = A.TS_LAYOUT_AUTO, A.TS_LAYOUT_REGISTER, A.TS_LAYOUT_STREAMED
 LAYOUT_STREAMED_GATHER, LAYOUT_STREAMED_ACCUM = A.TS_LAYOUT_STREAMED_GATHER, A.TS_LAYOUT_STREAMED_ACCUM
 
@@ -156,13 +159,15 @@ class Context:
     @staticmethod
     def _is_desc(code: "Code", ts_bits, ebn0_db: float, shift: float, n_frames: int,
                  seed: int, frame_base: int = 0, stream: int = 0, max_iter: int = 50,
-                 rate: Optional[float] = None, layout: int = 0, full_iterations: bool = False):
+                 rate: Optional[float] = None, layout: int = 0, full_iterations: bool = False,
+                 count_mode: int = IS_COUNT_ALL, shift_rule: int = SHIFT_EPS,
+                 pilot_frames: int = 0):
         t = _i32(ts_bits)
         rate = (1.0 - code.m / code.n) if rate is None else rate
         d = A.JobDesc()
         d.kind, d.code = A.TS_JOB_IS, code._h
         d.is_ = A.IsOpts(max_iter, ebn0_db, rate, shift, n_frames, seed, frame_base, stream,
-                         layout, int(full_iterations))
+                         layout, int(full_iterations), count_mode, shift_rule, pilot_frames)
         d.ts_bits, d.a = t.ctypes.data, t.size
         return d, t
 
@@ -397,12 +402,14 @@ class Code:
 
     def union_bound(self, n_ts: int, ebn0_db, n_frames: int, seed: int, shift: float = -1.0,
                     max_iter: int = 50, rate: Optional[float] = None, layout: int = 0,
-                    per_ts: bool = False) -> dict:
+                    per_ts: bool = False, count_mode: int = IS_COUNT_ALL,
+                    shift_rule: int = SHIFT_EPS, pilot_frames: int = 0) -> dict:
         """FER ~ sum over the first n_ts sets of the TS table of orbit x P_hat
         (ts_union_bound), one IS batch over all (set, SNR) pairs."""
         snr = np.ascontiguousarray(np.asarray(ebn0_db, dtype=np.float64).reshape(-1))
         rate = (1.0 - self.m / self.n) if rate is None else rate
-        o = A.UbOpts(n_ts, snr.size, snr.ctypes.data, max_iter, rate, shift, n_frames, seed, layout)
+        o = A.UbOpts(n_ts, snr.size, snr.ctypes.data, max_iter, rate, shift, n_frames, seed, layout,
+                     count_mode, shift_rule, pilot_frames)
         pts = (A.UbPoint * snr.size)()
         rs = (A.IsResult * (snr.size * n_ts))() if per_ts else None
         _check(lib().ts_union_bound(self.ctx.handle, self._h, C.byref(o), pts, rs))
@@ -419,11 +426,15 @@ class Code:
     def is_estimate(self, ts_bits, ebn0_db: float, shift: float, n_frames: int, seed: int,
                     frame_base: int = 0, stream: int = 0, max_iter: int = 50,
                     rate: Optional[float] = None, want_fail: bool = False,
-                    layout: int = 0, full_iterations: bool = False) -> dict:
+                    layout: int = 0, full_iterations: bool = False,
+                    count_mode: int = IS_COUNT_ALL, shift_rule: int = SHIFT_EPS,
+                    pilot_frames: int = 0) -> dict:
+        """want_fail: "fail" = per-frame flags (bit 0 the decode failed, bit 1 it
+        failed with every bit of the set in error at the end)."""
         rate = (1.0 - self.m / self.n) if rate is None else rate
         t = _i32(ts_bits)
         o = A.IsOpts(max_iter, ebn0_db, rate, shift, n_frames, seed, frame_base, stream, layout,
-                     int(full_iterations))
+                     int(full_iterations), count_mode, shift_rule, pilot_frames)
         r = A.IsResult()
         fo = np.zeros(n_frames, dtype=np.uint8) if want_fail else None
         _check(lib().ts_is_estimate(self.ctx.handle, self._h, t.ctypes.data, t.size, C.byref(o),

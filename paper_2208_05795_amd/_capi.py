@@ -15,6 +15,8 @@ TS_MEM_HOST, TS_MEM_DEVICE = 0, 1
 TS_LAYOUT_AUTO, TS_LAYOUT_REGISTER, TS_LAYOUT_STREAMED = 0, 1, 2
 TS_LAYOUT_STREAMED_GATHER, TS_LAYOUT_STREAMED_ACCUM = 3, 4
 TS_PAT_QC_ORBITS = 0x100
+TS_IS_COUNT_ALL, TS_IS_COUNT_TS = 0, 1
+TS_SHIFT_EPS, TS_SHIFT_PILOT = 0, 1
 TS_JOB_SEARCH, TS_JOB_IS = 1, 2
 TS_JOB_QUEUED, TS_JOB_RUNNING, TS_JOB_DONE, TS_JOB_CANCELLED = 0, 1, 2, 3
 
@@ -63,7 +65,8 @@ class IsOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("ebn0_db", C.c_double), ("rate", C.c_double),
                 ("shift", C.c_double), ("n_frames", C.c_int64), ("seed", C.c_uint64),
                 ("frame_base", C.c_uint64), ("stream", C.c_uint32), ("layout", C.c_int32),
-                ("full_iterations", C.c_int32)]
+                ("full_iterations", C.c_int32), ("count_mode", C.c_int32), ("shift_rule", C.c_int32),
+                ("pilot_frames", C.c_int64)]
 
 
 class IsResult(C.Structure):
@@ -75,7 +78,8 @@ class IsResult(C.Structure):
 class UbOpts(C.Structure):
     _fields_ = [("n_ts", C.c_int32), ("n_snr", C.c_int32), ("ebn0_db", C.c_void_p),
                 ("max_iter", C.c_int32), ("rate", C.c_double), ("shift", C.c_double),
-                ("n_frames", C.c_int64), ("seed", C.c_uint64), ("layout", C.c_int32)]
+                ("n_frames", C.c_int64), ("seed", C.c_uint64), ("layout", C.c_int32),
+                ("count_mode", C.c_int32), ("shift_rule", C.c_int32), ("pilot_frames", C.c_int64)]
 
 
 class UbPoint(C.Structure):

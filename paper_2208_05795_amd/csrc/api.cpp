@@ -573,6 +573,65 @@ int is_eps_shift(ts_exec &ex, ts_code *code, const int32_t *d_t, int32_t a, cons
     return TS_OK;
 }
 
+// Mean shift chosen by pilot runs (TS_SHIFT_PILOT; a reading of Cole's
+// weighting, which leaves the shift open).  Grid point i of a request (eps*
+// its set's impulse threshold) is s_i = eps* (kPilotF0 + i kPilotDf); its
+// pilot estimate uses the request's options with P frames of its own, frame
+// counters frame_base + kPilotFrameOffset + i P (the request's stream), so the
+// pilot shares no frame with the estimate itself.  The chosen point has the
+// smallest relative variance Var / P_hat^2 among the points with at least
+// kPilotMinFail counted failures (ties: the smaller shift); without such a
+// point the shift is eps*.  All pilots of all requests run as one batch.
+constexpr int kPilotPoints = 9;
+constexpr double kPilotF0 = 0.5, kPilotDf = 0.0625;
+constexpr int64_t kPilotDefaultFrames = 2000;
+constexpr int kPilotMinFail = 10;
+constexpr uint64_t kPilotFrameOffset = 1ull << 40;
+
+int pilot_shifts(ts_exec &ex, std::vector<PilotReq> &reqs) {
+    if (reqs.empty()) return TS_OK;
+    std::vector<BatchJob> jobs;
+    std::vector<ts_is_result> res(reqs.size() * kPilotPoints);
+    for (size_t r = 0; r < reqs.size(); ++r) {
+        const PilotReq &q = reqs[r];
+        const int64_t P = q.io.pilot_frames > 0 ? q.io.pilot_frames : kPilotDefaultFrames;
+        for (int i = 0; i < kPilotPoints; ++i) {
+            BatchJob b;
+            b.kind = TS_JOB_IS;
+            b.code = q.code;
+            b.io = q.io;
+            b.io.shift = q.eps * (kPilotF0 + i * kPilotDf);
+            b.io.n_frames = P;
+            b.io.frame_base = q.io.frame_base + kPilotFrameOffset + (uint64_t)i * (uint64_t)P;
+            b.ts_bits = q.bits;
+            b.a = q.a;
+            b.is = &res[r * kPilotPoints + i];
+            jobs.push_back(b);
+        }
+    }
+    const int rc = run_batch(ex, jobs);
+    if (rc) return rc;
+    for (const BatchJob &b : jobs)
+        if (b.status != TS_OK) {
+            set_error("%s", b.err.c_str());
+            return b.status;
+        }
+    for (size_t r = 0; r < reqs.size(); ++r) {
+        double best = -1.0, shift = reqs[r].eps;
+        for (int i = 0; i < kPilotPoints; ++i) {
+            const ts_is_result &x = res[r * kPilotPoints + i];
+            if (x.n_fail < kPilotMinFail || !(x.p_hat > 0.0)) continue;
+            const double rv = x.var / (x.p_hat * x.p_hat);
+            if (best < 0.0 || rv < best) {
+                best = rv;
+                shift = x.shift_used;
+            }
+        }
+        *reqs[r].shift = shift;
+    }
+    return TS_OK;
+}
+
 // IS estimate from the fixed-order sums red = {sum w, sum w^2, failures,
 // sum (w - p)^2} of K frames.
 void is_fill_result(const double red[4], int64_t K, double shift, ts_is_result *res) {
@@ -596,6 +655,9 @@ int check_is_opts(const ts_code *code, const int32_t *ts_bits, int32_t a, const 
     if (!(o->rate > 0.0 && o->rate <= 1.0)) { set_error("rate out of range"); return TS_E_INVAL; }
     if (!std::isfinite(o->ebn0_db) || !std::isfinite(o->shift)) { set_error("Eb/N0 and shift must be finite"); return TS_E_INVAL; }
     if (o->layout < TS_LAYOUT_AUTO || o->layout > TS_LAYOUT_STREAMED_ACCUM) { set_error("bad layout"); return TS_E_INVAL; }
+    if (o->count_mode != TS_IS_COUNT_ALL && o->count_mode != TS_IS_COUNT_TS) { set_error("bad count_mode"); return TS_E_INVAL; }
+    if (o->shift_rule != TS_SHIFT_EPS && o->shift_rule != TS_SHIFT_PILOT) { set_error("bad shift_rule"); return TS_E_INVAL; }
+    if (o->pilot_frames < 0 || o->pilot_frames > (1ll << 24)) { set_error("pilot_frames must be 0..2^24"); return TS_E_INVAL; }
     std::vector<int32_t> t(ts_bits, ts_bits + a);
     std::sort(t.begin(), t.end());
     for (int i = 0; i < a; ++i)
@@ -618,8 +680,14 @@ int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const 
     if (!d_t.p) return TS_E_NOMEM;
     TSG_HIP(hipMemcpyAsync(d_t.p, t.data(), a * 4, hipMemcpyHostToDevice, s));
     if (shift < 0.0) {
-        const int rc = is_eps_shift(ex, code, d_t.as<int32_t>(), a, o, &shift);
+        int rc = is_eps_shift(ex, code, d_t.as<int32_t>(), a, o, &shift);
         if (rc) return rc;
+        if (o->shift_rule == TS_SHIFT_PILOT) {
+            std::vector<PilotReq> req(1);
+            req[0] = PilotReq{code, t.data(), a, *o, shift, &shift};
+            rc = pilot_shifts(ex, req);
+            if (rc) return rc;
+        }
     }
     const int64_t K = o->n_frames;
     DBuf d_fail(ex, (size_t)K), d_wf(ex, (size_t)K * 8), d_misc(ex, 64 * 4), d_red(ex, 8 * 8),
@@ -637,6 +705,7 @@ int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const 
     L.frame_base = o->frame_base;
     L.stream = o->stream;
     L.fp_exit = o->full_iterations ? 0 : 1;
+    L.count_mode = o->count_mode;
     L.ts = d_t.as<int32_t>();
     L.a = a;
     L.fail = d_fail.as<unsigned char>();

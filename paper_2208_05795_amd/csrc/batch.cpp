@@ -122,6 +122,15 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
             if (rc) return rc;
             for (size_t j = 0; j < sets.size(); ++j) kv.second[j]->shift = sh[j];
         }
+        // pilot-chosen shifts: one batch of pilots for all such jobs
+        std::vector<PilotReq> req;
+        for (IItem &it : I)
+            if (it.b->io.shift < 0.0 && it.b->io.shift_rule == TS_SHIFT_PILOT)
+                req.push_back(PilotReq{it.b->code, it.b->ts_bits, it.b->a, it.b->io, it.shift, &it.shift});
+        if (!req.empty()) {
+            rc = pilot_shifts(ex, req);
+            if (rc) return rc;
+        }
     }
     // ---- groups -----------------------------------------------------------
     std::vector<Group> G;
@@ -252,6 +261,7 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
         L.frame_base = it.b->io.frame_base;
         L.stream = it.b->io.stream;
         L.fp_exit = it.b->io.full_iterations ? 0 : 1;
+        L.count_mode = it.b->io.count_mode;
         L.ts = (const int *)(arena + it.ts);
         L.a = it.b->a;
         L.fail = arena + it.fail;

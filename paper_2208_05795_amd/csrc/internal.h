@@ -92,7 +92,7 @@ struct DevCode {
 // LDS layout of a streamed frame (host and device).
 struct LdsG {
     int np, W;
-    size_t app, acc, imask, wsyn, pcnt, cls, qtab, extra, total;
+    size_t app, acc, imask, wsyn, pcnt, moved, cls, qtab, extra, total;
 };
 
 // qbytes: size of the QC index tables copied to LDS (0 = read g_cn / g_vslot);
@@ -112,6 +112,8 @@ __host__ __device__ inline LdsG lds_layout_g(int n, int T, int qbytes, bool acc 
     L.wsyn = o;
     o += (size_t)(T + 2) * 4;
     L.pcnt = o;
+    o += (size_t)(T + 2) * 4;
+    L.moved = o;   // per iteration: some check message changed
     o += (size_t)(T + 2) * 4;
     L.cls = o;   // class table: dc, c0, stride, off
     o += (size_t)(4 * kGMaxCls + 2) * 4;
@@ -308,7 +310,7 @@ struct SearchLaunch {
     int *err;
     unsigned char *gscr;            // grid x slot_bytes scratch (nullptr: none)
     long long slot_bytes, hist_off;
-    int fp_exit;                    // register kind: end decodes at a fixed point
+    int fp_exit;                    // end decodes at a fixed point
 };
 
 int plan_search(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter, SearchPlan *plan);
@@ -343,7 +345,8 @@ struct IsDev {
     unsigned long long *counters;
     unsigned char *gscr;   // per-workgroup scratch (nullptr: none)
     long long slot_bytes, lam_off;
-    int fp_exit;           // register kind: end decodes at a fixed point
+    int fp_exit;           // end decodes at a fixed point
+    int count_mode;        // TS_IS_COUNT_ALL / TS_IS_COUNT_TS
 };
 
 struct IsJob {
@@ -375,6 +378,7 @@ struct IsLaunch {
     unsigned long long *counters;
     unsigned char *gscr;    // grid x slot_bytes scratch
     int fp_exit;            // end decodes at a fixed point
+    int count_mode;         // TS_IS_COUNT_ALL / TS_IS_COUNT_TS
 };
 // IS launch shape (plan.slot_bytes of scratch per workgroup)
 int plan_is(ts_ctx *ctx, const ts_code *c, int max_iter, int layout, SearchPlan *plan);
@@ -439,6 +443,16 @@ struct BatchJob {
     std::string err;
 };
 int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs);
+// Pilot-chosen IS shifts (TS_SHIFT_PILOT) of several requests, one batch.
+struct PilotReq {
+    ts_code *code;
+    const int32_t *bits;   // host [a]
+    int32_t a;
+    ts_is_opts io;         // the estimate's options
+    double eps;            // eps* of the set (the grid's unit)
+    double *shift;         // out
+};
+int pilot_shifts(ts_exec &ex, std::vector<PilotReq> &reqs);
 int tune_for_batch(ts_exec &ex, std::vector<BatchJob> &jobs);   // api.cpp
 
 // serve.cpp

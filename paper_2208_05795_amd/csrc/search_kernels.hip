@@ -308,7 +308,9 @@ struct Frame {
 
 struct DecRes {
     int fail, iters, tmin;
-    int run;   // iterations computed (below iters when a fixed point ends the decode)
+    int run;          // iterations computed (below iters when a fixed point ends the decode)
+    int nerr;         // 1s in the final hard decision
+    const int *app;   // LDS: the APP values of the decode's final hard decision
 };
 
 template <int DC, int CPT>
@@ -343,8 +345,10 @@ __device__ __forceinline__ DecRes run_decode(const Frame &F, const int (&nb)[CPT
     int cur = 0, nxt = 1, spare = 2;
     int iters = T, wmin = INT_MAX, tmin = 0, fixed = 0;
     bool verify = false;   // iteration t compares its messages with those of t - 1
+    const int *last = F.app;
     for (int t = 1; t <= T + 1; ++t) {
         const int *A = F.app + cur * np;
+        last = A;   // APP_{t-1}: the final values when the decode ends in this iteration
         int *N = F.app + nxt * np;
         int unsat = 0;
         if (verify) {   // the thread's messages, contiguous
@@ -441,8 +445,10 @@ __device__ __forceinline__ DecRes run_decode(const Frame &F, const int (&nb)[CPT
     DecRes r;
     r.iters = iters;
     r.tmin = tmin;
-    r.fail = F.pcnt[iters] > 0;
+    r.nerr = F.pcnt[iters];
+    r.fail = r.nerr > 0;
     r.run = fixed ? fixed - 1 : iters;
+    r.app = last;
     return r;
 }
 
@@ -908,8 +914,10 @@ __device__ __forceinline__ DecRes run_decode_l(const Frame &F, const int (&nb)[C
     DecRes r;
     r.iters = iters;
     r.tmin = tmin;
-    r.fail = F.pcnt[iters] > 0;
+    r.nerr = F.pcnt[iters];
+    r.fail = r.nerr > 0;
     r.run = fixed ? fixed : iters;
+    r.app = F.app;
     return r;
 }
 
@@ -1068,12 +1076,19 @@ __device__ __forceinline__ void is_channel(const IsChan &a, int n, unsigned long
     }
 }
 
-// A finished frame (thread 0): its failure flag and the sum of the normals of
-// its TS bits, from which the reduction forms the importance weight.
-__device__ __forceinline__ void is_finish(const IsDev &a, int f, const DecRes &r, const float *tn) {
+// A finished frame (thread 0): its flags (bit 0 the decode failed, bit 1 it
+// ended in the set's own error event: every TS bit decided 1 and at most 2a
+// bits in error in all) and the sum of the normals of its TS bits, from which
+// the reduction forms the importance weight.
+__device__ __forceinline__ void is_finish(const IsDev &a, int f, const DecRes &r, const float *tn,
+                                          const int *tsl) {
     double st = 0.0;
-    for (int q = 0; q < a.a; ++q) st += (double)tn[q];
-    a.fail[f] = (unsigned char)r.fail;
+    int t_err = r.fail && r.nerr <= 2 * a.a;
+    for (int q = 0; q < a.a; ++q) {
+        st += (double)tn[q];
+        t_err &= r.app[tsl[q]] < 0;
+    }
+    a.fail[f] = (unsigned char)(r.fail | (t_err << 1));
     a.wf[f] = st;
 }
 
@@ -1107,7 +1122,7 @@ __device__ __forceinline__ void is_jobs(const IsJob *jobs, int n_jobs, int *queu
         const int f = it - (int)J.item0;
         const DecRes r = dec.decode_frame(f);
         my_iters += r.run;
-        if (tid == 0) is_finish(J.a, f, r, dec.tn);
+        if (tid == 0) is_finish(J.a, f, r, dec.tn, dec.tsl);
     }
     if (cur >= 0 && tid == 0) atomicAdd(&J.a.counters[1], my_iters);
 }
@@ -1198,9 +1213,12 @@ __device__ __forceinline__ void red_tree(double *s0, double *s1, double *s2, int
     }
 }
 
+// cmask selects the failures that count: 1 every failure, 2 those with every
+// TS bit in error.
 __global__ __launch_bounds__(kRedThreads) void k_is_reduce(const double *wf, const unsigned char *fail,
                                                           long long n, int mode, double mean,
-                                                          double wconst, double coef, double *part) {
+                                                          double wconst, double coef, int cmask,
+                                                          double *part) {
     __shared__ double s0[kRedThreads], s1[kRedThreads], s2[kRedThreads];
     const int t = threadIdx.x;
     const long long c0 = (long long)blockIdx.x * kRedChunk;
@@ -1209,11 +1227,12 @@ __global__ __launch_bounds__(kRedThreads) void k_is_reduce(const double *wf, con
     const long long lo = c0 + (long long)t * per, hi = lo + per < c1 ? lo + per : c1;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     for (long long i = lo; i < hi; ++i) {
-        const double w = fail[i] ? exp(wconst + coef * wf[i]) : 0.0;
+        const bool counted = (fail[i] & cmask) != 0;
+        const double w = counted ? exp(wconst + coef * wf[i]) : 0.0;
         if (mode == 0) {
             a0 += w;
             a1 += w * w;
-            a2 += (double)fail[i];
+            a2 += counted ? 1.0 : 0.0;
         } else {
             a0 += (w - mean) * (w - mean);
         }
@@ -1285,6 +1304,8 @@ struct GFrame {
     void *msg;                         // global message slots of this workgroup
     unsigned long long *hist;          // global [T][W] or nullptr
     int *wsyn, *pcnt;                  // LDS
+    int *moved;                        // LDS per iteration: a check message changed
+    int fp_exit;                       // end the decode at a fixed point
     const int *cdc, *cc0, *cstr, *coff;   // LDS copy of the class table
     const int *g_cn, *g_vslot;         // the code's slot tables
     int ncls, n, np, W, T, m, dv_pad, n_tab;
@@ -1301,9 +1322,11 @@ __device__ __forceinline__ int g_lambda(const GFrame &F, int v) {
 }
 
 // Check pass of one check (sorted position p, class q); returns the parity of
-// the hard decisions of APP_{t-1} on its variables.
+// the hard decisions of APP_{t-1} on its variables.  chg gathers the bits in
+// which a new message on a real edge differs from the old one (from t = 2 on).
 template <class Rule, int DC, class M, bool kAcc>
-__device__ __forceinline__ int check_g(const GFrame &F, int q, int p, int t, int offset) {
+__device__ __forceinline__ int check_g(const GFrame &F, int q, int p, int t, int offset,
+                                       unsigned &chg) {
     const int stride = F.cstr[q];
     const size_t base = (size_t)F.coff[q] + (size_t)(p - F.cc0[q]);
     int nb[DC], val[DC], c2v[DC];
@@ -1323,11 +1346,15 @@ __device__ __forceinline__ int check_g(const GFrame &F, int q, int p, int t, int
     for (int j = 0; j < DC; ++j) par ^= (val[j] < 0);
     if (t <= F.T) {
         M *msg = (M *)F.msg;
+        int old[DC];
 #pragma unroll
-        for (int j = 0; j < DC; ++j) c2v[j] = t == 1 ? 0 : (int)msg[base + (size_t)j * stride];
+        for (int j = 0; j < DC; ++j) c2v[j] = old[j] = t == 1 ? 0 : (int)msg[base + (size_t)j * stride];
         Rule::template update<DC>(val, c2v, nb, F.n, offset);
 #pragma unroll
-        for (int j = 0; j < DC; ++j) msg[base + (size_t)j * stride] = (M)c2v[j];
+        for (int j = 0; j < DC; ++j) {
+            msg[base + (size_t)j * stride] = (M)c2v[j];
+            if (nb[j] != F.n) chg |= (unsigned)(old[j] ^ c2v[j]);
+        }
         if constexpr (kAcc) {
             // APP_t - lambda accumulated in LDS (exact integer sums, any order)
 #pragma unroll
@@ -1346,9 +1373,10 @@ __device__ DecRes run_decode_g(const GFrame &F, int offset) {
     const int B = blockDim.x, NW = B >> 6;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const M *msg = (const M *)F.msg;
-    int iters = T, wmin = INT_MAX, tmin = 0;
+    int iters = T, wmin = INT_MAX, tmin = 0, fixed = 0;
     for (int t = 1; t <= T + 1; ++t) {
         int unsat = 0, q = 0;
+        unsigned chg = 0;
         for (int p = tid; p < mm; p += B) {
             while (q + 1 < F.ncls && p >= F.cc0[q + 1]) ++q;
             int par = 0;
@@ -1356,7 +1384,7 @@ __device__ DecRes run_decode_g(const GFrame &F, int offset) {
 #define TSG_GCASE(D)                                                             \
     case D:                                                                      \
         if constexpr (D <= DCMAX && !(DCMAX == 32 && D == 24))                   \
-            par = check_g<Rule, D, M, kAcc>(F, q, p, t, offset);                 \
+            par = check_g<Rule, D, M, kAcc>(F, q, p, t, offset, chg);            \
         break;
                 TSG_GCASE(3) TSG_GCASE(4) TSG_GCASE(6) TSG_GCASE(8)
                 TSG_GCASE(12) TSG_GCASE(16) TSG_GCASE(24) TSG_GCASE(32)
@@ -1368,6 +1396,7 @@ __device__ DecRes run_decode_g(const GFrame &F, int offset) {
         if (t >= 2) {
             const int us = wave_sum(unsat);
             if (lane == 0 && us) atomicAdd(&F.wsyn[t - 1], us);
+            if (__any(chg != 0u) && lane == 0) F.moved[t] = 1;
         }
         __syncthreads();
         if (t >= 2) {
@@ -1378,6 +1407,12 @@ __device__ DecRes run_decode_g(const GFrame &F, int offset) {
             }
             if (w == 0) {
                 iters = t - 1;
+                break;
+            }
+            // no check message changed in iteration t: APP_t = APP_{t-1}, and
+            // every later iteration repeats iteration t - 1 (fixed point)
+            if (F.fp_exit && t <= T && F.moved[t] == 0) {
+                fixed = t;
                 break;
             }
         }
@@ -1420,11 +1455,20 @@ __device__ DecRes run_decode_g(const GFrame &F, int offset) {
         if (lane == 0 && pc) atomicAdd(&F.pcnt[t], pc);
         __syncthreads();
     }
+    if (fixed) {
+        // as in run_decode: the decode ends at T as if run to the end; the
+        // history rows after `run` are not written (the candidate writer
+        // reads row `run` for them)
+        if (tid == 0) F.pcnt[T] = F.pcnt[fixed - 1];
+        __syncthreads();
+    }
     DecRes r;
     r.iters = iters;
     r.tmin = tmin;
-    r.fail = F.pcnt[iters] > 0;
-    r.run = iters;
+    r.nerr = F.pcnt[iters];
+    r.fail = r.nerr > 0;
+    r.run = fixed ? fixed - 1 : iters;
+    r.app = F.app;   // APP_{t-1} of the iteration that ended the decode
     return r;
 }
 
@@ -1460,6 +1504,7 @@ __device__ __forceinline__ void g_bind(const DevCode &cd, int T, unsigned char *
     F.app = (int *)(frame + L.app);
     F.wsyn = (int *)(frame + L.wsyn);
     F.pcnt = (int *)(frame + L.pcnt);
+    F.moved = (int *)(frame + L.moved);
     F.msg = uni(slot);
     F.n = n;
     F.np = L.np;
@@ -1498,6 +1543,7 @@ struct GSearchDec {
         imask = (unsigned long long *)(frame + L.imask);
         W = L.W;
         F.imask = imask;
+        F.fp_exit = uni(J.a.fp_exit);
         F.lam_g = nullptr;
         F.lam_base = base_lambda<Rule>(J.a);
         F.lam_imp = F.lam_base;
@@ -1514,6 +1560,7 @@ struct GSearchDec {
         for (int i = tid; i < F.T + 2; i += B) {
             F.wsyn[i] = 0;
             F.pcnt[i] = 0;
+            F.moved[i] = 0;
         }
         __syncthreads();
         return run_decode_g<Rule, DCMAX, M, kAcc>(F, a->offset);
@@ -1555,6 +1602,7 @@ struct GIsDec {
         g_bind(J.cd, J.a.max_iter, frame, slot, F, L, kAcc);
         lam = uni((int *)(slot + J.a.lam_off));
         F.imask = nullptr;
+        F.fp_exit = uni(J.a.fp_exit);
         F.lam_g = lam;
         F.lam_base = F.lam_imp = 0;
         F.hist = nullptr;
@@ -1578,6 +1626,7 @@ struct GIsDec {
         for (int i = tid; i < F.T + 2; i += B) {
             F.wsyn[i] = 0;
             F.pcnt[i] = 0;
+            F.moved[i] = 0;
         }
         __syncthreads();
         return run_decode_g<SpaIsRule, DCMAX, int, kAcc>(F, 0);
@@ -1940,6 +1989,7 @@ IsDev make_is_dev(const IsLaunch &a, const SearchPlan &plan) {
     d.counters = a.counters;
     d.gscr = a.gscr;
     d.fp_exit = a.fp_exit;
+    d.count_mode = a.count_mode;
     d.slot_bytes = (long long)plan.slot_bytes;
     d.lam_off = (long long)plan.hist_off;
     return d;
@@ -1955,7 +2005,7 @@ int launch_is_reduce(hipStream_t stream, const IsDev &d, const double *wf, const
         return TS_E_INVAL;
     }
     hipLaunchKernelGGL(k_is_reduce, dim3(np), dim3(kRedThreads), 0, stream, wf, fail, (long long)n, mode,
-                       mean, d.wconst, d.shift / d.sigma, part);
+                       mean, d.wconst, d.shift / d.sigma, d.count_mode == TS_IS_COUNT_TS ? 2 : 1, part);
     TSG_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_is_reduce_final, dim3(1), dim3(kRedThreads), 0, stream, (const double *)part, np,
                        mode, out);

@@ -70,6 +70,9 @@ int ts_union_bound(ts_ctx *ctx, ts_code *code, const ts_ub_opts *o, ts_ub_point 
             b.io.frame_base = 0;
             b.io.stream = ((uint32_t)si << 16) | (uint32_t)t;
             b.io.layout = o->layout;
+            b.io.count_mode = o->count_mode;
+            b.io.shift_rule = o->shift_rule;
+            b.io.pilot_frames = o->pilot_frames;
             b.ts_bits = bh.data() + off[t];
             b.a = rh[5 * t];
             b.is = &res[(size_t)si * o->n_ts + t];

@@ -1,6 +1,8 @@
-"""The fixed-point exit of the register-layout decoders: a decode whose check
-messages do not change in an iteration stops computing and fills in its
-remaining iterations (each repeats the last).  Every output must equal that of
+"""The fixed-point exit of the decoders: a decode whose check messages do not
+change in an iteration stops computing and fills in its remaining iterations
+(each repeats the last).  Register layout: a hash of each thread's messages
+triggers a verifying iteration; streamed layout: every check compares the old
+message it reads with the new one it writes.  Every output must equal that of
 the same call with every iteration computed (full_iterations), bit for bit:
 per-pattern arrays, the TS table, IS estimates and failure flags; the exit
 must also actually fire (fewer computed edge-updates) where decodes fail.
@@ -167,3 +169,55 @@ def test_batch_exit_identical(ctx):
     _say("batch: identical with and without the exit")
     peg.free()
     qc.free()
+
+
+@pytest.mark.parametrize("variant", ["gather", "accum"])
+def test_streamed_spa_exit_identical(ctx, variant):
+    import paper_2208_05795_amd as tsg
+    code = workloads.peg1008_code()
+    g = ctx.load_code(code)
+    allp = g.pattern_list([tsg.PAT_SINGLES, tsg.PAT_PAIRS, tsg.PAT_TRIPLES])
+    g.free()
+    rng = np.random.default_rng(23)
+    pats = np.ascontiguousarray(allp[np.sort(rng.choice(len(allp), 1024, replace=False))])
+    lay = tsg.LAYOUT_STREAMED_GATHER if variant == "gather" else tsg.LAYOUT_STREAMED_ACCUM
+    kw = dict(decoder=tsg.DEC_SPA, max_iter=50, k_max=32 * 1024, k_den=1024, a_max=12, layout=lay)
+    e0, e1 = _assert_same(*_search_both(ctx, code, pats, **kw), f"peg SPA streamed {variant}")
+    assert e1 < e0
+
+
+def test_streamed_oms_exit_identical(ctx):
+    import paper_2208_05795_amd as tsg
+    code = workloads.qc2640_code()
+    g = ctx.load_code(code)
+    pats = g.make_patterns(tsg.PAT_TRIPLES)[::16]
+    g.free()
+    kw = dict(decoder=tsg.DEC_OMS, max_iter=20, llr_scale=1.2, a_max=12,
+              layout=tsg.LAYOUT_STREAMED)
+    _assert_same(*_search_both(ctx, code, pats, **kw), "qc2640 OMS streamed x1.2")
+
+
+@pytest.mark.parametrize("variant", ["gather", "accum"])
+def test_streamed_is_exit_identical(ctx, variant):
+    """IS frames on a 46x68-base serving code (column weights 3..5) that only
+    the streamed layout holds at its size, at an SNR where frames fail."""
+    import paper_2208_05795_amd as tsg
+    pool = workloads.serving_pool()
+    code = sorted(pool, key=lambda c: c.n)[1]
+    g = ctx.load_code(code)
+    rp, col = g.csr()
+    bits = sorted(set(int(x) for x in col[rp[0]:rp[1]]))[:4]
+    lay = tsg.LAYOUT_STREAMED_GATHER if variant == "gather" else tsg.LAYOUT_STREAMED_ACCUM
+    res = []
+    for full in (True, False):
+        res.append(g.is_estimate(bits, 1.5, 1.0, 4096, seed=5, want_fail=True, layout=lay,
+                                 full_iterations=full))
+    g.free()
+    a, b = res
+    assert np.array_equal(a["fail"], b["fail"])
+    for k in ("p_hat", "var", "sum_w", "sum_w2", "n_fail", "shift_used"):
+        assert a[k] == b[k], k
+    e0, e1 = a["stats"]["edge_updates"], b["stats"]["edge_updates"]
+    _say(f"IS streamed {variant} ({code.name}): identical, {int(a['n_fail'])} failing frames; "
+         f"computed edge-updates {e0} full, {e1} with the exit ({e1 / max(e0, 1):.3f})")
+    assert e1 <= e0

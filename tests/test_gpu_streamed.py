@@ -79,8 +79,9 @@ def test_layouts_identical_oms(ctx, oracle_mod, name):
     for r, t, st, lab in ((rb, tb, sb, "gather"), (rc, tc, sc, "accum")):
         _same(ra, r, f"{name} {lab}")
         assert ta == t
-        # the register layout's fixed-point exit may compute fewer iterations
-        assert sa["edge_updates"] <= st["edge_updates"] and sa["decodes"] == st["decodes"]
+        # the layouts' fixed-point exits may stop after different iterations
+        # (the streamed one compares each iteration's messages with the last)
+        assert sa["decodes"] == st["decodes"]
     _say(f"  identical: {len(ta)} TS, {sa['edge_updates']:.3e} edge-updates; decode ms register "
          f"{sa['decode_ms']:.2f} streamed gather {sb['decode_ms']:.2f} accum {sc['decode_ms']:.2f}")
     g.free()

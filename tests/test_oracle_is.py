@@ -98,7 +98,7 @@ def test_is_zero_shift_is_plain_monte_carlo(oracle_mod, tiny):
     c, oc = tiny
     r = oracle_mod.is_estimate(oc, [1, 2], 1.0, 0.0, 5000, seed=3,
                                decoder=oracle_mod.IS_LINEAR, want_fail=True)
-    assert r["p_hat"] == r["n_fail"] / 5000 == r["fail"].mean()
+    assert r["p_hat"] == r["n_fail"] / 5000 == (r["fail"] & 1).mean()
     assert r["sum_w2"] == r["sum_w"]
 
 
@@ -130,3 +130,54 @@ def test_is_spa_unbiased_against_plain_monte_carlo(oracle_mod, tiny, ebn0, shift
     print(f"\nIS SPA {ebn0} dB s={shift}: plain MC {mc['p_hat']:.4e} ({mc['n_fail']} failures), "
           f"IS {r['p_hat']:.4e} (rel. sd {math.sqrt(r['var']) / r['p_hat']:.3f}), z = {z:.2f}")
     assert abs(z) < 3.0
+
+
+def test_is_count_ts_events(oracle_mod, tiny):
+    """Counting only the set's own error events (every bit of T and at most 2a
+    bits in error at the end): flag bit 1 implies bit 0, it matches a re-decode
+    of the frame, and the estimate is the sum over exactly those frames."""
+    c, oc = tiny
+    T = [s for a, b, s in oracle_mod.brute_ts_list(oc, 3) if a == 3][0]
+    ebn0, shift, K = 3.0, 1.5, 3000
+    al = oracle_mod.is_estimate(oc, T, ebn0, shift, K, seed=4, stream=9, want_fail=True)
+    ts = oracle_mod.is_estimate(oc, T, ebn0, shift, K, seed=4, stream=9, want_fail=True,
+                                count_mode=oracle_mod.IS_COUNT_TS)
+    assert np.array_equal(al["fail"], ts["fail"])
+    f = ts["fail"]
+    assert ((f & 2) == 0).all() or (f[(f & 2) != 0] & 1).all()
+    assert ts["n_fail"] == int(((f >> 1) & 1).sum()) and al["n_fail"] == int((f & 1).sum())
+    assert 0 < ts["n_fail"] < al["n_fail"]
+    assert ts["p_hat"] <= al["p_hat"]
+    s2 = oracle_mod.sigma2(ebn0, 0.5)
+    sig = math.sqrt(s2)
+    rng = np.random.default_rng(2)
+    for fr in rng.choice(K, 40, replace=False):
+        n = oracle_mod.normals(4, int(fr), 9, oc.n)
+        y = 1.0 + sig * n
+        y[list(T)] -= shift
+        d = oracle_mod.decode_spa(oc, 2.0 * y / s2, 50)
+        err = d["app"] < 0
+        want = d["fail"] and err[list(T)].all() and err.sum() <= 2 * len(T)
+        assert bool(f[fr] & 1) == bool(d["fail"]) and bool(f[fr] & 2) == bool(want), fr
+
+
+def test_is_pilot_shift_rule(oracle_mod, tiny):
+    """The pilot rule picks, among the grid eps* (1/2 + i/16), the point with
+    the smallest relative variance (at least 10 counted failures), each point
+    estimated on its own frames frame_base + 2^40 + i P."""
+    c, oc = tiny
+    T = [s for a, b, s in oracle_mod.brute_ts_list(oc, 3) if a == 3][0]
+    ebn0, P = 4.0, 600
+    eps = oracle_mod.spa_eps_star(oc, T, ebn0)
+    s, rv = oracle_mod.is_pilot_shift(oc, T, ebn0, eps, P, seed=3, stream=5,
+                                      count_mode=oracle_mod.IS_COUNT_TS)
+    want = []
+    for i in range(9):
+        r = oracle_mod.is_estimate(oc, T, ebn0, eps * (0.5 + i / 16.0), P, seed=3, stream=5,
+                                   frame_base=(1 << 40) + i * P, count_mode=oracle_mod.IS_COUNT_TS)
+        want.append(r["var"] / r["p_hat"] ** 2 if r["n_fail"] >= 10 else -1.0)
+    assert np.allclose(rv, want, rtol=1e-12)
+    ok = [i for i in range(9) if want[i] >= 0]
+    assert ok
+    best = min(ok, key=lambda i: (want[i], i))
+    assert s == eps * (0.5 + best / 16.0)
