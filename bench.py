@@ -226,7 +226,7 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "i8+f32", "data": "synthetic",
+        "dtype": "i8+q20/f32", "data": "synthetic",
         "config": {"workload": "peg1008: (3,6) PEG N=1008 M=504, singles+pairs(d<=4)+triples, "
                                "OMS-i8 20it + SPA-f32 50it, a_max 12, 3 dB, + IS top-4 TS",
                    "patterns": int(P), "is_frames_per_ts": args.is_frames},

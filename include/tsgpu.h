@@ -141,7 +141,9 @@ int ts_make_patterns(ts_ctx *ctx, const ts_code *code, int32_t kind, int32_t *ou
 /* ---- impulse search with bisection (Section III) --------------------------- */
 
 #define TS_DEC_OMS_I8 0     /* offset min-sum, saturating int8 messages */
-#define TS_DEC_SPA_F32 1    /* sum-product, float32 */
+#define TS_DEC_SPA_F32 1    /* sum-product: float32 phi arithmetic; channel values,
+                             * messages and APP sums stored as Q20 fixed point
+                             * (int32, step 2^-20) */
 /* quantised normalised layered min-sum (Section III, Fig. 2): channel values
  * and check-to-variable messages on 4 bits ([-7, 7]; llr_scale sets the
  * channel scale, q = sat7(round(llr_scale h))), variable-to-check messages and
