@@ -52,6 +52,9 @@ VALU_SLOTS_PER_EU = {"oms": 15.0, "spa": 2 * (3 * 4 + 5) + 6.0}
 # HBM traffic per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled x2 and x1 by a 1 GiB copy); None once the kernel changes.
 MEASURED_TRAFFIC_BYTES = {"spa": (582.81e6 + 10101.54e6)}
+# Same for the streamed-layout launch of the QC-2640 triples search (qc2640
+# section); None until measured on the current kernel.
+MEASURED_STREAMED_TRAFFIC_BYTES = None
 
 
 def parse():
@@ -70,7 +73,9 @@ def parse():
     p.add_argument("--no-layered", action="store_true")
     p.add_argument("--only", choices=["batch", "serve", "qc2640", "layered"],
                    help="run only this section (profiling aid); prints its JSON object")
-    p.add_argument("--serve-seconds", type=float, default=10.0)
+    p.add_argument("--serve-seconds", type=float, default=60.0)
+    p.add_argument("--serve-capacity-jobs", type=int, default=300,
+                   help="jobs of the stream rerun all at once and through the plain calls")
     p.add_argument("--serve-rate", type=float, default=20.0)
     return p.parse_args()
 
@@ -88,7 +93,8 @@ def main():
 
     if args.only:
         fn = {"batch": lambda: bench_batch(tsg),
-              "serve": lambda: bench_serve(tsg, args.serve_seconds, args.serve_rate),
+              "serve": lambda: bench_serve(tsg, args.serve_seconds, args.serve_rate,
+                                           capacity_jobs=args.serve_capacity_jobs),
               "qc2640": lambda: bench_qc2640(tsg),
               "layered": lambda: bench_layered(tsg)}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
@@ -240,7 +246,8 @@ def main():
     if not args.no_batch:
         line["batched"] = bench_batch(tsg)
     if not args.no_serve:
-        line["served"] = bench_serve(tsg, args.serve_seconds, args.serve_rate)
+        line["served"] = bench_serve(tsg, args.serve_seconds, args.serve_rate,
+                                     capacity_jobs=args.serve_capacity_jobs)
     if not args.no_qc2640:
         line["qc2640"] = bench_qc2640(tsg)
     if not args.no_layered:
@@ -533,12 +540,12 @@ def _plain_run(tsg, pool, graphs, jobs):
     return {"edge_updates": int(eu), "seconds": wall, "edge_updates_per_s": eu / wall}
 
 
-def bench_serve(tsg, seconds, rate, stress_seconds=5.0):
+def bench_serve(tsg, seconds, rate, stress_seconds=5.0, capacity_jobs=300):
     """Poisson arrivals of search and IS jobs on the 46x68-base code pool:
-    the paced stream under a 32 GiB HBM budget (latency), the same jobs all
-    submitted at once (capacity) and one after another through the plain
-    per-job calls, and a short paced stream under a 1 GiB budget (admission
-    stress)."""
+    the paced stream under a 32 GiB HBM budget (latency), the stream's first
+    capacity_jobs jobs all submitted at once (capacity) and one after another
+    through the plain per-job calls, and a short paced stream under a 1 GiB
+    budget (admission stress)."""
     import numpy as np
     import workloads
     pool = workloads.serving_pool()
@@ -553,10 +560,11 @@ def bench_serve(tsg, seconds, rate, stress_seconds=5.0):
     jobs = _serve_stream(pool, graphs, rng, seconds, rate)
     _say(f"served: {len(jobs)} jobs paced over {seconds:.0f} s")
     paced = _serve_run(tsg, pool, graphs, jobs, 32 << 30, True)
-    _say("served: the same jobs submitted at once")
-    burst = _serve_run(tsg, pool, graphs, jobs, 32 << 30, False)
+    cap = jobs[:capacity_jobs]
+    _say(f"served: the first {len(cap)} jobs submitted at once")
+    burst = _serve_run(tsg, pool, graphs, cap, 32 << 30, False)
     _say("plain: the same jobs one after another")
-    plain = _plain_run(tsg, pool, graphs, jobs)
+    plain = _plain_run(tsg, pool, graphs, cap)
     stress_jobs = _serve_stream(pool, graphs, np.random.default_rng(55), stress_seconds, rate)
     _say(f"served: {len(stress_jobs)} jobs paced over {stress_seconds:.0f} s under a 1 GiB budget")
     stress = _serve_run(tsg, pool, graphs, stress_jobs, 1 << 30, True)
@@ -564,7 +572,7 @@ def bench_serve(tsg, seconds, rate, stress_seconds=5.0):
                        "(N up to 25.7k), 50/50 search (OMS-i8 20it) / IS (SPA-f32 50it, 2..5 dB), "
                        "10^3..10^5 frames log-uniform, 4 worker slots, 32 GiB HBM budget"}
     out.update(paced)
-    out["all_at_once"] = burst
+    out["all_at_once"] = dict(burst, jobs_of_stream=len(cap))
     out["plain_sequential"] = plain
     out["served_vs_plain"] = burst["edge_updates_per_s"] / plain["edge_updates_per_s"]
     out["stress_1GiB"] = stress
@@ -597,13 +605,31 @@ def bench_qc2640(tsg):
     t_reduced = time.perf_counter() - t0
     same = bool(np.array_equal(recs[["a", "b", "orbit", "k_crit"]], recs_r[["a", "b", "orbit", "k_crit"]]))
     spectrum = g.spectrum(a_max=12, b_max=12, by_orbit=False)
+    # the same search in the streamed layout (messages through global memory),
+    # the form the edge-major roofline describes
+    g.reset_ts()
+    rs = g.impulse_search(pats, layout=tsg.LAYOUT_STREAMED, **kw)
+    recs_s, _ = g.collect_arrays()
+    st_s = rs["stats"]
+    same_s = bool(np.array_equal(recs, recs_s))
     n_ts = min(16, len(recs_r))
     snrs = [2.0, 3.0, 4.0, 5.0]
     t0 = time.perf_counter()
-    ub = g.union_bound(n_ts, snrs, 100000, seed=3, shift=-1.0, per_ts=True)
+    ub = g.union_bound(n_ts, snrs, 100000, seed=3, shift=-1.0, per_ts=True,
+                       count_mode=tsg.IS_COUNT_TS, shift_rule=tsg.SHIFT_PILOT)
     t_ub = time.perf_counter() - t0
     eu_ub = ub["stats"]["edge_updates"]
     ctx.close()
+    launch_s = st_s["decode_ms"] * 1e-3 / max(st_s["decode_launches"], 1)
+    eu_launch = st_s["edge_updates"] / max(st_s["decode_launches"], 1)
+    ach = BYTES_PER_EU["spa"] * eu_launch / launch_s / 1e9
+    roof_s = {"bound": "hbm", "kernel": "k_search_g<SpaRule>", "unit": "GB/s",
+              "bytes_per_edge_update": BYTES_PER_EU["spa"], "units_per_launch": eu_launch,
+              "launch_ms": launch_s * 1e3, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+              "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": MEASURED_STREAMED_TRAFFIC_BYTES,
+              "variant": "accumulating" if st_s["checks_per_thread"] else "gathering",
+              "grid_blocks": st_s["grid_blocks"], "block_threads": st_s["block_threads"],
+              "same_ts": same_s}
     cells = {f"{a},{b}": int(spectrum[a, b]) for a in range(spectrum.shape[0])
              for b in range(spectrum.shape[1]) if spectrum[a, b]}
     return {"workload": "QC (3,6) N=2640 Z=440 girth 8 (seed 3): SPA-f32 50it search over "
@@ -613,14 +639,18 @@ def bench_qc2640(tsg):
             "search": {"seconds": t_search, "edge_updates": eu_search,
                        "edge_updates_per_s": eu_search / t_search,
                        "hbm_equivalent_frac": BYTES_PER_EU["spa"] * eu_search / t_search / (HBM_PEAK_GBS * 1e9)},
+            "roofline_streamed": roof_s,
             "search_orbit_reduced": {"patterns": int(len(reps)), "seconds": t_reduced,
                                      "edge_updates": rr["stats"]["edge_updates"],
                                      "speedup": t_search / t_reduced, "same_ts": same},
             "union_bound": {"seconds": t_ub, "edge_updates": eu_ub, "edge_updates_per_s": eu_ub / t_ub,
                             "fer": {f"{p['ebn0_db']:g}dB": {"fer": p["fer"], "ci": [p["ci_lo"], p["ci_hi"]]}
                                     for p in ub["points"]},
-                            # per SNR, per set of the table: (shift eps*, failing frames, P_hat)
-                            "per_ts": {f"{p['ebn0_db']:g}dB": [[r["shift_used"], r["n_fail"], r["p_hat"]]
+                            "estimator": "mean shift chosen by pilots over eps* (1/2 + i/16); "
+                                         "counts the set's own error events",
+                            # per SNR, per set of the table: (shift, counted frames, P_hat, CI)
+                            "per_ts": {f"{p['ebn0_db']:g}dB": [[r["shift_used"], r["n_fail"], r["p_hat"],
+                                                                [r["ci_lo"], r["ci_hi"]]]
                                                                for r in rows]
                                        for p, rows in zip(ub["points"], ub["per_ts"])}}}
 
