@@ -241,6 +241,8 @@ int ts_reset_ts(ts_ctx *ctx, ts_code *code);
                              * bit of T in error (the frames of T's own error event) */
 #define TS_SHIFT_EPS 0      /* shift < 0: s = eps* of the SPA impulse on the whole set */
 #define TS_SHIFT_PILOT 1    /* shift < 0: s chosen by pilot runs (ts_is_estimate) */
+#define TS_SHIFT_MIX 2      /* shift < 0: a mixture of the shifts eps* k/16, k = 0..16
+                             * (ts_is_estimate) */
 
 typedef struct {
     int32_t max_iter;        /* SPA iterations */
@@ -253,7 +255,7 @@ typedef struct {
     int32_t layout;          /* TS_LAYOUT_* (AUTO: register layout when it fits) */
     int32_t full_iterations; /* as in ts_search_opts (also for the eps* searches) */
     int32_t count_mode;      /* TS_IS_COUNT_ALL or TS_IS_COUNT_TS */
-    int32_t shift_rule;      /* TS_SHIFT_EPS or TS_SHIFT_PILOT (used when shift < 0) */
+    int32_t shift_rule;      /* TS_SHIFT_EPS, TS_SHIFT_PILOT or TS_SHIFT_MIX (shift < 0) */
     int64_t pilot_frames;    /* TS_SHIFT_PILOT: frames per grid point (0: 2000) */
 } ts_is_opts;
 
@@ -263,12 +265,26 @@ typedef struct {
     double shift_used;
 } ts_is_result;
 
-/* Frame f draws n_v ~ N(0,1) from Philox4x32-10 (counter (v>>2, f_lo, f_hi,
- * stream), key = seed, Box-Muller), receives y_v = 1 - s[v in T] + sigma n_v,
- * is decoded by float32 SPA, and contributes 1[fail] w with
- * w = exp(-a s^2/(2 sigma^2) + (s/sigma) sum_{v in T} n_v).  P = mean, Var =
- * sample variance / K, 95% CI = P +- 1.96 sqrt(Var).  fail_out (optional host
- * array [n_frames]) receives each frame's failure flag. */
+/* Importance sampling of one set T (Section I/II, Cole's TS weighting; the
+ * estimator is a reading, the paper leaves it open).  Frame f draws
+ * n_v ~ N(0,1) from Philox4x32-10 (counter (v>>2, f_lo, f_hi, stream), key =
+ * seed, Box-Muller), receives y_v = 1 - s[v in T] + sigma n_v, is decoded by
+ * the sum-product decoder, and contributes 1[counted] w, where counted is
+ * "failed" (TS_IS_COUNT_ALL) or "ended in T's own error event: every bit of T
+ * and at most 2a bits in all decided 1" (TS_IS_COUNT_TS), and
+ * w = exp(-a s^2/(2 sigma^2) + (s/sigma) sum_{v in T} n_v) is the likelihood
+ * ratio.  P = mean, Var = sample variance / K, 95% CI = P +- 1.96 sqrt(Var).
+ * The shift s: the given one (shift >= 0); eps* of the SPA impulse on the
+ * whole set (TS_SHIFT_EPS); the grid point eps* (1/2 + i/16), i = 0..8, whose
+ * pilot estimate (its own frames frame_base + 2^40 + i P, P = pilot_frames)
+ * has the least relative variance among points with >= 10 counted frames
+ * (TS_SHIFT_PILOT); or, TS_SHIFT_MIX, the frames split in frame order over
+ * the 17 shifts s_k = eps* k/16 (frame f in component floor(17 f / K)), each
+ * counted frame weighted by the balance heuristic
+ * w = 1 / sum_k (K_k/K) exp((s_k/sigma) D - a s_k^2/(2 sigma^2)),
+ * D = sum_{v in T} (1 - y_v)/sigma (shift_used reports eps*).  fail_out
+ * (optional host array [n_frames]) receives each frame's flags: bit 0 the
+ * decode failed, bit 1 it ended in T's own error event. */
 int ts_is_estimate(ts_ctx *ctx, ts_code *code, const int32_t *ts_bits, int32_t a,
                    const ts_is_opts *opts, ts_is_result *res, uint8_t *fail_out);
 
@@ -306,7 +322,7 @@ typedef struct {
     uint64_t seed;           /* Philox key; stream tag of (set t, SNR i) = (i << 16) | t */
     int32_t layout;          /* TS_LAYOUT_* */
     int32_t count_mode;      /* TS_IS_COUNT_ALL or TS_IS_COUNT_TS (as in ts_is_opts) */
-    int32_t shift_rule;      /* TS_SHIFT_EPS or TS_SHIFT_PILOT (as in ts_is_opts) */
+    int32_t shift_rule;      /* TS_SHIFT_EPS, TS_SHIFT_PILOT or TS_SHIFT_MIX (as in ts_is_opts) */
     int64_t pilot_frames;    /* as in ts_is_opts */
 } ts_ub_opts;
 

@@ -45,7 +45,8 @@ class IsOpts(C.Structure):
     _fields_ = [("decoder", C.c_int32), ("max_iter", C.c_int32), ("ebn0_db", C.c_double), ("rate", C.c_double),
                 ("shift", C.c_double), ("n_frames", C.c_int64), ("seed", C.c_uint64),
                 ("frame_base", C.c_uint64), ("stream", C.c_uint32), ("threads", C.c_int32),
-                ("count_mode", C.c_int32)]
+                ("count_mode", C.c_int32), ("n_mix", C.c_int32), ("mix_s0", C.c_double),
+                ("mix_ds", C.c_double)]
 
 
 class IsResult(C.Structure):
@@ -341,13 +342,15 @@ IS_COUNT_ALL, IS_COUNT_TS = 0, 1
 def is_estimate(oc: OCode, ts, ebn0_db: float, shift: float, n_frames: int, seed: int,
                 frame_base: int = 0, stream: int = 0, max_iter: int = 50,
                 rate: Optional[float] = None, threads: int = 0, want_fail: bool = False,
-                decoder: int = IS_SPA, count_mode: int = 0):
-    """want_fail: "fail" = per-frame flags (bit 0 failed, bit 1 failed with all
-    of T in error); count_mode IS_COUNT_TS counts only the latter."""
+                decoder: int = IS_SPA, count_mode: int = 0, mix=None):
+    """want_fail: "fail" = per-frame flags (bit 0 failed, bit 1 the set's own
+    error event); count_mode IS_COUNT_TS counts only the latter.  mix = (m, s0,
+    ds): the frames split over the m shifts s0 + k ds (balance heuristic)."""
     t = _i32(ts)
     rate = oc.code.rate if rate is None else rate
+    m, s0, ds = mix if mix else (0, 0.0, 0.0)
     o = IsOpts(decoder, max_iter, ebn0_db, rate, shift, n_frames, seed, frame_base, stream,
-               threads, count_mode)
+               threads, count_mode, m, s0, ds)
     r = IsResult()
     fo = np.zeros(n_frames, dtype=np.uint8) if want_fail else None
     eu = C.c_int64()
@@ -370,7 +373,7 @@ def is_pilot_shift(oc: OCode, ts, ebn0_db: float, eps_star: float, pilot_frames:
     t = _i32(ts)
     rate = oc.code.rate if rate is None else rate
     o = IsOpts(IS_SPA, max_iter, ebn0_db, rate, 0.0, 2, seed, frame_base, stream, threads,
-               count_mode)
+               count_mode, 0, 0.0, 0.0)
     rv = np.zeros(9, dtype=np.float64)
     s = lib().or_is_pilot_shift(oc.handle, t, t.size, C.byref(o), eps_star, pilot_frames, rv)
     return s, rv

@@ -16,6 +16,14 @@
  * error in all (the failures of the union bound's term for T; wide decoding
  * failures and other sets' events are not T's).
  *
+ * A mixture of m shifts s_k = mix_s0 + k mix_ds (multiple importance sampling
+ * with the balance heuristic): frame f is drawn at the shift of component
+ * j = floor(f m / K), so the components hold K_k frames each, in frame order,
+ * and a counted frame weighs
+ *   w = p(y) / sum_k (K_k / K) p_k(y),   p the unshifted and p_k the
+ * shifted Gaussian densities of the a TS bits; with D = sum_{v in T} (1 - y_v) / sigma,
+ * p_k(y) / p(y) = exp((s_k / sigma) D - a s_k^2 / (2 sigma^2)).
+ *
  * Noise comes from Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random
  * numbers: as easy as 1, 2, 3", SC'11): counter (v>>2, frame_lo, frame_hi,
  * stream), key = the 64-bit seed; the four words give the normals of variables
@@ -109,7 +117,6 @@ int or_is_estimate(const or_code *c, const int32_t *ts, int a, const or_is_opts 
     if (o->n_frames < 2 || a < 1 || o->max_iter < 1) return -1;
     if (o->count_mode != OR_IS_COUNT_ALL && o->count_mode != OR_IS_COUNT_TS) return -1;
     double sigma2 = or_sigma2(o->ebn0_db, o->rate), sigma = sqrt(sigma2);
-    double s = o->shift;
     uint8_t *in_t = calloc((size_t)c->n, 1);
     for (int i = 0; i < a; i++) in_t[ts[i]] = 1;
     double *wf = malloc(sizeof(double) * (size_t)o->n_frames);   /* 1[fail] w per frame */
@@ -129,6 +136,8 @@ int or_is_estimate(const or_code *c, const int32_t *ts, int a, const or_is_opts 
 #pragma omp for schedule(dynamic, 64)
         for (int64_t f = 0; f < o->n_frames; f++) {
             or_normals(o->seed, o->frame_base + (uint64_t)f, o->stream, c->n, nz);
+            double s = o->shift;
+            if (o->n_mix > 0) s = o->mix_s0 + (double)((f * o->n_mix) / o->n_frames) * o->mix_ds;
             double sum_t = 0.0, sum_y = 0.0;
             for (int v = 0; v < c->n; v++) {
                 double y = 1.0 - (in_t[v] ? s : 0.0) + sigma * nz[v];
@@ -154,7 +163,22 @@ int or_is_estimate(const or_code *c, const int32_t *ts, int a, const or_is_opts 
             for (int v = 0; v < c->n; v++) n_err += app[v] < 0.0;
             t_err = t_err && n_err <= 2 * a;
             const int counted = o->count_mode == OR_IS_COUNT_TS ? t_err : r.fail;
-            double w = exp(-a * s * s / (2.0 * sigma2) + (s / sigma) * sum_t);
+            double w;
+            if (o->n_mix > 0) {
+                /* D = sum over T of (1 - y_v) / sigma = a s / sigma - sum_t */
+                const double D = a * s / sigma - sum_t;
+                double den = 0.0;
+                for (int k = 0; k < o->n_mix; k++) {
+                    const double sk = o->mix_s0 + k * o->mix_ds;
+                    const int64_t f0 = (k * o->n_frames + o->n_mix - 1) / o->n_mix;
+                    const int64_t f1 = ((k + 1) * o->n_frames + o->n_mix - 1) / o->n_mix;
+                    den += (double)(f1 - f0) / (double)o->n_frames *
+                           exp((sk / sigma) * D - a * sk * sk / (2.0 * sigma2));
+                }
+                w = 1.0 / den;
+            } else {
+                w = exp(-a * s * s / (2.0 * sigma2) + (s / sigma) * sum_t);
+            }
             wf[f] = counted ? w : 0.0;
             failv[f] = (uint8_t)(r.fail | (t_err << 1));
         }
@@ -183,7 +207,7 @@ int or_is_estimate(const or_code *c, const int32_t *ts, int a, const or_is_opts 
     res->sum_w2 = sw2;
     res->n = o->n_frames;
     res->n_fail = nf;
-    res->shift_used = s;
+    res->shift_used = o->n_mix > 0 ? o->mix_s0 + (o->n_mix - 1) * o->mix_ds : o->shift;
     if (edge_updates) *edge_updates = eu;
     if (fail_out) memcpy(fail_out, failv, (size_t)o->n_frames);
     free(in_t);

@@ -188,6 +188,8 @@ typedef struct {
     uint32_t stream;        /* Philox stream tag */
     int32_t threads;
     int32_t count_mode;     /* OR_IS_COUNT_ALL / OR_IS_COUNT_TS */
+    int32_t n_mix;          /* 0: every frame at `shift`; m > 0: a mixture of m shifts */
+    double mix_s0, mix_ds;  /* component k: shift mix_s0 + k mix_ds (see or_is.c) */
 } or_is_opts;
 typedef struct {
     double p_hat, var, ci_lo, ci_hi, sum_w, sum_w2;

@@ -20,14 +20,14 @@ __all__ = ["DEC_LNMS", "Context", "Code", "TsRecord", "TsgError", "DEC_OMS", "DE
            "PAT_SINGLES", "PAT_PAIRS", "PAT_TRIPLES", "EXTRACT_PATH", "EXTRACT_CRITICAL",
            "LAYOUT_AUTO", "LAYOUT_REGISTER", "LAYOUT_STREAMED", "LAYOUT_STREAMED_GATHER",
            "LAYOUT_STREAMED_ACCUM", "PAT_QC_ORBITS", "IS_COUNT_ALL", "IS_COUNT_TS", "SHIFT_EPS",
-           "SHIFT_PILOT"]
+           "SHIFT_PILOT", "SHIFT_MIX"]
 
 DEC_OMS, DEC_SPA, DEC_LNMS = A.TS_DEC_OMS_I8, A.TS_DEC_SPA_F32, A.TS_DEC_LNMS_Q4
 PAT_SINGLES, PAT_PAIRS, PAT_TRIPLES = A.TS_PAT_SINGLES, A.TS_PAT_PAIRS, A.TS_PAT_TRIPLES
 PAT_QC_ORBITS = A.TS_PAT_QC_ORBITS
 EXTRACT_PATH, EXTRACT_CRITICAL = A.TS_EXTRACT_PATH, A.TS_EXTRACT_CRITICAL
 IS_COUNT_ALL, IS_COUNT_TS = A.TS_IS_COUNT_ALL, A.TS_IS_COUNT_TS
-SHIFT_EPS, SHIFT_PILOT = A.TS_SHIFT_EPS, A.TS_SHIFT_PILOT
+SHIFT_EPS, SHIFT_PILOT, SHIFT_MIX = A.TS_SHIFT_EPS, A.TS_SHIFT_PILOT, A.TS_SHIFT_MIX
 LAYOUT_AUTO, LAYOUT_REGISTER, LAYOUT_STREAMED = A.TS_LAYOUT_AUTO, A.TS_LAYOUT_REGISTER, A.TS_LAYOUT_STREAMED
 LAYOUT_STREAMED_GATHER, LAYOUT_STREAMED_ACCUM = A.TS_LAYOUT_STREAMED_GATHER, A.TS_LAYOUT_STREAMED_ACCUM
 

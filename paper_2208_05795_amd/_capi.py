@@ -16,7 +16,7 @@ TS_LAYOUT_AUTO, TS_LAYOUT_REGISTER, TS_LAYOUT_STREAMED = 0, 1, 2
 TS_LAYOUT_STREAMED_GATHER, TS_LAYOUT_STREAMED_ACCUM = 3, 4
 TS_PAT_QC_ORBITS = 0x100
 TS_IS_COUNT_ALL, TS_IS_COUNT_TS = 0, 1
-TS_SHIFT_EPS, TS_SHIFT_PILOT = 0, 1
+TS_SHIFT_EPS, TS_SHIFT_PILOT, TS_SHIFT_MIX = 0, 1, 2
 TS_JOB_SEARCH, TS_JOB_IS = 1, 2
 TS_JOB_QUEUED, TS_JOB_RUNNING, TS_JOB_DONE, TS_JOB_CANCELLED = 0, 1, 2, 3
 

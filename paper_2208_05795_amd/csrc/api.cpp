@@ -632,6 +632,20 @@ int pilot_shifts(ts_exec &ex, std::vector<PilotReq> &reqs) {
     return TS_OK;
 }
 
+// The mixture of TS_SHIFT_MIX up to eps* (a reading of Cole's weighting): the
+// frames are split evenly, in frame order, over the shifts
+// eps* (kMixF0 + k kMixDf), k < kMixPoints, and every counted frame is weighted
+// by the balance heuristic over all of them (the likelihood ratio of the
+// unshifted density over the mixture density).  The unshifted component
+// bounds every weight by the number of components, and the others cover the
+// set's displacements up to eps*, so no frame's weight can run away the way a
+// single shift's does for failures far from it.
+void set_mixture(IsLaunch *L, double eps) {
+    L->n_mix = kMixPoints;
+    L->mix_s0 = eps * kMixF0;
+    L->mix_ds = eps * kMixDf;
+}
+
 // IS estimate from the fixed-order sums red = {sum w, sum w^2, failures,
 // sum (w - p)^2} of K frames.
 void is_fill_result(const double red[4], int64_t K, double shift, ts_is_result *res) {
@@ -656,7 +670,10 @@ int check_is_opts(const ts_code *code, const int32_t *ts_bits, int32_t a, const 
     if (!std::isfinite(o->ebn0_db) || !std::isfinite(o->shift)) { set_error("Eb/N0 and shift must be finite"); return TS_E_INVAL; }
     if (o->layout < TS_LAYOUT_AUTO || o->layout > TS_LAYOUT_STREAMED_ACCUM) { set_error("bad layout"); return TS_E_INVAL; }
     if (o->count_mode != TS_IS_COUNT_ALL && o->count_mode != TS_IS_COUNT_TS) { set_error("bad count_mode"); return TS_E_INVAL; }
-    if (o->shift_rule != TS_SHIFT_EPS && o->shift_rule != TS_SHIFT_PILOT) { set_error("bad shift_rule"); return TS_E_INVAL; }
+    if (o->shift_rule != TS_SHIFT_EPS && o->shift_rule != TS_SHIFT_PILOT && o->shift_rule != TS_SHIFT_MIX) {
+        set_error("bad shift_rule");
+        return TS_E_INVAL;
+    }
     if (o->pilot_frames < 0 || o->pilot_frames > (1ll << 24)) { set_error("pilot_frames must be 0..2^24"); return TS_E_INVAL; }
     std::vector<int32_t> t(ts_bits, ts_bits + a);
     std::sort(t.begin(), t.end());
@@ -706,6 +723,7 @@ int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const 
     L.stream = o->stream;
     L.fp_exit = o->full_iterations ? 0 : 1;
     L.count_mode = o->count_mode;
+    if (o->shift < 0.0 && o->shift_rule == TS_SHIFT_MIX) set_mixture(&L, shift);
     L.ts = d_t.as<int32_t>();
     L.a = a;
     L.fail = d_fail.as<unsigned char>();
@@ -827,6 +845,15 @@ int exec_init(ts_exec &ex, ts_ctx *ctx, hipStream_t stream, bool stream_alloc) {
         ex.own_stream = true;
     }
     ex.stream_alloc = stream_alloc;
+    if (stream_alloc) {
+        // keep freed stream-ordered memory in the device's pool instead of
+        // returning it at every synchronisation (serving batches allocate an
+        // arena per batch)
+        hipMemPool_t pool = nullptr;
+        uint64_t keep = UINT64_MAX;
+        if (hipDeviceGetDefaultMemPool(&pool, ctx->device) == hipSuccess && pool)
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
     for (auto &e : ex.ev) TSG_HIP(hipEventCreate(&e));
     TSG_HIP(hipHostMalloc((void **)&ex.pinned, 64 * sizeof(int), hipHostMallocDefault));
     for (auto &e : ex.job_ev) TSG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));

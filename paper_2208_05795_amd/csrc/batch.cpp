@@ -93,8 +93,10 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
             rc = plan_search_shape(ex, b.code, &b.so, it.P, &it.plan);
             if (rc) return rc;
             it.t0 = first_iter(b.code, &b.so);
-            it.rec_cap = std::min<int64_t>(rec_capacity(&b.so, it.t0, it.P, true, ex.ctx->rec_bytes, nullptr),
-                                           2 * it.P + 4096);
+            // the capacity a plain call gives the job (its worst case, up to
+            // the context's record buffer), so that a batch re-runs no job
+            // the plain call would not re-run
+            it.rec_cap = rec_capacity(&b.so, it.t0, it.P, true, ex.ctx->rec_bytes, nullptr);
             S.push_back(it);
         } else {
             IItem it;
@@ -207,10 +209,18 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
     if (o == 0) return TS_OK;
     unsigned char *arena = (unsigned char *)ex.dalloc(o);
     if (!arena) { set_error("device allocation of %zu bytes for the batch failed", o); return TS_E_NOMEM; }
+    // freed only once no launch of the batch can still use it (the side
+    // streams run the IS groups while the main stream post-processes, and an
+    // error may end the batch early)
     struct Free {
         ts_exec &ex;
         void *p;
-        ~Free() { ex.dfree(p); }
+        ~Free() {
+            for (int i = 0; i < ts_exec::kSide; ++i)
+                if (ex.side[i]) (void)hipStreamSynchronize(ex.side[i]);
+            (void)hipStreamSynchronize(ex.stream);
+            ex.dfree(p);
+        }
     } arena_guard{ex, arena};
     rc = launch_fill(s, (int *)arena, 0, (int64_t)(zero / 4));
     if (rc) return rc;
@@ -262,6 +272,7 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
         L.stream = it.b->io.stream;
         L.fp_exit = it.b->io.full_iterations ? 0 : 1;
         L.count_mode = it.b->io.count_mode;
+        if (it.b->io.shift < 0.0 && it.b->io.shift_rule == TS_SHIFT_MIX) set_mixture(&L, it.shift);
         L.ts = (const int *)(arena + it.ts);
         L.a = it.b->a;
         L.fail = arena + it.fail;
@@ -295,10 +306,16 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
         TSG_HIP(hipMemcpyAsync(arena + g.jobs, hj.data(), hj.size(), hipMemcpyHostToDevice, s));
     }
     TSG_HIP(hipStreamSynchronize(s));
-    // ---- launches: largest groups first, spread over the side streams ------
+    // ---- launches, spread over the side streams: the search groups first
+    // (largest first), then the IS groups (largest first).  The main stream
+    // waits for the search groups only, so the search jobs' sieves and
+    // read-outs run while the IS groups still decode.
     std::vector<int> order(G.size());
     for (size_t i = 0; i < G.size(); ++i) order[i] = (int)i;
-    std::sort(order.begin(), order.end(), [&](int x, int y) { return G[x].work > G[y].work; });
+    std::sort(order.begin(), order.end(), [&](int x, int y) {
+        if (G[x].search != G[y].search) return G[x].search;
+        return G[x].work > G[y].work;
+    });
     TSG_HIP(hipEventRecord(ex.ev[0], s));
     TSG_HIP(hipEventRecord(ex.join_ev, s));
     int used = 0;
@@ -316,18 +333,17 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
                                 g.n_items);
         if (rc) return rc;
         used = std::max(used, si + 1);
+        const bool last_search = g.search && (k + 1 == order.size() || !G[order[k + 1]].search);
+        if (last_search) {   // the main stream waits for the search groups
+            for (int i = 0; i < used; ++i) {
+                TSG_HIP(hipEventRecord(ex.side_ev[i], ex.side[i]));
+                TSG_HIP(hipStreamWaitEvent(s, ex.side_ev[i], 0));
+            }
+        }
     }
-    for (int i = 0; i < used; ++i) {
-        TSG_HIP(hipEventRecord(ex.side_ev[i], ex.side[i]));
-        TSG_HIP(hipStreamWaitEvent(s, ex.side_ev[i], 0));
-    }
-    TSG_HIP(hipEventRecord(ex.ev[1], s));
     std::vector<int> zh(zero / 4);
     if (zero) TSG_HIP(hipMemcpyAsync(zh.data(), arena, zero, hipMemcpyDeviceToHost, s));
     TSG_HIP(hipStreamSynchronize(s));
-    float dec_ms = 0.0f;
-    TSG_HIP(hipEventElapsedTime(&dec_ms, ex.ev[0], ex.ev[1]));
-    ex.stats.decode_ms += dec_ms;
     ex.stats.decode_launches += (int)G.size();
     // ---- per search job: sieve into its own table, read out -----------------
     std::vector<SItem *> rerun;
@@ -372,37 +388,6 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
         }
     }
     ex.stats.candidates += cands;
-    // ---- per IS job: fixed-order reductions ----------------------------------
-    std::vector<double> red(I.size() * 4);
-    for (IItem &it : I) {
-        rc = launch_is_reduce(s, make_is_dev(it.L, it.plan), it.L.wf, it.L.fail, it.K, 0, 0.0,
-                              (double *)(arena + it.red), (double *)(arena + it.part));
-        if (rc) return rc;
-    }
-    for (size_t i = 0; i < I.size(); ++i)
-        TSG_HIP(hipMemcpyAsync(&red[4 * i], arena + I[i].red, 32, hipMemcpyDeviceToHost, s));
-    TSG_HIP(hipStreamSynchronize(s));
-    for (size_t i = 0; i < I.size(); ++i) {
-        rc = launch_is_reduce(s, make_is_dev(I[i].L, I[i].plan), I[i].L.wf, I[i].L.fail, I[i].K, 1,
-                              red[4 * i] / (double)I[i].K, (double *)(arena + I[i].red),
-                              (double *)(arena + I[i].part));
-        if (rc) return rc;
-    }
-    std::vector<double> red2(I.size() * 4);
-    for (size_t i = 0; i < I.size(); ++i)
-        TSG_HIP(hipMemcpyAsync(&red2[4 * i], arena + I[i].red, 32, hipMemcpyDeviceToHost, s));
-    TSG_HIP(hipStreamSynchronize(s));
-    for (size_t i = 0; i < I.size(); ++i) {
-        IItem &it = I[i];
-        double r[4] = {red[4 * i], red[4 * i + 1], red[4 * i + 2], red2[4 * i + 3]};
-        is_fill_result(r, it.K, it.shift, it.b->is);
-        const int *misc = zh.data() + it.misc / 4;
-        unsigned long long cnt[2];
-        std::memcpy(cnt, misc + 4, 16);
-        it.b->edge_updates = (int64_t)cnt[1] * it.b->code->e;
-        ex.stats.decodes += it.K;
-        ex.stats.edge_updates += it.b->edge_updates;
-    }
     // ---- TS read-out ------------------------------------------------------
     for (size_t i = 0; i < S.size(); ++i) {
         SItem &it = S[i];
@@ -434,6 +419,50 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
         it->b->edge_updates = ex.stats.edge_updates - eu0;
         table_free(ex, t);
         if (rc) return rc;
+    }
+    // ---- the IS groups: wait for every side stream --------------------------
+    for (int i = 0; i < used; ++i) {
+        TSG_HIP(hipEventRecord(ex.side_ev[i], ex.side[i]));
+        TSG_HIP(hipStreamWaitEvent(s, ex.side_ev[i], 0));
+    }
+    TSG_HIP(hipEventRecord(ex.ev[1], s));
+    if (zero && !I.empty()) TSG_HIP(hipMemcpyAsync(zh.data(), arena, zero, hipMemcpyDeviceToHost, s));
+    TSG_HIP(hipStreamSynchronize(s));
+    {
+        float dec_ms = 0.0f;
+        TSG_HIP(hipEventElapsedTime(&dec_ms, ex.ev[0], ex.ev[1]));
+        ex.stats.decode_ms += dec_ms;
+    }
+    // ---- per IS job: fixed-order reductions ----------------------------------
+    std::vector<double> red(I.size() * 4);
+    for (IItem &it : I) {
+        rc = launch_is_reduce(s, make_is_dev(it.L, it.plan), it.L.wf, it.L.fail, it.K, 0, 0.0,
+                              (double *)(arena + it.red), (double *)(arena + it.part));
+        if (rc) return rc;
+    }
+    for (size_t i = 0; i < I.size(); ++i)
+        TSG_HIP(hipMemcpyAsync(&red[4 * i], arena + I[i].red, 32, hipMemcpyDeviceToHost, s));
+    TSG_HIP(hipStreamSynchronize(s));
+    for (size_t i = 0; i < I.size(); ++i) {
+        rc = launch_is_reduce(s, make_is_dev(I[i].L, I[i].plan), I[i].L.wf, I[i].L.fail, I[i].K, 1,
+                              red[4 * i] / (double)I[i].K, (double *)(arena + I[i].red),
+                              (double *)(arena + I[i].part));
+        if (rc) return rc;
+    }
+    std::vector<double> red2(I.size() * 4);
+    for (size_t i = 0; i < I.size(); ++i)
+        TSG_HIP(hipMemcpyAsync(&red2[4 * i], arena + I[i].red, 32, hipMemcpyDeviceToHost, s));
+    TSG_HIP(hipStreamSynchronize(s));
+    for (size_t i = 0; i < I.size(); ++i) {
+        IItem &it = I[i];
+        double r[4] = {red[4 * i], red[4 * i + 1], red[4 * i + 2], red2[4 * i + 3]};
+        is_fill_result(r, it.K, it.shift, it.b->is);
+        const int *misc = zh.data() + it.misc / 4;
+        unsigned long long cnt[2];
+        std::memcpy(cnt, misc + 4, 16);
+        it.b->edge_updates = (int64_t)cnt[1] * it.b->code->e;
+        ex.stats.decodes += it.K;
+        ex.stats.edge_updates += it.b->edge_updates;
     }
     TSG_HIP(hipStreamSynchronize(s));
     return TS_OK;

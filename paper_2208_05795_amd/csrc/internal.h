@@ -34,6 +34,10 @@ std::string last_error_copy();
 // Limits of the device kernels (checked by the host before every launch).
 constexpr int kMaxIter = 64;      // iterations per decode
 constexpr int kMaxWidth = 16;     // impulse pattern width
+constexpr int kMixMax = 32;       // components of an IS shift mixture
+// The shift mixture of TS_SHIFT_MIX: eps* k/16, k = 0..16
+constexpr int kMixPoints = 17;
+constexpr double kMixF0 = 0.0, kMixDf = 0.0625;
 constexpr int kMaxAmax = 16;      // largest TS kept
 constexpr int kCapMax = 2 * kMaxAmax;  // |S u I| bound for sieving
 constexpr int kDvMax = 8;         // variable degree bound of the sieve kernel
@@ -347,6 +351,10 @@ struct IsDev {
     long long slot_bytes, lam_off;
     int fp_exit;           // end decodes at a fixed point
     int count_mode;        // TS_IS_COUNT_ALL / TS_IS_COUNT_TS
+    // mixture of shifts (n_mix > 0): frame f takes component j = f n_mix / n_frames,
+    // shift mix_s0 + j mix_ds, and the balance-heuristic weight of all components
+    int n_mix;
+    double mix_s0, mix_ds;
 };
 
 struct IsJob {
@@ -379,6 +387,8 @@ struct IsLaunch {
     unsigned char *gscr;    // grid x slot_bytes scratch
     int fp_exit;            // end decodes at a fixed point
     int count_mode;         // TS_IS_COUNT_ALL / TS_IS_COUNT_TS
+    int n_mix;              // 0: one shift; else the mixture of IsDev
+    double mix_s0, mix_ds;
 };
 // IS launch shape (plan.slot_bytes of scratch per workgroup)
 int plan_is(ts_ctx *ctx, const ts_code *c, int max_iter, int layout, SearchPlan *plan);
@@ -453,6 +463,8 @@ struct PilotReq {
     double *shift;         // out
 };
 int pilot_shifts(ts_exec &ex, std::vector<PilotReq> &reqs);
+// TS_SHIFT_MIX: the mixture around eps* on an IS launch
+void set_mixture(IsLaunch *L, double eps);
 int tune_for_batch(ts_exec &ex, std::vector<BatchJob> &jobs);   // api.cpp
 
 // serve.cpp

@@ -1021,10 +1021,19 @@ __device__ __forceinline__ void philox4x32_10(unsigned c[4], unsigned k0, unsign
 // Channel parameters of the IS frames of one job (scalar copies).
 struct IsChan {
     unsigned k0, k1, stream;
-    int a;
+    int a, n_mix;
     float shift, sigma, two_over_s2;
     unsigned long long frame_base;
+    long long n_frames;
+    double mix_s0, mix_ds;
 };
+
+// The mean shift of frame f: the job's shift, or its mixture component's.
+__device__ __forceinline__ float frame_shift(const IsChan &a, int f) {
+    if (!a.n_mix) return a.shift;
+    const long long j = ((long long)f * a.n_mix) / a.n_frames;
+    return (float)(a.mix_s0 + (double)j * a.mix_ds);
+}
 
 __device__ __forceinline__ IsChan is_chan(const IsDev &d) {
     IsChan c;
@@ -1036,6 +1045,10 @@ __device__ __forceinline__ IsChan is_chan(const IsDev &d) {
     c.sigma = uni((float)d.sigma);
     c.two_over_s2 = uni((float)(2.0 / d.sigma2));
     c.frame_base = uni(d.frame_base);
+    c.n_frames = uni(d.n_frames);
+    c.n_mix = uni(d.n_mix);
+    c.mix_s0 = uni(d.mix_s0);
+    c.mix_ds = uni(d.mix_ds);
     return c;
 }
 
@@ -1047,7 +1060,7 @@ __device__ __forceinline__ IsChan is_chan(const IsDev &d) {
 // stores the values; the normals of the TS bits go to tn.
 template <class Put>
 __device__ __forceinline__ void is_channel(const IsChan &a, int n, unsigned long long frame,
-                                           const int *tsl, float *tn, Put put) {
+                                           float shift, const int *tsl, float *tn, Put put) {
     const int B = blockDim.x, tid = threadIdx.x;
     const float two_pi = 6.2831853071795865f;
     for (int g = tid; 4 * g < n; g += B) {
@@ -1068,7 +1081,7 @@ __device__ __forceinline__ void is_channel(const IsChan &a, int n, unsigned long
                 int slot = -1;
                 for (int q = 0; q < a.a; ++q)
                     if (tsl[q] == v) slot = q;
-                const float y = 1.0f - (slot >= 0 ? a.shift : 0.0f) + a.sigma * nv[i];
+                const float y = 1.0f - (slot >= 0 ? shift : 0.0f) + a.sigma * nv[i];
                 put(v, to_q20(y * a.two_over_s2));
                 if (slot >= 0) tn[slot] = nv[i];
             }
@@ -1162,7 +1175,7 @@ struct RegIsDec {
 
     __device__ __forceinline__ DecRes decode_frame(int f) {
         const int B = blockDim.x, tid = threadIdx.x, n = F.n, np = F.np;
-        is_channel(a, n, a.frame_base + (unsigned long long)f, tsl, tn, [&](int v, int l) {
+        is_channel(a, n, a.frame_base + (unsigned long long)f, frame_shift(a, f), tsl, tn, [&](int v, int l) {
             F.lam[v] = l;
             F.app[v] = l;
             F.app[np + v] = l;
@@ -1213,12 +1226,37 @@ __device__ __forceinline__ void red_tree(double *s0, double *s1, double *s2, int
     }
 }
 
+// Importance weight of a counted frame f of a mixture of m shifts s_k = s0 + k ds
+// (frame f drawn from component j = f m / n): with S = a s_j / sigma - sum_T n,
+// the sum of the frame's TS-bit displacements in units of sigma,
+// w = 1 / sum_k alpha_k exp((s_k / sigma) S - a s_k^2 / (2 sigma^2)), alpha_k the
+// share of frames in component k (the balance heuristic), by log-sum-exp.
+struct MixW {
+    int m, a;
+    long long n;
+    double s0, ds, sigma;
+};
+__device__ __forceinline__ double mix_term(const MixW &x, int k, double S) {
+    const long long f0 = (k * x.n + x.m - 1) / x.m, f1 = ((k + 1) * x.n + x.m - 1) / x.m;
+    const double sk = x.s0 + (double)k * x.ds;
+    return log((double)(f1 - f0) / (double)x.n) + sk / x.sigma * S - x.a * sk * sk / (2.0 * x.sigma * x.sigma);
+}
+__device__ double mix_weight(const MixW &x, long long f, double sum_n) {
+    const long long j = (f * x.m) / x.n;
+    const double S = x.a * (x.s0 + (double)j * x.ds) / x.sigma - sum_n;
+    double mx = -1e300;
+    for (int k = 0; k < x.m; ++k) mx = fmax(mx, mix_term(x, k, S));
+    double t = 0.0;
+    for (int k = 0; k < x.m; ++k) t += exp(mix_term(x, k, S) - mx);
+    return exp(-(mx + log(t)));
+}
+
 // cmask selects the failures that count: 1 every failure, 2 those with every
 // TS bit in error.
 __global__ __launch_bounds__(kRedThreads) void k_is_reduce(const double *wf, const unsigned char *fail,
                                                           long long n, int mode, double mean,
                                                           double wconst, double coef, int cmask,
-                                                          double *part) {
+                                                          MixW mix, double *part) {
     __shared__ double s0[kRedThreads], s1[kRedThreads], s2[kRedThreads];
     const int t = threadIdx.x;
     const long long c0 = (long long)blockIdx.x * kRedChunk;
@@ -1228,7 +1266,7 @@ __global__ __launch_bounds__(kRedThreads) void k_is_reduce(const double *wf, con
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     for (long long i = lo; i < hi; ++i) {
         const bool counted = (fail[i] & cmask) != 0;
-        const double w = counted ? exp(wconst + coef * wf[i]) : 0.0;
+        const double w = !counted ? 0.0 : mix.m ? mix_weight(mix, i, wf[i]) : exp(wconst + coef * wf[i]);
         if (mode == 0) {
             a0 += w;
             a1 += w * w;
@@ -1616,7 +1654,7 @@ struct GIsDec {
         const int B = blockDim.x, tid = threadIdx.x, n = F.n;
         int *lm = lam;
         int *app = F.app;
-        is_channel(a, n, a.frame_base + (unsigned long long)f, tsl, tn, [&](int v, int l) {
+        is_channel(a, n, a.frame_base + (unsigned long long)f, frame_shift(a, f), tsl, tn, [&](int v, int l) {
             lm[v] = l;
             app[v] = l;
         });
@@ -1990,6 +2028,9 @@ IsDev make_is_dev(const IsLaunch &a, const SearchPlan &plan) {
     d.gscr = a.gscr;
     d.fp_exit = a.fp_exit;
     d.count_mode = a.count_mode;
+    d.n_mix = a.n_mix;
+    d.mix_s0 = a.mix_s0;
+    d.mix_ds = a.mix_ds;
     d.slot_bytes = (long long)plan.slot_bytes;
     d.lam_off = (long long)plan.hist_off;
     return d;
@@ -2004,8 +2045,10 @@ int launch_is_reduce(hipStream_t stream, const IsDev &d, const double *wf, const
         set_error("empty reduction");
         return TS_E_INVAL;
     }
+    MixW mix{d.n_mix, d.a, (long long)n, d.mix_s0, d.mix_ds, d.sigma};
     hipLaunchKernelGGL(k_is_reduce, dim3(np), dim3(kRedThreads), 0, stream, wf, fail, (long long)n, mode,
-                       mean, d.wconst, d.shift / d.sigma, d.count_mode == TS_IS_COUNT_TS ? 2 : 1, part);
+                       mean, d.wconst, d.shift / d.sigma, d.count_mode == TS_IS_COUNT_TS ? 2 : 1, mix,
+                       part);
     TSG_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_is_reduce_final, dim3(1), dim3(kRedThreads), 0, stream, (const double *)part, np,
                        mode, out);

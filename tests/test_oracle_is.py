@@ -181,3 +181,30 @@ def test_is_pilot_shift_rule(oracle_mod, tiny):
     assert ok
     best = min(ok, key=lambda i: (want[i], i))
     assert s == eps * (0.5 + best / 16.0)
+
+
+@pytest.mark.parametrize("ebn0,s0,ds,m", [(3.0, 0.5, 0.125, 9), (5.0, 0.6, 0.1, 5)])
+def test_is_mixture_closed_form_linear_decoder(oracle_mod, tiny, ebn0, s0, ds, m):
+    """Mixture of shifts (balance heuristic) against the exact Q(sqrt(a)/sigma)
+    of the linear test decoder: within 3 sigma and 5%."""
+    c, oc = tiny
+    T = [3, 17, 40, 81]
+    a = len(T)
+    s2 = oracle_mod.sigma2(ebn0, 0.5)
+    exact = _q(math.sqrt(a) / math.sqrt(s2))
+    r = oracle_mod.is_estimate(oc, T, ebn0, 0.0, 45000, seed=98, decoder=oracle_mod.IS_LINEAR,
+                               mix=(m, s0, ds))
+    sd = math.sqrt(r["var"])
+    assert abs(r["p_hat"] - exact) < 3.0 * sd, (r["p_hat"], exact, sd)
+    assert abs(r["p_hat"] - exact) / exact < 0.05
+    assert r["shift_used"] == pytest.approx(s0 + (m - 1) * ds)
+
+
+def test_is_mixture_of_one_is_the_single_shift(oracle_mod, tiny):
+    c, oc = tiny
+    T = [0, 8, 19]
+    one = oracle_mod.is_estimate(oc, T, 3.0, 1.3, 600, seed=5, want_fail=True)
+    mix = oracle_mod.is_estimate(oc, T, 3.0, 0.0, 600, seed=5, want_fail=True, mix=(1, 1.3, 0.0))
+    assert np.array_equal(one["fail"], mix["fail"])
+    assert mix["p_hat"] == pytest.approx(one["p_hat"], rel=1e-12)
+    assert mix["var"] == pytest.approx(one["var"], rel=1e-9)
