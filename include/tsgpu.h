@@ -288,6 +288,23 @@ typedef struct {
 int ts_is_estimate(ts_ctx *ctx, ts_code *code, const int32_t *ts_bits, int32_t a,
                    const ts_is_opts *opts, ts_is_result *res, uint8_t *fail_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not call an allocator): ts_is_estimate with
+ * no device allocation.  Every device buffer of the call lives in one fixed
+ * device array of 32 MiB, set up by ts_create on the context's device and held
+ * by each GPU the library runs on until the process ends.  Same arguments,
+ * results and statistics as ts_is_estimate; the caller still owns ts_bits,
+ * res and fail_out (host).  Limits: shift >= 0 (no eps* or pilot search),
+ * n_frames <= 2^21, and codes whose IS launch shape is the register layout;
+ * the fixed-point exit is used when its save area fits beside the frames
+ * (results are identical either way).  Calls on one GPU share the array:
+ * calls that overlap on a GPU (two contexts on one device, used from two
+ * threads) race; calls on one context are serialised.  Errors: TS_E_INVAL
+ * beyond the limits (with the limit in the message), as ts_is_estimate
+ * otherwise. */
+int ts_is_estimate_noalloc(ts_ctx *ctx, ts_code *code, const int32_t *ts_bits, int32_t a,
+                           const ts_is_opts *opts, ts_is_result *res, uint8_t *fail_out);
+
 /* ---- cycle / EMD spectrum (Section II, Table II) ------------------------- */
 
 /* Simple cycles of length 4..max_len of a QC code through the position-0

@@ -126,6 +126,8 @@ PROTOTYPES = {
     "ts_reset_ts": (C.c_int, [C.c_void_p, C.c_void_p]),
     "ts_is_estimate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                  C.POINTER(IsOpts), C.POINTER(IsResult), C.c_void_p]),
+    "ts_is_estimate_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                         C.POINTER(IsOpts), C.POINTER(IsResult), C.c_void_p]),
     "ts_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     "ts_probe_lds": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "ts_cycle_emd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),

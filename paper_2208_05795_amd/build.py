@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtsgpu.so")
-SOURCES = ["api.cpp", "batch.cpp", "emd.cpp", "loader.cpp", "serve.cpp", "union.cpp", "probe.hip", "search_kernels.hip", "ts_kernels.hip"]
+SOURCES = ["api.cpp", "batch.cpp", "emd.cpp", "loader.cpp", "serve.cpp", "union.cpp", "probe.hip", "search_kernels.hip", "ts_kernels.hip", "noalloc.hip"]
 ARCH = os.environ.get("TSGPU_ARCH", "gfx950")
 
 

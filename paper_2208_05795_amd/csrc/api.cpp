@@ -944,7 +944,12 @@ int ts_create(const ts_ctx_opts *opts, ts_ctx **out) {
     }
     c->num_cu = ncu;
     c->lds_per_block = (size_t)lds;
-    const int rc = exec_init(c->main, c, opts ? (hipStream_t)opts->hip_stream : nullptr, false);
+    int rc = noalloc_init(dev);   // the no-allocation entry point's scratch on this device
+    if (rc) {
+        delete c;
+        return rc;
+    }
+    rc = exec_init(c->main, c, opts ? (hipStream_t)opts->hip_stream : nullptr, false);
     if (rc) {
         exec_fini(c->main);
         delete c;

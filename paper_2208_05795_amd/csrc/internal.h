@@ -467,6 +467,10 @@ int pilot_shifts(ts_exec &ex, std::vector<PilotReq> &reqs);
 void set_mixture(IsLaunch *L, double eps);
 int tune_for_batch(ts_exec &ex, std::vector<BatchJob> &jobs);   // api.cpp
 
+// noalloc.hip: device address of the no-allocation scratch (once per device,
+// with the device current)
+int noalloc_init(int device);
+
 // serve.cpp
 struct Server;
 void server_stop(ts_ctx *ctx);
