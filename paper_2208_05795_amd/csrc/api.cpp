@@ -239,7 +239,7 @@ static int tune_shape(ts_exec &ex, const std::vector<SearchPlan> &cands,
 }
 
 static bool same_shape(const SearchPlan &p, const SearchShape &s) {
-    return p.kind == s.kind && p.cpt == s.cpt && p.block == s.block;
+    return p.kind == s.kind && p.cpt == s.cpt && p.block == s.block && p.save_lds == s.save_lds;
 }
 
 static size_t scratch_bytes(const SearchPlan &p, int64_t P) {
@@ -410,6 +410,7 @@ int run_search(ts_exec &ex, ts_code *code, DevTable &table, const ts_search_opts
         sh.kind = plan.kind;
         sh.cpt = plan.cpt;
         sh.block = plan.block;
+        sh.save_lds = plan.save_lds;
         code->tuned[tune_key] = sh;
         rc = launch_fill(s, d_misc, 0, 64);   // the probe's counters are not the job's
         if (rc) return rc;
@@ -790,6 +791,7 @@ int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const 
         sh.kind = plan.kind;
         sh.cpt = plan.cpt;
         sh.block = plan.block;
+        sh.save_lds = plan.save_lds;
         code->tuned[is_tune_key(o->max_iter, o->layout)] = sh;
         rc = launch_fill(s, d_misc.as<int>(), 0, 64);
         if (rc) return rc;

@@ -142,7 +142,8 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
         // fit the same number of times into a CU's LDS share one, so that no job
         // loses occupancy to a larger code's frame
         const int lds_fit = (int)(ctx->lds_per_block / std::max<size_t>(p.lds, 1));
-        const auto key = std::make_tuple(search ? 1 : 0, p.kind, p.dc, p.cpt, p.decoder, p.block, lds_fit);
+        const auto key = std::make_tuple(search ? 1 : 0, p.kind, p.dc, p.cpt, p.decoder, p.block,
+                                         lds_fit * 2 + p.save_lds);
         auto f = gid.find(key);
         if (f != gid.end()) {
             Group &g = G[f->second];
@@ -253,6 +254,7 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
         const Group &g = G[it.group];
         a.gscr = g.scratch_bytes ? arena + g.scratch : nullptr;
         a.slot_bytes = (long long)g.plan.slot_bytes;
+        a.save_lds = g.plan.save_lds;
         a.hist_off = (long long)it.plan.hist_off;
     }
     for (size_t ii = 0; ii < I.size(); ++ii) {
@@ -297,6 +299,7 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
                 IsJob j{};
                 j.a = make_is_dev(I[m].L, I[m].plan);
                 j.a.slot_bytes = (long long)g.plan.slot_bytes;
+                j.a.save_lds = g.plan.save_lds;
                 j.cd = I[m].b->code->dev;
                 j.item0 = item0;
                 item0 += I[m].K;
@@ -318,12 +321,24 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
     });
     TSG_HIP(hipEventRecord(ex.ev[0], s));
     TSG_HIP(hipEventRecord(ex.join_ev, s));
-    int used = 0;
+    // IS groups whose frames take more than half a CU's LDS (one workgroup per
+    // CU) go to the first half of the side streams, the others to the second
+    // half, so that small frames run beside the large ones in the LDS and
+    // wave slots those leave free on every CU instead of after them
+    int used = 0, n_search = 0, n_big = 0, n_small = 0;
+    bool joined[ts_exec::kSide] = {};
+    constexpr int kHalf = ts_exec::kSide / 2;
     for (size_t k = 0; k < order.size(); ++k) {
         const Group &g = G[order[k]];
-        const int si = (int)(k % ts_exec::kSide);
+        int si;
+        if (g.search) si = n_search++ % ts_exec::kSide;
+        else if (g.plan.lds * 2 > ctx->lds_per_block) si = n_big++ % kHalf;
+        else si = kHalf + n_small++ % (ts_exec::kSide - kHalf);
         hipStream_t st = ex.side[si];
-        if ((int)k < ts_exec::kSide) TSG_HIP(hipStreamWaitEvent(st, ex.join_ev, 0));
+        if (!joined[si]) {
+            TSG_HIP(hipStreamWaitEvent(st, ex.join_ev, 0));
+            joined[si] = true;
+        }
         int *queue = (int *)(arena + g.queue);
         if (g.search)
             rc = launch_search_jobs(st, g.plan, (const SearchJob *)(arena + g.jobs), (int)g.members.size(),
@@ -336,6 +351,7 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
         const bool last_search = g.search && (k + 1 == order.size() || !G[order[k + 1]].search);
         if (last_search) {   // the main stream waits for the search groups
             for (int i = 0; i < used; ++i) {
+                if (!joined[i]) continue;
                 TSG_HIP(hipEventRecord(ex.side_ev[i], ex.side[i]));
                 TSG_HIP(hipStreamWaitEvent(s, ex.side_ev[i], 0));
             }
@@ -422,6 +438,7 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
     }
     // ---- the IS groups: wait for every side stream --------------------------
     for (int i = 0; i < used; ++i) {
+        if (!joined[i]) continue;
         TSG_HIP(hipEventRecord(ex.side_ev[i], ex.side[i]));
         TSG_HIP(hipStreamWaitEvent(s, ex.side_ev[i], 0));
     }

@@ -165,7 +165,7 @@ struct DevTable {
 
 // A decoder launch shape picked by the autotuner.
 struct SearchShape {
-    int kind = 0, cpt = 0, block = 0;
+    int kind = 0, cpt = 0, block = 0, save_lds = 0;
 };
 
 }  // namespace tsg
@@ -282,6 +282,7 @@ struct SearchPlan {
     int grid;       // persistent workgroups
     size_t slot_bytes;   // global scratch per workgroup (register kind: message save area)
     size_t hist_off;     // streamed: offset of the iteration history in a slot
+    int save_lds = 0;    // register kind: the message save area in LDS (after the hashes)
 };
 
 // Whether a plan is allowed under a TS_LAYOUT_* request (streamed plans carry
@@ -315,6 +316,7 @@ struct SearchLaunch {
     unsigned char *gscr;            // grid x slot_bytes scratch (nullptr: none)
     long long slot_bytes, hist_off;
     int fp_exit;                    // end decodes at a fixed point
+    int save_lds;                   // register kind: message save area in LDS
 };
 
 int plan_search(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter, SearchPlan *plan);
@@ -350,6 +352,7 @@ struct IsDev {
     unsigned char *gscr;   // per-workgroup scratch (nullptr: none)
     long long slot_bytes, lam_off;
     int fp_exit;           // end decodes at a fixed point
+    int save_lds;          // register kind: message save area in LDS
     int count_mode;        // TS_IS_COUNT_ALL / TS_IS_COUNT_TS
     // mixture of shifts (n_mix > 0): frame f takes component j = f n_mix / n_frames,
     // shift mix_s0 + j mix_ds, and the balance-heuristic weight of all components

@@ -119,7 +119,9 @@ extern "C" int ts_is_estimate_noalloc(ts_ctx *ctx, ts_code *code, const int32_t 
     off = al256(off + (size_t)K * sizeof(double));
     const int grid = (int)std::min<int64_t>(plan.grid, K);
     const size_t save = (size_t)grid * plan.slot_bytes;
-    const bool fp_exit = !o->full_iterations && save > 0 && off + save <= kNoAllocScratchBytes;
+    // the fixed-point exit needs the save area: in LDS (plan.save_lds) or here
+    const bool fp_exit = !o->full_iterations &&
+                         (plan.save_lds || (save > 0 && off + save <= kNoAllocScratchBytes));
     if (off > kNoAllocScratchBytes) {   // unreachable with noalloc_max_frames()
         set_error("no-allocation scratch too small");
         return TS_E_INVAL;
@@ -147,7 +149,7 @@ extern "C" int ts_is_estimate_noalloc(ts_ctx *ctx, ts_code *code, const int32_t 
     L.fail = d_fail;
     L.wf = d_wf;
     L.counters = (unsigned long long *)(misc + 4);
-    L.gscr = fp_exit ? base + off : nullptr;
+    L.gscr = fp_exit && !plan.save_lds ? base + off : nullptr;
     IsJob job{};
     job.a = make_is_dev(L, plan);
     job.cd = code->dev;

@@ -734,8 +734,9 @@ struct RegSearchDec {
         F.pcnt = (int *)(frame + L.pcnt);
         F.moved = (int *)(frame + L.moved);
         F.hsh = (unsigned *)(frame + L.total);
-        F.vsave = J.a.gscr && J.a.fp_exit ? (int *)uni(J.a.gscr + (size_t)blockIdx.x * J.a.slot_bytes)
-                                          : nullptr;
+        F.vsave = !J.a.fp_exit ? nullptr
+                  : J.a.save_lds ? (int *)(frame + L.total + (size_t)blockDim.x * 4)
+                  : J.a.gscr ? (int *)uni(J.a.gscr + (size_t)blockIdx.x * J.a.slot_bytes) : nullptr;
         F.n = n;
         F.np = L.np;
         F.W = L.W;
@@ -942,8 +943,9 @@ struct LayDec {
         F.pcnt = (int *)(frame + L.pcnt);
         F.moved = (int *)(frame + L.moved);
         F.hsh = (unsigned *)(frame + L.total);
-        F.vsave = J.a.gscr && J.a.fp_exit ? (int *)uni(J.a.gscr + (size_t)blockIdx.x * J.a.slot_bytes)
-                                          : nullptr;
+        F.vsave = !J.a.fp_exit ? nullptr
+                  : J.a.save_lds ? (int *)(frame + L.total + (size_t)blockDim.x * 4)
+                  : J.a.gscr ? (int *)uni(J.a.gscr + (size_t)blockIdx.x * J.a.slot_bytes) : nullptr;
         F.n = n;
         F.np = L.np;
         F.W = L.W;
@@ -1160,8 +1162,9 @@ struct RegIsDec {
         F.pcnt = (int *)(frame + L.pcnt);
         F.moved = (int *)(frame + L.moved);
         F.hsh = (unsigned *)(frame + L.total);
-        F.vsave = J.a.gscr && J.a.fp_exit ? (int *)uni(J.a.gscr + (size_t)blockIdx.x * J.a.slot_bytes)
-                                          : nullptr;
+        F.vsave = !J.a.fp_exit ? nullptr
+                  : J.a.save_lds ? (int *)(frame + L.total + (size_t)blockDim.x * 4)
+                  : J.a.gscr ? (int *)uni(J.a.gscr + (size_t)blockIdx.x * J.a.slot_bytes) : nullptr;
         F.n = n;
         F.np = L.np;
         F.W = L.W;
@@ -1819,6 +1822,19 @@ int plan_candidates(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter,
             p.slot_bytes = (size_t)block * cp * dc * 4;   // message save area (fixed-point test)
             p.hist_off = 0;
             out->push_back(p);
+            // the same shape with the save area in LDS, where it fits (the
+            // autotuner weighs the lost occupancy against the global traffic)
+            const size_t lds_s = lds_b + p.slot_bytes;
+            int per_cu_s = 0;
+            if (lds_s <= ctx->lds_per_block &&
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_s, (const void *)kern, block, lds_s) == hipSuccess &&
+                per_cu_s >= 1) {
+                p.lds = lds_s;
+                p.grid = per_cu_s * ctx->num_cu;
+                p.slot_bytes = 0;
+                p.save_lds = 1;
+                out->push_back(p);
+            }
         }
     }
     if (decoder != TS_DEC_LNMS_Q4) {   // the layered decoder has the register layout only
@@ -1931,6 +1947,7 @@ int launch_search(ts_exec &ex, const SearchPlan &plan0, const SearchLaunch &a) {
     }
     // register kind without scratch: no message save area (no fixed-point test)
     j.a.slot_bytes = (long long)plan.slot_bytes;
+    j.a.save_lds = plan.save_lds;
     j.a.hist_off = (long long)plan.hist_off;
     if (a.n_patterns <= 0) return TS_OK;
     void *dj = nullptr;
@@ -1983,6 +2000,17 @@ int plan_is_candidates(ts_ctx *ctx, const ts_code *c, int max_iter, int layout,
             p.slot_bytes = (size_t)b * cp * dc * 4;   // save area of the messages
             p.hist_off = 0;
             out->push_back(p);
+            const size_t lds_s = lds_b + p.slot_bytes;   // the save area in LDS
+            int per_cu_s = 0;
+            if (lds_s <= ctx->lds_per_block &&
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_s, (const void *)k->is, b, lds_s) == hipSuccess &&
+                per_cu_s >= 1) {
+                p.lds = lds_s;
+                p.grid = per_cu_s * ctx->num_cu;
+                p.slot_bytes = 0;
+                p.save_lds = 1;
+                out->push_back(p);
+            }
         }
     }
     if (layout != TS_LAYOUT_REGISTER) {
@@ -2032,6 +2060,7 @@ IsDev make_is_dev(const IsLaunch &a, const SearchPlan &plan) {
     d.mix_s0 = a.mix_s0;
     d.mix_ds = a.mix_ds;
     d.slot_bytes = (long long)plan.slot_bytes;
+    d.save_lds = plan.save_lds;
     d.lam_off = (long long)plan.hist_off;
     return d;
 }
