@@ -11,7 +11,7 @@ TS found, 10^4 frames each.  Inputs are resident on the device before timing.
 Beside it, with their own figures in the same JSON line:
   batched  - 64 QC codes of uneven size (bases 3x6/4x8/3x12/4x24, Z 16..384,
              N 96..9216), each with 4096 impulse patterns (OMS-i8, 20 it.) and
-             16384 IS frames (SPA-f32, 50 it., 3 dB, s = 1 on the shortest cycle
+             16384 IS frames (SPA with Q20 messages and f32 phi, 50 it., 3 dB, s = 1 on the shortest cycle
              through variable 0): every job alone versus all 128 in one batch
              (ts_run_batch), results checked identical;
   served   - a Poisson stream (20 jobs/s) of search and IS jobs on 46x68-base QC
@@ -51,10 +51,10 @@ VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 VALU_SLOTS_PER_EU = {"oms": 15.0, "spa": 2 * (3 * 4 + 5) + 6.0}
 # HBM traffic per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled x2 and x1 by a 1 GiB copy); None once the kernel changes.
-MEASURED_TRAFFIC_BYTES = {"spa": (876.62e6 + 10523.89e6)}
+MEASURED_TRAFFIC_BYTES = {"spa": (39.09e6 + 847.56e6)}
 # Same for the streamed-layout launch of the QC-2640 triples search (qc2640
 # section); None until measured on the current kernel.
-MEASURED_STREAMED_TRAFFIC_BYTES = 26853.8e6 + 635664.4e6
+MEASURED_STREAMED_TRAFFIC_BYTES = 27034.46e6 + 637329.51e6
 
 
 def parse():
@@ -230,7 +230,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "i8+q20/f32", "data": "synthetic",
         "config": {"workload": "peg1008: (3,6) PEG N=1008 M=504, singles+pairs(d<=4)+triples, "
-                               "OMS-i8 20it + SPA-f32 50it, a_max 12, 3 dB, + IS top-4 TS",
+                               "OMS-i8 20it + SPA-q20/f32 50it, a_max 12, 3 dB, + IS top-4 TS",
                    "patterns": int(P), "is_frames_per_ts": args.is_frames},
         "ts_found_per_s": ts_found / wall,
         "candidates_per_s": cands / wall,
@@ -437,7 +437,7 @@ def bench_batch(tsg):
     same_s = all(same_job(a, b) for a, b in zip(ref_s, got_s))
     ctx.close()
     return {"workload": "64 QC codes, bases 3x6/4x8/3x12/4x24, Z 16..384 (seed 4); per code 4096 "
-                        "impulse patterns OMS-i8 20it + 16384 IS frames SPA-f32 50it at 3 dB",
+                        "impulse patterns OMS-i8 20it + 16384 IS frames SPA (Q20 messages, f32 phi) 50it at 3 dB",
             "jobs": len(jobs), "edge_updates": eu, "ts_found": ts,
             "plain": {"seconds": t_plain, "edge_updates_per_s": eu / t_plain,
                       "ts_found_per_s": ts / t_plain},
@@ -574,7 +574,7 @@ def bench_serve(tsg, seconds, rate, stress_seconds=5.0, capacity_jobs=300):
     _say(f"served: {len(stress_jobs)} jobs paced over {stress_seconds:.0f} s under a 1 GiB budget")
     stress = _serve_run(tsg, pool, graphs, stress_jobs, 1 << 30, True)
     out = {"workload": f"Poisson {rate:g} jobs/s for {seconds:g} s, 46x68-base QC pool of 32 "
-                       "(N up to 25.7k), 50/50 search (OMS-i8 20it) / IS (SPA-f32 50it, 2..5 dB), "
+                       "(N up to 25.7k), 50/50 search (OMS-i8 20it) / IS (SPA-q20/f32 50it, 2..5 dB), "
                        "10^3..10^5 frames log-uniform, 4 worker slots, 32 GiB HBM budget"}
     out.update(paced)
     out["all_at_once"] = dict(burst, jobs_of_stream=len(cap))
@@ -637,7 +637,7 @@ def bench_qc2640(tsg):
               "same_ts": same_s}
     cells = {f"{a},{b}": int(spectrum[a, b]) for a in range(spectrum.shape[0])
              for b in range(spectrum.shape[1]) if spectrum[a, b]}
-    return {"workload": "QC (3,6) N=2640 Z=440 girth 8 (seed 3): SPA-f32 50it search over "
+    return {"workload": "QC (3,6) N=2640 Z=440 girth 8 (seed 3): SPA-q20/f32 50it search over "
                         f"{len(pats)} triples and over the {len(reps)} orbit representatives, then the "
                         f"union bound over the top {n_ts} TS x 4 SNRs x 1e5 IS frames",
             "ts_found": int(len(recs)), "spectrum_all_sets": cells,

@@ -12,9 +12,8 @@
 //   [384, p)            reduction partials, 3 doubles per 16384 frames
 //   [p, p + K)          per-frame flags
 //   [.., .. + 8K)       per-frame sums of the set's normals
-//   [.., end)           the decoder's save area of the fixed-point exit, when
-//                       it fits (otherwise every iteration is computed, with
-//                       the same results)
+// (the register-layout decoder keeps all other state of a frame in LDS and
+// registers, its fixed-point exit included)
 // Calls on one GPU share the array: calls that overlap on a GPU race, so a
 // caller serialises them (ts_ctx calls already are, by the context mutex; two
 // contexts on one GPU are not).
@@ -60,8 +59,7 @@ int noalloc_init(int device) {
 }
 
 int64_t noalloc_max_frames() {
-    // flags and sums (9 bytes a frame) and the partials, with room left for
-    // the fixed-point save area of a typical register shape
+    // flags and sums (9 bytes a frame) and the partials
     return (int64_t)1 << 21;
 }
 
@@ -118,10 +116,6 @@ extern "C" int ts_is_estimate_noalloc(ts_ctx *ctx, ts_code *code, const int32_t 
     double *d_wf = (double *)(base + off);
     off = al256(off + (size_t)K * sizeof(double));
     const int grid = (int)std::min<int64_t>(plan.grid, K);
-    const size_t save = (size_t)grid * plan.slot_bytes;
-    // the fixed-point exit needs the save area: in LDS (plan.save_lds) or here
-    const bool fp_exit = !o->full_iterations &&
-                         (plan.save_lds || (save > 0 && off + save <= kNoAllocScratchBytes));
     if (off > kNoAllocScratchBytes) {   // unreachable with noalloc_max_frames()
         set_error("no-allocation scratch too small");
         return TS_E_INVAL;
@@ -142,14 +136,14 @@ extern "C" int ts_is_estimate_noalloc(ts_ctx *ctx, ts_code *code, const int32_t 
     L.seed = o->seed;
     L.frame_base = o->frame_base;
     L.stream = o->stream;
-    L.fp_exit = fp_exit ? 1 : 0;
+    L.fp_exit = o->full_iterations ? 0 : 1;
     L.count_mode = o->count_mode;
     L.ts = d_t;
     L.a = a;
     L.fail = d_fail;
     L.wf = d_wf;
     L.counters = (unsigned long long *)(misc + 4);
-    L.gscr = fp_exit && !plan.save_lds ? base + off : nullptr;
+    L.gscr = nullptr;
     IsJob job{};
     job.a = make_is_dev(L, plan);
     job.cd = code->dev;

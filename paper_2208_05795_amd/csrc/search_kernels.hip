@@ -120,10 +120,13 @@ __device__ __forceinline__ T uni(T v) {
     return u.t;
 }
 
+// Check rules.  On entry val[j] is APP_{t-1} of the check's j-th neighbour and
+// c2v[j] the old message on that edge; on return c2v[j] is the new message and
+// val[j] its change, new - old.
 struct OmsRule {
     static constexpr int kDummy = 127;   // padded edges read as a saturated positive message
     template <int DC>
-    __device__ static __forceinline__ void update(const int (&val)[DC], int (&c2v)[DC],
+    __device__ static __forceinline__ void update(int (&val)[DC], int (&c2v)[DC],
                                                   const int (&nb)[DC], int pad_id, int offset) {
         int mn1 = 127, mn2 = 127, idx = 0, sgn = 0;
         int v2[DC];
@@ -147,7 +150,9 @@ struct OmsRule {
         for (int j = 0; j < DC; ++j) {
             int mag = (j == idx ? mn2 : mn1) - offset;
             mag = mag < 0 ? 0 : mag;
-            c2v[j] = (sgn ^ (v2[j] < 0)) ? -mag : mag;
+            const int m = (sgn ^ (v2[j] < 0)) ? -mag : mag;
+            val[j] = m - c2v[j];
+            c2v[j] = m;
         }
     }
 };
@@ -159,16 +164,16 @@ struct SpaRule {
     // a per-edge test.  Real APP values stay below 2^30 + 2^27 in magnitude.
     static constexpr int kDummy = 1 << 30;
     template <int DC>
-    __device__ static __forceinline__ void update(const int (&val)[DC], int (&c2v)[DC],
+    __device__ static __forceinline__ void update(int (&val)[DC], int (&c2v)[DC],
                                                   const int (&nb)[DC], int pad, int off) {
-        update_impl<DC, true>(val, c2v, nb, pad, off);
+        update_impl<DC, true>(val, c2v);
     }
+    // The per-edge temporaries are the phi terms (which become the exclusive
+    // sums in place) and the prefix sums; the v2c signs are bits of one word.
     template <int DC, bool kShortcuts>
-    __device__ static __forceinline__ void update_impl(const int (&val)[DC], int (&c2v)[DC],
-                                                       const int (&)[DC], int, int) {
+    __device__ static __forceinline__ void update_impl(int (&val)[DC], int (&c2v)[DC]) {
         float ph[DC];
-        int d[DC];
-        int sx = 0;   // sign bit = parity of the negative v2c messages
+        unsigned neg = 0;   // bit j: the v2c message of edge j is negative
         // Wavefront-uniform shortcuts (impulse frames, kShortcuts): where every
         // lane is in one regime, the other regime's arithmetic (whose result
         // the selection would drop) is skipped.  The values are those of the
@@ -179,54 +184,64 @@ struct SpaRule {
             bool small = true;
 #pragma unroll
             for (int j = 0; j < DC; ++j) {
-                d[j] = val[j] - c2v[j];
-                sx ^= d[j];
-                const float u = phi_in_u(d[j]);
+                const int d = val[j] - c2v[j];
+                neg |= (unsigned)(d < 0) << j;
+                const float u = phi_in_u(d);
                 ph[j] = phi_in_small(u);
                 small &= u < kPhiSmallU;
             }
             if (!__all(small)) {
 #pragma unroll
                 for (int j = 0; j < DC; ++j) {
-                    const float u = phi_in_u(d[j]);
+                    const float u = phi_in_u(val[j] - c2v[j]);
                     if (!(u < kPhiSmallU)) ph[j] = phi_in_big(u);
                 }
             }
         } else {
 #pragma unroll
             for (int j = 0; j < DC; ++j) {
-                d[j] = val[j] - c2v[j];
-                sx ^= d[j];
-                const float u = phi_in_u(d[j]);
+                const int d = val[j] - c2v[j];
+                neg |= (unsigned)(d < 0) << j;
+                const float u = phi_in_u(d);
                 ph[j] = u < kPhiSmallU ? phi_in_small(u) : phi_in_big(u);
             }
         }
-        // exclusive sums from prefix and suffix sums (no cancellation)
-        float pre[DC], suf[DC];
+        // exclusive sums from prefix and suffix sums (no cancellation): the
+        // suffix sums run from the right, in the same order of additions as
+        // a suffix array, and ph[j] becomes the exclusive sum of edge j
+        float pre[DC];
         pre[1] = ph[0];
 #pragma unroll
         for (int j = 1; j + 1 < DC; ++j) pre[j + 1] = pre[j] + ph[j];
-        suf[DC - 1] = ph[DC - 1];
+        float sf = ph[DC - 1];
+        ph[DC - 1] = pre[DC - 1];
 #pragma unroll
-        for (int j = DC - 2; j >= 1; --j) suf[j] = suf[j + 1] + ph[j];
-        auto excl = [&](int j) { return j == 0 ? suf[1] : (j == DC - 1 ? pre[DC - 1] : pre[j] + suf[j + 1]); };
+        for (int j = DC - 2; j >= 1; --j) {
+            const float e = pre[j] + sf;
+            sf = sf + ph[j];
+            ph[j] = e;
+        }
+        ph[0] = sf;
         bool plain = kShortcuts;
         if constexpr (kShortcuts) {
 #pragma unroll
-            for (int j = 0; j < DC; ++j) plain &= excl(j) >= kPhiYSeries;
+            for (int j = 0; j < DC; ++j) plain &= ph[j] >= kPhiYSeries;
         }
         // sign of the other edges' product applied to the float before the
         // (sign-symmetric) rounding to Q20
+        const unsigned par = (unsigned)__builtin_popcount(neg) & 1u;
         auto put = [&](int j, float f) {
-            const int sb = (sx ^ d[j]) & (int)0x80000000u;
-            c2v[j] = __float2int_rn(__int_as_float(__float_as_int(f) ^ sb));
+            const int sb = (int)((par ^ (neg >> j)) << 31);
+            const int m = __float2int_rn(__int_as_float(__float_as_int(f) ^ sb));
+            val[j] = m - c2v[j];
+            c2v[j] = m;
         };
         if (kShortcuts && __all(plain)) {
 #pragma unroll
-            for (int j = 0; j < DC; ++j) put(j, phi_out_q_plain(excl(j)));
+            for (int j = 0; j < DC; ++j) put(j, phi_out_q_plain(ph[j]));
         } else {
 #pragma unroll
-            for (int j = 0; j < DC; ++j) put(j, phi_out_q(fmaxf(excl(j), kPhiYMin)));
+            for (int j = 0; j < DC; ++j) put(j, phi_out_q(fmaxf(ph[j], kPhiYMin)));
         }
     }
 };
@@ -235,9 +250,9 @@ struct SpaRule {
 // extra paths cost the IS kernels more than they save).
 struct SpaIsRule : SpaRule {
     template <int DC>
-    __device__ static __forceinline__ void update(const int (&val)[DC], int (&c2v)[DC],
+    __device__ static __forceinline__ void update(int (&val)[DC], int (&c2v)[DC],
                                                   const int (&nb)[DC], int pad, int off) {
-        update_impl<DC, false>(val, c2v, nb, pad, off);
+        update_impl<DC, false>(val, c2v);
     }
 };
 
@@ -262,7 +277,8 @@ __device__ __forceinline__ int q4_impulse(int qb, int k) {
     return (int)q;
 }
 
-// Shared-memory layout of a frame (byte offsets).
+// Shared-memory layout of a frame (byte offsets): the channel values and a
+// ring of three APP buffers (the layered decoder uses two of them).
 struct Lds {
     int np, W, T;
     size_t lam, app, hist, imask, wsyn, pcnt, moved, extra, total;
@@ -297,12 +313,11 @@ __host__ __device__ inline Lds lds_layout(int n, int T, bool with_hist) {
 }
 
 struct Frame {
-    int *lam, *app;
+    int *lam, *app;   // LDS: channel values; APP slots (np apart)
     unsigned long long *hist;   // nullable
     int *wsyn, *pcnt;
-    int *moved;   // per iteration: bit 0 APP changed, bit 1 a check message changed
-    int *vsave;   // global save area of the messages (B x CPT x DC), or nullptr
-    unsigned *hsh;   // LDS after the frame: each thread's hash of its last messages
+    int *moved;   // per iteration: a check message changed
+    int *vsave;   // layered decoder: save area of the messages (B x CPT x DC), or nullptr
     int n, np, W, T;
 };
 
@@ -313,7 +328,10 @@ struct DecRes {
     const int *app;   // LDS: the APP values of the decode's final hard decision
 };
 
-template <int DC, int CPT>
+// The neighbours of the thread's checks (padded edges: n), as indices or, with
+// kBytes, as byte offsets into an int32 array (the flooding decoder addresses
+// both APP slots from them).
+template <int DC, int CPT, bool kBytes = false>
 __device__ __forceinline__ void load_neighbours(const DevCode &cd, int (&nb)[CPT][DC],
                                                 const int *tab = nullptr) {
     const int B = blockDim.x, tid = threadIdx.x;
@@ -325,17 +343,26 @@ __device__ __forceinline__ void load_neighbours(const DevCode &cd, int (&nb)[CPT
         for (int j = 0; j < DC; ++j) {
             int v = -1;
             if (chk < cd.m && j < cd.dc_pad) v = tab[(size_t)j * cd.m_tab + chk];
-            nb[c][j] = v < 0 ? cd.n : v;
+            nb[c][j] = (v < 0 ? cd.n : v) * (kBytes ? 4 : 1);
         }
     }
 }
 
-// One decode.  On entry lam[] holds the channel values, APP slots 0 and 1 equal
-// lam[], wsyn/pcnt are zero and all threads have passed a barrier.
+// One flooding decode.  On entry lam[] holds the channel values (slot n: the
+// padding value), APP slots 0 and 1 equal lam[], wsyn/pcnt/moved are zero and
+// all threads have passed a barrier.  Iteration t: each thread gathers
+// APP_{t-1} (slot cur) for its checks, takes the syndrome bit of x_{t-1},
+// applies the rule and adds the new messages into slot nxt (which holds lambda)
+// with integer atomics; the hard decision x_{t-1} by ballot; the third slot is
+// set to lambda for iteration t + 1; one barrier, then the stop tests.  Integer
+// sums are exact and order-free.  The rule also reports each message's change
+// (new - old): an iteration in which no message on a real edge changed leaves
+// APP_t = APP_{t-1}, and every later iteration repeats it (fixed point).
+// nb: byte offsets of the neighbours (padded edges: 4n).
 template <class Rule, int DC, int CPT>
 __device__ __forceinline__ DecRes run_decode(const Frame &F, const int (&nb)[CPT][DC],
-                                             int (&c2v)[CPT][DC], int offset) {
-    const int n = F.n, np = F.np, W = F.W, T = F.T;
+                                             int (&c2v)[CPT][DC], int offset, int fp_exit) {
+    const int n = F.n, np = F.np, W = F.W, T = F.T, n4 = F.n * 4;
     const int B = blockDim.x, NW = B >> 6;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
 #pragma unroll
@@ -344,34 +371,37 @@ __device__ __forceinline__ DecRes run_decode(const Frame &F, const int (&nb)[CPT
         for (int j = 0; j < DC; ++j) c2v[c][j] = 0;
     int cur = 0, nxt = 1, spare = 2;
     int iters = T, wmin = INT_MAX, tmin = 0, fixed = 0;
-    bool verify = false;   // iteration t compares its messages with those of t - 1
     const int *last = F.app;
     for (int t = 1; t <= T + 1; ++t) {
         const int *A = F.app + cur * np;
         last = A;   // APP_{t-1}: the final values when the decode ends in this iteration
-        int *N = F.app + nxt * np;
+        const char *Ab = (const char *)A;
+        char *Nb = (char *)(F.app + nxt * np);
         int unsat = 0;
-        if (verify) {   // the thread's messages, contiguous
-            int *vs = F.vsave + (unsigned)tid * (CPT * DC);
-#pragma unroll
-            for (int c = 0; c < CPT; ++c)
-#pragma unroll
-                for (int j = 0; j < DC; ++j) vs[c * DC + j] = c2v[c][j];
-        }
+        unsigned chg = 0;
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
             int val[DC];
 #pragma unroll
-            for (int j = 0; j < DC; ++j) val[j] = A[nb[c][j]];
+            for (int j = 0; j < DC; ++j) val[j] = *(const int *)(Ab + nb[c][j]);
             int par = 0;
 #pragma unroll
             for (int j = 0; j < DC; ++j) par ^= (val[j] < 0);
             unsat += par;
             if (t <= T) {
-                Rule::template update<DC>(val, c2v[c], nb[c], n, offset);
+                Rule::template update<DC>(val, c2v[c], nb[c], n4, offset);   // val: the changes
+                // Padded edges carry nothing (their dummy slot keeps its
+                // value).  The per-edge branch also keeps each atomic next
+                // to its message in the schedule: unconditional atomics were
+                // issued as one block after the check's arithmetic, which
+                // serialised LDS and VALU work (20% slower at 24 edges).
 #pragma unroll
-                for (int j = 0; j < DC; ++j)
-                    if (nb[c][j] != n) atomicAdd(&N[nb[c][j]], c2v[c][j]);
+                for (int j = 0; j < DC; ++j) {
+                    if (nb[c][j] != n4) {
+                        atomicAdd((int *)(Nb + nb[c][j]), c2v[c][j]);
+                        chg |= (unsigned)val[j];
+                    }
+                }
             }
         }
         if (t >= 2) {
@@ -385,30 +415,11 @@ __device__ __forceinline__ DecRes run_decode(const Frame &F, const int (&nb)[CPT
                 pc += __popcll(mask);
             }
             if (lane == 0 && pc) atomicAdd(&F.pcnt[t - 1], pc);
-        }
-        if (verify) {
-            const int *vs = F.vsave + (unsigned)tid * (CPT * DC);
-            unsigned chg = 0;   // padded edges carry nothing, so they are skipped
-#pragma unroll
-            for (int c = 0; c < CPT; ++c)
-#pragma unroll
-                for (int j = 0; j < DC; ++j)
-                    if (nb[c][j] != n) chg |= (unsigned)(c2v[c][j] ^ vs[c * DC + j]);
-            if (__any(chg != 0u) && lane == 0) atomicOr(&F.moved[t], 2);
+            if (__any(chg != 0u) && lane == 0) F.moved[t] = 1;
         }
         if (t < T) {
-            // a hash of the thread's new messages, unchanged on every thread,
-            // points to a fixed point (the next iteration verifies it)
-            unsigned hh = 0;
-#pragma unroll
-            for (int c = 0; c < CPT; ++c)
-#pragma unroll
-                for (int j = 0; j < DC; ++j) hh = hh * 0x9E3779B1u + (unsigned)c2v[c][j];
-            const unsigned hp = F.hsh[tid];
-            F.hsh[tid] = hh;
             int *S = F.app + spare * np;
             for (int v = tid; v < np; v += B) S[v] = F.lam[v];
-            if (t >= 2 && !__all(hh == hp) && lane == 0) atomicOr(&F.moved[t], 1);
         }
         __syncthreads();
         if (t >= 2) {
@@ -421,12 +432,10 @@ __device__ __forceinline__ DecRes run_decode(const Frame &F, const int (&nb)[CPT
                 iters = t - 1;
                 break;
             }
-            if (verify && (F.moved[t] & 2) == 0) {
+            if (fp_exit && t <= T && F.moved[t] == 0) {
                 fixed = t;
                 break;
             }
-            // the messages' hash did not change: iteration t + 1 checks them
-            verify = F.vsave && t < T && (F.moved[t] & 1) == 0;
         }
         const int tmp = cur;
         cur = nxt;
@@ -434,11 +443,11 @@ __device__ __forceinline__ DecRes run_decode(const Frame &F, const int (&nb)[CPT
         spare = tmp;
     }
     if (fixed) {
-        // No check message changed in iteration t = fixed (padded edges carry
-        // none), so APP_t = APP_{t-1} and every later iteration repeats
-        // iteration t - 1 = run: the decode ends at T as if run to the end.
-        // Of the records after run only the number of 1s at T is read here;
-        // the candidate writer reads history row run for the later ones.
+        // No check message changed in iteration t = fixed, so APP_t = APP_{t-1}
+        // and every later iteration repeats iteration t - 1 = run: the decode
+        // ends at T as if run to the end.  Of the records after run only the
+        // number of 1s at T is read here; the candidate writer reads history
+        // row run - 1 (the hard decision x_run) for the later ones.
         if (tid == 0) F.pcnt[T] = F.pcnt[fixed - 1];
         __syncthreads();
     }
@@ -719,7 +728,7 @@ struct RegSearchDec {
     const SearchLaunch *a;
     Frame F;
     unsigned long long *imask;
-    int W, offset;
+    int W, offset, fp_exit;
     int nb[CPT][DC];
     int c2v[CPT][DC];
 
@@ -733,10 +742,7 @@ struct RegSearchDec {
         F.wsyn = (int *)(frame + L.wsyn);
         F.pcnt = (int *)(frame + L.pcnt);
         F.moved = (int *)(frame + L.moved);
-        F.hsh = (unsigned *)(frame + L.total);
-        F.vsave = !J.a.fp_exit ? nullptr
-                  : J.a.save_lds ? (int *)(frame + L.total + (size_t)blockDim.x * 4)
-                  : J.a.gscr ? (int *)uni(J.a.gscr + (size_t)blockIdx.x * J.a.slot_bytes) : nullptr;
+        F.vsave = nullptr;
         F.n = n;
         F.np = L.np;
         F.W = L.W;
@@ -744,7 +750,8 @@ struct RegSearchDec {
         imask = (unsigned long long *)(frame + L.imask);
         W = L.W;
         offset = uni(J.a.offset);
-        load_neighbours<DC, CPT>(J.cd, nb);
+        fp_exit = uni(J.a.fp_exit);
+        load_neighbours<DC, CPT, true>(J.cd, nb);
     }
 
     __device__ __forceinline__ DecRes decode(int K) {
@@ -764,7 +771,7 @@ struct RegSearchDec {
             F.moved[i] = 0;
         }
         __syncthreads();
-        return run_decode<Rule, DC, CPT>(F, nb, c2v, offset);
+        return run_decode<Rule, DC, CPT>(F, nb, c2v, offset, fp_exit);
     }
     __device__ __forceinline__ const unsigned long long *hist() const { return F.hist; }
 };
@@ -936,15 +943,14 @@ struct LayDec {
         a = &J.a;
         const int n = uni(J.cd.n), T = uni(J.a.max_iter);
         const Lds L = lds_layout(n, T, true);
-        F.lam = (int *)(frame + L.lam);
+        F.lam = nullptr;
         F.app = (int *)(frame + L.app);
         F.hist = (unsigned long long *)(frame + L.hist);
         F.wsyn = (int *)(frame + L.wsyn);
         F.pcnt = (int *)(frame + L.pcnt);
         F.moved = (int *)(frame + L.moved);
-        F.hsh = (unsigned *)(frame + L.total);
         F.vsave = !J.a.fp_exit ? nullptr
-                  : J.a.save_lds ? (int *)(frame + L.total + (size_t)blockDim.x * 4)
+                  : J.a.save_lds ? (int *)(frame + L.total)
                   : J.a.gscr ? (int *)uni(J.a.gscr + (size_t)blockIdx.x * J.a.slot_bytes) : nullptr;
         F.n = n;
         F.np = L.np;
@@ -1148,6 +1154,7 @@ struct RegIsDec {
     Frame F;
     float *tn;
     int *tsl;
+    int fp_exit;
     int nb[CPT][DC];
     int c2v[CPT][DC];
 
@@ -1161,19 +1168,17 @@ struct RegIsDec {
         F.wsyn = (int *)(frame + L.wsyn);
         F.pcnt = (int *)(frame + L.pcnt);
         F.moved = (int *)(frame + L.moved);
-        F.hsh = (unsigned *)(frame + L.total);
-        F.vsave = !J.a.fp_exit ? nullptr
-                  : J.a.save_lds ? (int *)(frame + L.total + (size_t)blockDim.x * 4)
-                  : J.a.gscr ? (int *)uni(J.a.gscr + (size_t)blockIdx.x * J.a.slot_bytes) : nullptr;
+        F.vsave = nullptr;
         F.n = n;
         F.np = L.np;
         F.W = L.W;
         F.T = T;
+        fp_exit = uni(J.a.fp_exit);
         tn = (float *)(frame + L.extra);
         tsl = (int *)(tn + kMaxWidth);
         const int tid = threadIdx.x;
         if (tid < kMaxWidth) tsl[tid] = tid < J.a.a ? J.a.ts[tid] : -1;
-        load_neighbours<DC, CPT>(J.cd, nb);
+        load_neighbours<DC, CPT, true>(J.cd, nb);
     }
 
     __device__ __forceinline__ DecRes decode_frame(int f) {
@@ -1194,7 +1199,7 @@ struct RegIsDec {
             F.moved[i] = 0;
         }
         __syncthreads();
-        return run_decode<SpaIsRule, DC, CPT>(F, nb, c2v, 0);
+        return run_decode<SpaIsRule, DC, CPT>(F, nb, c2v, 0, fp_exit);
     }
 };
 
@@ -1363,8 +1368,8 @@ __device__ __forceinline__ int g_lambda(const GFrame &F, int v) {
 }
 
 // Check pass of one check (sorted position p, class q); returns the parity of
-// the hard decisions of APP_{t-1} on its variables.  chg gathers the bits in
-// which a new message on a real edge differs from the old one (from t = 2 on).
+// the hard decisions of APP_{t-1} on its variables.  chg gathers the bits of
+// the changes (new - old) of the messages on real edges (read from t = 2 on).
 template <class Rule, int DC, class M, bool kAcc>
 __device__ __forceinline__ int check_g(const GFrame &F, int q, int p, int t, int offset,
                                        unsigned &chg) {
@@ -1387,14 +1392,17 @@ __device__ __forceinline__ int check_g(const GFrame &F, int q, int p, int t, int
     for (int j = 0; j < DC; ++j) par ^= (val[j] < 0);
     if (t <= F.T) {
         M *msg = (M *)F.msg;
-        int old[DC];
 #pragma unroll
-        for (int j = 0; j < DC; ++j) c2v[j] = old[j] = t == 1 ? 0 : (int)msg[base + (size_t)j * stride];
-        Rule::template update<DC>(val, c2v, nb, F.n, offset);
+        for (int j = 0; j < DC; ++j) c2v[j] = t == 1 ? 0 : (int)msg[base + (size_t)j * stride];
+        // the sum-product rule without the wavefront-uniform shortcuts: they
+        // save arithmetic that this memory-bound pass does not wait on, and
+        // their registers spill here
+        if constexpr (std::is_same<Rule, SpaRule>::value) SpaRule::update_impl<DC, false>(val, c2v);
+        else Rule::template update<DC>(val, c2v, nb, F.n, offset);   // val: the changes
 #pragma unroll
         for (int j = 0; j < DC; ++j) {
             msg[base + (size_t)j * stride] = (M)c2v[j];
-            if (nb[j] != F.n) chg |= (unsigned)(old[j] ^ c2v[j]);
+            if (nb[j] != F.n) chg |= (unsigned)val[j];
         }
         if constexpr (kAcc) {
             // APP_t - lambda accumulated in LDS (exact integer sums, any order)
@@ -1806,10 +1814,8 @@ int plan_candidates(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter,
             const int block = ((c->m + cp - 1) / cp + 63) / 64 * 64;
             if (block > ke->max_block) continue;
             SearchKernel kern = decoder == TS_DEC_OMS_I8 ? ke->oms : (decoder == TS_DEC_SPA_F32 ? ke->spa : ke->lnms);
-            const size_t lds_b = lds + (size_t)block * 4;   // + the threads' message hashes
-            if (lds_b > ctx->lds_per_block) continue;
             int per_cu = 0;
-            TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, block, lds_b));
+            TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, block, lds));
             if (per_cu < 1) continue;
             SearchPlan p;
             p.kind = kPlanRegister;
@@ -1817,14 +1823,17 @@ int plan_candidates(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter,
             p.block = block;
             p.cpt = cp;
             p.dc = dc;
-            p.lds = lds_b;
+            p.lds = lds;
             p.grid = per_cu * ctx->num_cu;
-            p.slot_bytes = (size_t)block * cp * dc * 4;   // message save area (fixed-point test)
+            // the layered decoder's fixed-point test saves the messages of a
+            // verifying sweep (the flooding decoders see their changes directly)
+            p.slot_bytes = decoder == TS_DEC_LNMS_Q4 ? (size_t)block * cp * dc * 4 : 0;
             p.hist_off = 0;
             out->push_back(p);
+            if (!p.slot_bytes) continue;
             // the same shape with the save area in LDS, where it fits (the
             // autotuner weighs the lost occupancy against the global traffic)
-            const size_t lds_s = lds_b + p.slot_bytes;
+            const size_t lds_s = lds + p.slot_bytes;
             int per_cu_s = 0;
             if (lds_s <= ctx->lds_per_block &&
                 hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_s, (const void *)kern, block, lds_s) == hipSuccess &&
@@ -1984,10 +1993,8 @@ int plan_is_candidates(ts_ctx *ctx, const ts_code *c, int max_iter, int layout,
             if (!k) continue;
             const int b = ((c->m + cp - 1) / cp + 63) / 64 * 64;
             if (b > k->is_max_block) continue;
-            const size_t lds_b = lds + (size_t)b * 4;   // + the threads' message hashes
-            if (lds_b > ctx->lds_per_block) continue;
             int per_cu = 0;
-            TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k->is, b, lds_b));
+            TSG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k->is, b, lds));
             if (per_cu < 1) continue;
             SearchPlan p;
             p.kind = kPlanRegister;
@@ -1995,22 +2002,11 @@ int plan_is_candidates(ts_ctx *ctx, const ts_code *c, int max_iter, int layout,
             p.block = b;
             p.cpt = cp;
             p.dc = dc;
-            p.lds = lds_b;
+            p.lds = lds;
             p.grid = per_cu * ctx->num_cu;
-            p.slot_bytes = (size_t)b * cp * dc * 4;   // save area of the messages
+            p.slot_bytes = 0;
             p.hist_off = 0;
             out->push_back(p);
-            const size_t lds_s = lds_b + p.slot_bytes;   // the save area in LDS
-            int per_cu_s = 0;
-            if (lds_s <= ctx->lds_per_block &&
-                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_s, (const void *)k->is, b, lds_s) == hipSuccess &&
-                per_cu_s >= 1) {
-                p.lds = lds_s;
-                p.grid = per_cu_s * ctx->num_cu;
-                p.slot_bytes = 0;
-                p.save_lds = 1;
-                out->push_back(p);
-            }
         }
     }
     if (layout != TS_LAYOUT_REGISTER) {
