@@ -295,9 +295,9 @@ int ts_is_estimate(ts_ctx *ctx, ts_code *code, const int32_t *ts_bits, int32_t a
  * by each GPU the library runs on until the process ends.  Same arguments,
  * results and statistics as ts_is_estimate; the caller still owns ts_bits,
  * res and fail_out (host).  Limits: shift >= 0 (no eps* or pilot search),
- * n_frames <= 2^21, and codes whose IS launch shape is the register layout;
- * the fixed-point exit is used when its save area fits beside the frames
- * (results are identical either way).  Calls on one GPU share the array:
+ * n_frames <= 2^21, and codes whose IS launch shape is the register layout
+ * (whose frames stay in LDS and registers, fixed-point exit included).  Calls
+ * on one GPU share the array:
  * calls that overlap on a GPU (two contexts on one device, used from two
  * threads) race; calls on one context are serialised.  Errors: TS_E_INVAL
  * beyond the limits (with the limit in the message), as ts_is_estimate

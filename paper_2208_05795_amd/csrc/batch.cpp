@@ -299,7 +299,6 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
                 IsJob j{};
                 j.a = make_is_dev(I[m].L, I[m].plan);
                 j.a.slot_bytes = (long long)g.plan.slot_bytes;
-                j.a.save_lds = g.plan.save_lds;
                 j.cd = I[m].b->code->dev;
                 j.item0 = item0;
                 item0 += I[m].K;

@@ -280,9 +280,9 @@ struct SearchPlan {
     int dc;         // padded check degree of the kernel (streamed: largest class)
     size_t lds;     // dynamic LDS bytes
     int grid;       // persistent workgroups
-    size_t slot_bytes;   // global scratch per workgroup (register kind: message save area)
+    size_t slot_bytes;   // global scratch per workgroup (register kind: the layered decoder's message save area)
     size_t hist_off;     // streamed: offset of the iteration history in a slot
-    int save_lds = 0;    // register kind: the message save area in LDS (after the hashes)
+    int save_lds = 0;    // register kind: the layered decoder's message save area in LDS (after the frame)
 };
 
 // Whether a plan is allowed under a TS_LAYOUT_* request (streamed plans carry
@@ -316,7 +316,7 @@ struct SearchLaunch {
     unsigned char *gscr;            // grid x slot_bytes scratch (nullptr: none)
     long long slot_bytes, hist_off;
     int fp_exit;                    // end decodes at a fixed point
-    int save_lds;                   // register kind: message save area in LDS
+    int save_lds;                   // register kind: the layered decoder's message save area in LDS
 };
 
 int plan_search(ts_ctx *ctx, const ts_code *c, int decoder, int max_iter, SearchPlan *plan);
@@ -352,7 +352,6 @@ struct IsDev {
     unsigned char *gscr;   // per-workgroup scratch (nullptr: none)
     long long slot_bytes, lam_off;
     int fp_exit;           // end decodes at a fixed point
-    int save_lds;          // register kind: message save area in LDS
     int count_mode;        // TS_IS_COUNT_ALL / TS_IS_COUNT_TS
     // mixture of shifts (n_mix > 0): frame f takes component j = f n_mix / n_frames,
     // shift mix_s0 + j mix_ds, and the balance-heuristic weight of all components

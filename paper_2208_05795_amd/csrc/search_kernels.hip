@@ -2056,7 +2056,6 @@ IsDev make_is_dev(const IsLaunch &a, const SearchPlan &plan) {
     d.mix_s0 = a.mix_s0;
     d.mix_ds = a.mix_ds;
     d.slot_bytes = (long long)plan.slot_bytes;
-    d.save_lds = plan.save_lds;
     d.lam_off = (long long)plan.hist_off;
     return d;
 }
