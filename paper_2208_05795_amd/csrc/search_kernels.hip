@@ -405,7 +405,7 @@ __device__ __forceinline__ DecRes run_decode(const Frame &F, const int (&nb)[CPT
             }
         }
         if (t >= 2) {
-            const int us = wave_sum(unsat);
+            const int us = wave_sum_bits<count_bits(CPT)>(unsat);   // unsat <= CPT
             if (lane == 0 && us) atomicAdd(&F.wsyn[t - 1], us);
             int pc = 0;
             for (int i = wid; i < W; i += NW) {
@@ -875,7 +875,7 @@ __device__ __forceinline__ DecRes run_decode_l(const Frame &F, const int (&nb)[C
                 if (nb[c][j] != n) par ^= (A[nb[c][j]] < 0);
             unsat += par;
         }
-        const int us = wave_sum(unsat);
+        const int us = wave_sum_bits<count_bits(CPT)>(unsat);   // unsat <= CPT
         if (lane == 0 && us) atomicAdd(&F.wsyn[t], us);
         int pc = 0;
         for (int i = wid; i < W; i += NW) {

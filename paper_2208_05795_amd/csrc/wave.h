@@ -13,6 +13,19 @@ __device__ __forceinline__ int wave_sum(int x) {
     return x;
 }
 
+// Sum over the wavefront of values in [0, 2^B): one ballot and population
+// count per bit, instead of the six shuffle steps of wave_sum.
+template <int B>
+__device__ __forceinline__ int wave_sum_bits(int x) {
+    int s = 0;
+#pragma unroll
+    for (int b = 0; b < B; ++b) s += __popcll(__ballot((x >> b) & 1)) << b;
+    return s;
+}
+
+// Bits that hold a count in [0, n].
+constexpr int count_bits(int n) { return n < 2 ? 1 : 1 + count_bits(n >> 1); }
+
 __device__ __forceinline__ int wave_min(int x) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o, 64));

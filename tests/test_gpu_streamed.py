@@ -79,9 +79,10 @@ def test_layouts_identical_oms(ctx, oracle_mod, name):
     for r, t, st, lab in ((rb, tb, sb, "gather"), (rc, tc, sc, "accum")):
         _same(ra, r, f"{name} {lab}")
         assert ta == t
-        # the layouts' fixed-point exits may stop after different iterations
-        # (the streamed one compares each iteration's messages with the last)
+        # both layouts' fixed-point exits stop at the first iteration whose
+        # messages equal the last one's: the same iterations are computed
         assert sa["decodes"] == st["decodes"]
+        assert sa["edge_updates"] == st["edge_updates"], (lab, sa["edge_updates"], st["edge_updates"])
     _say(f"  identical: {len(ta)} TS, {sa['edge_updates']:.3e} edge-updates; decode ms register "
          f"{sa['decode_ms']:.2f} streamed gather {sb['decode_ms']:.2f} accum {sc['decode_ms']:.2f}")
     g.free()
@@ -96,10 +97,11 @@ def test_layouts_identical_spa(ctx, oracle_mod, name):
     _say(f"{name} SPA register vs streamed, {len(pats)} patterns")
     g = ctx.load_code(code)
     (ra, ta, sa), (rb, tb, sb), (rc, tc, sc) = _all_layouts(g, pats, decoder=tsg.DEC_SPA, a_max=12, **SPA)
-    for r, t, lab in ((rb, tb, "gather"), (rc, tc, "accum")):
+    for r, t, st, lab in ((rb, tb, sb, "gather"), (rc, tc, sc, "accum")):
         _same(ra, r, f"{name} {lab}")
         assert ta == t
-    _say(f"  identical: {len(ta)} TS; decode ms register {sa['decode_ms']:.2f} "
+        assert sa["edge_updates"] == st["edge_updates"], (lab, sa["edge_updates"], st["edge_updates"])
+    _say(f"  identical: {len(ta)} TS, {sa['edge_updates']:.3e} edge-updates; decode ms register {sa['decode_ms']:.2f} "
          f"streamed gather {sb['decode_ms']:.2f} accum {sc['decode_ms']:.2f}")
     g.free()
 
@@ -118,6 +120,8 @@ def test_layouts_identical_is(ctx, oracle_mod, name):
         assert np.array_equal(res[0]["fail"], r["fail"])
         for f in ("p_hat", "var", "sum_w", "sum_w2", "n_fail"):
             assert res[0][f] == r[f], f
+        # the same fixed-point iterations in both layouts
+        assert res[0]["stats"]["edge_updates"] == r["stats"]["edge_updates"]
     _say(f"{name} IS register vs streamed identical: p {res[0]['p_hat']:.4e}, "
          f"{int(res[0]['n_fail'])} failures")
     assert res[0]["n_fail"] > 0
