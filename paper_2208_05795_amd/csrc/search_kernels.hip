@@ -1723,7 +1723,7 @@ struct GEntry {
      {MaxBlockGIs<D, false>::value, MaxBlockGIs<D, true>::value},                                \
      {k_search_g<OmsRule, D, false>, k_search_g<OmsRule, D, true>},                              \
      {k_search_g<SpaRule, D, false>, k_search_g<SpaRule, D, true>}, {k_is_g<D, false>, k_is_g<D, true>}}
-const GEntry kGTable[] = {TSG_G(16), TSG_G(24), TSG_G(32)};
+const GEntry kGTable[] = {TSG_G(8), TSG_G(16), TSG_G(24), TSG_G(32)};
 #undef TSG_G
 
 const KEntry *find_kernel(int dc, int cpt) {
@@ -1746,7 +1746,12 @@ int padded_degree(const ts_code *c) {
     return 0;
 }
 
-int streamed_dcmax(const ts_code *c) { return c->dc_max <= 16 ? 16 : (c->dc_max <= 24 ? 24 : 32); }
+// Largest check-degree class of the streamed kernel for a code: the kernel's
+// registers are those of its widest class (8: 94-104 VGPRs for the SPA
+// search, against 128-144 for 16).
+int streamed_dcmax(const ts_code *c) {
+    return c->dc_max <= 8 ? 8 : (c->dc_max <= 16 ? 16 : (c->dc_max <= 24 ? 24 : 32));
+}
 
 // Streamed plans: both variants (cpt 0 gathering, 1 accumulating) and every
 // workgroup size up to the kernel's bound that fits.
