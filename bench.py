@@ -54,7 +54,7 @@ VALU_SLOTS_PER_EU = {"oms": 15.0, "spa": 2 * (3 * 4 + 5) + 6.0}
 MEASURED_TRAFFIC_BYTES = {"spa": (38.86e6 + 821.69e6)}
 # Same for the streamed-layout launch of the QC-2640 triples search (qc2640
 # section); None until measured on the current kernel.
-MEASURED_STREAMED_TRAFFIC_BYTES = 26484.60e6 + 636556.96e6
+MEASURED_STREAMED_TRAFFIC_BYTES = 239161.94e6 + 708311.64e6
 
 
 def parse():
