@@ -43,8 +43,9 @@ void *ts_exec::dalloc(size_t bytes) {
     if (bytes == 0) bytes = 4;
     void *p = nullptr;
     if (stream_alloc) {
-        if (hipMallocAsync(&p, bytes, stream) != hipSuccess) return nullptr;
-        return p;
+        const hipError_t e = ctx->pool ? hipMallocFromPoolAsync(&p, bytes, ctx->pool, stream)
+                                       : hipMallocAsync(&p, bytes, stream);
+        return e == hipSuccess ? p : nullptr;
     }
     if (ctx->alloc) return ctx->alloc(bytes, ctx->user);
     if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
@@ -847,14 +848,23 @@ int exec_init(ts_exec &ex, ts_ctx *ctx, hipStream_t stream, bool stream_alloc) {
         ex.own_stream = true;
     }
     ex.stream_alloc = stream_alloc;
-    if (stream_alloc) {
-        // keep freed stream-ordered memory in the device's pool instead of
-        // returning it at every synchronisation (serving batches allocate an
-        // arena per batch)
+    if (stream_alloc && !ctx->pool) {
+        // A pool of the context's own (the device's default pool is left as it
+        // is), which keeps freed memory instead of returning it at every
+        // synchronisation: serving batches allocate an arena per batch.  Where
+        // it cannot be made, the workers allocate from the default pool.
+        hipMemPoolProps props{};
+        props.allocType = hipMemAllocationTypePinned;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = ctx->device;
         hipMemPool_t pool = nullptr;
-        uint64_t keep = UINT64_MAX;
-        if (hipDeviceGetDefaultMemPool(&pool, ctx->device) == hipSuccess && pool)
+        if (hipMemPoolCreate(&pool, &props) == hipSuccess && pool) {
+            uint64_t keep = UINT64_MAX;
             (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+            ctx->pool = pool;
+        } else {
+            (void)hipGetLastError();
+        }
     }
     for (auto &e : ex.ev) TSG_HIP(hipEventCreate(&e));
     TSG_HIP(hipHostMalloc((void **)&ex.pinned, 64 * sizeof(int), hipHostMallocDefault));
@@ -983,6 +993,8 @@ int ts_destroy(ts_ctx *ctx) {
         std::lock_guard<std::recursive_mutex> g(ctx->mu);
         while (!ctx->codes.empty()) ts_free_code(ctx, ctx->codes.back());
         exec_fini(ctx->main);
+        // the workers (stopped above) have freed their memory into the pool
+        if (ctx->pool) (void)hipMemPoolDestroy(ctx->pool);
     }
     delete ctx;
     return TS_OK;

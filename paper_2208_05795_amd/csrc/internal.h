@@ -222,6 +222,7 @@ struct ts_ctx {
     int num_cu = 0;
     size_t lds_per_block = 0;
     std::atomic<tsg::Server *> server{nullptr};   // set once under mu, read without it
+    hipMemPool_t pool = nullptr;   // the serving workers' stream-ordered device memory
     double t0 = 0.0;   // creation time (ms, steady clock)
 };
 
