@@ -59,6 +59,21 @@ void ts_exec::dfree(void *p) {
     else (void)hipFree(p);
 }
 
+int ts_exec::bulk_buf(size_t bytes, unsigned char **p) {
+    if (bytes > bulk_cap) {
+        TSG_HIP(hipStreamSynchronize(stream));   // a copy may still use the old one
+        if (bulk) (void)hipHostFree(bulk);
+        bulk = nullptr;
+        bulk_cap = 0;
+        size_t cap = (size_t)1 << 20;
+        while (cap < bytes) cap <<= 1;
+        TSG_HIP(hipHostMalloc((void **)&bulk, cap, hipHostMallocDefault));
+        bulk_cap = cap;
+    }
+    *p = bulk;
+    return TS_OK;
+}
+
 int ts_exec::stage(const void *src, size_t bytes, void **dev, int *slot) {
     if (bytes > kJobSlotBytes) {
         tsg::set_error("job descriptors exceed %zu bytes", kJobSlotBytes);
@@ -890,6 +905,7 @@ void exec_fini(ts_exec &ex) {
     }
     if (ex.join_ev) (void)hipEventDestroy(ex.join_ev);
     if (ex.pinned) (void)hipHostFree(ex.pinned);
+    if (ex.bulk) (void)hipHostFree(ex.bulk);
     if (ex.job_host) (void)hipHostFree(ex.job_host);
     if (ex.job_dev) (void)hipFree(ex.job_dev);
     if (ex.own_stream && ex.stream) (void)hipStreamDestroy(ex.stream);
@@ -1114,9 +1130,13 @@ int ts_impulse_search(ts_ctx *ctx, ts_code *code, const ts_search_opts *o, const
     for (int i = 0; i < 5; ++i) dev_out[i] = out_buf.as<int32_t>() + i * P;
     rc = run_search(ex, code, code->table, o, pat_buf.as<int32_t>(), (int64_t)P, width, dev_out, true);
     if (rc) return rc;
-    for (int i = 0; i < 5; ++i)
-        TSG_HIP(hipMemcpyAsync(d_out[i], dev_out[i], P * 4, hipMemcpyDeviceToHost, ex.stream));
+    // the five output arrays are one device block: one copy, then host copies
+    unsigned char *h = nullptr;
+    rc = ex.bulk_buf(P * 5 * 4, &h);
+    if (rc) return rc;
+    TSG_HIP(hipMemcpyAsync(h, out_buf.p, P * 5 * 4, hipMemcpyDeviceToHost, ex.stream));
     TSG_HIP(hipStreamSynchronize(ex.stream));
+    for (int i = 0; i < 5; ++i) std::memcpy(d_out[i], h + (size_t)i * P * 4, P * 4);
     return TS_OK;
 }
 

@@ -189,16 +189,24 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
     for (IItem &it : I) { it.misc = zero; zero += kMisc; }
     for (Group &g : G) { g.queue = zero; zero += kMisc; }
     size_t o = al(zero);
+    // the search jobs' outputs and the IS jobs' reduction results each form
+    // one block, read back with one copy
+    const size_t out0 = o;
+    for (SItem &it : S) { it.out = o; o += (size_t)it.P * 5 * 4; }
+    const size_t out_bytes = o - out0;
+    o = al(o);
+    const size_t red0 = o;
+    for (IItem &it : I) { it.red = o; o += 8 * 8; }
+    const size_t red_bytes = o - red0;
+    o = al(o);
     for (SItem &it : S) {
         it.pat = o; o = al(o + (size_t)it.P * it.b->width * 4);
-        it.out = o; o = al(o + (size_t)it.P * 5 * 4);
         it.recs = o; o = al(o + (size_t)it.rec_cap * kRecStride * 4);
     }
     for (IItem &it : I) {
         it.ts = o; o = al(o + kMaxWidth * 4);
         it.fail = o; o = al(o + (size_t)it.K);
         it.wf = o; o = al(o + (size_t)it.K * 8);
-        it.red = o; o = al(o + 8 * 8);
         it.part = o; o = al(o + (size_t)is_reduce_parts(it.K) * 3 * 8);
     }
     for (Group &g : G) {
@@ -363,6 +371,7 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
     // ---- per search job: sieve into its own table, read out -----------------
     std::vector<SItem *> rerun;
     std::vector<DevTable> tables(S.size());
+    std::vector<char> done(S.size(), 0);   // outputs read back with the block below
     int64_t cands = 0;
     for (size_t i = 0; i < S.size(); ++i) {
         SItem &it = S[i];
@@ -396,13 +405,27 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
             if (rc) return rc;
             ex.stats.extract_launches++;
         }
-        for (int k = 0; k < 5; ++k) {
-            it.b->out[k].resize((size_t)it.P);
-            TSG_HIP(hipMemcpyAsync(it.b->out[k].data(), arena + it.out + (size_t)k * it.P * 4,
-                                   (size_t)it.P * 4, hipMemcpyDeviceToHost, s));
-        }
+        done[i] = 1;
     }
     ex.stats.candidates += cands;
+    // every search job's outputs (the sieves add the candidate counts): one
+    // copy into pinned memory
+    if (out_bytes) {
+        unsigned char *h = nullptr;
+        rc = ex.bulk_buf(out_bytes, &h);
+        if (rc) return rc;
+        TSG_HIP(hipMemcpyAsync(h, arena + out0, out_bytes, hipMemcpyDeviceToHost, s));
+        TSG_HIP(hipStreamSynchronize(s));
+        for (size_t i = 0; i < S.size(); ++i) {
+            if (!done[i]) continue;
+            SItem &it = S[i];
+            for (int k = 0; k < 5; ++k) {
+                it.b->out[k].resize((size_t)it.P);
+                std::memcpy(it.b->out[k].data(), h + (it.out - out0) + (size_t)k * it.P * 4,
+                            (size_t)it.P * 4);
+            }
+        }
+    }
     // ---- TS read-out ------------------------------------------------------
     for (size_t i = 0; i < S.size(); ++i) {
         SItem &it = S[i];
@@ -450,25 +473,35 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
         ex.stats.decode_ms += dec_ms;
     }
     // ---- per IS job: fixed-order reductions ----------------------------------
-    std::vector<double> red(I.size() * 4);
+    // the reduction results of all IS jobs (8 doubles apart): one copy
+    auto read_red = [&](std::vector<double> &dst) -> int {
+        dst.assign(I.size() * 4, 0.0);
+        if (!red_bytes) return TS_OK;
+        unsigned char *h = nullptr;
+        int r = ex.bulk_buf(red_bytes, &h);
+        if (r) return r;
+        TSG_HIP(hipMemcpyAsync(h, arena + red0, red_bytes, hipMemcpyDeviceToHost, s));
+        TSG_HIP(hipStreamSynchronize(s));
+        for (size_t i = 0; i < I.size(); ++i) std::memcpy(&dst[4 * i], h + 64 * i, 32);
+        return TS_OK;
+    };
+    std::vector<double> red;
     for (IItem &it : I) {
         rc = launch_is_reduce(s, make_is_dev(it.L, it.plan), it.L.wf, it.L.fail, it.K, 0, 0.0,
                               (double *)(arena + it.red), (double *)(arena + it.part));
         if (rc) return rc;
     }
-    for (size_t i = 0; i < I.size(); ++i)
-        TSG_HIP(hipMemcpyAsync(&red[4 * i], arena + I[i].red, 32, hipMemcpyDeviceToHost, s));
-    TSG_HIP(hipStreamSynchronize(s));
+    rc = read_red(red);
+    if (rc) return rc;
     for (size_t i = 0; i < I.size(); ++i) {
         rc = launch_is_reduce(s, make_is_dev(I[i].L, I[i].plan), I[i].L.wf, I[i].L.fail, I[i].K, 1,
                               red[4 * i] / (double)I[i].K, (double *)(arena + I[i].red),
                               (double *)(arena + I[i].part));
         if (rc) return rc;
     }
-    std::vector<double> red2(I.size() * 4);
-    for (size_t i = 0; i < I.size(); ++i)
-        TSG_HIP(hipMemcpyAsync(&red2[4 * i], arena + I[i].red, 32, hipMemcpyDeviceToHost, s));
-    TSG_HIP(hipStreamSynchronize(s));
+    std::vector<double> red2;
+    rc = read_red(red2);
+    if (rc) return rc;
     for (size_t i = 0; i < I.size(); ++i) {
         IItem &it = I[i];
         double r[4] = {red[4 * i], red[4 * i + 1], red[4 * i + 2], red2[4 * i + 3]};

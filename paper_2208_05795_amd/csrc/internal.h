@@ -197,8 +197,16 @@ struct ts_exec {
     hipEvent_t side_ev[kSide] = {};
     hipEvent_t join_ev = nullptr;
 
+    // pinned host buffer for bulk transfers (one copy instead of one per
+    // array; pageable copies cost a host round trip each)
+    unsigned char *bulk = nullptr;
+    size_t bulk_cap = 0;
+
     void *dalloc(size_t bytes);
     void dfree(void *p);
+    // a pinned host buffer of at least `bytes` (valid until the next call;
+    // growing it first waits for this executor's stream)
+    int bulk_buf(size_t bytes, unsigned char **p);
     // copies bytes (<= kJobSlotBytes) of job descriptors into a free slot; the
     // caller launches with *dev and then calls staged(slot)
     int stage(const void *src, size_t bytes, void **dev, int *slot);
