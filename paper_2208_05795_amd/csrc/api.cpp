@@ -96,20 +96,7 @@ void ts_exec::staged(int slot) {
     job_used[slot] = true;
 }
 
-namespace {
 
-// RAII device buffer from an executor
-struct DBuf {
-    ts_exec &ex;
-    void *p = nullptr;
-    DBuf(ts_exec &e, size_t bytes) : ex(e) { p = e.dalloc(bytes); }
-    ~DBuf() { ex.dfree(p); }
-    DBuf(const DBuf &) = delete;
-    DBuf &operator=(const DBuf &) = delete;
-    template <class T> T *as() { return (T *)p; }
-};
-
-}  // namespace
 
 namespace tsg {
 

@@ -426,14 +426,19 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
             }
         }
     }
-    // ---- TS read-out ------------------------------------------------------
-    for (size_t i = 0; i < S.size(); ++i) {
-        SItem &it = S[i];
-        if (tables[i].cap && it.b->status == TS_OK) {
-            rc = collect_table(ex, tables[i], *it.b->recs, *it.b->bits);
-            if (rc) return rc;
+    // ---- TS read-out: every job's table at once -----------------------------
+    {
+        std::vector<const DevTable *> tp;
+        std::vector<std::vector<int32_t> *> rp, bp;
+        for (size_t i = 0; i < S.size(); ++i) {
+            if (!tables[i].cap || S[i].b->status != TS_OK) continue;
+            tp.push_back(&tables[i]);
+            rp.push_back(S[i].b->recs);
+            bp.push_back(S[i].b->bits);
         }
-        table_free(ex, tables[i]);
+        rc = tp.empty() ? TS_OK : collect_tables(ex, (int)tp.size(), tp.data(), rp.data(), bp.data());
+        for (DevTable &t : tables) table_free(ex, t);
+        if (rc) return rc;
     }
     // ---- jobs whose candidates overflowed the batch buffer run alone ---------
     for (SItem *it : rerun) {

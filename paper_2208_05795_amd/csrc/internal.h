@@ -213,6 +213,17 @@ struct ts_exec {
     void staged(int slot);
 };
 
+// RAII device buffer from an executor
+struct DBuf {
+    ts_exec &ex;
+    void *p = nullptr;
+    DBuf(ts_exec &e, size_t bytes) : ex(e) { p = e.dalloc(bytes); }
+    ~DBuf() { ex.dfree(p); }
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    template <class T> T *as() { return (T *)p; }
+};
+
 namespace tsg {
 struct Server;
 }
@@ -273,6 +284,9 @@ void table_free(ts_exec &ex, DevTable &t);
 int table_grow_if_needed(ts_exec &ex, DevTable &t, int64_t incoming);
 int collect_table(ts_exec &ex, const DevTable &t, std::vector<int32_t> &rec_host,
                   std::vector<int32_t> &bits_host);
+// The same for nt tables at once (two synchronisations in all).
+int collect_tables(ts_exec &ex, int nt, const DevTable *const *t, std::vector<int32_t> *const *rec_host,
+                   std::vector<int32_t> *const *bits_host);
 // The code's table in order (collect_table), read again only after a call that
 // may have changed it.  Caller holds ctx->mu.
 int table_readout(ts_ctx *ctx, const ts_code *code, const std::vector<int32_t> **recs,

@@ -24,6 +24,7 @@
 // compared on every hash match; the slot owner publishes the tuple with a
 // release store, readers acquire before comparing.
 #include <climits>
+#include <cstring>
 
 #include "internal.h"
 #include "wave.h"
@@ -571,56 +572,88 @@ int table_grow_if_needed(ts_exec &ex, DevTable &t, int64_t incoming) {
     return TS_OK;
 }
 
-int collect_table(ts_exec &ex, const DevTable &t, std::vector<int32_t> &rec_host,
-                  std::vector<int32_t> &bits_host) {
-    rec_host.clear();
-    bits_host.clear();
-    if (!t.cap) return TS_OK;
+int collect_tables(ts_exec &ex, int nt, const DevTable *const *t, std::vector<int32_t> *const *rec_host,
+                   std::vector<int32_t> *const *bits_host) {
+    size_t idx_total = 0;
+    std::vector<size_t> idx_off(nt);
+    for (int i = 0; i < nt; ++i) {
+        rec_host[i]->clear();
+        bits_host[i]->clear();
+        idx_off[i] = idx_total;
+        idx_total += (size_t)t[i]->cap;   // a power of two: room for the padded sort
+    }
+    if (!idx_total) return TS_OK;
     hipStream_t s = ex.stream;
-    int *d_n = (int *)ex.dalloc(16);
-    if (!d_n) return TS_E_NOMEM;
-    int *idx_all = (int *)ex.dalloc((size_t)t.cap * 4);
-    if (!idx_all) { ex.dfree(d_n); return TS_E_NOMEM; }
-    int rc = launch_fill(s, d_n, 0, 1);
+    DBuf d_n(ex, (size_t)nt * 4), idx(ex, idx_total * 4);
+    if (!d_n.p || !idx.p) return TS_E_NOMEM;
+    int rc = launch_fill(s, d_n.as<int>(), 0, nt);
     if (rc) return rc;
     const int blk = 256;
-    hipLaunchKernelGGL(k_compact, dim3((t.cap + blk - 1) / blk), dim3(blk), 0, s, t, idx_all, d_n);
+    for (int i = 0; i < nt; ++i) {
+        if (!t[i]->cap) continue;
+        hipLaunchKernelGGL(k_compact, dim3((t[i]->cap + blk - 1) / blk), dim3(blk), 0, s, *t[i],
+                           idx.as<int>() + idx_off[i], d_n.as<int>() + i);
+    }
     TSG_HIP(hipGetLastError());
-    TSG_HIP(hipMemcpyAsync(ex.pinned, d_n, 4, hipMemcpyDeviceToHost, s));
+    // the tables' sizes, one copy
+    unsigned char *h = nullptr;
+    rc = ex.bulk_buf((size_t)nt * 4, &h);
+    if (rc) return rc;
+    TSG_HIP(hipMemcpyAsync(h, d_n.p, (size_t)nt * 4, hipMemcpyDeviceToHost, s));
     TSG_HIP(hipStreamSynchronize(s));
-    const int n = ex.pinned[0];
-    int P = 1;
-    while (P < n) P <<= 1;
-    if (n > 0) {
+    std::vector<int> n(nt);
+    std::memcpy(n.data(), h, (size_t)nt * 4);
+    const int stride = 5 + kMaxAmax;
+    std::vector<size_t> out_off(nt);
+    size_t out_total = 0;
+    for (int i = 0; i < nt; ++i) {
+        out_off[i] = out_total;
+        out_total += (size_t)n[i] * stride;
+    }
+    if (!out_total) return TS_OK;
+    DBuf out(ex, out_total * 4);
+    if (!out.p) return TS_E_NOMEM;
+    for (int i = 0; i < nt; ++i) {
+        if (n[i] <= 0) continue;
+        int *ix = idx.as<int>() + idx_off[i];
+        int P = 1;
+        while (P < n[i]) P <<= 1;
         // pad to a power of two with -1 (sorts last)
-        if (P > n) {
-            rc = launch_fill(s, idx_all + n, -1, P - n);
+        if (P > n[i]) {
+            rc = launch_fill(s, ix + n[i], -1, P - n[i]);
             if (rc) return rc;
         }
         for (int k = 2; k <= P; k <<= 1)
             for (int j = k >> 1; j > 0; j >>= 1)
-                hipLaunchKernelGGL(k_bitonic, dim3((P + blk - 1) / blk), dim3(blk), 0, s, t, idx_all, P, k, j);
+                hipLaunchKernelGGL(k_bitonic, dim3((P + blk - 1) / blk), dim3(blk), 0, s, *t[i], ix, P, k, j);
+        hipLaunchKernelGGL(k_gather, dim3((n[i] + blk - 1) / blk), dim3(blk), 0, s, *t[i], ix, n[i],
+                           out.as<int>() + out_off[i], stride);
         TSG_HIP(hipGetLastError());
-        const int stride = 5 + kMaxAmax;
-        int *out = (int *)ex.dalloc((size_t)n * stride * 4);
-        if (!out) return TS_E_NOMEM;
-        hipLaunchKernelGGL(k_gather, dim3((n + blk - 1) / blk), dim3(blk), 0, s, t, idx_all, n, out, stride);
-        TSG_HIP(hipGetLastError());
-        std::vector<int32_t> raw((size_t)n * stride);
-        TSG_HIP(hipMemcpyAsync(raw.data(), out, raw.size() * 4, hipMemcpyDeviceToHost, s));
-        TSG_HIP(hipStreamSynchronize(s));
-        ex.dfree(out);
-        rec_host.resize((size_t)n * 5);
-        for (int i = 0; i < n; ++i) {
-            const int32_t *r = raw.data() + (size_t)i * stride;
-            for (int q = 0; q < 5; ++q) rec_host[(size_t)i * 5 + q] = r[q];
-            for (int q = 0; q < r[0]; ++q) bits_host.push_back(r[5 + q]);
+    }
+    // every table's sorted records, one copy
+    rc = ex.bulk_buf(out_total * 4, &h);
+    if (rc) return rc;
+    TSG_HIP(hipMemcpyAsync(h, out.p, out_total * 4, hipMemcpyDeviceToHost, s));
+    TSG_HIP(hipStreamSynchronize(s));
+    const int32_t *raw = (const int32_t *)h;
+    for (int i = 0; i < nt; ++i) {
+        std::vector<int32_t> &recs = *rec_host[i];
+        std::vector<int32_t> &bits = *bits_host[i];
+        recs.resize((size_t)n[i] * 5);
+        for (int q0 = 0; q0 < n[i]; ++q0) {
+            const int32_t *r = raw + out_off[i] + (size_t)q0 * stride;
+            for (int q = 0; q < 5; ++q) recs[(size_t)q0 * 5 + q] = r[q];
+            for (int q = 0; q < r[0]; ++q) bits.push_back(r[5 + q]);
         }
     }
-    ex.dfree(idx_all);
-    ex.dfree(d_n);
-    TSG_HIP(hipStreamSynchronize(s));
     return TS_OK;
+}
+
+int collect_table(ts_exec &ex, const DevTable &t, std::vector<int32_t> &rec_host,
+                  std::vector<int32_t> &bits_host) {
+    const DevTable *tp = &t;
+    std::vector<int32_t> *rp = &rec_host, *bp = &bits_host;
+    return collect_tables(ex, 1, &tp, &rp, &bp);
 }
 
 }  // namespace tsg
