@@ -121,13 +121,15 @@ __device__ __forceinline__ T uni(T v) {
 }
 
 // Check rules.  On entry val[j] is APP_{t-1} of the check's j-th neighbour and
-// c2v[j] the old message on that edge; on return c2v[j] is the new message and
-// val[j] its change, new - old.
+// c2v[j] the old message on that edge; on return c2v[j] is the new message.
+// Each new message is handed on as soon as it is formed, emit(j, new, new -
+// old), so that nothing of the edge stays live to the end of the check.
 struct OmsRule {
     static constexpr int kDummy = 127;   // padded edges read as a saturated positive message
-    template <int DC>
-    __device__ static __forceinline__ void update(int (&val)[DC], int (&c2v)[DC],
-                                                  const int (&nb)[DC], int pad_id, int offset) {
+    template <int DC, class Emit>
+    __device__ static __forceinline__ void update(const int (&val)[DC], int (&c2v)[DC],
+                                                  const int (&nb)[DC], int pad_id, int offset,
+                                                  Emit &&emit) {
         int mn1 = 127, mn2 = 127, idx = 0, sgn = 0;
         int v2[DC];
 #pragma unroll
@@ -151,8 +153,9 @@ struct OmsRule {
             int mag = (j == idx ? mn2 : mn1) - offset;
             mag = mag < 0 ? 0 : mag;
             const int m = (sgn ^ (v2[j] < 0)) ? -mag : mag;
-            val[j] = m - c2v[j];
+            const int d = m - c2v[j];
             c2v[j] = m;
+            emit(j, m, d);
         }
     }
 };
@@ -163,15 +166,15 @@ struct SpaRule {
     // check's sums (below the 2^-20 step of the results) and no sign, without
     // a per-edge test.  Real APP values stay below 2^30 + 2^27 in magnitude.
     static constexpr int kDummy = 1 << 30;
-    template <int DC>
-    __device__ static __forceinline__ void update(int (&val)[DC], int (&c2v)[DC],
-                                                  const int (&nb)[DC], int pad, int off) {
-        update_impl<DC, true>(val, c2v);
+    template <int DC, class Emit>
+    __device__ static __forceinline__ void update(const int (&val)[DC], int (&c2v)[DC],
+                                                  const int (&nb)[DC], int pad, int off, Emit &&emit) {
+        update_impl<DC, true>(val, c2v, emit);
     }
     // The per-edge temporaries are the phi terms (which become the exclusive
     // sums in place) and the prefix sums; the v2c signs are bits of one word.
-    template <int DC, bool kShortcuts>
-    __device__ static __forceinline__ void update_impl(int (&val)[DC], int (&c2v)[DC]) {
+    template <int DC, bool kShortcuts, class Emit>
+    __device__ static __forceinline__ void update_impl(const int (&val)[DC], int (&c2v)[DC], Emit &&emit) {
         float ph[DC];
         unsigned neg = 0;   // bit j: the v2c message of edge j is negative
         // Wavefront-uniform shortcuts (impulse frames, kShortcuts): where every
@@ -233,8 +236,9 @@ struct SpaRule {
         auto put = [&](int j, float f) {
             const int sb = (int)((par ^ (neg >> j)) << 31);
             const int m = __float2int_rn(__int_as_float(__float_as_int(f) ^ sb));
-            val[j] = m - c2v[j];
+            const int d = m - c2v[j];
             c2v[j] = m;
+            emit(j, m, d);
         };
         if (kShortcuts && __all(plain)) {
 #pragma unroll
@@ -249,10 +253,10 @@ struct SpaRule {
 // shortcuts (their channel values leave few checks in one regime, and the
 // extra paths cost the IS kernels more than they save).
 struct SpaIsRule : SpaRule {
-    template <int DC>
-    __device__ static __forceinline__ void update(int (&val)[DC], int (&c2v)[DC],
-                                                  const int (&nb)[DC], int pad, int off) {
-        update_impl<DC, false>(val, c2v);
+    template <int DC, class Emit>
+    __device__ static __forceinline__ void update(const int (&val)[DC], int (&c2v)[DC],
+                                                  const int (&nb)[DC], int pad, int off, Emit &&emit) {
+        update_impl<DC, false>(val, c2v, emit);
     }
 };
 
@@ -389,19 +393,18 @@ __device__ __forceinline__ DecRes run_decode(const Frame &F, const int (&nb)[CPT
             for (int j = 0; j < DC; ++j) par ^= (val[j] < 0);
             unsat += par;
             if (t <= T) {
-                Rule::template update<DC>(val, c2v[c], nb[c], n4, offset);   // val: the changes
                 // Padded edges carry nothing (their dummy slot keeps its
                 // value).  The per-edge branch also keeps each atomic next
                 // to its message in the schedule: unconditional atomics were
                 // issued as one block after the check's arithmetic, which
                 // serialised LDS and VALU work (20% slower at 24 edges).
-#pragma unroll
-                for (int j = 0; j < DC; ++j) {
-                    if (nb[c][j] != n4) {
-                        atomicAdd((int *)(Nb + nb[c][j]), c2v[c][j]);
-                        chg |= (unsigned)val[j];
+                const int *nbc = nb[c];
+                Rule::template update<DC>(val, c2v[c], nb[c], n4, offset, [&](int j, int m, int d) {
+                    if (nbc[j] != n4) {
+                        atomicAdd((int *)(Nb + nbc[j]), m);
+                        chg |= (unsigned)d;
                     }
-                }
+                });
             }
         }
         if (t >= 2) {
@@ -1397,12 +1400,16 @@ __device__ __forceinline__ int check_g(const GFrame &F, int q, int p, int t, int
         // the sum-product rule without the wavefront-uniform shortcuts: they
         // save arithmetic that this memory-bound pass does not wait on, and
         // their registers spill here
-        if constexpr (std::is_same<Rule, SpaRule>::value) SpaRule::update_impl<DC, false>(val, c2v);
-        else Rule::template update<DC>(val, c2v, nb, F.n, offset);   // val: the changes
+        // the changes are kept and the messages stored after the rule (stores
+        // and atomics inside it cost this pass registers)
+        int dv[DC];
+        auto keep = [&](int j, int, int d) { dv[j] = d; };
+        if constexpr (std::is_same<Rule, SpaRule>::value) SpaRule::update_impl<DC, false>(val, c2v, keep);
+        else Rule::template update<DC>(val, c2v, nb, F.n, offset, keep);
 #pragma unroll
         for (int j = 0; j < DC; ++j) {
             msg[base + (size_t)j * stride] = (M)c2v[j];
-            if (nb[j] != F.n) chg |= (unsigned)val[j];
+            if (nb[j] != F.n) chg |= (unsigned)dv[j];
         }
         if constexpr (kAcc) {
             // APP_t - lambda accumulated in LDS (exact integer sums, any order)
