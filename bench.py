@@ -51,7 +51,7 @@ VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 VALU_SLOTS_PER_EU = {"oms": 15.0, "spa": 2 * (3 * 4 + 5) + 6.0}
 # HBM traffic per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled x2 and x1 by a 1 GiB copy); None once the kernel changes.
-MEASURED_TRAFFIC_BYTES = {"spa": (38.86e6 + 821.69e6)}
+MEASURED_TRAFFIC_BYTES = {"spa": (30.24e6 + 118.07e6)}
 # Same for the streamed-layout launch of the QC-2640 triples search (qc2640
 # section); None until measured on the current kernel.
 MEASURED_STREAMED_TRAFFIC_BYTES = 239161.94e6 + 708311.64e6
