@@ -165,3 +165,43 @@ def test_batch_eps_shifts_equal_alone():
                 assert a[f] == got[f], f
             ctx.release(jid)
         _say(f"eps* shifts {[a['shift_used'] for a in alone]}: batch equals alone")
+
+
+def test_batch_against_oracle(oracle_mod):
+    """Jobs on three small codes in one batch, each compared with the oracle
+    directly: OMS searches bit-exact (k*, iteration counts, tmin, candidate
+    counts, the ordered TS list), IS estimates within 2% or inside the
+    oracle's 95% interval and failure counts within 0.5% of the frames."""
+    by_name = {c.name: c for c in workloads.batch_codes()}
+    codes = {"tiny": workloads.tiny_code(), "b4x8": by_name["batch35-4x8-z18"],
+             "b3x6": by_name["batch54-3x6-z64"]}
+    rng = np.random.default_rng(79)
+    jobs, refs = [], []
+    for name, c in codes.items():
+        oc = oracle_mod.OCode(c)
+        p2 = oracle_mod.patterns(oc, 2)
+        sel = np.sort(rng.choice(len(p2), min(len(p2), 400), replace=False))
+        pats = np.ascontiguousarray(p2[sel])
+        jobs.append(("search", name, pats, dict(a_max=12)))
+        refs.append(oracle_mod.search(oc, pats, a_max=12))
+        rp, col = oc.csr()
+        bits = sorted(set(int(x) for x in col[rp[0]:rp[1]]))[:4]
+        kw = dict(ebn0_db=3.0, shift=1.0, n_frames=3000, seed=5, stream=len(jobs))
+        jobs.append(("is", name, bits, kw))
+        refs.append(oracle_mod.is_estimate(oc, bits, kw["ebn0_db"], kw["shift"], kw["n_frames"],
+                                           seed=kw["seed"], stream=kw["stream"]))
+    _say(f"{len(jobs)} jobs on {len(codes)} codes in one batch against the oracle")
+    batched, _ = _batched(codes, jobs)
+    for (kind, name, _, kw), ref, got in zip(jobs, refs, batched):
+        if kind == "search":
+            for k in KEYS:
+                assert np.array_equal(got[0][k], np.asarray(ref[k])), (name, k)
+            assert got[1] == _ts(ref["ts"]), name
+        else:
+            K = kw["n_frames"]
+            _say(f"  IS {name}: p batch {got['p_hat']:.4e} oracle {ref['p_hat']:.4e} "
+                 f"ci [{ref['ci_lo']:.3e},{ref['ci_hi']:.3e}] fails {got['n_fail']} / {ref['n_fail']}")
+            inside = ref["ci_lo"] <= got["p_hat"] <= ref["ci_hi"]
+            close = abs(got["p_hat"] - ref["p_hat"]) <= 0.02 * abs(ref["p_hat"]) + 1e-300
+            assert inside or close, name
+            assert abs(got["n_fail"] - ref["n_fail"]) <= 0.005 * K, name

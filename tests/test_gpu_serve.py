@@ -100,6 +100,51 @@ def test_mix_equals_alone(jobs):
         assert overlap
 
 
+def test_served_against_oracle(jobs, oracle_mod):
+    """The tiny code's jobs of the mix, submitted together, against the oracle
+    directly: the OMS search bit-exact (outputs and ordered TS list), the IS
+    estimates within 2% or inside the oracle's 95% interval, failure counts
+    within 0.5% of the frames."""
+    import paper_2208_05795_amd as tsg
+    codes, job_list = jobs
+    tiny = [(k, n, kw) for k, n, kw in job_list if n == "tiny"]
+    oc = oracle_mod.OCode(codes["tiny"])
+    refs = []
+    for kind, _, kw in tiny:
+        if kind == "search":
+            refs.append(oracle_mod.search(oc, kw["patterns"], a_max=kw["a_max"]))
+        else:
+            refs.append(oracle_mod.is_estimate(oc, kw["ts_bits"], kw["ebn0_db"], kw["shift"],
+                                               kw["n_frames"], seed=kw["seed"], stream=kw["stream"]))
+    with tsg.Context(0, torch_stream=False, torch_alloc=False) as ctx:
+        c = ctx.load_code(codes["tiny"])
+        ctx.serve_start(4)
+        ids = []
+        for kind, _, kw in tiny:
+            kw2 = dict(kw)
+            if kind == "search":
+                ids.append(ctx.submit_search(c, kw2.pop("patterns"), **kw2))
+            else:
+                ids.append(ctx.submit_is(c, **kw2))
+        for (kind, _, kw), jid, ref in zip(tiny, ids, refs):
+            info = ctx.poll(jid, wait=True)
+            assert info["state"] == 2 and info["status"] == 0, info
+            if kind == "search":
+                out = ctx.job_outputs(jid)
+                for k in KEYS:
+                    assert np.array_equal(out[k], np.asarray(ref[k])), k
+                assert _ts(out["ts"]) == _ts(ref["ts"])
+            else:
+                got = info["is"]
+                _say(f"served IS {kw['ebn0_db']} dB: p {got['p_hat']:.4e} oracle {ref['p_hat']:.4e} "
+                     f"ci [{ref['ci_lo']:.3e},{ref['ci_hi']:.3e}]")
+                inside = ref["ci_lo"] <= got["p_hat"] <= ref["ci_hi"]
+                close = abs(got["p_hat"] - ref["p_hat"]) <= 0.02 * abs(ref["p_hat"]) + 1e-300
+                assert inside or close
+                assert abs(got["n_fail"] - ref["n_fail"]) <= 0.005 * kw["n_frames"]
+            ctx.release(jid)
+
+
 def test_budget_admission_and_cancel(jobs):
     import paper_2208_05795_amd as tsg
     codes, job_list = jobs
