@@ -463,6 +463,33 @@ __global__ void k_bitonic(DevTable t, int *idx, int P, int k, int j) {
     }
 }
 
+// The whole bitonic network of a table of at most kSortLds entries in one
+// workgroup: the slot indices in LDS, a barrier between stages (one launch
+// where the global form takes one per stage).  The order is a total order on
+// distinct sets, so the result equals the global form's.
+constexpr int kSortLds = 8192;
+constexpr int kSortThreads = 1024;
+__global__ __launch_bounds__(kSortThreads) void k_bitonic_lds(DevTable t, int *idx, int n, int P) {
+    __shared__ int sx[kSortLds];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < P; i += kSortThreads) sx[i] = i < n ? idx[i] : -1;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < P; i += kSortThreads) {
+                const int l = i ^ j;
+                if (l <= i) continue;
+                const int x = sx[i], y = sx[l];
+                if (after(t, x, y) == ((i & k) == 0)) {
+                    sx[i] = y;
+                    sx[l] = x;
+                }
+            }
+            __syncthreads();
+        }
+    for (int i = tid; i < n; i += kSortThreads) idx[i] = sx[i];
+}
+
 __global__ void k_gather(DevTable t, const int *idx, int n, int *out, int stride) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -618,14 +645,19 @@ int collect_tables(ts_exec &ex, int nt, const DevTable *const *t, std::vector<in
         int *ix = idx.as<int>() + idx_off[i];
         int P = 1;
         while (P < n[i]) P <<= 1;
-        // pad to a power of two with -1 (sorts last)
-        if (P > n[i]) {
-            rc = launch_fill(s, ix + n[i], -1, P - n[i]);
-            if (rc) return rc;
+        if (P <= kSortLds) {   // one launch, padded in LDS
+            hipLaunchKernelGGL(k_bitonic_lds, dim3(1), dim3(kSortThreads), 0, s, *t[i], ix, n[i], P);
+        } else {
+            // pad to a power of two with -1 (sorts last), one launch per stage
+            if (P > n[i]) {
+                rc = launch_fill(s, ix + n[i], -1, P - n[i]);
+                if (rc) return rc;
+            }
+            for (int k = 2; k <= P; k <<= 1)
+                for (int j = k >> 1; j > 0; j >>= 1)
+                    hipLaunchKernelGGL(k_bitonic, dim3((P + blk - 1) / blk), dim3(blk), 0, s, *t[i], ix, P,
+                                       k, j);
         }
-        for (int k = 2; k <= P; k <<= 1)
-            for (int j = k >> 1; j > 0; j >>= 1)
-                hipLaunchKernelGGL(k_bitonic, dim3((P + blk - 1) / blk), dim3(blk), 0, s, *t[i], ix, P, k, j);
         hipLaunchKernelGGL(k_gather, dim3((n[i] + blk - 1) / blk), dim3(blk), 0, s, *t[i], ix, n[i],
                            out.as<int>() + out_off[i], stride);
         TSG_HIP(hipGetLastError());

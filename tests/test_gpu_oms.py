@@ -52,6 +52,23 @@ def test_code_load_matches_oracle(ctx, oracle_mod, name):
     g.free()
 
 
+def test_tiny_triples_large_table(ctx, oracle_mod, tiny):
+    """Singles, pairs and tree-path triples of the tiny code with a_max 12:
+    about 14,000 TS, so the ordered read-out takes the multi-launch sort of
+    large tables (tables of up to 8192 sets sort in one launch, as every
+    other test here does)."""
+    code, oc = tiny
+    pats = oracle_mod.pattern_list(oc, [1, 2, 3])
+    ref = oracle_mod.search(oc, pats, a_max=12)
+    _say(f"tiny triples, {len(pats)} patterns, {len(ref['ts'])} TS")
+    assert len(ref["ts"]) > 8192
+    g = ctx.load_code(code)
+    got = g.impulse_search(pats, a_max=12)
+    _same(got, ref)
+    assert _ts(g.collect()) == _ts(ref["ts"])
+    g.free()
+
+
 def test_patterns_match_oracle(ctx, oracle_mod):
     for code in (workloads.tiny_code(), workloads.peg1008_code()):
         g = ctx.load_code(code)
