@@ -802,22 +802,19 @@ int run_is(ts_exec &ex, ts_code *code, const int32_t *ts_bits, int32_t a, const 
     const int grid = (int)std::min<int64_t>(plan.grid, K), block = plan.block;
     rc = launch(plan, K, nullptr);
     if (rc) return rc;
-    const IsDev dres = make_is_dev(L, plan);
-    rc = launch_is_reduce(s, dres, L.wf, L.fail, K, 0, 0.0, d_red.as<double>(), d_part.as<double>());
+    const RedJob rj = make_red_job(make_is_dev(L, plan), L.wf, L.fail, K, d_red.as<double>(),
+                                   d_part.as<double>());
+    rc = launch_is_reduce(s, rj, 0);
+    if (rc) return rc;
+    rc = launch_is_reduce(s, rj, 1);
     if (rc) return rc;
     double red[4];
-    TSG_HIP(hipMemcpyAsync(ex.pinned, d_red.p, 32, hipMemcpyDeviceToHost, s));
-    TSG_HIP(hipStreamSynchronize(s));
-    std::memcpy(red, ex.pinned, 32);
-    const double p = red[0] / (double)K;
-    rc = launch_is_reduce(s, dres, L.wf, L.fail, K, 1, p, d_red.as<double>(), d_part.as<double>());
-    if (rc) return rc;
     TSG_HIP(hipMemcpyAsync(ex.pinned, d_red.p, 32, hipMemcpyDeviceToHost, s));
     TSG_HIP(hipMemcpyAsync(ex.pinned + 8, d_misc.as<int>() + 4, 16, hipMemcpyDeviceToHost, s));
     if (fail_out) TSG_HIP(hipMemcpyAsync(fail_out, d_fail.p, (size_t)K, hipMemcpyDeviceToHost, s));
     TSG_HIP(hipEventRecord(ex.ev[2], s));
     TSG_HIP(hipStreamSynchronize(s));
-    red[3] = ((double *)ex.pinned)[3];
+    std::memcpy(red, ex.pinned, 32);
     unsigned long long cnt[2];
     std::memcpy(cnt, ex.pinned + 8, 16);
     float ms = 0.0f, tot = 0.0f;

@@ -199,19 +199,25 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
     for (IItem &it : I) { it.red = o; o += 8 * 8; }
     const size_t red_bytes = o - red0;
     o = al(o);
-    for (SItem &it : S) {
-        it.pat = o; o = al(o + (size_t)it.P * it.b->width * 4);
-        it.recs = o; o = al(o + (size_t)it.rec_cap * kRecStride * 4);
+    // the inputs (patterns, the sets' bits, job and reduction descriptors)
+    // form one block, uploaded with one copy
+    const size_t up0 = o;
+    for (SItem &it : S) { it.pat = o; o = al(o + (size_t)it.P * it.b->width * 4); }
+    for (IItem &it : I) { it.ts = o; o = al(o + kMaxWidth * 4); }
+    for (Group &g : G) {
+        g.jobs = o;
+        o = al(o + g.members.size() * (g.search ? sizeof(SearchJob) : sizeof(IsJob)));
     }
+    const size_t redj = o;
+    o = al(o + I.size() * sizeof(RedJob));
+    const size_t up_bytes = o - up0;
+    for (SItem &it : S) { it.recs = o; o = al(o + (size_t)it.rec_cap * kRecStride * 4); }
     for (IItem &it : I) {
-        it.ts = o; o = al(o + kMaxWidth * 4);
         it.fail = o; o = al(o + (size_t)it.K);
         it.wf = o; o = al(o + (size_t)it.K * 8);
         it.part = o; o = al(o + (size_t)is_reduce_parts(it.K) * 3 * 8);
     }
     for (Group &g : G) {
-        g.jobs = o;
-        o = al(o + g.members.size() * (g.search ? sizeof(SearchJob) : sizeof(IsJob)));
         g.scratch = o;
         o = al(o + g.scratch_bytes);
     }
@@ -233,14 +239,13 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
     } arena_guard{ex, arena};
     rc = launch_fill(s, (int *)arena, 0, (int64_t)(zero / 4));
     if (rc) return rc;
-    // ---- inputs and job descriptors ----------------------------------------
-    // Host sources of the uploads stay alive until the synchronisation below:
-    // an asynchronous copy from pageable memory may read them after it returns.
-    std::vector<std::vector<int32_t>> host_ts(I.size());
-    std::vector<std::vector<unsigned char>> host_jobs(G.size());
+    // ---- inputs and job descriptors: one image in pinned memory, one copy ---
+    unsigned char *hu = nullptr;
+    rc = ex.bulk_buf(up_bytes, &hu);
+    if (rc) return rc;
+    std::memset(hu, 0, up_bytes);
     for (SItem &it : S) {
-        TSG_HIP(hipMemcpyAsync(arena + it.pat, it.b->patterns, (size_t)it.P * it.b->width * 4,
-                               hipMemcpyHostToDevice, s));
+        std::memcpy(hu + (it.pat - up0), it.b->patterns, (size_t)it.P * it.b->width * 4);
         SearchLaunch &a = it.a;
         fill_search_launch(it.b->code, &it.b->so, it.t0, it.b->width, &a);
         int32_t *out = (int32_t *)(arena + it.out);
@@ -265,12 +270,12 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
         a.save_lds = g.plan.save_lds;
         a.hist_off = (long long)it.plan.hist_off;
     }
+    int red_parts = 0;
     for (size_t ii = 0; ii < I.size(); ++ii) {
         IItem &it = I[ii];
-        std::vector<int32_t> &t = host_ts[ii];
-        t.assign(it.b->ts_bits, it.b->ts_bits + it.b->a);
-        std::sort(t.begin(), t.end());
-        TSG_HIP(hipMemcpyAsync(arena + it.ts, t.data(), t.size() * 4, hipMemcpyHostToDevice, s));
+        int32_t *t = (int32_t *)(hu + (it.ts - up0));
+        std::copy(it.b->ts_bits, it.b->ts_bits + it.b->a, t);
+        std::sort(t, t + it.b->a);
         IsLaunch &L = it.L;
         L.code = &it.b->code->dev;
         L.max_iter = it.b->io.max_iter;
@@ -290,10 +295,16 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
         L.counters = (unsigned long long *)(arena + it.misc + 16);
         const Group &g = G[it.group];
         L.gscr = g.scratch_bytes ? arena + g.scratch : nullptr;
+        RedJob rj = make_red_job(make_is_dev(L, it.plan), L.wf, L.fail, it.K, (double *)(arena + it.red),
+                                 (double *)(arena + it.part));
+        if (rj.np < 1) { set_error("empty IS reduction"); return TS_E_INVAL; }
+        rj.part0 = red_parts;
+        red_parts += rj.np;
+        std::memcpy(hu + (redj - up0) + ii * sizeof(RedJob), &rj, sizeof(RedJob));
     }
     for (size_t gi = 0; gi < G.size(); ++gi) {
         Group &g = G[gi];
-        std::vector<unsigned char> &hj = host_jobs[gi];
+        unsigned char *hj = hu + (g.jobs - up0);
         long long item0 = 0;
         for (int m : g.members) {
             if (g.search) {
@@ -302,7 +313,8 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
                 j.cd = S[m].b->code->dev;
                 j.item0 = item0;
                 item0 += S[m].P;
-                hj.insert(hj.end(), (unsigned char *)&j, (unsigned char *)&j + sizeof(j));
+                std::memcpy(hj, &j, sizeof(j));
+                hj += sizeof(j);
             } else {
                 IsJob j{};
                 j.a = make_is_dev(I[m].L, I[m].plan);
@@ -310,11 +322,12 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
                 j.cd = I[m].b->code->dev;
                 j.item0 = item0;
                 item0 += I[m].K;
-                hj.insert(hj.end(), (unsigned char *)&j, (unsigned char *)&j + sizeof(j));
+                std::memcpy(hj, &j, sizeof(j));
+                hj += sizeof(j);
             }
         }
-        TSG_HIP(hipMemcpyAsync(arena + g.jobs, hj.data(), hj.size(), hipMemcpyHostToDevice, s));
     }
+    TSG_HIP(hipMemcpyAsync(arena + up0, hu, up_bytes, hipMemcpyHostToDevice, s));
     TSG_HIP(hipStreamSynchronize(s));
     // ---- launches, spread over the side streams: the search groups first
     // (largest first), then the IS groups (largest first).  The main stream
@@ -478,39 +491,25 @@ int run_batch(ts_exec &ex, std::vector<BatchJob> &jobs) {
         TSG_HIP(hipEventElapsedTime(&dec_ms, ex.ev[0], ex.ev[1]));
         ex.stats.decode_ms += dec_ms;
     }
-    // ---- per IS job: fixed-order reductions ----------------------------------
-    // the reduction results of all IS jobs (8 doubles apart): one copy
-    auto read_red = [&](std::vector<double> &dst) -> int {
-        dst.assign(I.size() * 4, 0.0);
-        if (!red_bytes) return TS_OK;
+    // ---- IS reductions: every job's two passes in two launches each ---------
+    // (the reduction results of all IS jobs, 8 doubles apart: one copy)
+    std::vector<double> red(I.size() * 4, 0.0);
+    if (!I.empty()) {
+        const RedJob *dj = (const RedJob *)(arena + redj);
+        rc = launch_is_reduce_jobs(s, dj, (int)I.size(), red_parts, 0);
+        if (rc) return rc;
+        rc = launch_is_reduce_jobs(s, dj, (int)I.size(), red_parts, 1);
+        if (rc) return rc;
         unsigned char *h = nullptr;
-        int r = ex.bulk_buf(red_bytes, &h);
-        if (r) return r;
+        rc = ex.bulk_buf(red_bytes, &h);
+        if (rc) return rc;
         TSG_HIP(hipMemcpyAsync(h, arena + red0, red_bytes, hipMemcpyDeviceToHost, s));
         TSG_HIP(hipStreamSynchronize(s));
-        for (size_t i = 0; i < I.size(); ++i) std::memcpy(&dst[4 * i], h + 64 * i, 32);
-        return TS_OK;
-    };
-    std::vector<double> red;
-    for (IItem &it : I) {
-        rc = launch_is_reduce(s, make_is_dev(it.L, it.plan), it.L.wf, it.L.fail, it.K, 0, 0.0,
-                              (double *)(arena + it.red), (double *)(arena + it.part));
-        if (rc) return rc;
+        for (size_t i = 0; i < I.size(); ++i) std::memcpy(&red[4 * i], h + 64 * i, 32);
     }
-    rc = read_red(red);
-    if (rc) return rc;
-    for (size_t i = 0; i < I.size(); ++i) {
-        rc = launch_is_reduce(s, make_is_dev(I[i].L, I[i].plan), I[i].L.wf, I[i].L.fail, I[i].K, 1,
-                              red[4 * i] / (double)I[i].K, (double *)(arena + I[i].red),
-                              (double *)(arena + I[i].part));
-        if (rc) return rc;
-    }
-    std::vector<double> red2;
-    rc = read_red(red2);
-    if (rc) return rc;
     for (size_t i = 0; i < I.size(); ++i) {
         IItem &it = I[i];
-        double r[4] = {red[4 * i], red[4 * i + 1], red[4 * i + 2], red2[4 * i + 3]};
+        double r[4] = {red[4 * i], red[4 * i + 1], red[4 * i + 2], red[4 * i + 3]};
         is_fill_result(r, it.K, it.shift, it.b->is);
         const int *misc = zh.data() + it.misc / 4;
         unsigned long long cnt[2];

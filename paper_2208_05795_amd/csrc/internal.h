@@ -429,12 +429,34 @@ int launch_search_jobs(hipStream_t s, const SearchPlan &plan, const SearchJob *d
 int launch_is_jobs(hipStream_t s, const SearchPlan &plan, const IsJob *d_jobs, int n_jobs,
                    int *queue, long long n_items);
 int occupancy_grid(ts_ctx *ctx, const SearchPlan &plan, int decoder, bool search, int *grid);
-// Reduction of the weights of n IS frames of job d (wf: sums of the TS-bit
-// normals).  mode 0: out[0..2] = sum w, sum w^2, failures; mode 1: out[3] =
-// sum (w - mean)^2.  part: device scratch of 3 * is_reduce_parts(n) doubles.
+// Importance weights of a mixture of m shifts s0 + k ds (m = 0: one shift).
+struct MixW {
+    int m, a;
+    long long n;
+    double s0, ds, sigma;
+};
+// Reduction of the weights of the n IS frames of one job (wf: sums of the
+// TS-bit normals, fail: per-frame flags).  mode 0: out[0..2] = sum w, sum w^2,
+// counted failures; mode 1: out[3] = sum (w - mean)^2, mean = out[0] / n read
+// on the device (after mode 0 on the same stream).  part: device scratch of
+// 3 * is_reduce_parts(n) doubles.  In a launch over many jobs, job i takes
+// the blocks from part0 on.
+struct RedJob {
+    const double *wf;
+    const unsigned char *fail;
+    long long n;
+    double wconst, coef;
+    MixW mix;
+    int cmask, part0, np;
+    double *part, *out;
+};
 int is_reduce_parts(int64_t n);
-int launch_is_reduce(hipStream_t s, const IsDev &d, const double *wf, const unsigned char *fail,
-                     int64_t n, int mode, double mean, double *out, double *part);
+RedJob make_red_job(const IsDev &d, const double *wf, const unsigned char *fail, int64_t n, double *out,
+                    double *part);
+int launch_is_reduce(hipStream_t s, const RedJob &j, int mode);
+// d_jobs: device array of nj jobs with part0 ascending from 0, total_parts
+// blocks in all.
+int launch_is_reduce_jobs(hipStream_t s, const RedJob *d_jobs, int nj, int total_parts, int mode);
 
 // api.cpp: the work of one search / IS call on an executor
 double sigma2_of(double ebn0_db, double rate);

@@ -157,21 +157,18 @@ extern "C" int ts_is_estimate_noalloc(ts_ctx *ctx, ts_code *code, const int32_t 
     ex.staged(slot);
     if (rc) return rc;
     TSG_HIP(hipEventRecord(ex.ev[1], s));
-    const IsDev dres = make_is_dev(L, plan);
-    rc = launch_is_reduce(s, dres, d_wf, d_fail, K, 0, 0.0, d_red, d_part);
+    const RedJob rj = make_red_job(make_is_dev(L, plan), d_wf, d_fail, K, d_red, d_part);
+    rc = launch_is_reduce(s, rj, 0);
     if (rc) return rc;
-    TSG_HIP(hipMemcpyAsync(ex.pinned, d_red, 32, hipMemcpyDeviceToHost, s));
-    TSG_HIP(hipStreamSynchronize(s));
+    rc = launch_is_reduce(s, rj, 1);
+    if (rc) return rc;
     double red[4];
-    std::memcpy(red, ex.pinned, 32);
-    rc = launch_is_reduce(s, dres, d_wf, d_fail, K, 1, red[0] / (double)K, d_red, d_part);
-    if (rc) return rc;
     TSG_HIP(hipMemcpyAsync(ex.pinned, d_red, 32, hipMemcpyDeviceToHost, s));
     TSG_HIP(hipMemcpyAsync(ex.pinned + 8, misc + 4, 16, hipMemcpyDeviceToHost, s));
     if (fail_out) TSG_HIP(hipMemcpyAsync(fail_out, d_fail, (size_t)K, hipMemcpyDeviceToHost, s));
     TSG_HIP(hipEventRecord(ex.ev[2], s));
     TSG_HIP(hipStreamSynchronize(s));
-    red[3] = ((double *)ex.pinned)[3];
+    std::memcpy(red, ex.pinned, 32);
     unsigned long long cnt[2];
     std::memcpy(cnt, ex.pinned + 8, 16);
     float ms = 0.0f, tot = 0.0f;

@@ -1242,11 +1242,6 @@ __device__ __forceinline__ void red_tree(double *s0, double *s1, double *s2, int
 // the sum of the frame's TS-bit displacements in units of sigma,
 // w = 1 / sum_k alpha_k exp((s_k / sigma) S - a s_k^2 / (2 sigma^2)), alpha_k the
 // share of frames in component k (the balance heuristic), by log-sum-exp.
-struct MixW {
-    int m, a;
-    long long n;
-    double s0, ds, sigma;
-};
 __device__ __forceinline__ double mix_term(const MixW &x, int k, double S) {
     const long long f0 = (k * x.n + x.m - 1) / x.m, f1 = ((k + 1) * x.n + x.m - 1) / x.m;
     const double sk = x.s0 + (double)k * x.ds;
@@ -1262,22 +1257,24 @@ __device__ double mix_weight(const MixW &x, long long f, double sum_n) {
     return exp(-(mx + log(t)));
 }
 
-// cmask selects the failures that count: 1 every failure, 2 those with every
-// TS bit in error.
-__global__ __launch_bounds__(kRedThreads) void k_is_reduce(const double *wf, const unsigned char *fail,
-                                                          long long n, int mode, double mean,
-                                                          double wconst, double coef, int cmask,
-                                                          MixW mix, double *part) {
+// Stage 1 of a job's reduction: block blk of its frames (kRedChunk frames,
+// a fixed split over the threads and a fixed tree, so the sums do not depend
+// on the launch).  cmask selects the failures that count: 1 every failure,
+// 2 those with every TS bit in error.  Mode 1 takes the mean weight from the
+// job's mode-0 result on the device.
+__device__ void reduce_frames(const RedJob &j, int mode, int blk) {
     __shared__ double s0[kRedThreads], s1[kRedThreads], s2[kRedThreads];
     const int t = threadIdx.x;
-    const long long c0 = (long long)blockIdx.x * kRedChunk;
+    const long long n = j.n;
+    const double mean = mode ? j.out[0] / (double)n : 0.0;
+    const long long c0 = (long long)blk * kRedChunk;
     const long long c1 = c0 + kRedChunk < n ? c0 + kRedChunk : n;
     const long long per = (kRedChunk + kRedThreads - 1) / kRedThreads;
     const long long lo = c0 + (long long)t * per, hi = lo + per < c1 ? lo + per : c1;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     for (long long i = lo; i < hi; ++i) {
-        const bool counted = (fail[i] & cmask) != 0;
-        const double w = !counted ? 0.0 : mix.m ? mix_weight(mix, i, wf[i]) : exp(wconst + coef * wf[i]);
+        const bool counted = (j.fail[i] & j.cmask) != 0;
+        const double w = !counted ? 0.0 : j.mix.m ? mix_weight(j.mix, i, j.wf[i]) : exp(j.wconst + j.coef * j.wf[i]);
         if (mode == 0) {
             a0 += w;
             a1 += w * w;
@@ -1291,23 +1288,24 @@ __global__ __launch_bounds__(kRedThreads) void k_is_reduce(const double *wf, con
     s2[t] = a2;
     red_tree(s0, s1, s2, t);
     if (t == 0) {
-        part[3 * blockIdx.x] = s0[0];
-        part[3 * blockIdx.x + 1] = s1[0];
-        part[3 * blockIdx.x + 2] = s2[0];
+        j.part[3 * blk] = s0[0];
+        j.part[3 * blk + 1] = s1[0];
+        j.part[3 * blk + 2] = s2[0];
     }
 }
 
-__global__ __launch_bounds__(kRedThreads) void k_is_reduce_final(const double *part, int n_parts, int mode,
-                                                                double *out) {
+// Stage 2: the job's partial sums in a fixed order; mode 0 writes out[0..2]
+// (sum w, sum w^2, counted failures), mode 1 out[3] (sum (w - mean)^2).
+__device__ void reduce_parts(const RedJob &j, int mode) {
     __shared__ double s0[kRedThreads], s1[kRedThreads], s2[kRedThreads];
     const int t = threadIdx.x;
-    const int per = (n_parts + kRedThreads - 1) / kRedThreads;
-    const int lo = t * per, hi = lo + per < n_parts ? lo + per : n_parts;
+    const int per = (j.np + kRedThreads - 1) / kRedThreads;
+    const int lo = t * per, hi = lo + per < j.np ? lo + per : j.np;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     for (int i = lo; i < hi; ++i) {
-        a0 += part[3 * i];
-        a1 += part[3 * i + 1];
-        a2 += part[3 * i + 2];
+        a0 += j.part[3 * i];
+        a1 += j.part[3 * i + 1];
+        a2 += j.part[3 * i + 2];
     }
     s0[t] = a0;
     s1[t] = a1;
@@ -1315,13 +1313,35 @@ __global__ __launch_bounds__(kRedThreads) void k_is_reduce_final(const double *p
     red_tree(s0, s1, s2, t);
     if (t == 0) {
         if (mode == 0) {
-            out[0] = s0[0];
-            out[1] = s1[0];
-            out[2] = s2[0];
+            j.out[0] = s0[0];
+            j.out[1] = s1[0];
+            j.out[2] = s2[0];
         } else {
-            out[3] = s0[0];
+            j.out[3] = s0[0];
         }
     }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_is_reduce(RedJob j, int mode) {
+    reduce_frames(j, mode, blockIdx.x);
+}
+__global__ __launch_bounds__(kRedThreads) void k_is_reduce_final(RedJob j, int mode) { reduce_parts(j, mode); }
+
+// Many jobs in one launch: block b belongs to the last job whose part0 <= b.
+__global__ __launch_bounds__(kRedThreads) void k_is_reduce_jobs(const RedJob *jobs, int nj, int mode) {
+    const int b = blockIdx.x;
+    int lo = 0, hi = nj - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].part0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const RedJob j = jobs[lo];
+    reduce_frames(j, mode, b - j.part0);
+}
+__global__ __launch_bounds__(kRedThreads) void k_is_reduce_final_jobs(const RedJob *jobs, int mode) {
+    const RedJob j = jobs[blockIdx.x];
+    reduce_parts(j, mode);
 }
 
 __global__ void k_fill(int *p, int value, long long count) {
@@ -2074,22 +2094,47 @@ IsDev make_is_dev(const IsLaunch &a, const SearchPlan &plan) {
 
 int is_reduce_parts(int64_t n) { return (int)((n + kRedChunk - 1) / kRedChunk); }
 
-int launch_is_reduce(hipStream_t stream, const IsDev &d, const double *wf, const unsigned char *fail,
-                     int64_t n, int mode, double mean, double *out, double *part) {
-    const int np = is_reduce_parts(n);
-    if (np < 1) {
+RedJob make_red_job(const IsDev &d, const double *wf, const unsigned char *fail, int64_t n, double *out,
+                    double *part) {
+    RedJob j{};
+    j.wf = wf;
+    j.fail = fail;
+    j.n = n;
+    j.wconst = d.wconst;
+    j.coef = d.shift / d.sigma;
+    j.mix = MixW{d.n_mix, d.a, (long long)n, d.mix_s0, d.mix_ds, d.sigma};
+    j.cmask = d.count_mode == TS_IS_COUNT_TS ? 2 : 1;
+    j.part0 = 0;
+    j.np = is_reduce_parts(n);
+    j.part = part;
+    j.out = out;
+    return j;
+}
+
+int launch_is_reduce(hipStream_t stream, const RedJob &j, int mode) {
+    if (j.np < 1) {
         set_error("empty reduction");
         return TS_E_INVAL;
     }
-    MixW mix{d.n_mix, d.a, (long long)n, d.mix_s0, d.mix_ds, d.sigma};
-    hipLaunchKernelGGL(k_is_reduce, dim3(np), dim3(kRedThreads), 0, stream, wf, fail, (long long)n, mode,
-                       mean, d.wconst, d.shift / d.sigma, d.count_mode == TS_IS_COUNT_TS ? 2 : 1, mix,
-                       part);
+    hipLaunchKernelGGL(k_is_reduce, dim3(j.np), dim3(kRedThreads), 0, stream, j, mode);
     TSG_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_is_reduce_final, dim3(1), dim3(kRedThreads), 0, stream, (const double *)part, np,
-                       mode, out);
+    hipLaunchKernelGGL(k_is_reduce_final, dim3(1), dim3(kRedThreads), 0, stream, j, mode);
     TSG_HIP(hipGetLastError());
     return TS_OK;
 }
+
+int launch_is_reduce_jobs(hipStream_t stream, const RedJob *d_jobs, int nj, int total_parts, int mode) {
+    if (nj < 1) return TS_OK;
+    if (total_parts < nj) {
+        set_error("empty reduction");
+        return TS_E_INVAL;
+    }
+    hipLaunchKernelGGL(k_is_reduce_jobs, dim3(total_parts), dim3(kRedThreads), 0, stream, d_jobs, nj, mode);
+    TSG_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_is_reduce_final_jobs, dim3(nj), dim3(kRedThreads), 0, stream, d_jobs, mode);
+    TSG_HIP(hipGetLastError());
+    return TS_OK;
+}
+
 
 }  // namespace tsg
