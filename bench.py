@@ -357,7 +357,8 @@ def _job_results(ctx, ids, jobs):
 
 
 def bench_batch(tsg):
-    """64 uneven QC codes: every job alone, then all of them as one batch."""
+    """64 uneven QC codes: every job alone, then all of them as one batch, three
+    alternating times after a warm-up of each; the medians are reported."""
     import numpy as np
     import workloads
     codes = workloads.batch_codes()
@@ -398,15 +399,19 @@ def bench_batch(tsg):
         st = ctx.stats()
         return _job_results(ctx, ids, jobs), st
 
-    _say("batched: warm-up (autotunes every code)")
-    plain(jobs)
-    batched(jobs)
-    t0 = time.perf_counter()
-    ref = plain(jobs)
-    t_plain = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    got, st = batched(jobs)
-    t_batch = time.perf_counter() - t0
+    def timed_pairs(js, reps):
+        """reps alternating runs of each form; the medians and every time."""
+        tp, tb, same = [], [], True
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            ref = plain(js)
+            tp.append(time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            got, st = batched(js)
+            tb.append(time.perf_counter() - t0)
+            same = same and all(same_job(a, b) for a, b in zip(ref, got))
+        return float(np.median(tp)), float(np.median(tb)), tp, tb, ref, st, same
+
     def same_job(a, b):
         if a[0] != b[0] or a[3] != b[3]:
             return False
@@ -414,7 +419,10 @@ def bench_batch(tsg):
             return a[1] == b[1] and a[2] == b[2]
         return (np.array_equal(a[1], b[1]) and np.array_equal(a[2][0], b[2][0])
                 and np.array_equal(a[2][1], b[2][1]))
-    same = all(same_job(a, b) for a, b in zip(ref, got))
+    _say("batched: warm-up (autotunes every code)")
+    plain(jobs)
+    batched(jobs)
+    t_plain, t_batch, tps, tbs, ref, st, same = timed_pairs(jobs, 3)
     eu = sum(r[3] for r in ref)
     ts = sum(len(r[2][0]) for r in ref if r[0] == "search")
     # the same codes with small jobs (256 patterns, 1024 IS frames): a plain
@@ -427,14 +435,8 @@ def bench_batch(tsg):
             small.append((kind, g, data, dict(kw, n_frames=1024)))
     plain(small)
     batched(small)
-    t0 = time.perf_counter()
-    ref_s = plain(small)
-    t_plain_s = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    got_s, _ = batched(small)
-    t_batch_s = time.perf_counter() - t0
+    t_plain_s, t_batch_s, tps_s, tbs_s, ref_s, _, same_s = timed_pairs(small, 3)
     eu_s = sum(r[3] for r in ref_s)
-    same_s = all(same_job(a, b) for a, b in zip(ref_s, got_s))
     ctx.close()
     return {"workload": "64 QC codes, bases 3x6/4x8/3x12/4x24, Z 16..384 (seed 4); per code 4096 "
                         "impulse patterns OMS-i8 20it + 16384 IS frames SPA (Q20 messages, f32 phi) 50it at 3 dB",
@@ -444,8 +446,11 @@ def bench_batch(tsg):
             "batched": {"seconds": t_batch, "edge_updates_per_s": eu / t_batch,
                         "ts_found_per_s": ts / t_batch, "decode_launches": st["decode_launches"]},
             "speedup": t_plain / t_batch, "results_identical": bool(same),
+            "timing": "median of 3 alternating runs of each form",
+            "plain_runs_s": tps, "batched_runs_s": tbs,
             "small_jobs": {"workload": "the same 64 codes, 256 patterns + 1024 IS frames per code",
                            "plain_s": t_plain_s, "batched_s": t_batch_s,
+                           "plain_runs_s": tps_s, "batched_runs_s": tbs_s,
                            "plain_edge_updates_per_s": eu_s / t_plain_s,
                            "batched_edge_updates_per_s": eu_s / t_batch_s,
                            "speedup": t_plain_s / t_batch_s, "results_identical": bool(same_s)}}
